@@ -1,0 +1,144 @@
+// hd_internal.hpp — structures shared by the host planner and the gfx950
+// kernels of the HDArray runtime.  All are plain data, laid out identically
+// on host and device.
+//
+// GDEF representation (Sec. 2.1 "GDEF", per element exact): every array is
+// viewed as G = n0*n1 rows of n2 elements (normalised planes, rows, cols).
+// Each row holds a run-length list of intervals [start_i, start_{i+1}) with
+// one (owner, holders) state each; adjacent intervals always differ, so the
+// list of a row is unique.  The list of row g lives at ivl[g*cap .. g*cap+cnt[g]).
+#pragma once
+#include <stdint.h>
+
+namespace hd {
+
+constexpr int kHost = 63;
+constexpr int kMaxDev = 63;
+constexpr int kMaxCap = 256;        // largest per-row interval capacity
+constexpr int kMaxRunsRow = 256;    // runs one use row may produce
+constexpr int kMaxCallArrays = 8;   // distinct arrays in one ApplyKernel
+constexpr int kMaxBoundaries = 1024;// elementary boundaries of one GDEF row update
+
+struct Ivl {
+  int32_t start;
+  int32_t owner;
+  uint64_t holders;
+};
+
+struct ArrDev {
+  int64_t n[3];
+  int32_t esize;
+  int32_t cap;
+  Ivl *ivl;
+  int32_t *cnt;
+  char *buf[64];  // endpoint buffers; [63] = host buffer (pinned, device-mapped)
+};
+
+// A use segment of one row for destination dst, or a def segment of device
+// dst (flags bit 0: the host also holds the value afterwards, for Write).
+struct Seg {
+  int32_t dst;
+  int32_t c0, c1;
+  int32_t flags;
+};
+
+// One item of a stacking level: a run (level 1: src, dst, [a0,a1) = cols) or
+// a rectangle (level 2: cols [a0,a1), rows [b0,b1)); pos0/pos1 carry the
+// stacked extent once the item is a head.
+struct Item {
+  int32_t src, dst, a0, a1, b0, b1, pos0, pos1;
+};
+
+struct MsgRec {
+  int32_t aidx, arr, src, dst;
+  int32_t lo[3], hi[3];
+  int32_t argpos, esize;
+  int64_t off, bytes;
+};
+
+struct CallArr {
+  int32_t arr;      // runtime array id
+  int32_t argpos;   // first argument position in the call
+  int32_t esize;
+  int32_t is3d;
+  int64_t n[3];
+  int32_t slice0, slice1;  // level-1 slices (use rows) of this array
+  int32_t grp0, grp1;      // level-1 groups (planes with use rows)
+};
+
+struct MsgHdr {
+  int64_t nmsg;
+  int64_t bytes;
+};
+
+// One stacking level: slices with a (group, position) key and an item list.
+struct Level {
+  int32_t nsl;
+  const int32_t *grp;  // [nsl]
+  const int32_t *pos;  // [nsl]
+  const int32_t *ioff; // [nsl]
+  const int32_t *icnt; // [nsl]
+  const Item *items;
+  // scratch
+  uint64_t *bmask;     // [nchunk]
+  int32_t *bcnt;       // [nchunk]
+  int32_t *bbase;      // [nchunk]
+  int32_t *bandslice;  // [nsl+1]
+  int32_t *nb;         // [1]
+  int32_t *hoff;       // [nsl]
+  int32_t *hcnt;       // [nsl]
+  Item *heads;         // pool
+  int32_t *head_top;   // [1]
+  int64_t head_cap;
+};
+
+struct WorkBox {
+  int32_t dev;
+  int32_t pad;
+  int32_t lo[3], hi[3];
+  int64_t tile0;  // first tile index of this box in the launch
+};
+
+// Per-call constant data uploaded once per plan.
+struct PlanDev {
+  int32_t ncarr;
+  int32_t has3d;
+  CallArr carr[kMaxCallArrays];
+  // level 1
+  int32_t nsl1;
+  const int32_t *grp1;
+  const int32_t *pos1;
+  const int64_t *grow1;  // global row of each slice
+  const int32_t *seg0;
+  const int32_t *nseg;
+  const Seg *useg;
+  int32_t ngrp;
+  const int32_t *grp_aidx;   // [ngrp]
+  const int32_t *grp_plane;  // [ngrp]
+  // level 2 (3-D arrays): slices = groups
+  const int32_t *grp2;  // [ngrp] = aidx
+  const int32_t *pos2;  // [ngrp] = plane
+  // GDEF update rows
+  int32_t ngrow;
+  const int32_t *gr_aidx;
+  const int64_t *gr_row;
+  const int32_t *gr_slice;  // level-1 slice of this row or -1
+  const int32_t *gr_dseg0;
+  const int32_t *gr_ndseg;
+  const Seg *dseg;
+};
+
+struct Work {
+  int32_t *roff;   // [nsl1] run pool offset of each use row
+  int32_t *rcnt;   // [nsl1]
+  Item *runs;
+  int32_t *run_top;
+  int64_t run_cap;
+  int32_t *goff;   // [ngrp] level-1 output offset per group
+  int32_t *gcnt;   // [ngrp]
+  Item *l1out;     // level-1 output (3-D)
+  int64_t l1_cap;
+  int32_t *err;    // device error word (first error wins)
+};
+
+}  // namespace hd

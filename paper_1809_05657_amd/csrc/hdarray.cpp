@@ -1,0 +1,1528 @@
+// hdarray.cpp — host side of the MI355X HDArray runtime: the C ABI of
+// include/hdarray.h, the planner that turns partitions, offsets and absolute
+// sections into per-row use / def segments (Sec. 3, Table 1-2), the plan
+// cache, and the enqueue of one ApplyKernel on two HIP streams:
+//   meta stream: communication-set derivation (Eq. 1-2) and GDEF update
+//                (Eq. 3-4) — metadata only, overlapping the previous kernel;
+//   data stream: pack, unpack (the wire is the staging buffer on one GPU),
+//                the user kernel over all logical devices in one launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hdarray.h"
+#include "hd_internal.hpp"
+
+namespace hd {
+hipError_t launch_runs(const PlanDev &P, const ArrDev *A, const Work &W, hipStream_t s);
+hipError_t launch_level(const Level &L, int32_t *err, hipStream_t s);
+hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr, int64_t cap,
+                          int mode, hipStream_t s);
+hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
+hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
+                       int unpack, hipStream_t s);
+int64_t tiles_for(int kind, const int32_t *lo, const int32_t *hi, int esize, int th);
+hipError_t launch_user(int kind, int th, const WorkBox *wb, int nbox, const ArrDev *A, const int *args,
+                       int64_t ntiles, const float *coef, hipStream_t s);
+hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const ArrDev *A, int arr, double *pf,
+                         uint32_t *pi, void *res, hipStream_t s);
+hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipStream_t s);
+int reduce_blocks();
+}  // namespace hd
+
+using namespace hd;
+
+// ---------------------------------------------------------------- state
+struct Shape {
+  int kind;  // 0 box (normalised, half-open), 1 trapezoid (2-D)
+  int64_t lo[3], hi[3];
+  int64_t c[8];
+};
+
+struct hd_array {
+  int id;
+  int type;  // 0 f32, 1 i32, 2 f64
+  int esize;
+  int dim;
+  int64_t n[3];
+  int64_t N;
+  std::string sym;
+  char *host;
+  char *host_dev;
+  char *buf[kMaxDev];
+  Ivl *ivl;
+  int32_t *cnt;
+  int cap;
+};
+
+struct Partition {
+  int dim, ndev;
+  int64_t lo[kMaxDev][3], hi[kMaxDev][3];
+};
+
+struct Kernel {
+  std::string name;
+  int builtin;  // 1 jacobi2d, 2 copy, 3 stencil3d7, 4 matmul, 5 tri2d
+  int noff[8][2];
+  int32_t off[8][2][64][3];
+  std::map<std::tuple<int, int, int, int>, std::vector<Shape>> abs;  // (part, arr, dev, uod)
+  int64_t version;
+};
+
+struct Plan {
+  PlanDev P;
+  void *mem = nullptr;
+  int nsl1 = 0, ngrp = 0, ngrow = 0, has3d = 0;
+  int64_t stg_bound = 0;  // bytes
+  // user kernel
+  int ukind = 0, th = 16;
+  int uargs[3] = {0, 0, 0};
+  WorkBox *wb = nullptr;
+  int nbox = 0;
+  int64_t ntiles = 0;
+};
+
+struct Runtime {
+  bool inited = false;
+  int device = 0;
+  hipStream_t data = nullptr, meta = nullptr;
+  hd_alloc_fn ualloc = nullptr;
+  hd_free_fn ufree = nullptr;
+  void *uctx = nullptr;
+  int row_cap = kMaxCap;
+  std::vector<hd_array *> arrays;
+  std::vector<Partition> parts;
+  std::vector<Kernel> kernels;
+  std::unordered_map<std::string, int> kidx;
+  ArrDev *d_arrs = nullptr;
+  std::vector<ArrDev> h_arrs;
+  int arr_cap = 0;
+  std::map<std::vector<int64_t>, Plan *> plans;
+  // workspace
+  Work W{};
+  int64_t ws_nsl = 0, ws_ngrp = 0, ws_items = 0;
+  uint64_t *bmask = nullptr;
+  int32_t *bcnt = nullptr, *bbase = nullptr, *bandslice = nullptr, *hoff = nullptr, *hcnt = nullptr;
+  Item *heads = nullptr;
+  int32_t *counters = nullptr;  // [0] run_top [1] head_top [2] nb [3] err
+  MsgRec *tab[2] = {nullptr, nullptr};
+  MsgHdr *hdr[2] = {nullptr, nullptr};
+  hipEvent_t ev_cs[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
+  bool free_pending[2] = {false, false};
+  int parity = 0, last_tab = -1;
+  char *staging = nullptr;
+  int64_t staging_cap = 0;
+  double *red_pf = nullptr;
+  uint32_t *red_pi = nullptr;
+  void *red_res_dev = nullptr;
+  char *red_res_host = nullptr;
+  hd_stats_t stats{};
+  // opt-in phase timing
+  int prof = 0;  // bit p: time phase p
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_pending;
+};
+
+static Runtime R;
+static thread_local int g_last_error = 0;
+
+static int fail(int code) {
+  g_last_error = code;
+  return code;
+}
+
+#define HIPCK(x)                                                                              \
+  do {                                                                                        \
+    hipError_t _e = (x);                                                                      \
+    if (_e != hipSuccess) {                                                                   \
+      fprintf(stderr, "hdarray: HIP error %s at %s:%d\n", hipGetErrorString(_e), __FILE__, __LINE__); \
+      return fail(HD_EHIP);                                                                   \
+    }                                                                                         \
+  } while (0)
+
+static void *dalloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (R.ualloc) return R.ualloc(bytes, R.uctx);
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+static void dfree(void *p) {
+  if (!p) return;
+  if (R.ufree)
+    R.ufree(p, R.uctx);
+  else
+    (void)hipFree(p);
+}
+
+static void normalise(int dim, const int64_t *v, int64_t fill, int64_t *out) {
+  out[0] = out[1] = fill;
+  if (dim == 1) out[2] = v[0];
+  if (dim == 2) {
+    out[1] = v[0];
+    out[2] = v[1];
+  }
+  if (dim == 3) {
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+  }
+}
+
+static int64_t floordiv(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) q--;
+  return q;
+}
+
+// ------------------------------------------------------------ array table
+static int push_arrdev(hd_array *a) {
+  ArrDev &d = R.h_arrs[a->id];
+  memset(&d, 0, sizeof(d));
+  for (int k = 0; k < 3; ++k) d.n[k] = a->n[k];
+  d.esize = a->esize;
+  d.cap = a->cap;
+  d.ivl = a->ivl;
+  d.cnt = a->cnt;
+  for (int e = 0; e < kMaxDev; ++e) d.buf[e] = a->buf[e];
+  d.buf[kHost] = a->host_dev;
+  HIPCK(hipMemcpyAsync(R.d_arrs + a->id, &d, sizeof(ArrDev), hipMemcpyHostToDevice, R.meta));
+  HIPCK(hipStreamSynchronize(R.meta));
+  return HD_OK;
+}
+
+static int ensure_buf(hd_array *a, int dev) {
+  if (dev == kHost || a->buf[dev]) return HD_OK;
+  // the meta stream may be reading the table entry; order the update after it
+  HIPCK(hipStreamSynchronize(R.meta));
+  HIPCK(hipStreamSynchronize(R.data));
+  void *p = dalloc((size_t)a->N * a->esize);
+  if (!p) return fail(HD_ENOMEM);
+  HIPCK(hipMemset(p, 0, (size_t)a->N * a->esize));
+  a->buf[dev] = (char *)p;
+  return push_arrdev(a);
+}
+
+// ------------------------------------------------------------- init/exit
+extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char *dpath) {
+  (void)kpath;
+  (void)dpath;
+  if (R.inited) return R.device;
+  for (int i = 0; i < argc && argv; ++i) {
+    if (argv[i] && !strncmp(argv[i], "--hd-row-cap=", 13)) {
+      int c = atoi(argv[i] + 13);
+      if (c >= 4 && c <= kMaxCap) R.row_cap = c;
+    }
+  }
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  R.device = dev;
+  HIPCK(hipStreamCreateWithFlags(&R.meta, hipStreamNonBlocking));
+  for (int k = 0; k < 2; ++k) {
+    HIPCK(hipEventCreateWithFlags(&R.ev_cs[k], hipEventDisableTiming));
+    HIPCK(hipEventCreateWithFlags(&R.ev_free[k], hipEventDisableTiming));
+  }
+  R.arr_cap = 4096;
+  R.h_arrs.assign(R.arr_cap, ArrDev{});
+  R.d_arrs = (ArrDev *)dalloc(sizeof(ArrDev) * R.arr_cap);
+  R.counters = (int32_t *)dalloc(64);
+  if (!R.d_arrs || !R.counters) return fail(HD_ENOMEM);
+  HIPCK(hipMemset(R.counters, 0, 64));
+  R.W.run_top = R.counters + 0;
+  R.W.err = R.counters + 3;
+  HIPCK(hipHostMalloc((void **)&R.red_res_host, 64, hipHostMallocDefault));
+  R.red_res_dev = dalloc(64);
+  R.red_pf = (double *)dalloc(sizeof(double) * kMaxDev * 64 * 4);
+  R.red_pi = (uint32_t *)dalloc(sizeof(uint32_t) * kMaxDev * 64 * 4);
+  R.inited = true;
+  return dev;
+}
+
+static void free_ws();
+
+extern "C" void hdarray_exit(void) {
+  if (!R.inited) return;
+  (void)hipStreamSynchronize(R.meta);
+  (void)hipStreamSynchronize(R.data);
+  for (auto &kv : R.plans) {
+    dfree(kv.second->mem);
+    delete kv.second;
+  }
+  R.plans.clear();
+  for (hd_array *a : R.arrays) {
+    if (!a) continue;
+    for (int e = 0; e < kMaxDev; ++e) dfree(a->buf[e]);
+    dfree(a->ivl);
+    dfree(a->cnt);
+    (void)hipHostFree(a->host);
+    delete a;
+  }
+  R.arrays.clear();
+  free_ws();
+  dfree(R.d_arrs);
+  dfree(R.counters);
+  dfree(R.red_res_dev);
+  dfree(R.red_pf);
+  dfree(R.red_pi);
+  (void)hipHostFree(R.red_res_host);
+  for (int k = 0; k < 2; ++k) {
+    (void)hipEventDestroy(R.ev_cs[k]);
+    (void)hipEventDestroy(R.ev_free[k]);
+  }
+  for (auto &p : R.prof_pending) {
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  for (hipEvent_t e : R.ev_pool) (void)hipEventDestroy(e);
+  (void)hipStreamDestroy(R.meta);
+  hd_alloc_fn ua = R.ualloc;
+  hd_free_fn uf = R.ufree;
+  void *uc = R.uctx;
+  hipStream_t ds = R.data;
+  R = Runtime();
+  R.ualloc = ua;
+  R.ufree = uf;
+  R.uctx = uc;
+  R.data = ds;
+}
+
+extern "C" void hdarray_show_device_info(int dev_id) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev_id) != hipSuccess) {
+    g_last_error = HD_EHIP;
+    return;
+  }
+  printf("HDArray device %d: %s (%s), %d CUs, %.1f GiB HBM, wavefront %d, LDS/CU %zu KiB\n", dev_id, p.name,
+         p.gcnArchName, p.multiProcessorCount, p.totalGlobalMem / 1073741824.0, p.warpSize,
+         (size_t)p.maxSharedMemoryPerMultiProcessor / 1024);
+}
+
+extern "C" int hdarray_set_stream(void *s) {
+  R.data = (hipStream_t)s;
+  return HD_OK;
+}
+
+extern "C" int hdarray_set_allocator(hd_alloc_fn a, hd_free_fn f, void *ctx) {
+  if ((a == nullptr) != (f == nullptr)) return fail(HD_EINVAL);
+  R.ualloc = a;
+  R.ufree = f;
+  R.uctx = ctx;
+  return HD_OK;
+}
+
+extern "C" int hdarray_last_error(void) { return g_last_error; }
+
+extern "C" const char *hdarray_error_string(int code) {
+  switch (code) {
+    case HD_OK: return "ok";
+    case HD_EINVAL: return "invalid argument";
+    case HD_EBOUNDS: return "section outside the array";
+    case HD_ERACE: return "def sections of different devices overlap";
+    case HD_EKERNEL: return "unknown kernel";
+    case HD_ENOMEM: return "out of memory";
+    case HD_EHIP: return "HIP runtime error";
+    case HD_ESTATE: return "runtime not initialised";
+    case HD_ECAPACITY: return "GDEF row list or work pool capacity exceeded";
+  }
+  return "unknown error";
+}
+
+// ---------------------------------------------------------------- create
+extern "C" hd_array_t *hdarray_create(const char *sym, const char *type, const void *uA, int dim,
+                                      const int64_t *sizes) {
+  if (!R.inited) {
+    fail(HD_ESTATE);
+    return nullptr;
+  }
+  if (dim < 1 || dim > 3 || !type || !sizes) {
+    fail(HD_EINVAL);
+    return nullptr;
+  }
+  int t;
+  if (!strcmp(type, "float"))
+    t = 0;
+  else if (!strcmp(type, "int"))
+    t = 1;
+  else if (!strcmp(type, "double"))
+    t = 2;
+  else {
+    fail(HD_EINVAL);
+    return nullptr;
+  }
+  if ((int)R.arrays.size() >= R.arr_cap) {
+    fail(HD_ENOMEM);
+    return nullptr;
+  }
+  hd_array *a = new hd_array();
+  a->id = (int)R.arrays.size();
+  a->type = t;
+  a->esize = t == 2 ? 8 : 4;
+  a->dim = dim;
+  a->sym = sym ? sym : "";
+  normalise(dim, sizes, 1, a->n);
+  for (int k = 0; k < 3; ++k)
+    if (a->n[k] < 1 || a->n[k] > (1ll << 31) - 1) {
+      delete a;
+      fail(HD_EINVAL);
+      return nullptr;
+    }
+  a->N = a->n[0] * a->n[1] * a->n[2];
+  size_t bytes = (size_t)a->N * a->esize;
+  if (hipHostMalloc((void **)&a->host, bytes, hipHostMallocDefault) != hipSuccess) {
+    delete a;
+    fail(HD_ENOMEM);
+    return nullptr;
+  }
+  if (uA)
+    memcpy(a->host, uA, bytes);
+  else
+    memset(a->host, 0, bytes);
+  void *hd = nullptr;
+  if (hipHostGetDevicePointer(&hd, a->host, 0) != hipSuccess) hd = a->host;
+  a->host_dev = (char *)hd;
+  a->cap = (int)std::min<int64_t>(R.row_cap, a->n[2]);
+  if (a->cap < 4) a->cap = std::min<int64_t>(4, a->n[2]) > 0 ? 4 : 1;
+  const int64_t rows = a->n[0] * a->n[1];
+  a->ivl = (Ivl *)dalloc(sizeof(Ivl) * rows * a->cap);
+  a->cnt = (int32_t *)dalloc(sizeof(int32_t) * rows);
+  if (!a->ivl || !a->cnt) {
+    fail(HD_ENOMEM);
+    return nullptr;
+  }
+  // every row: one interval [0, n2) owned and held by the host (Sec. 2.1:
+  // before any device writes, the host holds the only copy)
+  if (launch_init_rows(a->ivl, a->cnt, rows, a->cap, R.meta) != hipSuccess) {
+    fail(HD_EHIP);
+    return nullptr;
+  }
+  R.arrays.push_back(a);
+  if (push_arrdev(a) != HD_OK) return nullptr;
+  return a;
+}
+
+extern "C" int hdarray_array_id(const hd_array_t *a) { return a ? a->id : -1; }
+
+static hd_array *get_arr(hd_array_t *a) {
+  if (!a || a->id < 0 || a->id >= (int)R.arrays.size() || R.arrays[a->id] != a) return nullptr;
+  return a;
+}
+
+// ------------------------------------------------------------ partitions
+static void block_factors(int P, int dim, int *f) {
+  int best[3] = {P, 1, 1}, bs = P + 1, bm = P + 1;
+  if (dim == 1) {
+    f[0] = P;
+    return;
+  }
+  for (int a = 1; a <= P; ++a) {
+    if (P % a) continue;
+    if (dim == 2) {
+      int b = P / a;
+      if (a < b) continue;
+      int sp = a - b;
+      if (sp < bs || (sp == bs && a < bm)) {
+        bs = sp;
+        bm = a;
+        best[0] = a;
+        best[1] = b;
+      }
+    } else {
+      for (int b = 1; b <= P / a; ++b) {
+        if ((P / a) % b) continue;
+        int c = P / a / b;
+        if (!(a >= b && b >= c)) continue;
+        int sp = a - c;
+        if (sp < bs || (sp == bs && a < bm)) {
+          bs = sp;
+          bm = a;
+          best[0] = a;
+          best[1] = b;
+          best[2] = c;
+        }
+      }
+    }
+  }
+  for (int k = 0; k < dim; ++k) f[k] = best[k];
+}
+
+extern "C" int hdarray_partition(hd_part_t type, int dim, const int64_t *sizes, const int64_t *rlo,
+                                 const int64_t *rhi, int ndev) {
+  if (!R.inited) return fail(HD_ESTATE);
+  if (dim < 1 || dim > 3 || ndev < 1 || ndev > kMaxDev || !sizes || !rlo || !rhi) return fail(HD_EINVAL);
+  if (type < HD_ROW || type > HD_BLOCK) return fail(HD_EINVAL);
+  for (int k = 0; k < dim; ++k)
+    if (rlo[k] < 0 || rhi[k] > sizes[k] || rlo[k] > rhi[k]) return fail(HD_EBOUNDS);
+  int f[3] = {1, 1, 1};
+  if (type == HD_ROW)
+    f[0] = ndev;
+  else if (type == HD_COL)
+    f[dim == 1 ? 0 : 1] = ndev;
+  else
+    block_factors(ndev, dim, f);
+  Partition p{};
+  p.dim = dim;
+  p.ndev = ndev;
+  for (int d = 0; d < ndev; ++d) {
+    int g[3] = {0, 0, 0}, rem = d;
+    for (int k = dim - 1; k >= 0; --k) {
+      g[k] = rem % f[k];
+      rem /= f[k];
+    }
+    int64_t lo[3], hi[3];
+    for (int k = 0; k < dim; ++k) {
+      const int64_t L = rlo[k], N = rhi[k] - rlo[k];
+      lo[k] = L + (int64_t)g[k] * N / f[k];
+      hi[k] = L + ((int64_t)g[k] + 1) * N / f[k];
+    }
+    normalise(dim, lo, 0, p.lo[d]);
+    normalise(dim, hi, 1, p.hi[d]);
+  }
+  R.parts.push_back(p);
+  return (int)R.parts.size() - 1;
+}
+
+extern "C" int hdarray_partition_manual(int dim, int ndev, const int64_t *lo, const int64_t *hi) {
+  if (!R.inited) return fail(HD_ESTATE);
+  if (dim < 1 || dim > 3 || ndev < 1 || ndev > kMaxDev || !lo || !hi) return fail(HD_EINVAL);
+  Partition p{};
+  p.dim = dim;
+  p.ndev = ndev;
+  for (int d = 0; d < ndev; ++d) {
+    for (int k = 0; k < dim; ++k)
+      if (lo[d * dim + k] < 0 || lo[d * dim + k] > hi[d * dim + k]) return fail(HD_EBOUNDS);
+    normalise(dim, lo + d * dim, 0, p.lo[d]);
+    normalise(dim, hi + d * dim, 1, p.hi[d]);
+  }
+  R.parts.push_back(p);
+  return (int)R.parts.size() - 1;
+}
+
+extern "C" int hdarray_partition_region(int part, int dev, int64_t *lo3, int64_t *hi3) {
+  if (part < 0 || part >= (int)R.parts.size()) return fail(HD_EINVAL);
+  const Partition &p = R.parts[part];
+  if (dev < 0 || dev >= p.ndev) return fail(HD_EINVAL);
+  memcpy(lo3, p.lo[dev], sizeof(int64_t) * 3);
+  memcpy(hi3, p.hi[dev], sizeof(int64_t) * 3);
+  return HD_OK;
+}
+
+static bool part_dev_empty(const Partition &p, int d) {
+  for (int k = 0; k < 3; ++k)
+    if (p.lo[d][k] >= p.hi[d][k]) return true;
+  return false;
+}
+
+// --------------------------------------------------------------- kernels
+extern "C" int hdarray_register_kernel(const char *kname, const char *builtin) {
+  if (!R.inited) return fail(HD_ESTATE);
+  if (!kname || !builtin) return fail(HD_EINVAL);
+  int b = 0;
+  if (!strcmp(builtin, "jacobi2d"))
+    b = 1;
+  else if (!strcmp(builtin, "copy"))
+    b = 2;
+  else if (!strcmp(builtin, "stencil3d7"))
+    b = 3;
+  else if (!strcmp(builtin, "matmul"))
+    b = 4;
+  else if (!strcmp(builtin, "tri2d"))
+    b = 5;
+  else
+    return fail(HD_EKERNEL);
+  if (R.kidx.count(kname)) return fail(HD_EINVAL);
+  Kernel k;
+  k.name = kname;
+  k.builtin = b;
+  memset(k.noff, 0, sizeof(k.noff));
+  memset(k.off, 0, sizeof(k.off));
+  k.version = 0;
+  R.kernels.push_back(std::move(k));
+  R.kidx[kname] = (int)R.kernels.size() - 1;
+  return (int)R.kernels.size() - 1;
+}
+
+static Kernel *get_kernel(const char *kname) {
+  if (!kname) return nullptr;
+  auto it = R.kidx.find(kname);
+  return it == R.kidx.end() ? nullptr : &R.kernels[it->second];
+}
+
+extern "C" int hdarray_set_offsets(const char *kname, int arg, int use_or_def, int noff, const int32_t *off) {
+  Kernel *k = get_kernel(kname);
+  if (!k) return fail(HD_EKERNEL);
+  if (arg < 0 || arg >= 8 || use_or_def < 0 || use_or_def > 1 || noff < 0 || noff > 64 || (noff && !off))
+    return fail(HD_EINVAL);
+  k->noff[arg][use_or_def] = noff;
+  for (int i = 0; i < noff; ++i)
+    for (int j = 0; j < 3; ++j) k->off[arg][use_or_def][i][j] = off[i * 3 + j];
+  k->version++;
+  return HD_OK;
+}
+
+static int set_abs(const char *kname, int part, hd_array_t *ah, int dev, int dim, const int64_t *lo,
+                   const int64_t *hi, int uod) {
+  Kernel *k = get_kernel(kname);
+  hd_array *a = get_arr(ah);
+  if (!k) return fail(HD_EKERNEL);
+  if (!a || part < 0 || part >= (int)R.parts.size() || dev < 0 || dev >= kMaxDev || dim != a->dim || !lo || !hi)
+    return fail(HD_EINVAL);
+  Shape s{};
+  normalise(dim, lo, 0, s.lo);
+  normalise(dim, hi, 1, s.hi);
+  for (int j = 0; j < 3; ++j)
+    if (s.lo[j] < 0 || s.hi[j] > a->n[j] || s.lo[j] > s.hi[j]) return fail(HD_EBOUNDS);
+  k->abs[std::make_tuple(part, a->id, dev, uod)].push_back(s);
+  k->version++;
+  return HD_OK;
+}
+
+extern "C" int hdarray_set_absolute_use(const char *kname, int part, hd_array_t *a, int dev, int dim,
+                                        const int64_t *lo, const int64_t *hi) {
+  return set_abs(kname, part, a, dev, dim, lo, hi, 0);
+}
+extern "C" int hdarray_set_absolute_def(const char *kname, int part, hd_array_t *a, int dev, int dim,
+                                        const int64_t *lo, const int64_t *hi) {
+  return set_abs(kname, part, a, dev, dim, lo, hi, 1);
+}
+
+static int set_trap(const char *kname, int part, hd_array_t *ah, int dev, const int64_t *c, int uod) {
+  Kernel *k = get_kernel(kname);
+  hd_array *a = get_arr(ah);
+  if (!k) return fail(HD_EKERNEL);
+  if (!a || a->dim != 2 || part < 0 || part >= (int)R.parts.size() || dev < 0 || dev >= kMaxDev || !c)
+    return fail(HD_EINVAL);
+  if (c[0] != c[2] || c[4] != c[6] || c[0] > c[4]) return fail(HD_EINVAL);
+  Shape s{};
+  s.kind = 1;
+  memcpy(s.c, c, sizeof(s.c));
+  k->abs[std::make_tuple(part, a->id, dev, uod)].push_back(s);
+  k->version++;
+  return HD_OK;
+}
+extern "C" int hdarray_set_trapezoid_use(const char *kname, int part, hd_array_t *a, int dev,
+                                         const int64_t *corners) {
+  return set_trap(kname, part, a, dev, corners, 0);
+}
+extern "C" int hdarray_set_trapezoid_def(const char *kname, int part, hd_array_t *a, int dev,
+                                         const int64_t *corners) {
+  return set_trap(kname, part, a, dev, corners, 1);
+}
+
+extern "C" int hdarray_clear_sections(const char *kname, int part, hd_array_t *ah, int dev) {
+  Kernel *k = get_kernel(kname);
+  hd_array *a = get_arr(ah);
+  if (!k) return fail(HD_EKERNEL);
+  if (!a) return fail(HD_EINVAL);
+  for (auto &kv : k->abs) {
+    if (std::get<0>(kv.first) == part && std::get<1>(kv.first) == a->id && (dev < 0 || std::get<2>(kv.first) == dev))
+      kv.second.clear();
+  }
+  k->version++;
+  return HD_OK;
+}
+
+// ---------------------------------------------------------------- planner
+// Row spans of a shape: calls fn(plane, row, c0, c1) with [c0, c1) clipped.
+template <typename F>
+static void shape_rows(const Shape &s, const int64_t *n, F fn) {
+  if (s.kind == 0) {
+    int64_t lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::max<int64_t>(s.lo[k], 0);
+      hi[k] = std::min<int64_t>(s.hi[k], n[k]);
+      if (lo[k] >= hi[k]) return;
+    }
+    for (int64_t p = lo[0]; p < hi[0]; ++p)
+      for (int64_t r = lo[1]; r < hi[1]; ++r) fn(p, r, lo[2], hi[2]);
+  } else {
+    const int64_t r0 = s.c[0], r1 = s.c[4];
+    for (int64_t r = std::max<int64_t>(r0, 0); r <= std::min<int64_t>(r1, n[1] - 1); ++r) {
+      int64_t l, rt;
+      if (r1 == r0) {
+        l = s.c[1];
+        rt = s.c[3];
+      } else {
+        l = s.c[1] + floordiv((r - r0) * (s.c[5] - s.c[1]), r1 - r0);
+        rt = s.c[3] + floordiv((r - r0) * (s.c[7] - s.c[3]), r1 - r0);
+      }
+      l = std::max<int64_t>(l, 0);
+      rt = std::min<int64_t>(rt, n[2] - 1);
+      if (l <= rt) fn(0, r, l, rt + 1);
+    }
+  }
+}
+
+struct Span {
+  int64_t row;
+  int32_t e, c0, c1, flags;
+};
+
+// Per row, per endpoint: union of the spans (overlapping or touching merged).
+static void merge_spans(std::vector<Span> &v) {
+  std::sort(v.begin(), v.end(), [](const Span &a, const Span &b) {
+    return std::tie(a.row, a.e, a.c0) < std::tie(b.row, b.e, b.c0);
+  });
+  size_t o = 0;
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (o && v[o - 1].row == v[i].row && v[o - 1].e == v[i].e && v[i].c0 <= v[o - 1].c1) {
+      v[o - 1].c1 = std::max(v[o - 1].c1, v[i].c1);
+    } else {
+      v[o++] = v[i];
+    }
+  }
+  v.resize(o);
+}
+
+struct CallArray {
+  hd_array *a;
+  int argpos;
+  std::vector<Shape> use[64];
+  std::vector<Shape> def[64];
+  int def_flags = 0;
+};
+
+template <typename T>
+static size_t push_blob(std::vector<char> &blob, const std::vector<T> &v) {
+  size_t off = (blob.size() + 255) / 256 * 256;
+  blob.resize(off + v.size() * sizeof(T) + 16);
+  if (!v.empty()) memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+  return off;
+}
+
+static void free_ws() {
+  dfree(R.W.roff);
+  dfree(R.W.rcnt);
+  dfree(R.W.runs);
+  dfree(R.W.goff);
+  dfree(R.W.gcnt);
+  dfree(R.W.l1out);
+  dfree(R.bmask);
+  dfree(R.bcnt);
+  dfree(R.bbase);
+  dfree(R.bandslice);
+  dfree(R.hoff);
+  dfree(R.hcnt);
+  dfree(R.heads);
+  for (int k = 0; k < 2; ++k) {
+    dfree(R.tab[k]);
+    dfree(R.hdr[k]);
+    R.tab[k] = nullptr;
+    R.hdr[k] = nullptr;
+  }
+  dfree(R.staging);
+  R.staging = nullptr;
+  R.staging_cap = 0;
+  R.W.roff = R.W.rcnt = R.W.goff = R.W.gcnt = nullptr;
+  R.W.runs = R.W.l1out = nullptr;
+  R.bmask = nullptr;
+  R.bcnt = R.bbase = R.bandslice = R.hoff = R.hcnt = nullptr;
+  R.heads = nullptr;
+  R.ws_nsl = R.ws_ngrp = R.ws_items = 0;
+}
+
+static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg) {
+  nsl = std::max<int64_t>(nsl, ngrp);
+  if (nsl <= R.ws_nsl && ngrp <= R.ws_ngrp && items <= R.ws_items && stg <= R.staging_cap) return HD_OK;
+  HIPCK(hipStreamSynchronize(R.meta));
+  HIPCK(hipStreamSynchronize(R.data));
+  if (nsl > R.ws_nsl || ngrp > R.ws_ngrp || items > R.ws_items) {
+    const int64_t ns = std::max(nsl, R.ws_nsl) + 64, ng = std::max(ngrp, R.ws_ngrp) + 64;
+    const int64_t it = std::max(items, R.ws_items);
+    // keep the staging buffer; release the rest
+    char *stgsave = R.staging;
+    int64_t stgcap = R.staging_cap;
+    R.staging = nullptr;
+    free_ws();
+    R.staging = stgsave;
+    R.staging_cap = stgcap;
+    const int64_t nch = ns / 64 + 2;
+    R.W.roff = (int32_t *)dalloc(4 * ns);
+    R.W.rcnt = (int32_t *)dalloc(4 * ns);
+    R.W.runs = (Item *)dalloc(sizeof(Item) * it);
+    R.W.run_cap = it;
+    R.W.goff = (int32_t *)dalloc(4 * ng);
+    R.W.gcnt = (int32_t *)dalloc(4 * ng);
+    R.W.l1out = (Item *)dalloc(sizeof(Item) * it);
+    R.W.l1_cap = it;
+    R.bmask = (uint64_t *)dalloc(8 * nch);
+    R.bcnt = (int32_t *)dalloc(4 * nch);
+    R.bbase = (int32_t *)dalloc(4 * nch);
+    R.bandslice = (int32_t *)dalloc(4 * (ns + 1));
+    R.hoff = (int32_t *)dalloc(4 * ns);
+    R.hcnt = (int32_t *)dalloc(4 * ns);
+    R.heads = (Item *)dalloc(sizeof(Item) * it);
+    for (int k = 0; k < 2; ++k) {
+      R.tab[k] = (MsgRec *)dalloc(sizeof(MsgRec) * it);
+      R.hdr[k] = (MsgHdr *)dalloc(sizeof(MsgHdr));
+      if (R.hdr[k]) HIPCK(hipMemset(R.hdr[k], 0, sizeof(MsgHdr)));
+    }
+    if (!R.W.roff || !R.W.rcnt || !R.W.runs || !R.W.goff || !R.W.gcnt || !R.W.l1out || !R.bmask || !R.bcnt ||
+        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
+        !R.hdr[1])
+      return fail(HD_ENOMEM);
+    HIPCK(hipMemset(R.W.roff, 0, 4 * ns));
+    HIPCK(hipMemset(R.W.rcnt, 0, 4 * ns));
+    R.ws_nsl = ns;
+    R.ws_ngrp = ng;
+    R.ws_items = it;
+    R.last_tab = -1;
+    R.free_pending[0] = R.free_pending[1] = false;
+  }
+  if (stg > R.staging_cap) {
+    dfree(R.staging);
+    R.staging = (char *)dalloc(stg);
+    if (!R.staging) return fail(HD_ENOMEM);
+    R.staging_cap = stg;
+  }
+  return HD_OK;
+}
+
+// Builds the device plan for one communication + GDEF update.  cas: the
+// distinct arrays of the call in argument order with per-endpoint use and
+// def shapes.
+static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
+  if (cas.size() > (size_t)kMaxCallArrays) return fail(HD_EINVAL);
+  std::vector<int32_t> grp1, pos1, seg0, nseg, grp_aidx, grp_plane, grp2, pos2;
+  std::vector<int64_t> grow1;
+  std::vector<Seg> useg, dseg;
+  std::vector<int32_t> gr_aidx, gr_slice, gr_dseg0, gr_ndseg;
+  std::vector<int64_t> gr_row;
+  PlanDev &P = pl->P;
+  memset(&P, 0, sizeof(P));
+  P.ncarr = (int)cas.size();
+  int64_t stg = 0;
+  int has3d = 0;
+  for (size_t j = 0; j < cas.size(); ++j) {
+    CallArray &ca = cas[j];
+    hd_array *a = ca.a;
+    CallArr &C = P.carr[j];
+    C.arr = a->id;
+    C.argpos = ca.argpos;
+    C.esize = a->esize;
+    C.is3d = a->n[0] > 1;
+    for (int k = 0; k < 3; ++k) C.n[k] = a->n[k];
+    has3d |= C.is3d;
+    // use spans
+    std::vector<Span> us;
+    for (int e = 0; e < 64; ++e)
+      for (const Shape &s : ca.use[e])
+        shape_rows(s, a->n, [&](int64_t p, int64_t r, int64_t c0, int64_t c1) {
+          us.push_back(Span{p * a->n[1] + r, e, (int32_t)c0, (int32_t)c1, 0});
+        });
+    merge_spans(us);
+    // def spans, race check across devices
+    std::vector<Span> ds;
+    for (int e = 0; e < 64; ++e)
+      for (const Shape &s : ca.def[e])
+        shape_rows(s, a->n, [&](int64_t p, int64_t r, int64_t c0, int64_t c1) {
+          ds.push_back(Span{p * a->n[1] + r, e, (int32_t)c0, (int32_t)c1, ca.def_flags});
+        });
+    merge_spans(ds);
+    {
+      std::vector<Span> byc = ds;
+      std::sort(byc.begin(), byc.end(),
+                [](const Span &x, const Span &y) { return std::tie(x.row, x.c0) < std::tie(y.row, y.c0); });
+      for (size_t i = 1; i < byc.size(); ++i)
+        if (byc[i].row == byc[i - 1].row && byc[i].c0 < byc[i - 1].c1 && byc[i].e != byc[i - 1].e)
+          return fail(HD_ERACE);
+    }
+    C.slice0 = (int32_t)grow1.size();
+    C.grp0 = (int32_t)grp_aidx.size();
+    // slices: one per row with use spans, in row order; a group per plane
+    size_t i = 0;
+    std::vector<std::pair<int64_t, int32_t>> slice_of_row;  // (row, slice)
+    while (i < us.size()) {
+      const int64_t row = us[i].row;
+      const int32_t plane = (int32_t)(row / a->n[1]);
+      if (grp_aidx.size() == (size_t)C.grp0 || grp_plane.back() != plane) {
+        grp_aidx.push_back((int32_t)j);
+        grp_plane.push_back(plane);
+        grp2.push_back((int32_t)j);
+        pos2.push_back(plane);
+      }
+      const int32_t s = (int32_t)grow1.size();
+      grp1.push_back((int32_t)grp_aidx.size() - 1);
+      pos1.push_back((int32_t)(row % a->n[1]));
+      grow1.push_back(row);
+      seg0.push_back((int32_t)useg.size());
+      int cnt = 0;
+      for (; i < us.size() && us[i].row == row; ++i) {
+        useg.push_back(Seg{us[i].e, us[i].c0, us[i].c1, 0});
+        stg += (int64_t)(us[i].c1 - us[i].c0) * a->esize;
+        ++cnt;
+      }
+      nseg.push_back(cnt);
+      slice_of_row.push_back({row, s});
+    }
+    C.slice1 = (int32_t)grow1.size();
+    C.grp1 = (int32_t)grp_aidx.size();
+    stg += 16;
+    // GDEF rows: rows with use or def spans
+    size_t a_i = 0, b_i = 0;
+    while (a_i < slice_of_row.size() || b_i < ds.size()) {
+      const int64_t ra = a_i < slice_of_row.size() ? slice_of_row[a_i].first : INT64_MAX;
+      const int64_t rb = b_i < ds.size() ? ds[b_i].row : INT64_MAX;
+      const int64_t row = std::min(ra, rb);
+      gr_aidx.push_back((int32_t)j);
+      gr_row.push_back(row);
+      gr_slice.push_back(ra == row ? slice_of_row[a_i].second : -1);
+      if (ra == row) ++a_i;
+      gr_dseg0.push_back((int32_t)dseg.size());
+      int cnt = 0;
+      while (b_i < ds.size() && ds[b_i].row == row) {
+        dseg.push_back(Seg{ds[b_i].e, ds[b_i].c0, ds[b_i].c1, ds[b_i].flags});
+        ++b_i;
+        ++cnt;
+      }
+      gr_ndseg.push_back(cnt);
+    }
+  }
+  P.has3d = has3d;
+  P.nsl1 = (int32_t)grow1.size();
+  P.ngrp = (int32_t)grp_aidx.size();
+  P.ngrow = (int32_t)gr_row.size();
+  pl->nsl1 = P.nsl1;
+  pl->ngrp = P.ngrp;
+  pl->ngrow = P.ngrow;
+  pl->has3d = has3d;
+  pl->stg_bound = stg;
+  // one device allocation for all plan arrays
+  std::vector<char> blob;
+  size_t o_grp1 = push_blob(blob, grp1), o_pos1 = push_blob(blob, pos1), o_grow1 = push_blob(blob, grow1);
+  size_t o_seg0 = push_blob(blob, seg0), o_nseg = push_blob(blob, nseg), o_useg = push_blob(blob, useg);
+  size_t o_ga = push_blob(blob, grp_aidx), o_gp = push_blob(blob, grp_plane);
+  size_t o_g2 = push_blob(blob, grp2), o_p2 = push_blob(blob, pos2);
+  size_t o_gra = push_blob(blob, gr_aidx), o_grr = push_blob(blob, gr_row), o_grs = push_blob(blob, gr_slice);
+  size_t o_grd0 = push_blob(blob, gr_dseg0), o_grnd = push_blob(blob, gr_ndseg), o_ds = push_blob(blob, dseg);
+  size_t o_wb = (blob.size() + 255) / 256 * 256;
+  blob.resize(o_wb + sizeof(WorkBox) * kMaxDev + 16);
+  pl->mem = dalloc(blob.size());
+  if (!pl->mem) return fail(HD_ENOMEM);
+  char *b = (char *)pl->mem;
+  P.grp1 = (const int32_t *)(b + o_grp1);
+  P.pos1 = (const int32_t *)(b + o_pos1);
+  P.grow1 = (const int64_t *)(b + o_grow1);
+  P.seg0 = (const int32_t *)(b + o_seg0);
+  P.nseg = (const int32_t *)(b + o_nseg);
+  P.useg = (const Seg *)(b + o_useg);
+  P.grp_aidx = (const int32_t *)(b + o_ga);
+  P.grp_plane = (const int32_t *)(b + o_gp);
+  P.grp2 = (const int32_t *)(b + o_g2);
+  P.pos2 = (const int32_t *)(b + o_p2);
+  P.gr_aidx = (const int32_t *)(b + o_gra);
+  P.gr_row = (const int64_t *)(b + o_grr);
+  P.gr_slice = (const int32_t *)(b + o_grs);
+  P.gr_dseg0 = (const int32_t *)(b + o_grd0);
+  P.gr_ndseg = (const int32_t *)(b + o_grnd);
+  P.dseg = (const Seg *)(b + o_ds);
+  pl->wb = (WorkBox *)(b + o_wb);
+  // work boxes are filled by the caller into the host blob first
+  pl->nbox = 0;
+  HIPCK(hipMemcpy(pl->mem, blob.data(), blob.size(), hipMemcpyHostToDevice));
+  // workspace sizing: items bounded by 8 per segment (at least 4M)
+  const int64_t items = std::max<int64_t>(int64_t(1) << 22, 8 * (int64_t)useg.size());
+  return ensure_ws(P.nsl1, P.ngrp, items, stg);
+}
+
+static Level make_level(int which, const PlanDev &P) {
+  Level L{};
+  if (which == 1) {
+    L.nsl = P.nsl1;
+    L.grp = P.grp1;
+    L.pos = P.pos1;
+    L.ioff = R.W.roff;
+    L.icnt = R.W.rcnt;
+    L.items = R.W.runs;
+  } else {
+    L.nsl = P.ngrp;
+    L.grp = P.grp2;
+    L.pos = P.pos2;
+    L.ioff = R.W.goff;
+    L.icnt = R.W.gcnt;
+    L.items = R.W.l1out;
+  }
+  L.bmask = R.bmask;
+  L.bcnt = R.bcnt;
+  L.bbase = R.bbase;
+  L.bandslice = R.bandslice;
+  L.nb = R.counters + 2;
+  L.hoff = R.hoff;
+  L.hcnt = R.hcnt;
+  L.heads = R.heads;
+  L.head_top = R.counters + 1;
+  L.head_cap = R.ws_items;
+  return L;
+}
+
+static hipEvent_t prof_event() {
+  if (!R.ev_pool.empty()) {
+    hipEvent_t e = R.ev_pool.back();
+    R.ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct PhaseTimer {
+  int phase;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  PhaseTimer(int ph, hipStream_t st) : phase(ph), s(st) {
+    if (!((R.prof >> ph) & 1)) return;
+    a = prof_event();
+    b = prof_event();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~PhaseTimer() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, s);
+    R.prof_pending.push_back({phase, {a, b}});
+  }
+};
+
+extern "C" int hdarray_profile(int enable) {
+  R.prof = enable;
+  return HD_OK;
+}
+
+extern "C" int hdarray_profile_read(hd_profile_t *out) {
+  if (!out) return fail(HD_EINVAL);
+  memset(out, 0, sizeof(*out));
+  if (!R.inited) return fail(HD_ESTATE);
+  HIPCK(hipStreamSynchronize(R.meta));
+  HIPCK(hipStreamSynchronize(R.data));
+  for (auto &p : R.prof_pending) {
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    out->ms[p.first] += ms;
+    out->count[p.first] += 1;
+    R.ev_pool.push_back(p.second.first);
+    R.ev_pool.push_back(p.second.second);
+  }
+  R.prof_pending.clear();
+  return HD_OK;
+}
+
+// Enqueues communication (meta: derive; data: pack, unpack) and the GDEF
+// update for a plan; the user kernel (if any) follows on the data stream.
+static int enqueue(Plan *pl, const float *coef) {
+  const int slot = R.parity;
+  R.parity ^= 1;
+  if (R.free_pending[slot]) HIPCK(hipStreamWaitEvent(R.meta, R.ev_free[slot], 0));
+  const PlanDev &P = pl->P;
+  Work W = R.W;
+  {
+  PhaseTimer tm(0, R.meta);
+  HIPCK(launch_runs(P, R.d_arrs, W, R.meta));
+  Level L1 = make_level(1, P);
+  if (!pl->has3d) {
+    HIPCK(launch_level(L1, W.err, R.meta));
+    HIPCK(launch_compact(P, L1, W, R.tab[slot], R.hdr[slot], R.ws_items, 0, R.meta));
+  } else {
+    HIPCK(launch_level(L1, W.err, R.meta));
+    HIPCK(launch_compact(P, L1, W, R.tab[slot], R.hdr[slot], R.ws_items, 1, R.meta));
+    Level L2 = make_level(2, P);
+    HIPCK(launch_level(L2, W.err, R.meta));
+    HIPCK(launch_compact(P, L2, W, R.tab[slot], R.hdr[slot], R.ws_items, 2, R.meta));
+  }
+  HIPCK(hipEventRecord(R.ev_cs[slot], R.meta));
+  HIPCK(launch_gdef(P, R.d_arrs, W, R.meta));
+  }
+  // data stream
+  HIPCK(hipStreamWaitEvent(R.data, R.ev_cs[slot], 0));
+  const int64_t bw = pl->stg_bound / 4 + 1;
+  {
+    PhaseTimer tm(1, R.data);
+    HIPCK(launch_pack(R.tab[slot], R.hdr[slot], R.d_arrs, (uint32_t *)R.staging, bw, 0, R.data));
+  }
+  {
+    PhaseTimer tm(2, R.data);
+    HIPCK(launch_pack(R.tab[slot], R.hdr[slot], R.d_arrs, (uint32_t *)R.staging, bw, 1, R.data));
+  }
+  HIPCK(hipEventRecord(R.ev_free[slot], R.data));
+  R.free_pending[slot] = true;
+  R.last_tab = slot;
+  if (pl->ukind) {
+    PhaseTimer tm(3, R.data);
+    HIPCK(launch_user(pl->ukind, pl->th, pl->wb, pl->nbox, R.d_arrs, pl->uargs, pl->ntiles, coef, R.data));
+  }
+  return HD_OK;
+}
+
+// ---------------------------------------------------------- apply kernel
+struct KSpec {
+  int nargs, out, nin, in[2], dim, nscal;
+};
+static bool kspec(int b, KSpec &s) {
+  memset(&s, 0, sizeof(s));
+  switch (b) {
+    case 1:
+    case 5:
+      s = KSpec{2, 0, 1, {1, 0}, 2, 0};
+      return true;
+    case 2:
+      s = KSpec{2, 0, 1, {1, 0}, 0, 0};
+      return true;
+    case 3:
+      s = KSpec{2, 0, 1, {1, 0}, 3, 7};
+      return true;
+    case 4:
+      s = KSpec{3, 2, 2, {0, 1}, 2, 0};
+      return true;
+  }
+  return false;
+}
+
+// LUSE_d / LDEF_d of one argument (Table 1 offsets composed with the work
+// region, '*' = whole extent, clipped; or the absolute sections).
+static void arg_region(const Kernel &k, int part, int arg, hd_array *a, int uod, int d, const int64_t *wlo,
+                       const int64_t *whi, std::vector<Shape> &out) {
+  bool absmode = false;
+  for (const auto &kv : k.abs)
+    if (std::get<0>(kv.first) == part && std::get<1>(kv.first) == a->id && std::get<3>(kv.first) == uod &&
+        !kv.second.empty())
+      absmode = true;
+  if (absmode) {
+    auto it = k.abs.find(std::make_tuple(part, a->id, d, uod));
+    if (it != k.abs.end()) out.insert(out.end(), it->second.begin(), it->second.end());
+    return;
+  }
+  for (int o = 0; o < k.noff[arg][uod]; ++o) {
+    int32_t off3[3] = {0, 0, 0};
+    bool star3[3] = {false, false, false};
+    for (int j = 0; j < a->dim; ++j) {
+      const int nj = 3 - a->dim + j;
+      const int32_t v = k.off[arg][uod][o][j];
+      if (v == HD_STAR)
+        star3[nj] = true;
+      else
+        off3[nj] = v;
+    }
+    Shape s{};
+    bool empty = false;
+    for (int q = 0; q < 3; ++q) {
+      if (star3[q]) {
+        s.lo[q] = 0;
+        s.hi[q] = a->n[q];
+      } else {
+        s.lo[q] = std::max<int64_t>(wlo[q] + off3[q], 0);
+        s.hi[q] = std::min<int64_t>(whi[q] + off3[q], a->n[q]);
+      }
+      if (s.lo[q] >= s.hi[q]) empty = true;
+    }
+    if (!empty) out.push_back(s);
+  }
+}
+
+static int user_kind(int builtin) {
+  switch (builtin) {
+    case 1: return 1;
+    case 2: return 2;
+    case 3: return 3;
+    case 4: return 4;
+    case 5: return 5;
+  }
+  return 0;
+}
+
+extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, const hd_arg_t *args) {
+  if (!R.inited) return fail(HD_ESTATE);
+  Kernel *k = get_kernel(kname);
+  if (!k) return fail(HD_EKERNEL);
+  if (part < 0 || part >= (int)R.parts.size()) return fail(HD_EINVAL);
+  const Partition &pt = R.parts[part];
+  KSpec ks;
+  if (!kspec(k->builtin, ks)) return fail(HD_EKERNEL);
+  // split arrays and scalars; arrays come first in built-in argument lists
+  std::vector<hd_array *> A;
+  std::vector<double> sc;
+  for (int i = 0; i < nargs; ++i) {
+    if (args[i].kind == HD_ARG_ARRAY) {
+      hd_array *a = get_arr(args[i].v.array);
+      if (!a || !sc.empty()) return fail(HD_EINVAL);
+      A.push_back(a);
+    } else if (args[i].kind == HD_ARG_FLOAT) {
+      sc.push_back(args[i].v.f);
+    } else if (args[i].kind == HD_ARG_INT) {
+      sc.push_back((double)args[i].v.i);
+    } else {
+      return fail(HD_EINVAL);
+    }
+  }
+  if ((int)A.size() != ks.nargs || (int)sc.size() < ks.nscal) return fail(HD_EINVAL);
+  hd_array *ao = A[ks.out];
+  for (int i = 0; i < ks.nin; ++i)
+    if (A[ks.in[i]] == ao) return fail(HD_EINVAL);
+  if (ao->type != 0 && k->builtin != 2) return fail(HD_EINVAL);
+  if (ks.dim && ao->dim != ks.dim) return fail(HD_EINVAL);
+  if (pt.dim != ao->dim) return fail(HD_EINVAL);
+  switch (k->builtin) {
+    case 1:
+    case 2:
+    case 3:
+      if (memcmp(A[0]->n, A[1]->n, sizeof(A[0]->n)) || A[0]->esize != A[1]->esize) return fail(HD_EINVAL);
+      if (k->builtin != 2 && A[1]->type != 0) return fail(HD_EINVAL);
+      break;
+    case 5:
+      if (memcmp(A[0]->n, A[1]->n, sizeof(A[0]->n)) || A[1]->type != 0 || A[0]->n[1] != A[0]->n[2])
+        return fail(HD_EINVAL);
+      break;
+    case 4:
+      if (A[0]->type || A[1]->type || A[0]->dim != 2 || A[1]->dim != 2) return fail(HD_EINVAL);
+      if (A[0]->n[2] != A[1]->n[1] || A[2]->n[1] != A[0]->n[1] || A[2]->n[2] != A[1]->n[2]) return fail(HD_EINVAL);
+      break;
+  }
+  for (int d = 0; d < pt.ndev; ++d)
+    for (int j = 0; j < 3; ++j)
+      if (pt.hi[d][j] > ao->n[j]) return fail(HD_EBOUNDS);
+  // plan cache key
+  std::vector<int64_t> key = {1, (int64_t)(k - &R.kernels[0]), part, k->version};
+  for (hd_array *a : A) key.push_back(a->id);
+  Plan *pl = nullptr;
+  auto it = R.plans.find(key);
+  if (it != R.plans.end()) {
+    pl = it->second;
+  } else {
+    std::vector<CallArray> cas;
+    for (int i = 0; i < (int)A.size(); ++i) {
+      bool seen = false;
+      for (auto &c : cas)
+        if (c.a == A[i]) seen = true;
+      if (seen) continue;
+      cas.emplace_back();
+      cas.back().a = A[i];
+      cas.back().argpos = i;
+    }
+    for (auto &c : cas)
+      for (int i = 0; i < (int)A.size(); ++i) {
+        if (A[i] != c.a) continue;
+        for (int d = 0; d < pt.ndev; ++d) {
+          if (part_dev_empty(pt, d)) continue;
+          arg_region(*k, part, i, c.a, 0, d, pt.lo[d], pt.hi[d], c.use[d]);
+          arg_region(*k, part, i, c.a, 1, d, pt.lo[d], pt.hi[d], c.def[d]);
+        }
+      }
+    // every device touching an array gets its buffer
+    for (auto &c : cas)
+      for (int d = 0; d < kMaxDev; ++d)
+        if (!c.use[d].empty() || !c.def[d].empty())
+          if (ensure_buf(c.a, d) != HD_OK) return g_last_error;
+    for (int d = 0; d < pt.ndev; ++d) {
+      if (part_dev_empty(pt, d)) continue;
+      for (hd_array *a : A)
+        if (ensure_buf(a, d) != HD_OK) return g_last_error;
+    }
+    pl = new Plan();
+    if (build_plan(cas, pl) != HD_OK) {
+      dfree(pl->mem);
+      delete pl;
+      return g_last_error;
+    }
+    // work boxes of the user kernel
+    pl->ukind = user_kind(k->builtin);
+    pl->th = 16;
+    std::vector<WorkBox> wb;
+    int64_t t0 = 0;
+    for (int d = 0; d < pt.ndev; ++d) {
+      if (part_dev_empty(pt, d)) continue;
+      WorkBox w{};
+      w.dev = d;
+      for (int q = 0; q < 3; ++q) {
+        w.lo[q] = (int32_t)pt.lo[d][q];
+        w.hi[q] = (int32_t)pt.hi[d][q];
+      }
+      w.tile0 = t0;
+      t0 += tiles_for(pl->ukind == 5 ? 1 : pl->ukind, w.lo, w.hi, ao->esize, pl->th);
+      wb.push_back(w);
+    }
+    pl->nbox = (int)wb.size();
+    pl->ntiles = t0;
+    if (!wb.empty()) HIPCK(hipMemcpy(pl->wb, wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice));
+    if (k->builtin == 4) {
+      pl->uargs[0] = A[0]->id;
+      pl->uargs[1] = A[1]->id;
+      pl->uargs[2] = A[2]->id;
+    } else {
+      pl->uargs[0] = A[0]->id;
+      pl->uargs[1] = A[1]->id;
+    }
+    R.plans[key] = pl;
+    R.stats.plans_built++;
+  }
+  float coef[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int e = 0; e < 7 && e < (int)sc.size(); ++e) coef[e] = (float)sc[e];
+  R.stats.calls++;
+  return enqueue(pl, coef);
+}
+
+// ---------------------------------------------------- write/read/reduce
+static int part_boxes(int part, hd_array *a, std::vector<int> &devs) {
+  if (part < 0 || part >= (int)R.parts.size()) return fail(HD_EINVAL);
+  const Partition &pt = R.parts[part];
+  if (pt.dim != a->dim) return fail(HD_EINVAL);
+  for (int d = 0; d < pt.ndev; ++d) {
+    if (part_dev_empty(pt, d)) continue;
+    for (int k = 0; k < 3; ++k)
+      if (pt.hi[d][k] > a->n[k]) return fail(HD_EBOUNDS);
+    devs.push_back(d);
+  }
+  for (size_t x = 0; x < devs.size(); ++x)
+    for (size_t y = x + 1; y < devs.size(); ++y) {
+      bool ov = true;
+      for (int k = 0; k < 3; ++k)
+        if (pt.hi[devs[x]][k] <= pt.lo[devs[y]][k] || pt.hi[devs[y]][k] <= pt.lo[devs[x]][k]) ov = false;
+      if (ov) return fail(HD_EINVAL);
+    }
+  return HD_OK;
+}
+
+static Shape part_shape(const Partition &pt, int d) {
+  Shape s{};
+  for (int k = 0; k < 3; ++k) {
+    s.lo[k] = pt.lo[d][k];
+    s.hi[k] = pt.hi[d][k];
+  }
+  return s;
+}
+
+// plan for an array-only communication (Read: use by the host; Reduce: use by
+// each device of its region; Write: def by each device with the host)
+static Plan *io_plan(int op, int part, hd_array *a) {
+  std::vector<int64_t> key = {2, op, part, a->id};
+  auto it = R.plans.find(key);
+  if (it != R.plans.end()) return it->second;
+  std::vector<int> devs;
+  if (part_boxes(part, a, devs) != HD_OK) return nullptr;
+  const Partition &pt = R.parts[part];
+  std::vector<CallArray> cas(1);
+  cas[0].a = a;
+  cas[0].argpos = 0;
+  for (int d : devs) {
+    if (op == 0) cas[0].use[kHost].push_back(part_shape(pt, d));
+    if (op == 1) cas[0].use[d].push_back(part_shape(pt, d));
+    if (op == 2) cas[0].def[d].push_back(part_shape(pt, d));
+  }
+  cas[0].def_flags = op == 2 ? 1 : 0;
+  for (int d : devs)
+    if (ensure_buf(a, d) != HD_OK) return nullptr;
+  Plan *pl = new Plan();
+  if (build_plan(cas, pl) != HD_OK) {
+    dfree(pl->mem);
+    delete pl;
+    return nullptr;
+  }
+  std::vector<WorkBox> wb;
+  for (int d : devs) {
+    WorkBox w{};
+    w.dev = d;
+    for (int q = 0; q < 3; ++q) {
+      w.lo[q] = (int32_t)pt.lo[d][q];
+      w.hi[q] = (int32_t)pt.hi[d][q];
+    }
+    wb.push_back(w);
+  }
+  pl->nbox = (int)wb.size();
+  if (!wb.empty() && hipMemcpy(pl->wb, wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    fail(HD_EHIP);
+    return nullptr;
+  }
+  R.plans[key] = pl;
+  R.stats.plans_built++;
+  return pl;
+}
+
+static int check_err() {
+  int32_t e = 0;
+  HIPCK(hipMemcpy(&e, R.counters + 3, 4, hipMemcpyDeviceToHost));
+  if (e) {
+    HIPCK(hipMemset(R.counters + 3, 0, 4));
+    return fail(e);
+  }
+  return HD_OK;
+}
+
+extern "C" int hdarray_sync(void) {
+  if (!R.inited) return fail(HD_ESTATE);
+  HIPCK(hipStreamSynchronize(R.meta));
+  HIPCK(hipStreamSynchronize(R.data));
+  return check_err();
+}
+
+extern "C" int hdarray_write(hd_array_t *ah, const void *uA, int part) {
+  if (!R.inited) return fail(HD_ESTATE);
+  hd_array *a = get_arr(ah);
+  if (!a || !uA) return fail(HD_EINVAL);
+  Plan *pl = io_plan(2, part, a);
+  if (!pl) return g_last_error;
+  const Partition &pt = R.parts[part];
+  // the host buffer may be in use by queued packs / unpacks
+  HIPCK(hipStreamSynchronize(R.data));
+  const size_t es = a->esize;
+  for (int d = 0; d < pt.ndev; ++d) {
+    if (part_dev_empty(pt, d)) continue;
+    const int64_t *lo = pt.lo[d], *hi = pt.hi[d];
+    for (int64_t p = lo[0]; p < hi[0]; ++p) {
+      const size_t base = ((size_t)p * a->n[1] + lo[1]) * a->n[2] + lo[2];
+      const size_t pitch = a->n[2] * es, w = (hi[2] - lo[2]) * es, rows = hi[1] - lo[1];
+      for (size_t r = 0; r < rows; ++r)
+        memcpy(a->host + (base + r * a->n[2]) * es, (const char *)uA + (base + r * a->n[2]) * es, w);
+      HIPCK(hipMemcpy2DAsync(a->buf[d] + base * es, pitch, a->host + base * es, pitch, w, rows,
+                             hipMemcpyHostToDevice, R.data));
+    }
+  }
+  // GDEF: definitions by each device with the host as a second holder; no
+  // communication (the plan has no use rows)
+  pl->ukind = 0;
+  HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, R.meta));
+  return HD_OK;
+}
+
+extern "C" int hdarray_read(hd_array_t *ah, void *uA, int part) {
+  if (!R.inited) return fail(HD_ESTATE);
+  hd_array *a = get_arr(ah);
+  if (!a || !uA) return fail(HD_EINVAL);
+  Plan *pl = io_plan(0, part, a);
+  if (!pl) return g_last_error;
+  if (enqueue(pl, nullptr) != HD_OK) return g_last_error;
+  HIPCK(hipStreamSynchronize(R.data));
+  HIPCK(hipStreamSynchronize(R.meta));
+  int rc = check_err();
+  if (rc != HD_OK) return rc;
+  const Partition &pt = R.parts[part];
+  const size_t es = a->esize;
+  for (int d = 0; d < pt.ndev; ++d) {
+    if (part_dev_empty(pt, d)) continue;
+    const int64_t *lo = pt.lo[d], *hi = pt.hi[d];
+    for (int64_t p = lo[0]; p < hi[0]; ++p)
+      for (int64_t r = lo[1]; r < hi[1]; ++r) {
+        const size_t base = ((size_t)p * a->n[1] + r) * a->n[2] + lo[2];
+        memcpy((char *)uA + base * es, a->host + base * es, (hi[2] - lo[2]) * es);
+      }
+  }
+  return HD_OK;
+}
+
+extern "C" int hdarray_reduce(hd_array_t *ah, void *res, hd_reduce_t op, int part) {
+  if (!R.inited) return fail(HD_ESTATE);
+  hd_array *a = get_arr(ah);
+  if (!a || !res || op < HD_SUM || op > HD_MIN) return fail(HD_EINVAL);
+  Plan *pl = io_plan(1, part, a);
+  if (!pl) return g_last_error;
+  if (enqueue(pl, nullptr) != HD_OK) return g_last_error;
+  HIPCK(launch_reduce(a->type, op, pl->wb, pl->nbox, R.d_arrs, a->id, R.red_pf, R.red_pi, R.red_res_dev, R.data));
+  HIPCK(hipMemcpyAsync(R.red_res_host, R.red_res_dev, 8, hipMemcpyDeviceToHost, R.data));
+  HIPCK(hipStreamSynchronize(R.data));
+  HIPCK(hipStreamSynchronize(R.meta));
+  int rc = check_err();
+  if (rc != HD_OK) return rc;
+  memcpy(res, R.red_res_host, a->esize);
+  return HD_OK;
+}
+
+// ----------------------------------------------------------------- dumps
+extern "C" int hdarray_get_stats(hd_stats_t *st) {
+  if (!st) return fail(HD_EINVAL);
+  *st = R.stats;
+  if (R.inited && R.last_tab >= 0) {
+    if (hipStreamSynchronize(R.meta) != hipSuccess || hipStreamSynchronize(R.data) != hipSuccess)
+      return fail(HD_EHIP);
+    MsgHdr h{};
+    HIPCK(hipMemcpy(&h, R.hdr[R.last_tab], sizeof(h), hipMemcpyDeviceToHost));
+    st->last_messages = h.nmsg;
+    st->last_bytes = h.bytes;
+  }
+  return HD_OK;
+}
+
+extern "C" int64_t hdarray_debug_messages(int64_t *out, int64_t cap) {
+  if (!R.inited) return fail(HD_ESTATE);
+  if (hdarray_sync() != HD_OK) return g_last_error;
+  if (R.last_tab < 0) return 0;
+  MsgHdr h{};
+  HIPCK(hipMemcpy(&h, R.hdr[R.last_tab], sizeof(h), hipMemcpyDeviceToHost));
+  std::vector<MsgRec> m(h.nmsg);
+  if (h.nmsg) HIPCK(hipMemcpy(m.data(), R.tab[R.last_tab], sizeof(MsgRec) * h.nmsg, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < h.nmsg && i < cap; ++i) {
+    int64_t *o = out + 12 * i;
+    o[0] = m[i].argpos;
+    o[1] = m[i].arr;
+    o[2] = m[i].src;
+    o[3] = m[i].dst;
+    for (int k = 0; k < 3; ++k) {
+      o[4 + k] = m[i].lo[k];
+      o[7 + k] = m[i].hi[k];
+    }
+    o[10] = m[i].off;
+    o[11] = m[i].bytes;
+  }
+  return h.nmsg;
+}
+
+extern "C" int64_t hdarray_debug_pack(void *out, int64_t cap) {
+  if (!R.inited) return fail(HD_ESTATE);
+  if (hdarray_sync() != HD_OK) return g_last_error;
+  if (R.last_tab < 0) return 0;
+  MsgHdr h{};
+  HIPCK(hipMemcpy(&h, R.hdr[R.last_tab], sizeof(h), hipMemcpyDeviceToHost));
+  const int64_t n = std::min(h.bytes, cap);
+  if (n > 0) HIPCK(hipMemcpy(out, R.staging, n, hipMemcpyDeviceToHost));
+  return h.bytes;
+}
+
+extern "C" int hdarray_debug_gdef(hd_array_t *ah, int8_t *owner, uint64_t *holders) {
+  hd_array *a = get_arr(ah);
+  if (!a) return fail(HD_EINVAL);
+  if (hdarray_sync() != HD_OK) return g_last_error;
+  const int64_t rows = a->n[0] * a->n[1];
+  std::vector<int32_t> cnt(rows);
+  std::vector<Ivl> iv((size_t)rows * a->cap);
+  HIPCK(hipMemcpy(cnt.data(), a->cnt, 4 * rows, hipMemcpyDeviceToHost));
+  HIPCK(hipMemcpy(iv.data(), a->ivl, sizeof(Ivl) * rows * a->cap, hipMemcpyDeviceToHost));
+  for (int64_t g = 0; g < rows; ++g) {
+    const Ivl *L = iv.data() + g * a->cap;
+    for (int i = 0; i < cnt[g]; ++i) {
+      const int64_t e = (i + 1 < cnt[g]) ? L[i + 1].start : a->n[2];
+      for (int64_t c = L[i].start; c < e; ++c) {
+        if (owner) owner[g * a->n[2] + c] = (int8_t)L[i].owner;
+        if (holders) holders[g * a->n[2] + c] = L[i].holders;
+      }
+    }
+  }
+  return HD_OK;
+}
+
+extern "C" int hdarray_debug_device_buffer(hd_array_t *ah, int dev, void *out) {
+  hd_array *a = get_arr(ah);
+  if (!a || !out || dev < 0 || dev > kHost) return fail(HD_EINVAL);
+  if (hdarray_sync() != HD_OK) return g_last_error;
+  if (dev == kHost) {
+    memcpy(out, a->host, (size_t)a->N * a->esize);
+    return HD_OK;
+  }
+  if (!a->buf[dev]) {
+    memset(out, 0, (size_t)a->N * a->esize);
+    return HD_OK;
+  }
+  HIPCK(hipMemcpy(out, a->buf[dev], (size_t)a->N * a->esize, hipMemcpyDeviceToHost));
+  return HD_OK;
+}
+
+extern "C" void *hdarray_device_ptr(hd_array_t *ah, int dev) {
+  hd_array *a = get_arr(ah);
+  if (!a || dev < 0 || dev >= kMaxDev) {
+    fail(HD_EINVAL);
+    return nullptr;
+  }
+  if (ensure_buf(a, dev) != HD_OK) return nullptr;
+  return a->buf[dev];
+}

@@ -1,0 +1,284 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: message tables, pack buffers, expanded GDEF maps and integer / FP32
+stencil data bit-exact; matmul within K * 2^-24 * (|A||B|)_ij (K = inner
+dimension, FP32 accumulation in another order).  Every case runs the same
+program (tests/programs.py) on both sides from the same seeded inputs.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import canon, programs as prog
+from workloads import S3D_COEFFS, jacobi_inputs, stencil3d_inputs, matmul_inputs, ternary_matmul_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hd():
+    import paper_1809_05657_amd as hdm
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    hdm.load()
+    return hdm
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def same_call(rt, orc, arrays, what):
+    """messages, pack bytes and GDEF of the given array pairs must match."""
+    mg, mo = rt.messages(), orc.messages()
+    assert mg.shape == mo.shape, f"{what}: {len(mg)} vs {len(mo)} messages"
+    # array ids may differ between the two runtimes only if creation order did
+    assert np.array_equal(mg, mo), f"{what}: message tables differ\n{mg[:8]}\n{mo[:8]}"
+    pg, po = rt.pack(), orc.pack()
+    assert np.array_equal(pg, po), f"{what}: pack buffers differ"
+    for ag, ao in arrays:
+        og, hg = rt.gdef(ag)
+        oo, ho = orc.gdef(ao)
+        assert np.array_equal(og, oo), f"{what}: owner map differs"
+        assert np.array_equal(hg, ho), f"{what}: holder map differs"
+
+
+def test_jacobi_small_parity(hd):
+    """jacobi_small: 256^2, 4 row partitions, absolute use +-1, 10 steps."""
+    say("case jacobi_small 256x256 ndev=4 steps=10")
+    A0, B0 = jacobi_inputs(256, 1)
+    rt, orc = hd.Runtime(), O.Oracle()
+    g = prog.jacobi_rows(rt, A0, B0)
+    o = prog.jacobi_rows(orc, A0, B0)
+    for it in range(10):
+        if it % 2 == 0:
+            rt.apply("jacAB", g[2], [g[0], g[1]])
+            orc.apply("jacAB", o[2], [o[0], o[1]])
+        else:
+            rt.apply("jacBA", g[2], [g[1], g[0]])
+            orc.apply("jacBA", o[2], [o[1], o[0]])
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"step {it}")
+    for ag, ao in ((g[0], o[0]), (g[1], o[1])):
+        assert np.array_equal(rt.read(ag, g[2]), orc.read(ao, o[2]))
+    assert orc.bad_reads() == 0
+
+
+def test_jacobi_paper_mode_parity(hd):
+    """Sec. 5.1 paper mode: A = J(B) then B = A each iteration."""
+    say("case jacobi paper mode 64x48 ndev=3")
+    A0, B0 = jacobi_inputs(64, 7)
+    A0, B0 = A0[:, :48].copy(), B0[:, :48].copy()
+    rt, orc = hd.Runtime(), O.Oracle()
+    res = []
+    for api in (rt, orc):
+        A, B, p = prog.jacobi_rows(api, A0, B0, ndev=3)
+        api.kernel("cp", prog.K_COPY)
+        api.set_offsets("cp", 1, 0, [(0, 0)])
+        api.set_offsets("cp", 0, 1, [(0, 0)])
+        res.append((A, B, p))
+    for it in range(4):
+        for (A, B, p), api in zip(res, (rt, orc)):
+            api.apply("jacAB", p, [A, B])
+        same_call(rt, orc, [(res[0][0], res[1][0]), (res[0][1], res[1][1])], f"jacobi {it}")
+        for (A, B, p), api in zip(res, (rt, orc)):
+            api.apply("cp", p, [B, A])
+        same_call(rt, orc, [(res[0][1], res[1][1])], f"copy {it}")
+        assert len(rt.messages()) == 0
+    assert np.array_equal(rt.read(res[0][1], res[0][2]), orc.read(res[1][1], res[1][2]))
+
+
+@pytest.mark.parametrize("n0,n1,ndev,use_box", [(64, 64, 16, False), (96, 80, 16, False), (70, 45, 6, True),
+                                                (37, 300, 4, False), (130, 520, 8, True)])
+def test_block_parity(hd, n0, n1, ndev, use_box):
+    """BLOCK partitions with 5-point offsets (cross) or a full-box use; sizes
+    that span several tiles and leave ragged tails."""
+    say(f"case block {n0}x{n1} ndev={ndev} box={use_box}")
+    rng = np.random.default_rng(n0 * 1000 + n1)
+    A0 = rng.random((n0, n1), dtype=np.float32)
+    B0 = rng.random((n0, n1), dtype=np.float32)
+    rt, orc = hd.Runtime(), O.Oracle()
+    g = prog.jacobi_blocks(rt, A0, B0, ndev, use_box)
+    o = prog.jacobi_blocks(orc, A0, B0, ndev, use_box)
+    for it in range(4):
+        k, ag, ao = ("jacAB", [g[0], g[1]], [o[0], o[1]]) if it % 2 == 0 else ("jacBA", [g[1], g[0]], [o[1], o[0]])
+        rt.apply(k, g[2], ag)
+        orc.apply(k, o[2], ao)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"step {it}")
+    assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+    assert np.array_equal(rt.read(g[1], g[2]), orc.read(o[1], o[2]))
+
+
+@pytest.mark.parametrize("n,P", [(64, 4), (96, 3)])
+def test_gemm_parity(hd, n, P):
+    """Listings 2-3 GEMM: the gather of B (first call), then no messages;
+    random inputs within the FP32 bound, ternary inputs bit-exact."""
+    say(f"case gemm n={n} P={P}")
+    for kind, (a0, b0) in (("random", matmul_inputs(n, 3)), ("ternary", ternary_matmul_inputs(n, 4))):
+        rt, orc = hd.Runtime(), O.Oracle()
+        g = prog.gemm(rt, a0, b0, P)
+        o = prog.gemm(orc, a0, b0, P)
+        for it in range(2):
+            rt.apply("gemm", g[3], list(g[:3]))
+            orc.apply("gemm", o[3], list(o[:3]))
+            same_call(rt, orc, [(g[1], o[1]), (g[2], o[2])], f"{kind} call {it}")
+        cg = rt.read(g[2], g[3])
+        c64 = a0.astype(np.float64) @ b0.astype(np.float64)
+        if kind == "ternary":
+            assert np.array_equal(cg, c64.astype(np.float32))
+        else:
+            bound = n * 2.0 ** -24 * (np.abs(a0).astype(np.float64) @ np.abs(b0).astype(np.float64))
+            assert np.all(np.abs(cg - c64) <= bound)
+
+
+@pytest.mark.parametrize("n,cuts", [(32, [0, 10, 21, 32]), (150, [0, 1, 40, 41, 97, 150])])
+def test_trapezoid_parity(hd, n, cuts):
+    say(f"case trapezoid n={n} cuts={cuts}")
+    A0, B0 = jacobi_inputs(n, 9)
+    rt, orc = hd.Runtime(), O.Oracle()
+    g = prog.tri(rt, A0, B0, cuts)
+    o = prog.tri(orc, A0, B0, cuts)
+    for it in range(4):
+        k, ag, ao = ("triAB", [g[0], g[1]], [o[0], o[1]]) if it % 2 == 0 else ("triBA", [g[1], g[0]], [o[1], o[0]])
+        rt.apply(k, g[2], ag)
+        orc.apply(k, o[2], ao)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"step {it}")
+    assert orc.bad_reads() == 0
+    assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+
+
+@pytest.mark.parametrize("shape,ndev", [((12, 12, 12), 8), ((20, 17, 300), 8), ((9, 33, 65), 12)])
+def test_stencil3d_parity(hd, shape, ndev):
+    """7-point stencil on 3-D blocks: boxes stacked over rows and planes,
+    FP32 fused multiply-adds bit-exact against the C library's fmaf."""
+    say(f"case stencil3d {shape} ndev={ndev}")
+    rng = np.random.default_rng(sum(shape))
+    u0 = rng.random(shape, dtype=np.float32)
+    coef = [float(c) for c in S3D_COEFFS]
+    rt, orc = hd.Runtime(), O.Oracle()
+    g = prog.stencil3d(rt, u0, ndev)
+    o = prog.stencil3d(orc, u0, ndev)
+    for it in range(3):
+        k, ag, ao = ("s3dUV", [g[0], g[1]], [o[0], o[1]]) if it % 2 == 0 else ("s3dVU", [g[1], g[0]], [o[1], o[0]])
+        rt.apply(k, g[2], ag, coef)
+        orc.apply(k, o[2], ao, coef)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"step {it}")
+    assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_programs_parity(hd, seed):
+    """Random Write / copy-kernel sequences with random absolute use boxes and
+    partitions (2-D and 3-D), including ragged and empty regions."""
+    say(f"case random program seed={seed}")
+    rng = np.random.default_rng(500 + seed)
+    dim = 2 if seed % 3 else 3
+    shape = tuple(int(x) for x in rng.integers(5, 40 if dim == 2 else 9, size=dim))
+    x0 = rng.random(shape, dtype=np.float32)
+    y0 = rng.random(shape, dtype=np.float32)
+    ndev = int(rng.integers(2, 9))
+    kind = int(rng.integers(0, 3))
+    steps = []
+    for step in range(6):
+        dec = []
+        for d in range(ndev):
+            boxes = []
+            for _ in range(int(rng.integers(0, 3))):
+                blo = [int(rng.integers(0, s)) for s in shape]
+                bhi = [int(rng.integers(b + 1, s + 1)) for b, s in zip(blo, shape)]
+                boxes.append((blo, bhi))
+            dec.append(boxes)
+        steps.append(dec)
+    rt, orc = hd.Runtime(), O.Oracle()
+    res = []
+    for api in (rt, orc):
+        X, Y = api.create(x0), api.create(y0)
+        p = api.partition(kind, shape, ndev=ndev)
+        api.write(X, x0, p)
+        for step, dec in enumerate(steps):
+            out, inp = (X, Y) if step % 2 else (Y, X)
+            kname = f"k{step}"
+            api.kernel(kname, prog.K_COPY)
+            for d in range(ndev):
+                lo, hi = api.part_region(p, d)
+                if any(a >= b for a, b in zip(lo, hi)):
+                    continue
+                dlo, dhi = lo[3 - dim:], hi[3 - dim:]
+                api.set_absolute(kname, p, out, d, 1, dlo, dhi)
+                api.set_absolute(kname, p, inp, d, 0, dlo, dhi)
+                for blo, bhi in dec[d]:
+                    api.set_absolute(kname, p, inp, d, 0, blo, bhi)
+        res.append((X, Y, p))
+    for step in range(6):
+        for (X, Y, p), api in zip(res, (rt, orc)):
+            out, inp = (X, Y) if step % 2 else (Y, X)
+            api.apply(f"k{step}", p, [out, inp])
+        same_call(rt, orc, [(res[0][0], res[1][0]), (res[0][1], res[1][1])], f"step {step}")
+    for i in range(2):
+        assert np.array_equal(rt.read(res[0][i], res[0][2]), orc.read(res[1][i], res[1][2]))
+        same_call(rt, orc, [(res[0][i], res[1][i])], f"read {i}")
+
+
+def test_read_write_reduce_parity(hd):
+    say("case read/write/reduce")
+    n = 40
+    A0, B0 = jacobi_inputs(n, 4)
+    rt, orc = hd.Runtime(), O.Oracle()
+    g = prog.jacobi_rows(rt, A0, B0, ndev=3)
+    o = prog.jacobi_rows(orc, A0, B0, ndev=3)
+    assert np.array_equal(rt.read(g[1], g[2]), B0)
+    rt.apply("jacAB", g[2], [g[0], g[1]])
+    orc.apply("jacAB", o[2], [o[0], o[1]])
+    a = rt.read(g[0], g[2])
+    assert np.array_equal(a, orc.read(o[0], o[2]))
+    same_call(rt, orc, [(g[0], o[0])], "read")
+    s_g = rt.reduce(g[0], prog.ROW * 0 + 0, g[2])
+    s_o = orc.reduce(o[0], 0, o[2])
+    assert abs(s_g - s_o) <= 2 * n * n * 2.0 ** -24 * float(np.sum(np.abs(a)))
+    for op in (2, 3):
+        assert rt.reduce(g[0], op, g[2]) == np.float32(orc.reduce(o[0], op, o[2]))
+    iv = (np.arange(n * n, dtype=np.int64).reshape(n, n) * 7919 - 3 * n * n).astype(np.int32)
+    Ig, Io = rt.create(shape=(n, n), type_=1), orc.create(shape=(n, n), type_=1)
+    rt.write(Ig, iv, g[2])
+    orc.write(Io, iv, o[2])
+    for op in range(4):
+        assert rt.reduce(Ig, op, g[2]) == orc.reduce(Io, op, o[2])
+    D0 = np.random.default_rng(1).random((n, n))
+    Dg, Do = rt.create(shape=(n, n), type_=2), orc.create(shape=(n, n), type_=2)
+    rt.write(Dg, D0, g[2])
+    orc.write(Do, D0, o[2])
+    assert np.array_equal(rt.read(Dg, g[2]), D0)
+    for op in (2, 3):
+        assert rt.reduce(Dg, op, g[2]) == orc.reduce(Do, op, o[2])
+
+
+def test_error_paths_gpu(hd):
+    rt = hd.Runtime()
+    n = 16
+    A, B = rt.create(shape=(n, n)), rt.create(shape=(n, n))
+    p = rt.partition(prog.ROW, (n, n), ndev=2)
+    rt.kernel("jac", prog.K_JACOBI2D)
+    rt.set_absolute("jac", p, A, 0, 1, (0, 0), (9, n))
+    rt.set_absolute("jac", p, A, 1, 1, (8, 0), (n, n))
+    with pytest.raises(hd.HDArrayError) as e:
+        rt.apply("jac", p, [A, B])
+    assert e.value.code == hd.ERACE
+    with pytest.raises(hd.HDArrayError) as e:
+        rt.set_absolute("jac", p, A, 0, 0, (0, 0), (n + 1, n))
+    assert e.value.code == hd.EBOUNDS
+    with pytest.raises(hd.HDArrayError) as e:
+        rt.set_trapezoid("jac", p, A, 0, 0, [0, 0, 1, 3, 5, 0, 5, 5])
+    assert e.value.code == hd.EINVAL
+    with pytest.raises(hd.HDArrayError):
+        rt.apply("jac", p, [A, A])
+    with pytest.raises(hd.HDArrayError) as e:
+        rt.kernel("bad", "nosuchkernel")
+    assert e.value.code == hd.EKERNEL
+    q = rt.partition_manual([(0, 0), (4, 0)], [(8, n), (n, n)])
+    with pytest.raises(hd.HDArrayError) as e:
+        rt.write(A, np.zeros((n, n), np.float32), q)
+    assert e.value.code == hd.EINVAL
