@@ -181,6 +181,28 @@ int hdarray_reduce(hd_array_t *a, void *res, hd_reduce_t op, int part);
 
 /* ---------------------------------------------------------- extensions */
 
+/* Batched step.  Between hdarray_batch_begin() and hdarray_batch_end(),
+ * hdarray_apply_kernel() validates and records its call instead of running
+ * it.  The recorded calls must touch pairwise distinct arrays and use the
+ * built-ins jacobi2d, tri2d or copy.  hdarray_batch_end() returns a batch id;
+ * hdarray_batch_run(id) enqueues one execution of every recorded call —
+ * communication sets, packs, unpacks, kernels and GDEF updates — as one
+ * persistent kernel (phases separated by grid-wide barriers with a bounded
+ * wait) replayed from a HIP graph.  Results are bit-identical to running the
+ * calls one by one.  A barrier that times out (workgroups not co-resident)
+ * makes the launch exit early; the next synchronising call then returns
+ * HD_EHIP. */
+int hdarray_batch_begin(void);
+int hdarray_batch_end(void);
+int hdarray_batch_run(int batch);
+/* Chooses the rows per stencil tile (8, 16, 32) and the words per pack
+ * iteration (1, 4) of the given batches by timing each of the 6 candidates
+ * on `reps` runs of the sequence batches[0..n) after one warm-up run.  These
+ * runs are real steps of the program: 6 * (reps + 1) sequences execute.  The
+ * tile shape does not change any result.  Returns the chosen
+ * (rows << 8 | words) or a negative error. */
+int hdarray_batch_autotune(const int *batches, int n, int reps);
+
 /* Stream (hipStream_t) for data movement and kernels. */
 int hdarray_set_stream(void *hip_stream);
 

@@ -1,0 +1,271 @@
+// hd_dev_data.hpp — device functions of the data path (pack / unpack and the
+// built-in user kernels), shared by the per-call kernels (hd_data.hip) and
+// the persistent batched kernel (hd_batch.hip), so both perform the same
+// operations in the same order.
+//
+// Built-in kernels (device d reads its own buffers and writes its work box
+// of the output; buffers are full-extent and row-major):
+//   jacobi2d   A[i][j] = (((B[i][j-1] + B[i][j+1]) + B[i-1][j]) + B[i+1][j]) / 4
+//              on interior cells (Sec. 5.1), A = B on the array boundary
+//   tri2d      the same update on 1 <= j < i <= n-2, copy on the other cells
+//              with j <= i; cells with j > i are not written
+//   copy       out = in (raw 4- or 8-byte elements)
+//   stencil3d7 acc = c0*u; acc = fma(c_e, u[x+e], acc) for e = -i,+i,-j,+j,-k,+k
+//              on interior cells, copy on the boundary
+// FP32 throughout, no contraction beyond the explicit fused multiply-adds.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hd_internal.hpp"
+
+namespace hd {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+struct Coef7 {
+  float c[7];
+};
+
+// Flat tile index so that each XCD (workgroups are dealt round-robin over the
+// 8 XCDs) walks a contiguous range of tiles: neighbouring tiles, which share
+// halo rows, then hit the same L2.
+__device__ inline int64_t xcd_remap(int64_t bid, int64_t ntiles) {
+  const int64_t q = ntiles >> 3, r = ntiles & 7;
+  const int64_t x = bid & 7, k = bid >> 3;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+__device__ inline int find_box(const WorkBox *__restrict__ wb, int nbox, int64_t t) {
+  int lo = 0, hi = nbox - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (wb[mid].tile0 <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------ pack / unpack
+__device__ inline int find_msg(const MsgRec *__restrict__ M, int64_t n, int64_t byteoff) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (M[mid].off <= byteoff)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return (int)lo;
+}
+
+// Packed word w of the staging buffer <-> element word of the section in the
+// source (pack) or destination (unpack) endpoint's buffer, at the same global
+// coordinates.  Sections are row-major inside each box.  m caches the message
+// of the previous word.
+__device__ inline void dev_pack_word(const MsgRec *__restrict__ M, int64_t n, const ArrDev *__restrict__ A,
+                                     uint32_t *__restrict__ stg, int unpack, int64_t w, int &m) {
+  if (!(M[m].off <= 4 * w && 4 * w < M[m].off + M[m].bytes)) m = find_msg(M, n, 4 * w);
+  const MsgRec &r = M[m];
+  const int64_t lw = w - (r.off >> 2);
+  if (4 * lw >= r.bytes) return;  // alignment padding between arrays
+  const int k = r.esize >> 2;
+  const int64_t wid = (int64_t)(r.hi[2] - r.lo[2]) * k;
+  const int64_t rows = r.hi[1] - r.lo[1];
+  const int64_t c = lw % wid, t = lw / wid;
+  const int64_t rr = t % rows, p = t / rows;
+  const ArrDev &a = A[r.arr];
+  const int64_t g = (((int64_t)r.lo[0] + p) * a.n[1] + r.lo[1] + rr) * a.n[2] * k + (int64_t)r.lo[2] * k + c;
+  if (!unpack)
+    stg[w] = reinterpret_cast<const uint32_t *>(a.buf[r.src])[g];
+  else
+    reinterpret_cast<uint32_t *>(a.buf[r.dst])[g] = stg[w];
+}
+
+// Grid-stride over the words of the whole table (the count is device-resident).
+__device__ inline void dev_pack(const MsgRec *__restrict__ M, const MsgHdr *__restrict__ H,
+                                const ArrDev *__restrict__ A, uint32_t *__restrict__ stg, int unpack, int64_t first,
+                                int64_t stride) {
+  const int64_t n = H->nmsg;
+  const int64_t words = H->bytes >> 2;
+  int m = 0;
+  for (int64_t w = first; w < words; w += stride) dev_pack_word(M, n, A, stg, unpack, w, m);
+}
+
+// ------------------------------------------------------------ jacobi / tri
+// One wave computes a tile of TH rows x 256 columns of one box; each lane
+// owns 4 consecutive columns, the left / right neighbours come from the
+// adjacent lanes (lanes 0 and 63 load the tile's edge columns).
+template <int TH, bool TRI>
+__device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
+  const int lane = threadIdx.x & 63;
+  const int h = B.hi[1] - B.lo[1];
+  const int nty = (h + TH - 1) / TH;
+  const int ty = (int)(lt % nty), tx = (int)(lt / nty);
+  const int r0 = B.lo[1] + ty * TH;
+  const int r1 = min(r0 + TH, B.hi[1]);
+  const int c = B.lo[2] + tx * 256 + 4 * lane;
+  const ArrDev &ai = A[B.ain];
+  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
+  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
+  f4 v[TH + 2];
+  float Lh[TH + 2], Rh[TH + 2];
+#pragma unroll
+  for (int k = 0; k < TH + 2; ++k) {
+    const int r = r0 - 1 + k;
+    f4 x = {0.f, 0.f, 0.f, 0.f};
+    float l = 0.f, rr = 0.f;
+    if (r >= 0 && r < N1 && r <= r1) {
+      const float *p = in + (int64_t)r * N2;
+      if (vec && c + 4 <= N2) {
+        x = *reinterpret_cast<const f4 *>(p + c);
+      } else {
+        if (c < N2) x.x = p[c];
+        if (c + 1 < N2) x.y = p[c + 1];
+        if (c + 2 < N2) x.z = p[c + 2];
+        if (c + 3 < N2) x.w = p[c + 3];
+      }
+      if (lane == 0 && c >= 1 && c - 1 < N2) l = p[c - 1];
+      if (lane == 63 && c + 4 < N2) rr = p[c + 4];
+    }
+    const float lw = __shfl_up(x.w, 1);
+    const float rx = __shfl_down(x.x, 1);
+    Lh[k] = lane == 0 ? l : lw;
+    Rh[k] = lane == 63 ? rr : rx;
+    v[k] = x;
+  }
+#pragma unroll
+  for (int k = 1; k <= TH; ++k) {
+    const int i = r0 + k - 1;
+    if (i >= r1) break;
+    const f4 up = v[k - 1], cu = v[k], dn = v[k + 1];
+    const float cv[6] = {Lh[k], cu.x, cu.y, cu.z, cu.w, Rh[k]};
+    const float uv[4] = {up.x, up.y, up.z, up.w};
+    const float dv[4] = {dn.x, dn.y, dn.z, dn.w};
+    float o[4];
+    bool wr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = c + e;
+      bool interior, write = j < B.hi[2];
+      if (TRI) {
+        write = write && j <= i;
+        interior = j >= 1 && j < i && i <= N1 - 2;
+      } else {
+        interior = i >= 1 && i <= N1 - 2 && j >= 1 && j <= N2 - 2;
+      }
+      float s = cv[e] + cv[e + 2];
+      s = s + uv[e];
+      s = s + dv[e];
+      o[e] = interior ? s * 0.25f : cv[e + 1];
+      wr[e] = write;
+    }
+    float *q = out + (int64_t)i * N2 + c;
+    if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
+      f4 ov = {o[0], o[1], o[2], o[3]};
+      __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (wr[e]) q[e] = o[e];
+    }
+  }
+}
+
+__host__ __device__ inline int64_t jacobi_tiles(const WorkBox &B, int th) {
+  const int64_t h = B.hi[1] - B.lo[1], w = B.hi[2] - B.lo[2];
+  if (h <= 0 || w <= 0 || B.hi[0] <= B.lo[0]) return 0;
+  return ((h + th - 1) / th) * ((w + 255) / 256);
+}
+
+// --------------------------------------------------------------------- copy
+// One wave: 16 rows x 256 words of one plane of the box.
+__device__ inline void dev_copy_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
+  const int lane = threadIdx.x & 63;
+  const ArrDev &ai = A[B.ain];
+  const int k = ai.esize >> 2;
+  const int h = B.hi[1] - B.lo[1];
+  const int64_t wwords = (int64_t)(B.hi[2] - B.lo[2]) * k;
+  const int nty = (h + 15) / 16;
+  const int ntx = (int)((wwords + 255) / 256);
+  const int ty = (int)(lt % nty);
+  const int64_t rest = lt / nty;
+  const int tx = (int)(rest % ntx);
+  const int p = B.lo[0] + (int)(rest / ntx);
+  const uint32_t *__restrict__ in = reinterpret_cast<const uint32_t *>(ai.buf[B.dev]);
+  uint32_t *__restrict__ out = reinterpret_cast<uint32_t *>(A[B.aout].buf[B.dev]);
+  const int64_t rowwords = ai.n[2] * k;
+  const int64_t c0 = (int64_t)B.lo[2] * k + (int64_t)tx * 256 + 4 * lane;
+  const int64_t cend = (int64_t)B.hi[2] * k;
+  const bool vec = (rowwords & 3) == 0 && (c0 & 3) == 0;
+  for (int r = B.lo[1] + ty * 16; r < min(B.lo[1] + ty * 16 + 16, B.hi[1]); ++r) {
+    const int64_t base = ((int64_t)p * ai.n[1] + r) * rowwords;
+    if (vec && c0 + 4 <= cend) {
+      *reinterpret_cast<uint4 *>(out + base + c0) = *reinterpret_cast<const uint4 *>(in + base + c0);
+    } else {
+      for (int e = 0; e < 4; ++e)
+        if (c0 + e < cend) out[base + c0 + e] = in[base + c0 + e];
+    }
+  }
+}
+
+__host__ __device__ inline int64_t copy_tiles(const WorkBox &B, int esize) {
+  const int64_t d = B.hi[0] - B.lo[0], h = B.hi[1] - B.lo[1], w = B.hi[2] - B.lo[2];
+  if (d <= 0 || h <= 0 || w <= 0) return 0;
+  return d * ((h + 15) / 16) * ((w * (esize / 4) + 255) / 256);
+}
+
+// -------------------------------------------------------------- stencil3d7
+// One wave: one (plane, row) x 256 columns; tile = 4 consecutive rows.
+__device__ inline void dev_s3d_row(const WorkBox &B, int64_t lt, int wv, const ArrDev *__restrict__ A,
+                                   const Coef7 &cf) {
+  const int lane = threadIdx.x & 63;
+  const int h = B.hi[1] - B.lo[1];
+  const int w = B.hi[2] - B.lo[2];
+  const int nty = (h + 3) / 4, ntx = (w + 255) / 256;
+  const int ty = (int)(lt % nty);
+  const int64_t rest = lt / nty;
+  const int tx = (int)(rest % ntx);
+  const int i = B.lo[0] + (int)(rest / ntx);
+  const int j = B.lo[1] + ty * 4 + wv;
+  if (j >= B.hi[1]) return;
+  const ArrDev &ai = A[B.ain];
+  const float *__restrict__ u = reinterpret_cast<const float *>(ai.buf[B.dev]);
+  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  const int N0 = (int)ai.n[0], N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const int64_t si = (int64_t)N1 * N2, sj = N2;
+  const int c = B.lo[2] + tx * 256 + 4 * lane;
+  const int64_t x0 = (int64_t)i * si + (int64_t)j * sj;
+  const bool rowint = i >= 1 && i <= N0 - 2 && j >= 1 && j <= N1 - 2;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = c + e;
+    if (k >= B.hi[2]) break;
+    const int64_t x = x0 + k;
+    float r;
+    if (rowint && k >= 1 && k <= N2 - 2) {
+      float acc = cf.c[0] * u[x];
+      acc = __builtin_fmaf(cf.c[1], u[x - si], acc);
+      acc = __builtin_fmaf(cf.c[2], u[x + si], acc);
+      acc = __builtin_fmaf(cf.c[3], u[x - sj], acc);
+      acc = __builtin_fmaf(cf.c[4], u[x + sj], acc);
+      acc = __builtin_fmaf(cf.c[5], u[x - 1], acc);
+      acc = __builtin_fmaf(cf.c[6], u[x + 1], acc);
+      r = acc;
+    } else {
+      r = u[x];
+    }
+    out[x] = r;
+  }
+}
+
+__host__ __device__ inline int64_t s3d_tiles(const WorkBox &B) {
+  const int64_t d = B.hi[0] - B.lo[0], h = B.hi[1] - B.lo[1], w = B.hi[2] - B.lo[2];
+  if (d <= 0 || h <= 0 || w <= 0) return 0;
+  return d * ((h + 3) / 4) * ((w + 255) / 256);
+}
+
+}  // namespace hd

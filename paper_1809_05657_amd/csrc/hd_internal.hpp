@@ -92,10 +92,13 @@ struct Level {
   int64_t head_cap;
 };
 
+// One device's work box of a user kernel launch.  kind: 1 jacobi2d,
+// 2 copy, 3 stencil3d7, 4 matmul, 5 tri2d; arrays by runtime id.
 struct WorkBox {
   int32_t dev;
-  int32_t pad;
+  int32_t kind;
   int32_t lo[3], hi[3];
+  int32_t aout, ain, ain2, cidx;  // cidx: coefficient set of the box
   int64_t tile0;  // first tile index of this box in the launch
 };
 
@@ -103,7 +106,7 @@ struct WorkBox {
 struct PlanDev {
   int32_t ncarr;
   int32_t has3d;
-  CallArr carr[kMaxCallArrays];
+  const CallArr *carr;
   // level 1
   int32_t nsl1;
   const int32_t *grp1;
@@ -139,6 +142,23 @@ struct Work {
   Item *l1out;     // level-1 output (3-D)
   int64_t l1_cap;
   int32_t *err;    // device error word (first error wins)
+};
+
+// Arguments of the persistent batched step.
+struct BatchArgs {
+  PlanDev P;
+  Level L1, L2;
+  Work W;
+  ArrDev *A;
+  MsgRec *tab;
+  MsgHdr *hdr;
+  int64_t tab_cap;
+  uint32_t *stg;
+  const WorkBox *wb;
+  int nbox;
+  int64_t ntiles;
+  unsigned *bar;
+  int64_t spin_limit;  // device-clock ticks
 };
 
 }  // namespace hd

@@ -29,13 +29,15 @@ hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRe
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
 hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
                        int unpack, hipStream_t s);
-int64_t tiles_for(int kind, const int32_t *lo, const int32_t *hi, int esize, int th);
-hipError_t launch_user(int kind, int th, const WorkBox *wb, int nbox, const ArrDev *A, const int *args,
-                       int64_t ntiles, const float *coef, hipStream_t s);
+int64_t tiles_for(int kind, const WorkBox &B, int esize, int th);
+hipError_t launch_user(int kind, int th, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
+                       const float *coef, hipStream_t s);
 hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const ArrDev *A, int arr, double *pf,
                          uint32_t *pi, void *res, hipStream_t s);
 hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipStream_t s);
 int reduce_blocks();
+int batch_max_blocks(int th, int pw);
+hipError_t launch_batch(const BatchArgs &a, int th, int pw, int grid, hipStream_t s);
 }  // namespace hd
 
 using namespace hd;
@@ -84,11 +86,14 @@ struct Plan {
   int64_t stg_bound = 0;  // bytes
   // user kernel
   int ukind = 0, th = 16;
-  int uargs[3] = {0, 0, 0};
   WorkBox *wb = nullptr;
   int nbox = 0;
   int64_t ntiles = 0;
 };
+
+struct CallArray;
+struct RecCall;
+struct Batch;
 
 struct Runtime {
   bool inited = false;
@@ -125,6 +130,14 @@ struct Runtime {
   void *red_res_dev = nullptr;
   char *red_res_host = nullptr;
   hd_stats_t stats{};
+  // batch recording
+  bool recording = false;
+  std::vector<struct RecCall> rec;
+  std::vector<struct Batch *> batches;
+  int64_t ws_epoch = 0;
+  int last_batch = -1;
+  hipEvent_t ev_meta = nullptr, ev_data = nullptr;
+  hipStream_t cap = nullptr;
   // opt-in phase timing
   int prof = 0;  // bit p: time phase p
   std::vector<hipEvent_t> ev_pool;
@@ -226,6 +239,9 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   HIPCK(hipGetDevice(&dev));
   R.device = dev;
   HIPCK(hipStreamCreateWithFlags(&R.meta, hipStreamNonBlocking));
+  HIPCK(hipStreamCreateWithFlags(&R.cap, hipStreamNonBlocking));
+  HIPCK(hipEventCreateWithFlags(&R.ev_meta, hipEventDisableTiming));
+  HIPCK(hipEventCreateWithFlags(&R.ev_data, hipEventDisableTiming));
   for (int k = 0; k < 2; ++k) {
     HIPCK(hipEventCreateWithFlags(&R.ev_cs[k], hipEventDisableTiming));
     HIPCK(hipEventCreateWithFlags(&R.ev_free[k], hipEventDisableTiming));
@@ -247,6 +263,7 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
 }
 
 static void free_ws();
+static void free_batches();
 
 extern "C" void hdarray_exit(void) {
   if (!R.inited) return;
@@ -257,6 +274,7 @@ extern "C" void hdarray_exit(void) {
     delete kv.second;
   }
   R.plans.clear();
+  free_batches();
   for (hd_array *a : R.arrays) {
     if (!a) continue;
     for (int e = 0; e < kMaxDev; ++e) dfree(a->buf[e]);
@@ -282,6 +300,9 @@ extern "C" void hdarray_exit(void) {
     (void)hipEventDestroy(p.second.second);
   }
   for (hipEvent_t e : R.ev_pool) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(R.ev_meta);
+  (void)hipEventDestroy(R.ev_data);
+  (void)hipStreamDestroy(R.cap);
   (void)hipStreamDestroy(R.meta);
   hd_alloc_fn ua = R.ualloc;
   hd_free_fn uf = R.ufree;
@@ -689,6 +710,12 @@ struct CallArray {
   int def_flags = 0;
 };
 
+struct RecCall {
+  std::vector<CallArray> cas;
+  std::vector<WorkBox> boxes;
+};
+
+
 template <typename T>
 static size_t push_blob(std::vector<char> &blob, const std::vector<T> &v) {
   size_t off = (blob.size() + 255) / 256 * 256;
@@ -773,6 +800,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg) {
     R.ws_nsl = ns;
     R.ws_ngrp = ng;
     R.ws_items = it;
+    R.ws_epoch++;
     R.last_tab = -1;
     R.free_pending[0] = R.free_pending[1] = false;
   }
@@ -781,6 +809,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg) {
     R.staging = (char *)dalloc(stg);
     if (!R.staging) return fail(HD_ENOMEM);
     R.staging_cap = stg;
+    R.ws_epoch++;
   }
   return HD_OK;
 }
@@ -789,7 +818,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg) {
 // distinct arrays of the call in argument order with per-endpoint use and
 // def shapes.
 static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
-  if (cas.size() > (size_t)kMaxCallArrays) return fail(HD_EINVAL);
+  std::vector<CallArr> carr(cas.size());
   std::vector<int32_t> grp1, pos1, seg0, nseg, grp_aidx, grp_plane, grp2, pos2;
   std::vector<int64_t> grow1;
   std::vector<Seg> useg, dseg;
@@ -803,7 +832,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   for (size_t j = 0; j < cas.size(); ++j) {
     CallArray &ca = cas[j];
     hd_array *a = ca.a;
-    CallArr &C = P.carr[j];
+    CallArr &C = carr[j];
     C.arr = a->id;
     C.argpos = ca.argpos;
     C.esize = a->esize;
@@ -896,6 +925,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   pl->stg_bound = stg;
   // one device allocation for all plan arrays
   std::vector<char> blob;
+  size_t o_carr = push_blob(blob, carr);
   size_t o_grp1 = push_blob(blob, grp1), o_pos1 = push_blob(blob, pos1), o_grow1 = push_blob(blob, grow1);
   size_t o_seg0 = push_blob(blob, seg0), o_nseg = push_blob(blob, nseg), o_useg = push_blob(blob, useg);
   size_t o_ga = push_blob(blob, grp_aidx), o_gp = push_blob(blob, grp_plane);
@@ -907,6 +937,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   pl->mem = dalloc(blob.size());
   if (!pl->mem) return fail(HD_ENOMEM);
   char *b = (char *)pl->mem;
+  P.carr = (const CallArr *)(b + o_carr);
   P.grp1 = (const int32_t *)(b + o_grp1);
   P.pos1 = (const int32_t *)(b + o_pos1);
   P.grow1 = (const int64_t *)(b + o_grow1);
@@ -1052,9 +1083,10 @@ static int enqueue(Plan *pl, const float *coef) {
   HIPCK(hipEventRecord(R.ev_free[slot], R.data));
   R.free_pending[slot] = true;
   R.last_tab = slot;
+  R.last_batch = -1;
   if (pl->ukind) {
     PhaseTimer tm(3, R.data);
-    HIPCK(launch_user(pl->ukind, pl->th, pl->wb, pl->nbox, R.d_arrs, pl->uargs, pl->ntiles, coef, R.data));
+    HIPCK(launch_user(pl->ukind, pl->th, pl->wb, pl->nbox, R.d_arrs, pl->ntiles, coef, R.data));
   }
   return HD_OK;
 }
@@ -1135,6 +1167,63 @@ static int user_kind(int builtin) {
   return 0;
 }
 
+// Use / def shapes of every distinct array of a call (argument order) and
+// the work boxes of its user kernel (tile prefixes left to the caller).
+static int prepare_call(const Kernel &k, int part, const std::vector<hd_array *> &A, std::vector<CallArray> &cas,
+                        std::vector<WorkBox> &wb) {
+  const Partition &pt = R.parts[part];
+  for (int i = 0; i < (int)A.size(); ++i) {
+    bool seen = false;
+    for (auto &c : cas)
+      if (c.a == A[i]) seen = true;
+    if (seen) continue;
+    cas.emplace_back();
+    cas.back().a = A[i];
+    cas.back().argpos = i;
+  }
+  for (auto &c : cas)
+    for (int i = 0; i < (int)A.size(); ++i) {
+      if (A[i] != c.a) continue;
+      for (int d = 0; d < pt.ndev; ++d) {
+        if (part_dev_empty(pt, d)) continue;
+        arg_region(k, part, i, c.a, 0, d, pt.lo[d], pt.hi[d], c.use[d]);
+        arg_region(k, part, i, c.a, 1, d, pt.lo[d], pt.hi[d], c.def[d]);
+      }
+    }
+  // every device touching an array gets its buffer
+  for (auto &c : cas)
+    for (int d = 0; d < kMaxDev; ++d)
+      if (!c.use[d].empty() || !c.def[d].empty())
+        if (ensure_buf(c.a, d) != HD_OK) return g_last_error;
+  for (int d = 0; d < pt.ndev; ++d) {
+    if (part_dev_empty(pt, d)) continue;
+    for (hd_array *a : A)
+      if (ensure_buf(a, d) != HD_OK) return g_last_error;
+  }
+  const int kind = user_kind(k.builtin);
+  for (int d = 0; d < pt.ndev; ++d) {
+    if (part_dev_empty(pt, d)) continue;
+    WorkBox w{};
+    w.dev = d;
+    w.kind = kind;
+    for (int q = 0; q < 3; ++q) {
+      w.lo[q] = (int32_t)pt.lo[d][q];
+      w.hi[q] = (int32_t)pt.hi[d][q];
+    }
+    if (k.builtin == 4) {
+      w.ain = A[0]->id;
+      w.ain2 = A[1]->id;
+      w.aout = A[2]->id;
+    } else {
+      w.aout = A[0]->id;
+      w.ain = A[1]->id;
+      w.ain2 = A[1]->id;
+    }
+    wb.push_back(w);
+  }
+  return HD_OK;
+}
+
 extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, const hd_arg_t *args) {
   if (!R.inited) return fail(HD_ESTATE);
   Kernel *k = get_kernel(kname);
@@ -1185,6 +1274,15 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
   for (int d = 0; d < pt.ndev; ++d)
     for (int j = 0; j < 3; ++j)
       if (pt.hi[d][j] > ao->n[j]) return fail(HD_EBOUNDS);
+  float coef[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int e = 0; e < 7 && e < (int)sc.size(); ++e) coef[e] = (float)sc[e];
+  if (R.recording) {
+    if (k->builtin != 1 && k->builtin != 2 && k->builtin != 5) return fail(HD_EINVAL);
+    RecCall rc;
+    if (prepare_call(*k, part, A, rc.cas, rc.boxes) != HD_OK) return g_last_error;
+    R.rec.push_back(std::move(rc));
+    return HD_OK;
+  }
   // plan cache key
   std::vector<int64_t> key = {1, (int64_t)(k - &R.kernels[0]), part, k->version};
   for (hd_array *a : A) key.push_back(a->id);
@@ -1194,73 +1292,27 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
     pl = it->second;
   } else {
     std::vector<CallArray> cas;
-    for (int i = 0; i < (int)A.size(); ++i) {
-      bool seen = false;
-      for (auto &c : cas)
-        if (c.a == A[i]) seen = true;
-      if (seen) continue;
-      cas.emplace_back();
-      cas.back().a = A[i];
-      cas.back().argpos = i;
-    }
-    for (auto &c : cas)
-      for (int i = 0; i < (int)A.size(); ++i) {
-        if (A[i] != c.a) continue;
-        for (int d = 0; d < pt.ndev; ++d) {
-          if (part_dev_empty(pt, d)) continue;
-          arg_region(*k, part, i, c.a, 0, d, pt.lo[d], pt.hi[d], c.use[d]);
-          arg_region(*k, part, i, c.a, 1, d, pt.lo[d], pt.hi[d], c.def[d]);
-        }
-      }
-    // every device touching an array gets its buffer
-    for (auto &c : cas)
-      for (int d = 0; d < kMaxDev; ++d)
-        if (!c.use[d].empty() || !c.def[d].empty())
-          if (ensure_buf(c.a, d) != HD_OK) return g_last_error;
-    for (int d = 0; d < pt.ndev; ++d) {
-      if (part_dev_empty(pt, d)) continue;
-      for (hd_array *a : A)
-        if (ensure_buf(a, d) != HD_OK) return g_last_error;
-    }
+    std::vector<WorkBox> wb;
+    if (prepare_call(*k, part, A, cas, wb) != HD_OK) return g_last_error;
     pl = new Plan();
     if (build_plan(cas, pl) != HD_OK) {
       dfree(pl->mem);
       delete pl;
       return g_last_error;
     }
-    // work boxes of the user kernel
     pl->ukind = user_kind(k->builtin);
     pl->th = 16;
-    std::vector<WorkBox> wb;
     int64_t t0 = 0;
-    for (int d = 0; d < pt.ndev; ++d) {
-      if (part_dev_empty(pt, d)) continue;
-      WorkBox w{};
-      w.dev = d;
-      for (int q = 0; q < 3; ++q) {
-        w.lo[q] = (int32_t)pt.lo[d][q];
-        w.hi[q] = (int32_t)pt.hi[d][q];
-      }
+    for (WorkBox &w : wb) {
       w.tile0 = t0;
-      t0 += tiles_for(pl->ukind == 5 ? 1 : pl->ukind, w.lo, w.hi, ao->esize, pl->th);
-      wb.push_back(w);
+      t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, pl->th);
     }
     pl->nbox = (int)wb.size();
     pl->ntiles = t0;
     if (!wb.empty()) HIPCK(hipMemcpy(pl->wb, wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice));
-    if (k->builtin == 4) {
-      pl->uargs[0] = A[0]->id;
-      pl->uargs[1] = A[1]->id;
-      pl->uargs[2] = A[2]->id;
-    } else {
-      pl->uargs[0] = A[0]->id;
-      pl->uargs[1] = A[1]->id;
-    }
     R.plans[key] = pl;
     R.stats.plans_built++;
   }
-  float coef[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int e = 0; e < 7 && e < (int)sc.size(); ++e) coef[e] = (float)sc[e];
   R.stats.calls++;
   return enqueue(pl, coef);
 }
@@ -1430,14 +1482,19 @@ extern "C" int hdarray_reduce(hd_array_t *ah, void *res, hd_reduce_t op, int par
 }
 
 // ----------------------------------------------------------------- dumps
+static void last_table(MsgRec **tab, MsgHdr **hdr);
+
 extern "C" int hdarray_get_stats(hd_stats_t *st) {
   if (!st) return fail(HD_EINVAL);
   *st = R.stats;
-  if (R.inited && R.last_tab >= 0) {
+  MsgRec *ltab = nullptr;
+  MsgHdr *lhdr = nullptr;
+  if (R.inited) last_table(&ltab, &lhdr);
+  if (lhdr) {
     if (hipStreamSynchronize(R.meta) != hipSuccess || hipStreamSynchronize(R.data) != hipSuccess)
       return fail(HD_EHIP);
     MsgHdr h{};
-    HIPCK(hipMemcpy(&h, R.hdr[R.last_tab], sizeof(h), hipMemcpyDeviceToHost));
+    HIPCK(hipMemcpy(&h, lhdr, sizeof(h), hipMemcpyDeviceToHost));
     st->last_messages = h.nmsg;
     st->last_bytes = h.bytes;
   }
@@ -1447,11 +1504,14 @@ extern "C" int hdarray_get_stats(hd_stats_t *st) {
 extern "C" int64_t hdarray_debug_messages(int64_t *out, int64_t cap) {
   if (!R.inited) return fail(HD_ESTATE);
   if (hdarray_sync() != HD_OK) return g_last_error;
-  if (R.last_tab < 0) return 0;
+  MsgRec *tab = nullptr;
+  MsgHdr *hdr = nullptr;
+  last_table(&tab, &hdr);
+  if (!tab) return 0;
   MsgHdr h{};
-  HIPCK(hipMemcpy(&h, R.hdr[R.last_tab], sizeof(h), hipMemcpyDeviceToHost));
+  HIPCK(hipMemcpy(&h, hdr, sizeof(h), hipMemcpyDeviceToHost));
   std::vector<MsgRec> m(h.nmsg);
-  if (h.nmsg) HIPCK(hipMemcpy(m.data(), R.tab[R.last_tab], sizeof(MsgRec) * h.nmsg, hipMemcpyDeviceToHost));
+  if (h.nmsg) HIPCK(hipMemcpy(m.data(), tab, sizeof(MsgRec) * h.nmsg, hipMemcpyDeviceToHost));
   for (int64_t i = 0; i < h.nmsg && i < cap; ++i) {
     int64_t *o = out + 12 * i;
     o[0] = m[i].argpos;
@@ -1471,9 +1531,12 @@ extern "C" int64_t hdarray_debug_messages(int64_t *out, int64_t cap) {
 extern "C" int64_t hdarray_debug_pack(void *out, int64_t cap) {
   if (!R.inited) return fail(HD_ESTATE);
   if (hdarray_sync() != HD_OK) return g_last_error;
-  if (R.last_tab < 0) return 0;
+  MsgRec *tab = nullptr;
+  MsgHdr *hdr = nullptr;
+  last_table(&tab, &hdr);
+  if (!tab) return 0;
   MsgHdr h{};
-  HIPCK(hipMemcpy(&h, R.hdr[R.last_tab], sizeof(h), hipMemcpyDeviceToHost));
+  HIPCK(hipMemcpy(&h, hdr, sizeof(h), hipMemcpyDeviceToHost));
   const int64_t n = std::min(h.bytes, cap);
   if (n > 0) HIPCK(hipMemcpy(out, R.staging, n, hipMemcpyDeviceToHost));
   return h.bytes;
@@ -1525,4 +1588,220 @@ extern "C" void *hdarray_device_ptr(hd_array_t *ah, int dev) {
   }
   if (ensure_buf(a, dev) != HD_OK) return nullptr;
   return a->buf[dev];
+}
+
+// ------------------------------------------------------------------ batch
+
+struct Batch {
+  Plan pl;
+  std::vector<WorkBox> boxes;
+  WorkBox *d_wb = nullptr;
+  int64_t ntiles = 0;
+  int th = 16, pw = 1, grid = 0;
+  MsgRec *tab = nullptr;
+  MsgHdr *hdr = nullptr;
+  int64_t tab_cap = 0;
+  unsigned *bar = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t epoch = -1;
+  int gth = 0, gpw = 0;
+};
+
+static void drop_graph(Batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+static void free_batches() {
+  for (Batch *b : R.batches) {
+    if (!b) continue;
+    drop_graph(b);
+    dfree(b->pl.mem);
+    dfree(b->d_wb);
+    dfree(b->tab);
+    dfree(b->hdr);
+    dfree(b->bar);
+    delete b;
+  }
+  R.batches.clear();
+  R.rec.clear();
+  R.recording = false;
+}
+
+static void last_table(MsgRec **tab, MsgHdr **hdr) {
+  *tab = nullptr;
+  *hdr = nullptr;
+  if (R.last_batch >= 0 && R.last_batch < (int)R.batches.size()) {
+    *tab = R.batches[R.last_batch]->tab;
+    *hdr = R.batches[R.last_batch]->hdr;
+  } else if (R.last_tab >= 0) {
+    *tab = R.tab[R.last_tab];
+    *hdr = R.hdr[R.last_tab];
+  }
+}
+
+static int batch_config(Batch *b, int th, int pw) {
+  int64_t t0 = 0;
+  for (WorkBox &w : b->boxes) {
+    w.tile0 = t0;
+    t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, th);
+  }
+  b->ntiles = t0;
+  HIPCK(hipStreamSynchronize(R.data));
+  if (!b->boxes.empty())
+    HIPCK(hipMemcpy(b->d_wb, b->boxes.data(), sizeof(WorkBox) * b->boxes.size(), hipMemcpyHostToDevice));
+  b->th = th;
+  b->pw = pw;
+  b->grid = batch_max_blocks(th, pw);
+  if (b->grid <= 0) return fail(HD_EHIP);
+  return HD_OK;
+}
+
+extern "C" int hdarray_batch_begin(void) {
+  if (!R.inited) return fail(HD_ESTATE);
+  if (R.recording) return fail(HD_ESTATE);
+  R.recording = true;
+  R.rec.clear();
+  return HD_OK;
+}
+
+extern "C" int hdarray_batch_end(void) {
+  if (!R.inited || !R.recording) return fail(HD_ESTATE);
+  R.recording = false;
+  std::vector<CallArray> all;
+  std::vector<WorkBox> boxes;
+  std::vector<int> seen;
+  for (RecCall &c : R.rec) {
+    for (CallArray &ca : c.cas) {
+      if (std::find(seen.begin(), seen.end(), ca.a->id) != seen.end()) {
+        R.rec.clear();
+        return fail(HD_EINVAL);  // calls of a batch must touch distinct arrays
+      }
+      seen.push_back(ca.a->id);
+    }
+  }
+  for (RecCall &c : R.rec) {
+    for (CallArray &ca : c.cas) all.push_back(std::move(ca));
+    boxes.insert(boxes.end(), c.boxes.begin(), c.boxes.end());
+  }
+  R.rec.clear();
+  Batch *b = new Batch();
+  if (build_plan(all, &b->pl) != HD_OK) {
+    dfree(b->pl.mem);
+    delete b;
+    return g_last_error;
+  }
+  b->boxes = boxes;
+  b->tab_cap = R.ws_items;
+  b->tab = (MsgRec *)dalloc(sizeof(MsgRec) * b->tab_cap);
+  b->hdr = (MsgHdr *)dalloc(sizeof(MsgHdr));
+  b->bar = (unsigned *)dalloc(256);
+  b->d_wb = (WorkBox *)dalloc(sizeof(WorkBox) * (boxes.size() + 1));
+  if (!b->tab || !b->hdr || !b->bar || !b->d_wb) return fail(HD_ENOMEM);
+  HIPCK(hipMemset(b->hdr, 0, sizeof(MsgHdr)));
+  HIPCK(hipMemset(b->bar, 0, 256));
+  if (batch_config(b, 16, 1) != HD_OK) return g_last_error;
+  R.batches.push_back(b);
+  R.stats.plans_built++;
+  return (int)R.batches.size() - 1;
+}
+
+static int batch_capture(Batch *b) {
+  drop_graph(b);
+  // the batch may have grown the workspace: its plan was built before
+  int dev = 0, rate_khz = 0;
+  HIPCK(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+    rate_khz = 100000;
+  BatchArgs a{};
+  a.P = b->pl.P;
+  a.L1 = make_level(1, b->pl.P);
+  a.L2 = make_level(2, b->pl.P);
+  a.W = R.W;
+  a.A = R.d_arrs;
+  a.tab = b->tab;
+  a.hdr = b->hdr;
+  a.tab_cap = b->tab_cap;
+  a.stg = (uint32_t *)R.staging;
+  a.wb = b->d_wb;
+  a.nbox = (int)b->boxes.size();
+  a.ntiles = b->ntiles;
+  a.bar = b->bar;
+  a.spin_limit = (int64_t)rate_khz * 2000;  // two seconds
+  HIPCK(hipStreamBeginCapture(R.cap, hipStreamCaptureModeRelaxed));
+  hipError_t e = launch_batch(a, b->th, b->pw, b->grid, R.cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(R.cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(HD_EHIP);
+  }
+  b->graph = g;
+  HIPCK(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  b->epoch = R.ws_epoch;
+  b->gth = b->th;
+  b->gpw = b->pw;
+  return HD_OK;
+}
+
+extern "C" int hdarray_batch_run(int id) {
+  if (!R.inited || R.recording) return fail(HD_ESTATE);
+  if (id < 0 || id >= (int)R.batches.size() || !R.batches[id]) return fail(HD_EINVAL);
+  Batch *b = R.batches[id];
+  if (!b->exec || b->epoch != R.ws_epoch || b->gth != b->th || b->gpw != b->pw)
+    if (batch_capture(b) != HD_OK) return g_last_error;
+  // ordered after the metadata work of earlier calls, and before later ones
+  HIPCK(hipEventRecord(R.ev_meta, R.meta));
+  HIPCK(hipStreamWaitEvent(R.data, R.ev_meta, 0));
+  {
+    PhaseTimer tm(3, R.data);
+    HIPCK(hipGraphLaunch(b->exec, R.data));
+  }
+  HIPCK(hipEventRecord(R.ev_data, R.data));
+  HIPCK(hipStreamWaitEvent(R.meta, R.ev_data, 0));
+  R.last_batch = id;
+  R.stats.calls++;
+  return HD_OK;
+}
+
+extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
+  if (!R.inited || !ids || n <= 0 || reps <= 0) return fail(HD_EINVAL);
+  for (int i = 0; i < n; ++i)
+    if (ids[i] < 0 || ids[i] >= (int)R.batches.size()) return fail(HD_EINVAL);
+  const int ths[3] = {8, 16, 32}, pws[2] = {1, 4};
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bth = 16, bpw = 1;
+  for (int th : ths)
+    for (int pw : pws) {
+      for (int i = 0; i < n; ++i)
+        if (batch_config(R.batches[ids[i]], th, pw) != HD_OK) return g_last_error;
+      for (int i = 0; i < n; ++i)
+        if (hdarray_batch_run(ids[i]) != HD_OK) return g_last_error;
+      HIPCK(hipEventRecord(e0, R.data));
+      for (int r = 0; r < reps; ++r)
+        for (int i = 0; i < n; ++i)
+          if (hdarray_batch_run(ids[i]) != HD_OK) return g_last_error;
+      HIPCK(hipEventRecord(e1, R.data));
+      HIPCK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bth = th;
+        bpw = pw;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  for (int i = 0; i < n; ++i)
+    if (batch_config(R.batches[ids[i]], bth, bpw) != HD_OK) return g_last_error;
+  int rc = hdarray_sync();
+  if (rc != HD_OK) return rc;
+  return (bth << 8) | bpw;
 }

@@ -96,3 +96,34 @@ def stencil3d(api, u0, ndev=8):
     api.write(U, np.zeros_like(u0), p)
     api.write(V, u0, p)
     return U, V, p
+
+
+def batched_arrays(api, inst, seed=4):
+    """The batched workload: per array either the 5-point Jacobi with use
+    offsets (0,0),(0,+-1),(+-1,0) on irregular row splits, or the
+    lower-triangular stencil with trapezoid use / def sections.  Kernels
+    'b{i}AB' (A <- J(B)) and 'b{i}BA'.  Returns [(A, B, part, kind)]."""
+    from workloads import batched_values
+    out = []
+    for m in inst:
+        i, (H, W) = m["index"], m["shape"]
+        A0, B0 = batched_values(seed, i, (H, W))
+        A, B = api.create(A0), api.create(B0)
+        cuts = [0] + [int(c) for c in m["cuts"]] + [H]
+        nd = len(cuts) - 1
+        p = api.partition_manual([(cuts[d], 0) for d in range(nd)], [(cuts[d + 1], W) for d in range(nd)])
+        for k, o, s in ((f"b{i}AB", A, B), (f"b{i}BA", B, A)):
+            if m["kind"] == 0:
+                api.kernel(k, K_JACOBI2D)
+                api.set_offsets(k, 1, 0, J2D_OFFSETS)
+                api.set_offsets(k, 0, 1, [(0, 0)])
+            else:
+                api.kernel(k, K_TRI2D)
+                for d in range(nd):
+                    a, b = cuts[d], cuts[d + 1]
+                    api.set_trapezoid(k, p, s, d, 0, [a - 1, 0, a - 1, a - 1, b, 0, b, b])
+                    api.set_trapezoid(k, p, o, d, 1, [a, 0, a, a, b - 1, 0, b - 1, b - 1])
+        api.write(A, A0, p)
+        api.write(B, B0, p)
+        out.append((A, B, p, m["kind"]))
+    return out
