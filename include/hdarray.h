@@ -203,6 +203,35 @@ int hdarray_batch_run(int batch);
  * (rows << 8 | words) or a negative error. */
 int hdarray_batch_autotune(const int *batches, int n, int reps);
 
+/* Adjoint of one ApplyKernel of a "stencil3d7" kernel kname on partition
+ * part (reverse mode, for differentiation through time steps):
+ *   du_in   cotangent of the step's input (written here),
+ *   du_out  cotangent of the step's output (read on each device's work box),
+ *   u       the step's input values, holding the halos its forward step
+ *           exchanged,
+ *   coef    the 7 weights (host pointer),
+ *   cbar    device pointer to 7 doubles; the coefficient gradients of this
+ *           step, sum over interior outputs y of du_out[y] * u[y + off_e]
+ *           accumulated in FP64 in a fixed order, are added to it (may be
+ *           NULL).
+ * Each device computes the contribution of its own outputs on its use
+ * region (work box +- the kernel's use offsets); the contributions on halo
+ * cells travel back along the reverse of the use-region messages (derived
+ * from du_in's GDEF, in which every element is held by its owner only) and
+ * are added to the owners' values in message-table order.  du_in is then
+ * defined by the owners of the work boxes.  Asynchronous. */
+int hdarray_apply_adjoint(const char *kname, int part, hd_array_t *du_in, hd_array_t *du_out, hd_array_t *u,
+                          const float *coef, double *cbar);
+
+/* Write / Read with a device pointer instead of a host array (dense,
+ * full extent, device memory of the current GPU).  Write: each device's
+ * region is copied from dptr; that device becomes owner and only holder.
+ * Read: each device first obtains what it does not hold of its region
+ * (communication as for Reduce), then the regions are copied to dptr.
+ * Both are asynchronous on the data stream. */
+int hdarray_write_device(hd_array_t *a, const void *dptr, int part);
+int hdarray_read_device(hd_array_t *a, void *dptr, int part);
+
 /* Stream (hipStream_t) for data movement and kernels. */
 int hdarray_set_stream(void *hip_stream);
 

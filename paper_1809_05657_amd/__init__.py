@@ -109,6 +109,13 @@ def load():
         "hdarray_debug_device_buffer": (C.c_int, [P, C.c_int, P]),
         "hdarray_device_ptr": (P, [P, C.c_int]),
         "hdarray_profile": (C.c_int, [C.c_int]),
+        "hdarray_apply_adjoint": (C.c_int, [C.c_char_p, C.c_int, P, P, P, C.POINTER(C.c_float), P]),
+        "hdarray_write_device": (C.c_int, [P, P, C.c_int]),
+        "hdarray_read_device": (C.c_int, [P, P, C.c_int]),
+        "hdarray_batch_begin": (C.c_int, []),
+        "hdarray_batch_end": (C.c_int, []),
+        "hdarray_batch_run": (C.c_int, [C.c_int]),
+        "hdarray_batch_autotune": (C.c_int, [C.POINTER(C.c_int), C.c_int, C.c_int]),
         "hdarray_profile_read": (C.c_int, [C.POINTER(Profile)]),
     }
     for name, (res, args) in sig.items():
@@ -275,6 +282,30 @@ class Runtime:
         st = Stats()
         self._ck(self.L.hdarray_get_stats(C.byref(st)), "get_stats")
         return {f: getattr(st, f) for f, _ in Stats._fields_}
+
+    def apply_adjoint(self, kname, part, du_in, du_out, u, coeffs, cbar_ptr=None):
+        cf = (C.c_float * 7)(*[float(c) for c in coeffs])
+        return self._ck(self.L.hdarray_apply_adjoint(kname.encode(), part, du_in.h, du_out.h, u.h, cf,
+                                                     C.c_void_p(cbar_ptr) if cbar_ptr else None), "apply_adjoint")
+
+    def write_device(self, arr, dptr, part):
+        self._ck(self.L.hdarray_write_device(arr.h, C.c_void_p(dptr), part), "write_device")
+
+    def read_device(self, arr, dptr, part):
+        self._ck(self.L.hdarray_read_device(arr.h, C.c_void_p(dptr), part), "read_device")
+
+    def batch_begin(self):
+        self._ck(self.L.hdarray_batch_begin(), "batch_begin")
+
+    def batch_end(self):
+        return self._ck(self.L.hdarray_batch_end(), "batch_end")
+
+    def batch_run(self, bid):
+        self._ck(self.L.hdarray_batch_run(bid), "batch_run")
+
+    def batch_autotune(self, ids, reps=2):
+        arr = (C.c_int * len(ids))(*ids)
+        return self._ck(self.L.hdarray_batch_autotune(arr, len(ids), reps), "batch_autotune")
 
     def profile(self, enable=True):
         self._ck(self.L.hdarray_profile(int(enable)), "profile")

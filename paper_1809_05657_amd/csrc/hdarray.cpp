@@ -38,6 +38,10 @@ hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipSt
 int reduce_blocks();
 int batch_max_blocks(int th, int pw);
 hipError_t launch_batch(const BatchArgs &a, int th, int pw, int grid, hipStream_t s);
+int64_t adj_tiles(const WorkBox &B, const int64_t *n);
+hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const float *coef, double *part,
+                          double *cbar, const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg,
+                          int64_t bound_words, hipStream_t s);
 }  // namespace hd
 
 using namespace hd;
@@ -87,6 +91,9 @@ struct Plan {
   // user kernel
   int ukind = 0, th = 16;
   WorkBox *wb = nullptr;
+  // adjoint plans: extended-box tiles and coefficient partials
+  bool adjoint = false;
+  double *part = nullptr;
   int nbox = 0;
   int64_t ntiles = 0;
 };
@@ -138,6 +145,7 @@ struct Runtime {
   int last_batch = -1;
   hipEvent_t ev_meta = nullptr, ev_data = nullptr;
   hipStream_t cap = nullptr;
+  double *adj_cbar = nullptr;
   // opt-in phase timing
   int prof = 0;  // bit p: time phase p
   std::vector<hipEvent_t> ev_pool;
@@ -271,6 +279,7 @@ extern "C" void hdarray_exit(void) {
   (void)hipStreamSynchronize(R.data);
   for (auto &kv : R.plans) {
     dfree(kv.second->mem);
+    dfree(kv.second->part);
     delete kv.second;
   }
   R.plans.clear();
@@ -708,6 +717,7 @@ struct CallArray {
   std::vector<Shape> use[64];
   std::vector<Shape> def[64];
   int def_flags = 0;
+  bool no_holders = false;  // receivers do not become holders (adjoint partial sums)
 };
 
 struct RecCall {
@@ -902,7 +912,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
       const int64_t row = std::min(ra, rb);
       gr_aidx.push_back((int32_t)j);
       gr_row.push_back(row);
-      gr_slice.push_back(ra == row ? slice_of_row[a_i].second : -1);
+      gr_slice.push_back(ra == row && !ca.no_holders ? slice_of_row[a_i].second : -1);
       if (ra == row) ++a_i;
       gr_dseg0.push_back((int32_t)dseg.size());
       int cnt = 0;
@@ -1072,6 +1082,18 @@ static int enqueue(Plan *pl, const float *coef) {
   // data stream
   HIPCK(hipStreamWaitEvent(R.data, R.ev_cs[slot], 0));
   const int64_t bw = pl->stg_bound / 4 + 1;
+  if (pl->adjoint) {
+    {
+      PhaseTimer tm(3, R.data);
+      HIPCK(launch_adjoint(pl->wb, pl->nbox, pl->ntiles, coef, pl->part, R.adj_cbar, R.tab[slot], R.hdr[slot],
+                           R.d_arrs, (uint32_t *)R.staging, bw, R.data));
+    }
+    HIPCK(hipEventRecord(R.ev_free[slot], R.data));
+    R.free_pending[slot] = true;
+    R.last_tab = slot;
+    R.last_batch = -1;
+    return HD_OK;
+  }
   {
     PhaseTimer tm(1, R.data);
     HIPCK(launch_pack(R.tab[slot], R.hdr[slot], R.d_arrs, (uint32_t *)R.staging, bw, 0, R.data));
@@ -1362,7 +1384,7 @@ static Plan *io_plan(int op, int part, hd_array *a) {
   for (int d : devs) {
     if (op == 0) cas[0].use[kHost].push_back(part_shape(pt, d));
     if (op == 1) cas[0].use[d].push_back(part_shape(pt, d));
-    if (op == 2) cas[0].def[d].push_back(part_shape(pt, d));
+    if (op == 2 || op == 3) cas[0].def[d].push_back(part_shape(pt, d));
   }
   cas[0].def_flags = op == 2 ? 1 : 0;
   for (int d : devs)
@@ -1804,4 +1826,120 @@ extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
   int rc = hdarray_sync();
   if (rc != HD_OK) return rc;
   return (bth << 8) | bpw;
+}
+
+// ---------------------------------------------------------------- adjoint
+extern "C" int hdarray_apply_adjoint(const char *kname, int part, hd_array_t *dinh, hd_array_t *douth,
+                                     hd_array_t *uh, const float *coef, double *cbar) {
+  if (!R.inited) return fail(HD_ESTATE);
+  Kernel *k = get_kernel(kname);
+  if (!k) return fail(HD_EKERNEL);
+  if (k->builtin != 3) return fail(HD_EKERNEL);
+  hd_array *din = get_arr(dinh), *dout = get_arr(douth), *u = get_arr(uh);
+  if (!din || !dout || !u || !coef || part < 0 || part >= (int)R.parts.size()) return fail(HD_EINVAL);
+  if (din == dout || din == u || dout == u) return fail(HD_EINVAL);
+  for (hd_array *a : {din, dout, u})
+    if (a->type != 0 || a->dim != 3 || memcmp(a->n, u->n, sizeof(u->n))) return fail(HD_EINVAL);
+  const Partition &pt = R.parts[part];
+  if (pt.dim != 3) return fail(HD_EINVAL);
+  for (int d = 0; d < pt.ndev; ++d)
+    for (int j = 0; j < 3; ++j)
+      if (pt.hi[d][j] > u->n[j]) return fail(HD_EBOUNDS);
+  std::vector<int64_t> key = {3, (int64_t)(k - &R.kernels[0]), part, k->version, din->id, dout->id, u->id};
+  Plan *pl = nullptr;
+  auto it = R.plans.find(key);
+  if (it != R.plans.end()) {
+    pl = it->second;
+  } else {
+    std::vector<CallArray> cas(1);
+    cas[0].a = din;
+    cas[0].argpos = 0;
+    cas[0].no_holders = true;
+    std::vector<WorkBox> wb;
+    for (int d = 0; d < pt.ndev; ++d) {
+      if (part_dev_empty(pt, d)) continue;
+      // the use region of the forward input, on the cotangent array
+      arg_region(*k, part, 1, u, 0, d, pt.lo[d], pt.hi[d], cas[0].use[d]);
+      cas[0].def[d].push_back(part_shape(pt, d));
+      for (hd_array *a : {din, dout, u})
+        if (ensure_buf(a, d) != HD_OK) return g_last_error;
+      WorkBox w{};
+      w.dev = d;
+      w.kind = 3;
+      for (int q = 0; q < 3; ++q) {
+        w.lo[q] = (int32_t)pt.lo[d][q];
+        w.hi[q] = (int32_t)pt.hi[d][q];
+      }
+      w.aout = din->id;
+      w.ain = dout->id;
+      w.ain2 = u->id;
+      wb.push_back(w);
+    }
+    pl = new Plan();
+    if (build_plan(cas, pl) != HD_OK) {
+      dfree(pl->mem);
+      delete pl;
+      return g_last_error;
+    }
+    int64_t t0 = 0;
+    for (WorkBox &w : wb) {
+      w.tile0 = t0;
+      t0 += adj_tiles(w, u->n);
+    }
+    pl->adjoint = true;
+    pl->nbox = (int)wb.size();
+    pl->ntiles = t0;
+    pl->part = (double *)dalloc(sizeof(double) * 8 * (t0 + 1));
+    if (!pl->part) return fail(HD_ENOMEM);
+    if (!wb.empty()) HIPCK(hipMemcpy(pl->wb, wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice));
+    R.plans[key] = pl;
+    R.stats.plans_built++;
+  }
+  R.adj_cbar = cbar;
+  R.stats.calls++;
+  return enqueue(pl, coef);
+}
+
+extern "C" int hdarray_write_device(hd_array_t *ah, const void *dptr, int part) {
+  if (!R.inited) return fail(HD_ESTATE);
+  hd_array *a = get_arr(ah);
+  if (!a || !dptr) return fail(HD_EINVAL);
+  Plan *pl = io_plan(3, part, a);
+  if (!pl) return g_last_error;
+  const Partition &pt = R.parts[part];
+  const size_t es = a->esize;
+  for (int d = 0; d < pt.ndev; ++d) {
+    if (part_dev_empty(pt, d)) continue;
+    const int64_t *lo = pt.lo[d], *hi = pt.hi[d];
+    for (int64_t p = lo[0]; p < hi[0]; ++p) {
+      const size_t base = ((size_t)p * a->n[1] + lo[1]) * a->n[2] + lo[2];
+      const size_t pitch = a->n[2] * es, w = (hi[2] - lo[2]) * es, rows = hi[1] - lo[1];
+      HIPCK(hipMemcpy2DAsync(a->buf[d] + base * es, pitch, (const char *)dptr + base * es, pitch, w, rows,
+                             hipMemcpyDeviceToDevice, R.data));
+    }
+  }
+  HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, R.meta));
+  return HD_OK;
+}
+
+extern "C" int hdarray_read_device(hd_array_t *ah, void *dptr, int part) {
+  if (!R.inited) return fail(HD_ESTATE);
+  hd_array *a = get_arr(ah);
+  if (!a || !dptr) return fail(HD_EINVAL);
+  Plan *pl = io_plan(1, part, a);
+  if (!pl) return g_last_error;
+  if (enqueue(pl, nullptr) != HD_OK) return g_last_error;
+  const Partition &pt = R.parts[part];
+  const size_t es = a->esize;
+  for (int d = 0; d < pt.ndev; ++d) {
+    if (part_dev_empty(pt, d)) continue;
+    const int64_t *lo = pt.lo[d], *hi = pt.hi[d];
+    for (int64_t p = lo[0]; p < hi[0]; ++p) {
+      const size_t base = ((size_t)p * a->n[1] + lo[1]) * a->n[2] + lo[2];
+      const size_t pitch = a->n[2] * es, w = (hi[2] - lo[2]) * es, rows = hi[1] - lo[1];
+      HIPCK(hipMemcpy2DAsync((char *)dptr + base * es, pitch, a->buf[d] + base * es, pitch, w, rows,
+                             hipMemcpyDeviceToDevice, R.data));
+    }
+  }
+  return HD_OK;
 }
