@@ -90,6 +90,186 @@ def cpu_baseline_jacobi(n, steps):
     return steps / dt, dt
 
 
+def bench_matmul(hd, rt, steps, warmup):
+    """matmul: C = A.B, 4096^2 fp32, 8 row partitions; the first call gathers
+    B (448 MiB through pack/unpack), later calls communicate nothing."""
+    from workloads import matmul_inputs
+    n = 4096
+    a0, b0 = matmul_inputs(n, 3)
+    A, B, Cc = rt.create(a0), rt.create(b0), rt.create(shape=(n, n))
+    p = rt.partition(hd.ROW, (n, n), ndev=8)
+    rt.kernel("gemm", hd.K_MATMUL)
+    rt.set_offsets("gemm", 0, 0, [(0, "*")])
+    rt.set_offsets("gemm", 1, 0, [("*", 0)])
+    rt.set_offsets("gemm", 2, 1, [(0, 0)])
+    rt.write(A, a0, p)
+    rt.write(B, b0, p)
+    rt.sync()
+    rt.profile(0xF)
+    rt.profile_read()
+    rt.apply("gemm", p, [A, B, Cc])
+    rt.sync()
+    first = rt.profile_read()
+    st = rt.stats()
+    for _ in range(warmup):
+        rt.apply("gemm", p, [A, B, Cc])
+    rt.sync()
+    rt.profile(1 << 3)
+    rt.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rt.apply("gemm", p, [A, B, Cc])
+    rt.sync()
+    dt = time.perf_counter() - t0
+    kms, kc = rt.profile_read()["kernel"]
+    rt.profile(0)
+    flops = 2.0 * n ** 3
+    tf = flops / (kms / kc * 1e-3) / 1e12
+    moved = st["last_bytes"]
+    pk, up = first["pack"][0], first["unpack"][0]
+    return {"metric": METRIC, "value": steps / dt, "unit": "steps/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": dt * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "matmul: C=A.B 4096x4096 fp32 U[-1,1), 8 row partitions, use A (0,*), "
+                                   "B (*,0), def C (0,0)", "first_step_messages": st["last_messages"],
+                       "first_step_bytes": moved, "first_step_ms": sum(v[0] for v in first.values())},
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
+                         "traffic": None, "kernel": "k_mm_mfma", "avg_launch_us": kms / kc * 1e3},
+            "pack_unpack": {"bytes": moved, "pack_GBps": 2 * moved / (pk * 1e-3) / 1e9 if pk else None,
+                            "unpack_GBps": 2 * moved / (up * 1e-3) / 1e9 if up else None,
+                            "frac_hbm": (2 * moved / (pk * 1e-3) / 1e9) / HBM_PEAK_GBS if pk else None}}
+
+
+def bench_batched(hd, rt, steps, warmup):
+    """batched: 64 arrays (sides log-uniform in [512, 4096], 2-32 irregular
+    row partitions, 5-point or lower-triangular), ping-pong; plain per-call
+    steps vs one persistent graph-replayed launch per step."""
+    sys.path.insert(0, ROOT)
+    from tests import programs as prog
+    from workloads import batched_instance
+    inst = batched_instance(seed=4)
+    arrs = prog.batched_arrays(rt, inst)
+    cells = 0
+    for m in inst:
+        H, W = m["shape"]
+        cells += H * W if m["kind"] == 0 else H * (H + 1) // 2
+    bytes_step = 8 * cells
+
+    def plain(i):
+        for j, (A, B, p, kind) in enumerate(arrs):
+            if i % 2 == 0:
+                rt.apply(f"b{j}AB", p, [A, B])
+            else:
+                rt.apply(f"b{j}BA", p, [B, A])
+
+    for i in range(2):
+        plain(i)
+    rt.sync()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        plain(i)
+    rt.sync()
+    t_plain = (time.perf_counter() - t0) / steps
+    ids = []
+    for even in (True, False):
+        rt.batch_begin()
+        for j, (A, B, p, kind) in enumerate(arrs):
+            if even:
+                rt.apply(f"b{j}AB", p, [A, B])
+            else:
+                rt.apply(f"b{j}BA", p, [B, A])
+        ids.append(rt.batch_end())
+    cfg = rt.batch_autotune(ids, reps=2)
+    for i in range(warmup):
+        rt.batch_run(ids[i % 2])
+    rt.sync()
+    rt.profile(1 << 3)
+    rt.profile_read()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        rt.batch_run(ids[i % 2])
+    rt.sync()
+    t_batch = (time.perf_counter() - t0) / steps
+    kms, kc = rt.profile_read()["kernel"]
+    rt.profile(0)
+    ach = bytes_step / (kms / kc * 1e-3) / 1e9
+    return {"metric": METRIC, "value": 1.0 / t_batch, "unit": "steps/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "batched: 64 arrays, sides log-uniform [512,4096], 2-32 irregular row "
+                                   "partitions, 5-point or lower-triangular stencil, ping-pong",
+                       "cells": cells, "plain_steps_per_s": 1.0 / t_plain, "batched_over_plain": t_plain / t_batch,
+                       "autotuned_rows": cfg >> 8, "autotuned_pack_words": cfg & 255},
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch",
+                         "bytes_per_launch": bytes_step, "avg_launch_us": kms / kc * 1e3}}
+
+
+def bench_stencil3d(hd, rt, steps, warmup, n=512, T=64, ckpt=8):
+    """stencil3d: 7-point stencil n^3 fp32, 2x2x2 blocks; a full
+    differentiable pass (T forward steps with checkpoints, then the
+    checkpointed backward: recompute + adjoint steps)."""
+    import torch
+    from paper_1809_05657_amd import autograd as ag
+    from workloads import S3D_COEFFS, stencil3d_inputs
+    u0, w = stencil3d_inputs(n)
+    solver = ag.Stencil3D(rt, (n, n, n), ndev=8, T=T, ckpt=ckpt)
+    dev = torch.device("cuda:0")
+    u0_t, w_t = torch.from_numpy(u0).to(dev), torch.from_numpy(w).to(dev)
+    coef = [float(c) for c in S3D_COEFFS]
+    solver.forward(u0_t, coef)
+    solver.backward(w_t)
+    rt.profile(0xF)
+    rt.profile_read()
+    t0 = time.perf_counter()
+    solver.forward(u0_t, coef)
+    t1 = time.perf_counter()
+    solver.backward(w_t)
+    t2 = time.perf_counter()
+    ph = rt.profile_read()
+    rt.profile(0)
+    cells = n ** 3
+    fwd_bytes = 8 * cells
+    kms, kc = ph["kernel"]
+    return {"metric": METRIC, "value": 1.0 / (t2 - t0), "unit": "passes/s", "n_gpus": 1, "steps": 1,
+            "warmup": 1, "ms_per_step": (t2 - t0) * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"stencil3d: 7-point {n}^3 fp32, 8 devices (2x2x2), T={T}, checkpoint every "
+                                   f"{ckpt}; forward + checkpointed adjoint", "forward_ms": (t1 - t0) * 1e3,
+                       "backward_ms": (t2 - t1) * 1e3},
+            "phases_us": {k: (v[0] / max(v[1], 1)) * 1e3 for k, v in ph.items()},
+            "roofline": {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                         "traffic": None, "kernel": "k_s3d/k_s3d_adj", "bytes_per_forward_step": fwd_bytes,
+                         "avg_kernel_launch_us": kms / max(kc, 1) * 1e3}}
+
+
+def bench_copy_calib(hd, rt, steps, warmup):
+    """A plain copy of known size (8192 x 8192 fp32, one logical device, no
+    communication) through the built-in copy kernel: the reference for
+    scaling HBM traffic counters (256 MiB read + 256 MiB written per launch)."""
+    n = 8192
+    X, Y = rt.create(shape=(n, n)), rt.create(shape=(n, n))
+    p = rt.partition(hd.ROW, (n, n), ndev=1)
+    rt.kernel("cp", hd.K_COPY)
+    rt.set_offsets("cp", 1, 0, [(0, 0)])
+    rt.set_offsets("cp", 0, 1, [(0, 0)])
+    rt.write(X, np.ones((n, n), np.float32), p)
+    rt.write(Y, np.zeros((n, n), np.float32), p)
+    for _ in range(warmup):
+        rt.apply("cp", p, [Y, X])
+    rt.sync()
+    rt.profile(1 << 3)
+    rt.profile_read()
+    for _ in range(steps):
+        rt.apply("cp", p, [Y, X])
+    rt.sync()
+    kms, kc = rt.profile_read()["kernel"]
+    rt.profile(0)
+    b = 2 * 4 * n * n
+    return {"workload": "copy_calib", "bytes_per_launch": b, "avg_launch_us": kms / kc * 1e3,
+            "GBps": b / (kms / kc * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +278,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="jacobi_large",
+                    choices=["jacobi_large", "matmul", "batched", "stencil3d", "copy_calib"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs the ApplyKernel path on one GPU only (the logical devices are "
@@ -110,6 +292,13 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     rt = hd.Runtime(stream=stream.cuda_stream)
+    if args.workload != "jacobi_large":
+        fn = {"matmul": bench_matmul, "batched": bench_batched, "stencil3d": bench_stencil3d,
+              "copy_calib": bench_copy_calib}[args.workload]
+        out = fn(hd, rt, args.steps, args.warmup)
+        rt.close()
+        print(json.dumps(out), flush=True)
+        return
     n = args.n
     A, B, p = setup_jacobi_large(rt, hd, n)
 

@@ -56,6 +56,7 @@ class Profile(C.Structure):
 
 PHASES = ("derive+gdef", "pack", "unpack", "kernel")
 _lib = None
+_TORCH_CB = None
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -146,7 +147,6 @@ class Runtime:
     def __init__(self, use_torch_allocator=True, row_cap=None, stream=None):
         self.L = load()
         self.L.hdarray_exit()
-        self._cb = None
         if use_torch_allocator:
             self._install_torch_allocator()
         argv = []
@@ -160,22 +160,25 @@ class Runtime:
         self.arrays = []
 
     def _install_torch_allocator(self):
+        global _TORCH_CB
         try:
             import torch
         except ImportError:  # plain hipMalloc
             return
         if not torch.cuda.is_available():
             return
-        dev = torch.cuda.current_device()
+        if _TORCH_CB is None:
+            dev = torch.cuda.current_device()
 
-        def _alloc(n, ctx):
-            return torch.cuda.caching_allocator_alloc(int(n), dev, 0)
+            def _alloc(n, ctx):
+                return torch.cuda.caching_allocator_alloc(int(n), dev, 0)
 
-        def _free(p, ctx):
-            torch.cuda.caching_allocator_delete(p)
+            def _free(p, ctx):
+                torch.cuda.caching_allocator_delete(p)
 
-        self._cb = (_ALLOC_T(_alloc), _FREE_T(_free))
-        self.L.hdarray_set_allocator(self._cb[0], self._cb[1], None)
+            # module-level: the library keeps calling them across runtimes
+            _TORCH_CB = (_ALLOC_T(_alloc), _FREE_T(_free))
+        self.L.hdarray_set_allocator(_TORCH_CB[0], _TORCH_CB[1], None)
 
     def _ck(self, rc, what):
         if rc < 0:

@@ -28,12 +28,13 @@ class Stencil3D:
         self.S = [mk(f"seg{k}") for k in range(ckpt + 1)]      # states of one segment
         self.Ck = [mk(f"ckpt{k}") for k in range(T // ckpt)]  # u_0, u_ckpt, ...
         self.G = [mk("gA"), mk("gB")]                          # cotangents (ping-pong)
-        rt.kernel("s3d", K_STENCIL3D7)
-        rt.set_offsets("s3d", 1, 0, S3D_OFFSETS)
-        rt.set_offsets("s3d", 0, 1, [(0, 0, 0)])
-        rt.kernel("s3dcp", K_COPY)
-        rt.set_offsets("s3dcp", 1, 0, [(0, 0, 0)])
-        rt.set_offsets("s3dcp", 0, 1, [(0, 0, 0)])
+        if "s3d" not in rt.kernels:
+            rt.kernel("s3d", K_STENCIL3D7)
+            rt.set_offsets("s3d", 1, 0, S3D_OFFSETS)
+            rt.set_offsets("s3d", 0, 1, [(0, 0, 0)])
+            rt.kernel("s3dcp", K_COPY)
+            rt.set_offsets("s3dcp", 1, 0, [(0, 0, 0)])
+            rt.set_offsets("s3dcp", 0, 1, [(0, 0, 0)])
         self.coef = None
 
     def _segment(self, s):
