@@ -85,8 +85,12 @@ typedef struct {
  * creates the runtime's internal stream.  kpath names the kernel source in
  * the paper; here kernels are built in (see hdarray_register_kernel), so kpath
  * may be NULL.  dpath (device info file) is unused on one GPU and may be NULL.
- * argv may carry "--hd-row-cap=N" (capacity of a per-row GDEF list, default
- * 256).  Returns the HIP device id (>= 0) or a negative error. */
+ * argv may carry "--hd-row-cap=N" (capacity of a per-row GDEF list,
+ * 4..256, default 64; a row needing more intervals raises HD_ECAPACITY).
+ * Environment, read here: HD_SERIAL=1 runs the communication-set
+ * derivation and GDEF update on the data stream instead of overlapping
+ * them (a measurement aid); HD_JACOBI_ROWS=8|16|32 sets the rows per tile of
+ * the Jacobi / triangular kernels of later plans (default 16).  Returns the HIP device id (>= 0) or a negative error. */
 int hdarray_init(int argc, char **argv, const char *kpath, const char *dpath);
 
 /* HDArrayExit: waits for the GPU, frees every array, plan and buffer. */

@@ -109,7 +109,9 @@ struct Runtime {
   hd_alloc_fn ualloc = nullptr;
   hd_free_fn ufree = nullptr;
   void *uctx = nullptr;
-  int row_cap = kMaxCap;
+  int row_cap = 64;
+  bool serial = false;  // metadata work on the data stream (measurement aid)
+  int jacobi_rows = 16;
   std::vector<hd_array *> arrays;
   std::vector<Partition> parts;
   std::vector<Kernel> kernels;
@@ -242,6 +244,11 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
       int c = atoi(argv[i] + 13);
       if (c >= 4 && c <= kMaxCap) R.row_cap = c;
     }
+  }
+  if (const char *e = getenv("HD_SERIAL")) R.serial = atoi(e) != 0;
+  if (const char *e = getenv("HD_JACOBI_ROWS")) {
+    const int v = atoi(e);
+    if (v == 8 || v == 16 || v == 32) R.jacobi_rows = v;
   }
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
@@ -1057,27 +1064,31 @@ extern "C" int hdarray_profile_read(hd_profile_t *out) {
 // Enqueues communication (meta: derive; data: pack, unpack) and the GDEF
 // update for a plan; the user kernel (if any) follows on the data stream.
 static int enqueue(Plan *pl, const float *coef) {
+  const hipStream_t meta = R.serial ? R.data : R.meta;
   const int slot = R.parity;
   R.parity ^= 1;
-  if (R.free_pending[slot]) HIPCK(hipStreamWaitEvent(R.meta, R.ev_free[slot], 0));
+  if (R.free_pending[slot]) HIPCK(hipStreamWaitEvent(meta, R.ev_free[slot], 0));
   const PlanDev &P = pl->P;
   Work W = R.W;
   {
-  PhaseTimer tm(0, R.meta);
-  HIPCK(launch_runs(P, R.d_arrs, W, R.meta));
+  PhaseTimer tm(0, meta);
+  // adjoint: the cotangent array is defined by the owners of the work boxes
+  // first, so its use-region messages are exactly {(owner(x) -> d, x)}
+  if (pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
+  HIPCK(launch_runs(P, R.d_arrs, W, meta));
   Level L1 = make_level(1, P);
   if (!pl->has3d) {
-    HIPCK(launch_level(L1, W.err, R.meta));
-    HIPCK(launch_compact(P, L1, W, R.tab[slot], R.hdr[slot], R.ws_items, 0, R.meta));
+    HIPCK(launch_level(L1, W.err, meta));
+    HIPCK(launch_compact(P, L1, W, R.tab[slot], R.hdr[slot], R.ws_items, 0, meta));
   } else {
-    HIPCK(launch_level(L1, W.err, R.meta));
-    HIPCK(launch_compact(P, L1, W, R.tab[slot], R.hdr[slot], R.ws_items, 1, R.meta));
+    HIPCK(launch_level(L1, W.err, meta));
+    HIPCK(launch_compact(P, L1, W, R.tab[slot], R.hdr[slot], R.ws_items, 1, meta));
     Level L2 = make_level(2, P);
-    HIPCK(launch_level(L2, W.err, R.meta));
-    HIPCK(launch_compact(P, L2, W, R.tab[slot], R.hdr[slot], R.ws_items, 2, R.meta));
+    HIPCK(launch_level(L2, W.err, meta));
+    HIPCK(launch_compact(P, L2, W, R.tab[slot], R.hdr[slot], R.ws_items, 2, meta));
   }
-  HIPCK(hipEventRecord(R.ev_cs[slot], R.meta));
-  HIPCK(launch_gdef(P, R.d_arrs, W, R.meta));
+  HIPCK(hipEventRecord(R.ev_cs[slot], meta));
+  if (!pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
   }
   // data stream
   HIPCK(hipStreamWaitEvent(R.data, R.ev_cs[slot], 0));
@@ -1323,7 +1334,7 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
       return g_last_error;
     }
     pl->ukind = user_kind(k->builtin);
-    pl->th = 16;
+    pl->th = R.jacobi_rows;
     int64_t t0 = 0;
     for (WorkBox &w : wb) {
       w.tile0 = t0;
