@@ -112,7 +112,8 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   }
   {
     GdefLds S{my.g.iv, my.g.b, my.g.u, my.g.own, my.g.hold};
-    for (int t = gw; t < B.P.ngrow; t += nw) dev_gdef_row(B.P, B.A, B.W, t, S, kBatchMaxB);
+    for (int t = gw; t < B.P.ngrow; t += nw)
+      if (!dev_gdef_row_fast(B.P, B.A, B.W, t)) dev_gdef_row(B.P, B.A, B.W, t, S, kBatchMaxB);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   {

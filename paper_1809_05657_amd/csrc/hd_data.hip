@@ -27,6 +27,14 @@ __global__ __launch_bounds__(64) void k_jacobi(const WorkBox *__restrict__ wb, i
   dev_jacobi_tile<TH, TRI>(B, t - B.tile0, A);
 }
 
+template <int TH, int PF, bool TRI>
+__global__ __launch_bounds__(64) void k_jacobi_roll(const WorkBox *__restrict__ wb, int nbox,
+                                                    const ArrDev *__restrict__ A, int64_t ntiles) {
+  const int64_t t = xcd_remap(blockIdx.x, ntiles);
+  const WorkBox B = wb[find_box(wb, nbox, t)];
+  dev_jacobi_roll<TH, PF, TRI>(B, t - B.tile0, A);
+}
+
 __global__ __launch_bounds__(64) void k_copy(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
                                              int64_t ntiles) {
   const int64_t t = xcd_remap(blockIdx.x, ntiles);
@@ -156,7 +164,9 @@ hipError_t launch_user(int kind, int th, const WorkBox *wb, int nbox, const ArrD
   if (ntiles <= 0) return hipSuccess;
   switch (kind) {
     case 1:
-      if (th == 8)
+      if (th == 64)
+        hipLaunchKernelGGL((k_jacobi_roll<64, 4, false>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
+      else if (th == 8)
         hipLaunchKernelGGL((k_jacobi<8, false>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
       else if (th == 32)
         hipLaunchKernelGGL((k_jacobi<32, false>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
@@ -164,7 +174,9 @@ hipError_t launch_user(int kind, int th, const WorkBox *wb, int nbox, const ArrD
         hipLaunchKernelGGL((k_jacobi<16, false>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
       break;
     case 5:
-      if (th == 8)
+      if (th == 64)
+        hipLaunchKernelGGL((k_jacobi_roll<64, 4, true>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
+      else if (th == 8)
         hipLaunchKernelGGL((k_jacobi<8, true>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
       else if (th == 32)
         hipLaunchKernelGGL((k_jacobi<32, true>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);

@@ -112,16 +112,22 @@ __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, 
     nr = 0;
   }
   wave_lds_sync();
-  int off = 0;
-  if (lane == 0 && nr) {
-    off = atomicAdd(W.run_top, nr);
-    if ((int64_t)off + nr > W.run_cap) {
-      set_err(W.err, -8);
-      off = -1;
+  // storage: the row's own slot, or the spill pool after all slots
+  int off = s * kRunSlot;
+  if (nr > kRunSlot) {
+    const int64_t pool0 = (int64_t)P.nsl1 * kRunSlot;
+    if (lane == 0) {
+      off = atomicAdd(W.run_top, nr);
+      if (pool0 + off + nr > W.run_cap) {
+        set_err(W.err, -8);
+        off = -1;
+      } else {
+        off += (int)pool0;
+      }
     }
+    off = __shfl(off, 0);
+    if (off < 0) nr = 0;
   }
-  off = __shfl(off, 0);
-  if (off < 0) nr = 0;
   // rank sort by (col, dst): keys are unique (runs of one dst are disjoint)
   for (int i = lane; i < nr; i += 64) {
     const Item x = rr[i];
@@ -257,14 +263,10 @@ __device__ inline void dev_heads(const Level &L, int b, int32_t *err) {
   int nh = 0;
   for (int k = 0; k < cc; ++k)
     if (!(adj && contains(prv, pc, cur[k]))) ++nh;
-  int off = 0;
-  if (nh) {
-    off = atomicAdd(L.head_top, nh);
-    if ((int64_t)off + nh > L.head_cap) {
-      set_err(err, -8);
-      nh = 0;
-    }
-  }
+  // heads are a subset of the band's first slice's items: store them at the
+  // same positions of the head array (no allocation)
+  const int off = L.ioff[s0];
+  (void)err;
   L.hoff[b] = off;
   L.hcnt[b] = nh;
   int h = 0;
@@ -420,6 +422,100 @@ __device__ inline void dev_compact(const PlanDev &P, const Level &L, const Work 
 // (every receiver of an element becomes a holder) then definitions (owner =
 // definer, holders = {definer} [+ host for Write]).  LDS scratch private to
 // the wave: iv[kMaxCap], b[maxb], u[maxb], own[maxb], hold[maxb].
+// State of the elementary segment starting at x: old interval (lanes 0..n-1
+// hold the old list), then holder additions, then definitions.
+__device__ inline void gdef_state(int x, int n, int st, int ow, uint64_t ho, const Item *runs, int nrun,
+                                  const Seg *ds, int nds, int &own, uint64_t &hol) {
+  // last interval with start <= x (old starts in lanes 0..n-1, start[0] = 0);
+  // binary lifting with every lane active at every shuffle
+  int lo = 0;
+#pragma unroll
+  for (int step = 32; step >= 1; step >>= 1) {
+    const int cand = lo + step;
+    const int v = __shfl(st, cand & 63);
+    if (cand < n && v <= x) lo = cand;
+  }
+  own = __shfl(ow, lo);
+  hol = __shfl(ho, lo);
+  for (int e = 0; e < nrun; ++e) {
+    const Item r = runs[e];
+    if (r.a0 <= x && x < r.a1) hol |= 1ull << r.dst;
+  }
+  for (int e = 0; e < nds; ++e) {
+    const Seg d = ds[e];
+    if (d.c0 <= x && x < d.c1) {
+      own = d.dst;
+      hol = (1ull << d.dst) | ((d.flags & 1) ? (1ull << kHost) : 0ull);
+    }
+  }
+}
+
+// Register-only update of one row (one wave, no LDS): every boundary of the
+// old list and of the edits sits in one lane.  Returns false (row untouched)
+// when the row has more than 64 boundaries; the caller then uses dev_gdef_row.
+__device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t) {
+  const int lane = threadIdx.x & 63;
+  const int aidx = P.gr_aidx[t];
+  ArrDev &a = A[P.carr[aidx].arr];
+  const int64_t grow = P.gr_row[t];
+  const int n = a.cnt[grow];
+  const int W2 = (int)a.n[2];
+  Ivl *row = a.ivl + grow * (int64_t)a.cap;
+  const int sl = P.gr_slice[t];
+  const Item *runs = sl >= 0 ? W.runs + W.roff[sl] : nullptr;
+  const int nrun = sl >= 0 ? W.rcnt[sl] : 0;
+  const Seg *ds = P.dseg + P.gr_dseg0[t];
+  const int nds = P.gr_ndseg[t];
+  const int nb = n + 2 * (nrun + nds);
+  if (nb > 64) return false;
+  int st = 0x7fffffff, ow = 0;
+  uint64_t ho = 0;
+  if (lane < n) {
+    const Ivl v = row[lane];
+    st = v.start;
+    ow = v.owner;
+    ho = v.holders;
+  }
+  int b = 0x7fffffff;
+  if (lane < n) {
+    b = st;
+  } else if (lane < n + 2 * nrun) {
+    const Item r = runs[(lane - n) >> 1];
+    b = ((lane - n) & 1) ? (r.a1 < W2 ? r.a1 : 0) : r.a0;
+  } else if (lane < nb) {
+    const Seg d = ds[(lane - n - 2 * nrun) >> 1];
+    b = ((lane - n - 2 * nrun) & 1) ? (d.c1 < W2 ? d.c1 : 0) : d.c0;
+  }
+  // first occurrence of each value, and its predecessor value
+  bool first = lane < nb;
+  int pv = -1;
+  for (int j = 0; j < nb; ++j) {
+    const int y = __shfl(b, j);
+    if (j < lane && y == b) first = false;
+    if (y < b && y > pv) pv = y;
+  }
+  int own = 0, pown = 0;
+  uint64_t hol = 0, phol = 0;
+  // both calls are made by every lane (they contain shuffles)
+  gdef_state(first ? b : 0, n, st, ow, ho, runs, nrun, ds, nds, own, hol);
+  gdef_state(pv < 0 ? 0 : pv, n, st, ow, ho, runs, nrun, ds, nds, pown, phol);
+  const bool keep = first && (pv < 0 || own != pown || hol != phol);
+  int idx = 0;
+  for (int j = 0; j < nb; ++j) {
+    const int y = __shfl(b, j);
+    const int kj = __shfl((int)keep, j);
+    if (kj && y < b) ++idx;
+  }
+  const int nn = __popcll(__ballot(keep));
+  if (nn > a.cap) {
+    if (lane == 0) set_err(W.err, -8);
+    return true;
+  }
+  if (keep) row[idx] = Ivl{b, own, hol};
+  if (lane == 0) a.cnt[grow] = nn;
+  return true;
+}
+
 struct GdefLds {
   Ivl *iv;
   int32_t *b, *u, *own;

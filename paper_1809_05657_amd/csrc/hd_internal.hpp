@@ -18,6 +18,7 @@ constexpr int kMaxCap = 256;        // largest per-row interval capacity
 constexpr int kMaxRunsRow = 256;    // runs one use row may produce
 constexpr int kMaxCallArrays = 8;   // distinct arrays in one ApplyKernel
 constexpr int kMaxBoundaries = 1024;// elementary boundaries of one GDEF row update
+constexpr int kRunSlot = 16;        // runs stored in a use row's own slot; more spill to a pool
 
 struct Ivl {
   int32_t start;
@@ -134,9 +135,11 @@ struct PlanDev {
 struct Work {
   int32_t *roff;   // [nsl1] run pool offset of each use row
   int32_t *rcnt;   // [nsl1]
-  Item *runs;
-  int32_t *run_top;
+  Item *runs;      // [nsl1 * kRunSlot] row slots, then the spill pool
+  int32_t *run_top;  // spill pool top (relative to the pool start)
   int64_t run_cap;
+  int32_t *ovf_cnt;   // GDEF rows left to the large-row path
+  int32_t *ovf_list;
   int32_t *goff;   // [ngrp] level-1 output offset per group
   int32_t *gcnt;   // [ngrp]
   Item *l1out;     // level-1 output (3-D)

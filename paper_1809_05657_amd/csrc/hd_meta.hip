@@ -32,12 +32,26 @@ __global__ __launch_bounds__(1024) void k_compact(PlanDev P, Level L, Work W, Ms
   dev_compact(P, L, W, out, hdr, out_cap, mode);
 }
 
-__global__ __launch_bounds__(64) void k_gdef(PlanDev P, ArrDev *__restrict__ A, Work W) {
+// rows with at most 64 boundaries, register-only; larger rows are listed
+__global__ __launch_bounds__(256) void k_gdef(PlanDev P, ArrDev *__restrict__ A, Work W) {
+  const int wv = threadIdx.x >> 6;
+  for (int t = blockIdx.x * 4 + wv; t < P.ngrow; t += gridDim.x * 4) {
+    if (!dev_gdef_row_fast(P, A, W, t) && (threadIdx.x & 63) == 0) W.ovf_list[atomicAdd(W.ovf_cnt, 1)] = t;
+  }
+}
+
+// the listed large rows, one wave each with LDS scratch; resets the list
+__global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict__ A, Work W) {
   __shared__ Ivl s_iv[kMaxCap];
   __shared__ int32_t s_b[kGdefMaxB], s_u[kGdefMaxB], s_own[kGdefMaxB];
   __shared__ uint64_t s_hold[kGdefMaxB];
   GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
-  for (int t = blockIdx.x; t < P.ngrow; t += gridDim.x) dev_gdef_row(P, A, W, t, S, kGdefMaxB);
+  const int cnt = *W.ovf_cnt;
+  for (int q = blockIdx.x; q < cnt; q += gridDim.x) dev_gdef_row(P, A, W, W.ovf_list[q], S, kGdefMaxB);
+}
+
+__global__ void k_zero_ovf(int32_t *c) {
+  if (threadIdx.x == 0) *c = 0;
 }
 
 // Every row starts as one interval [0, n2) owned and held by the host.
@@ -82,8 +96,11 @@ hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipSt
 
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s) {
   if (P.ngrow == 0) return hipSuccess;
-  int grid = P.ngrow < 16384 ? P.ngrow : 16384;
-  hipLaunchKernelGGL(k_gdef, dim3(grid), dim3(64), 0, s, P, A, W);
+  int grid = cdiv(P.ngrow, 4);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_gdef, dim3(grid), dim3(256), 0, s, P, A, W);
+  hipLaunchKernelGGL(k_gdef_large, dim3(256), dim3(64), 0, s, P, A, W);
+  hipLaunchKernelGGL(k_zero_ovf, dim3(1), dim3(64), 0, s, W.ovf_cnt);
   return hipGetLastError();
 }
 

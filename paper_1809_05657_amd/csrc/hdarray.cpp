@@ -248,7 +248,7 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   if (const char *e = getenv("HD_SERIAL")) R.serial = atoi(e) != 0;
   if (const char *e = getenv("HD_JACOBI_ROWS")) {
     const int v = atoi(e);
-    if (v == 8 || v == 16 || v == 32) R.jacobi_rows = v;
+    if (v == 8 || v == 16 || v == 32 || v == 64) R.jacobi_rows = v;
   }
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
@@ -269,6 +269,7 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   HIPCK(hipMemset(R.counters, 0, 64));
   R.W.run_top = R.counters + 0;
   R.W.err = R.counters + 3;
+  R.W.ovf_cnt = R.counters + 4;
   HIPCK(hipHostMalloc((void **)&R.red_res_host, 64, hipHostMallocDefault));
   R.red_res_dev = dalloc(64);
   R.red_pf = (double *)dalloc(sizeof(double) * kMaxDev * 64 * 4);
@@ -755,6 +756,8 @@ static void free_ws() {
   dfree(R.hoff);
   dfree(R.hcnt);
   dfree(R.heads);
+  dfree(R.W.ovf_list);
+  R.W.ovf_list = nullptr;
   for (int k = 0; k < 2; ++k) {
     dfree(R.tab[k]);
     dfree(R.hdr[k]);
@@ -772,8 +775,8 @@ static void free_ws() {
   R.ws_nsl = R.ws_ngrp = R.ws_items = 0;
 }
 
-static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg) {
-  nsl = std::max<int64_t>(nsl, ngrp);
+static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int64_t ngrow) {
+  nsl = std::max<int64_t>(nsl, std::max<int64_t>(ngrp, ngrow));
   if (nsl <= R.ws_nsl && ngrp <= R.ws_ngrp && items <= R.ws_items && stg <= R.staging_cap) return HD_OK;
   HIPCK(hipStreamSynchronize(R.meta));
   HIPCK(hipStreamSynchronize(R.data));
@@ -803,6 +806,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg) {
     R.hoff = (int32_t *)dalloc(4 * ns);
     R.hcnt = (int32_t *)dalloc(4 * ns);
     R.heads = (Item *)dalloc(sizeof(Item) * it);
+    R.W.ovf_list = (int32_t *)dalloc(4 * ns);
     for (int k = 0; k < 2; ++k) {
       R.tab[k] = (MsgRec *)dalloc(sizeof(MsgRec) * it);
       R.hdr[k] = (MsgHdr *)dalloc(sizeof(MsgHdr));
@@ -975,9 +979,9 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   // work boxes are filled by the caller into the host blob first
   pl->nbox = 0;
   HIPCK(hipMemcpy(pl->mem, blob.data(), blob.size(), hipMemcpyHostToDevice));
-  // workspace sizing: items bounded by 8 per segment (at least 4M)
-  const int64_t items = std::max<int64_t>(int64_t(1) << 22, 8 * (int64_t)useg.size());
-  return ensure_ws(P.nsl1, P.ngrp, items, stg);
+  // workspace sizing: a slot of kRunSlot runs per use row plus a spill pool
+  const int64_t items = (int64_t)P.nsl1 * kRunSlot + std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)useg.size());
+  return ensure_ws(P.nsl1, P.ngrp, items, stg, P.ngrow);
 }
 
 static Level make_level(int which, const PlanDev &P) {
