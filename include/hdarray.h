@@ -89,8 +89,8 @@ typedef struct {
  * 4..256, default 64; a row needing more intervals raises HD_ECAPACITY).
  * Environment, read here: HD_SERIAL=1 runs the communication-set
  * derivation and GDEF update on the data stream instead of overlapping
- * them (a measurement aid); HD_JACOBI_ROWS=8|16|32 sets the rows per tile of
- * the Jacobi / triangular kernels of later plans (default 16).  Returns the HIP device id (>= 0) or a negative error. */
+ * them (a measurement aid); HD_JACOBI_ROWS=4|8|16 sets the rows per tile of
+ * the Jacobi / triangular kernels of later plans (default 8).  Returns the HIP device id (>= 0) or a negative error. */
 int hdarray_init(int argc, char **argv, const char *kpath, const char *dpath);
 
 /* HDArrayExit: waits for the GPU, frees every array, plan and buffer. */
@@ -199,7 +199,7 @@ int hdarray_reduce(hd_array_t *a, void *res, hd_reduce_t op, int part);
 int hdarray_batch_begin(void);
 int hdarray_batch_end(void);
 int hdarray_batch_run(int batch);
-/* Chooses the rows per stencil tile (8, 16, 32) and the words per pack
+/* Chooses the rows per stencil tile (4, 8, 16) and the words per pack
  * iteration (1, 4) of the given batches by timing each of the 6 candidates
  * on `reps` runs of the sequence batches[0..n) after one warm-up run.  These
  * runs are real steps of the program: 6 * (reps + 1) sequences execute.  The

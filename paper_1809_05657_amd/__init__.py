@@ -26,6 +26,7 @@ SUM, PROD, MAX, MIN = 0, 1, 2, 3
 K_JACOBI2D, K_COPY, K_MATMUL, K_TRI2D, K_STENCIL3D7 = 1, 2, 3, 4, 5
 BUILTIN_NAMES = {K_JACOBI2D: "jacobi2d", K_COPY: "copy", K_MATMUL: "matmul", K_TRI2D: "tri2d",
                  K_STENCIL3D7: "stencil3d7"}
+DEFAULT_JACOBI_ROWS = 8  # rows per stencil tile when HD_JACOBI_ROWS is unset (runtime default)
 EINVAL, EBOUNDS, ERACE, EKERNEL, ENOMEM, EHIP, ESTATE, ECAPACITY = -1, -2, -3, -4, -5, -6, -7, -8
 MSG_FIELDS = ("arg", "array", "src", "dst", "lo0", "lo1", "lo2", "hi0", "hi1", "hi2", "off", "bytes")
 _TYPE_NAME = {F32: b"float", I32: b"int", F64: b"double"}

@@ -23,7 +23,7 @@ constexpr int kBatchMaxB = 512;  // boundaries of one GDEF row update in a batch
 // per-wave LDS: union of the runs scratch and the GDEF scratch
 struct RunsLds {
   Ivl iv[kMaxCap];
-  Item rr[kMaxRunsRow];
+  Run rr[kMaxRunsRow];
 };
 struct GdefLdsB {
   Ivl iv[kMaxCap];
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   {
     const int nb = B.L1.nsl ? *B.L1.nb : 0;
-    for (int64_t b = gt; b < nb; b += gs) dev_heads(B.L1, (int)b, err);
+    for (int b = gw; b < nb; b += nw) dev_heads(B.L1, b);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   if (!B.P.has3d) {
@@ -95,33 +95,26 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
     {
       const int nb = B.L2.nsl ? *B.L2.nb : 0;
-      for (int64_t b = gt; b < nb; b += gs) dev_heads(B.L2, (int)b, err);
+      for (int b = gw; b < nb; b += nw) dev_heads(B.L2, b);
     }
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
     if (blockIdx.x == 0) dev_compact(B.P, B.L2, B.W, B.tab, B.hdr, B.tab_cap, 2);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
-  // pack, and the GDEF update (metadata only, independent of the data)
+  // pack + unpack in one pass, and the GDEF update (metadata only,
+  // independent of the data)
   const int64_t nmsg = B.hdr->nmsg, words = B.hdr->bytes >> 2;
   {
     int m = 0;
     for (int64_t q = gt; q * PW < words; q += gs)
 #pragma unroll
       for (int e = 0; e < PW; ++e)
-        if (q * PW + e < words) dev_pack_word(B.tab, nmsg, B.A, B.stg, 0, q * PW + e, m);
+        if (q * PW + e < words) dev_pack_word(B.tab, nmsg, B.A, B.stg, 2, q * PW + e, m);
   }
   {
     GdefLds S{my.g.iv, my.g.b, my.g.u, my.g.own, my.g.hold};
     for (int t = gw; t < B.P.ngrow; t += nw)
       if (!dev_gdef_row_fast(B.P, B.A, B.W, t)) dev_gdef_row(B.P, B.A, B.W, t, S, kBatchMaxB);
-  }
-  if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
-  {
-    int m = 0;
-    for (int64_t q = gt; q * PW < words; q += gs)
-#pragma unroll
-      for (int e = 0; e < PW; ++e)
-        if (q * PW + e < words) dev_pack_word(B.tab, nmsg, B.A, B.stg, 1, q * PW + e, m);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   // user kernels: one wave per tile
@@ -143,9 +136,9 @@ __global__ void k_zero_bar(unsigned *bar) {
 typedef void (*batch_kernel_t)(BatchArgs);
 
 static batch_kernel_t pick(int th, int pw) {
-  if (th == 8) return pw == 4 ? k_batch<8, 4> : k_batch<8, 1>;
-  if (th == 32) return pw == 4 ? k_batch<32, 4> : k_batch<32, 1>;
-  return pw == 4 ? k_batch<16, 4> : k_batch<16, 1>;
+  if (th == 4) return pw == 4 ? k_batch<4, 4> : k_batch<4, 1>;
+  if (th == 16) return pw == 4 ? k_batch<16, 4> : k_batch<16, 1>;
+  return pw == 4 ? k_batch<8, 4> : k_batch<8, 1>;
 }
 
 int batch_max_blocks(int th, int pw) {

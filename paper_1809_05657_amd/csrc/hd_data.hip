@@ -13,26 +13,41 @@ static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 int64_t mm_tiles(const int32_t *lo, const int32_t *hi);
 hipError_t launch_mm(const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles, hipStream_t s);
 
+// Pack / unpack (mode 0 / 1) or both in one pass (mode 2).  Every message is
+// cut into S equal spans (S from the average message size, so that the
+// workgroups share the volume); workgroups take (message, span) pairs, so the
+// record is read once per span and no word searches the table.
 __global__ __launch_bounds__(256) void k_pack(const MsgRec *__restrict__ M, const MsgHdr *__restrict__ H,
-                                              const ArrDev *__restrict__ A, uint32_t *__restrict__ stg,
-                                              int unpack) {
-  dev_pack(M, H, A, stg, unpack, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+                                              const ArrDev *__restrict__ A, uint32_t *__restrict__ stg, int mode) {
+  const int64_t nmsg = H->nmsg;
+  if (nmsg <= 0) return;
+  const int64_t words = H->bytes >> 2;
+  const int64_t G = gridDim.x;
+  int64_t S = (words + nmsg * 1024 - 1) / (nmsg * 1024);
+  const int64_t smax = G / nmsg > 1 ? G / nmsg : 1;
+  if (S > smax) S = smax;
+  if (S < 1) S = 1;
+  for (int64_t q = blockIdx.x; q < nmsg * S; q += G) {
+    const int64_t m = q / S, sub = q % S;
+    const MsgRec r = M[m];
+    const int64_t nw = r.bytes >> 2;
+    const int64_t b0 = nw * sub / S, b1 = nw * (sub + 1) / S;
+    if (nw < (int64_t(1) << 31))
+      dev_pack_span<int32_t>(r, A, stg, mode, (int32_t)b0, (int32_t)b1);
+    else
+      dev_pack_span<int64_t>(r, A, stg, mode, b0, b1);
+  }
 }
 
+// Four waves per workgroup, one tile each (4 x 256 columns of the same rows).
 template <int TH, bool TRI>
-__global__ __launch_bounds__(64) void k_jacobi(const WorkBox *__restrict__ wb, int nbox,
-                                               const ArrDev *__restrict__ A, int64_t ntiles) {
-  const int64_t t = xcd_remap(blockIdx.x, ntiles);
+__global__ __launch_bounds__(256) void k_jacobi(const WorkBox *__restrict__ wb, int nbox,
+                                                const ArrDev *__restrict__ A, int64_t ntiles) {
+  const int64_t nwg = (ntiles + 3) >> 2;
+  const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
+  if (t >= ntiles) return;
   const WorkBox B = wb[find_box(wb, nbox, t)];
   dev_jacobi_tile<TH, TRI>(B, t - B.tile0, A);
-}
-
-template <int TH, int PF, bool TRI>
-__global__ __launch_bounds__(64) void k_jacobi_roll(const WorkBox *__restrict__ wb, int nbox,
-                                                    const ArrDev *__restrict__ A, int64_t ntiles) {
-  const int64_t t = xcd_remap(blockIdx.x, ntiles);
-  const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_jacobi_roll<TH, PF, TRI>(B, t - B.tile0, A);
 }
 
 __global__ __launch_bounds__(64) void k_copy(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
@@ -136,8 +151,9 @@ __global__ void k_reduce_final(int nbox, const double *pf, const uint32_t *pi, v
 // ------------------------------------------------------------- launchers
 hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
                        int unpack, hipStream_t s) {
-  int grid = cdiv(bound_words, 256);
-  if (grid > 4096) grid = 4096;
+  // up to 4 workgroups per CU; fewer when the table cannot be that large
+  int grid = cdiv(bound_words, 1024);
+  if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, s, M, H, A, stg, unpack);
   return hipGetLastError();
@@ -164,25 +180,14 @@ hipError_t launch_user(int kind, int th, const WorkBox *wb, int nbox, const ArrD
   if (ntiles <= 0) return hipSuccess;
   switch (kind) {
     case 1:
-      if (th == 64)
-        hipLaunchKernelGGL((k_jacobi_roll<64, 4, false>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
-      else if (th == 8)
-        hipLaunchKernelGGL((k_jacobi<8, false>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
-      else if (th == 32)
-        hipLaunchKernelGGL((k_jacobi<32, false>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
-      else
-        hipLaunchKernelGGL((k_jacobi<16, false>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
-      break;
-    case 5:
-      if (th == 64)
-        hipLaunchKernelGGL((k_jacobi_roll<64, 4, true>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
-      else if (th == 8)
-        hipLaunchKernelGGL((k_jacobi<8, true>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
-      else if (th == 32)
-        hipLaunchKernelGGL((k_jacobi<32, true>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
-      else
-        hipLaunchKernelGGL((k_jacobi<16, true>), dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
-      break;
+    case 5: {
+      typedef void (*jk_t)(const WorkBox *, int, const ArrDev *, int64_t);
+      const bool tri = kind == 5;
+      jk_t k = tri ? k_jacobi<8, true> : k_jacobi<8, false>;
+      if (th == 4) k = tri ? k_jacobi<4, true> : k_jacobi<4, false>;
+      if (th == 16) k = tri ? k_jacobi<16, true> : k_jacobi<16, false>;
+      hipLaunchKernelGGL(k, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles);
+    } break;
     case 2:
       hipLaunchKernelGGL(k_copy, dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
       break;

@@ -63,7 +63,11 @@ __device__ inline int find_msg(const MsgRec *__restrict__ M, int64_t n, int64_t 
 // Packed word w of the staging buffer <-> element word of the section in the
 // source (pack) or destination (unpack) endpoint's buffer, at the same global
 // coordinates.  Sections are row-major inside each box.  m caches the message
-// of the previous word.
+// of the previous word.  mode 0 packs, 1 unpacks, 2 does both in one pass
+// (the word read from the source goes to the staging buffer and to the
+// destination).  Mode 2 is safe within one table: a message reads cells its
+// source owns and writes cells its destination does not hold, and the owner
+// of a cell always holds it, so no word is written and read in the same pass.
 __device__ inline void dev_pack_word(const MsgRec *__restrict__ M, int64_t n, const ArrDev *__restrict__ A,
                                      uint32_t *__restrict__ stg, int unpack, int64_t w, int &m) {
   if (!(M[m].off <= 4 * w && 4 * w < M[m].off + M[m].bytes)) m = find_msg(M, n, 4 * w);
@@ -77,10 +81,53 @@ __device__ inline void dev_pack_word(const MsgRec *__restrict__ M, int64_t n, co
   const int64_t rr = t % rows, p = t / rows;
   const ArrDev &a = A[r.arr];
   const int64_t g = (((int64_t)r.lo[0] + p) * a.n[1] + r.lo[1] + rr) * a.n[2] * k + (int64_t)r.lo[2] * k + c;
-  if (!unpack)
+  if (unpack == 0) {
     stg[w] = reinterpret_cast<const uint32_t *>(a.buf[r.src])[g];
-  else
+  } else if (unpack == 1) {
     reinterpret_cast<uint32_t *>(a.buf[r.dst])[g] = stg[w];
+  } else {
+    const uint32_t v = reinterpret_cast<const uint32_t *>(a.buf[r.src])[g];
+    stg[w] = v;
+    reinterpret_cast<uint32_t *>(a.buf[r.dst])[g] = v;
+  }
+}
+
+// Words [b0, b1) of message r (row-major inside its box), 4 per thread per
+// iteration; one workgroup of 256 threads.  IT: index type of the word
+// arithmetic (32-bit whenever the message has fewer than 2^31 words).
+template <typename IT>
+__device__ inline void dev_pack_span(const MsgRec &r, const ArrDev *__restrict__ A, uint32_t *__restrict__ stg,
+                                     int mode, IT b0, IT b1) {
+  const ArrDev &a = A[r.arr];
+  const IT k = (IT)(r.esize >> 2);
+  const IT wid = (IT)(r.hi[2] - r.lo[2]) * k, rows = (IT)(r.hi[1] - r.lo[1]);
+  const int64_t rowpitch = a.n[2] * (int64_t)k;
+  const int64_t base = ((int64_t)r.lo[0] * a.n[1] + r.lo[1]) * rowpitch + (int64_t)r.lo[2] * k;
+  const int64_t planepitch = a.n[1] * rowpitch;
+  const uint32_t *__restrict__ src = reinterpret_cast<const uint32_t *>(a.buf[r.src]);
+  uint32_t *__restrict__ dst = reinterpret_cast<uint32_t *>(a.buf[r.dst]);
+  uint32_t *__restrict__ sp = stg + (r.off >> 2);
+  for (IT q = b0 + (IT)threadIdx.x; q < b1; q += 4 * 256) {
+    int64_t g[4];
+    bool ok[4];
+    uint32_t v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const IT lw = q + (IT)(e * 256);
+      ok[e] = lw < b1;
+      const IT c = lw % wid, t = lw / wid;
+      const IT rr = t % rows, p = t / rows;
+      g[e] = base + (int64_t)p * planepitch + (int64_t)rr * rowpitch + (int64_t)c;
+      if (ok[e]) v[e] = mode == 1 ? sp[lw] : src[g[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (!ok[e]) continue;
+      const IT lw = q + (IT)(e * 256);
+      if (mode != 1) sp[lw] = v[e];
+      if (mode != 0) dst[g[e]] = v[e];
+    }
+  }
 }
 
 // Grid-stride over the words of the whole table (the count is device-resident).
@@ -96,13 +143,14 @@ __device__ inline void dev_pack(const MsgRec *__restrict__ M, const MsgHdr *__re
 // ------------------------------------------------------------ jacobi / tri
 // One wave computes a tile of TH rows x 256 columns of one box; each lane
 // owns 4 consecutive columns, the left / right neighbours come from the
-// adjacent lanes (lanes 0 and 63 load the tile's edge columns).
+// adjacent lanes (lanes 0 and 63 load the tile's edge columns).  Tiles are
+// numbered along a row of tiles first, so consecutive waves cover
+// consecutive 1 KiB pieces of the same rows.
 template <int TH, bool TRI>
 __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
   const int lane = threadIdx.x & 63;
-  const int h = B.hi[1] - B.lo[1];
-  const int nty = (h + TH - 1) / TH;
-  const int ty = (int)(lt % nty), tx = (int)(lt / nty);
+  const int ntx = (B.hi[2] - B.lo[2] + 255) / 256;
+  const int tx = (int)(lt % ntx), ty = (int)(lt / ntx);
   const int r0 = B.lo[1] + ty * TH;
   const int r1 = min(r0 + TH, B.hi[1]);
   const int c = B.lo[2] + tx * 256 + 4 * lane;
@@ -143,89 +191,6 @@ __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDe
     if (i >= r1) break;
     const f4 up = v[k - 1], cu = v[k], dn = v[k + 1];
     const float cv[6] = {Lh[k], cu.x, cu.y, cu.z, cu.w, Rh[k]};
-    const float uv[4] = {up.x, up.y, up.z, up.w};
-    const float dv[4] = {dn.x, dn.y, dn.z, dn.w};
-    float o[4];
-    bool wr[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int j = c + e;
-      bool interior, write = j < B.hi[2];
-      if (TRI) {
-        write = write && j <= i;
-        interior = j >= 1 && j < i && i <= N1 - 2;
-      } else {
-        interior = i >= 1 && i <= N1 - 2 && j >= 1 && j <= N2 - 2;
-      }
-      float s = cv[e] + cv[e + 2];
-      s = s + uv[e];
-      s = s + dv[e];
-      o[e] = interior ? s * 0.25f : cv[e + 1];
-      wr[e] = write;
-    }
-    float *q = out + (int64_t)i * N2 + c;
-    if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
-      f4 ov = {o[0], o[1], o[2], o[3]};
-      __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q));
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (wr[e]) q[e] = o[e];
-    }
-  }
-}
-
-// Tall-tile variant: the wave walks TH rows keeping a rolling window of
-// rows in registers and loading PF rows ahead (same operations per cell as
-// dev_jacobi_tile, so results are identical).
-template <int TH, int PF, bool TRI>
-__device__ inline void dev_jacobi_roll(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
-  constexpr int RING = PF + 2;
-  const int lane = threadIdx.x & 63;
-  const int h = B.hi[1] - B.lo[1];
-  const int nty = (h + TH - 1) / TH;
-  const int ty = (int)(lt % nty), tx = (int)(lt / nty);
-  const int r0 = B.lo[1] + ty * TH;
-  const int r1 = min(r0 + TH, B.hi[1]);
-  const int c = B.lo[2] + tx * 256 + 4 * lane;
-  const ArrDev &ai = A[B.ain];
-  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
-  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
-  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
-  const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
-  f4 v[RING];
-  float Lh[RING], Rh[RING];
-  auto load = [&](int r, int slot) {
-    f4 x = {0.f, 0.f, 0.f, 0.f};
-    float l = 0.f, rr = 0.f;
-    if (r >= 0 && r < N1 && r <= r1) {
-      const float *p = in + (int64_t)r * N2;
-      if (vec && c + 4 <= N2) {
-        x = *reinterpret_cast<const f4 *>(p + c);
-      } else {
-        if (c < N2) x.x = p[c];
-        if (c + 1 < N2) x.y = p[c + 1];
-        if (c + 2 < N2) x.z = p[c + 2];
-        if (c + 3 < N2) x.w = p[c + 3];
-      }
-      if (lane == 0 && c >= 1 && c - 1 < N2) l = p[c - 1];
-      if (lane == 63 && c + 4 < N2) rr = p[c + 4];
-    }
-    v[slot] = x;
-    Lh[slot] = l;
-    Rh[slot] = rr;
-  };
-  // rows r0-1 .. r0+PF are in flight before the first computation
-#pragma unroll
-  for (int k = 0; k < PF + 1 && k < RING; ++k) load(r0 - 1 + k, k);
-#pragma unroll
-  for (int k = 1; k <= TH; ++k) {
-    const int i = r0 + k - 1;
-    if (i >= r1) break;
-    if (k + PF < TH + 2) load(r0 - 1 + k + PF, (k + PF) % RING);
-    const f4 up = v[(k - 1) % RING], cu = v[k % RING], dn = v[(k + 1) % RING];
-    const float lw = __shfl_up(cu.w, 1), rx = __shfl_down(cu.x, 1);
-    const float cv[6] = {lane == 0 ? Lh[k % RING] : lw, cu.x, cu.y, cu.z, cu.w, lane == 63 ? Rh[k % RING] : rx};
     const float uv[4] = {up.x, up.y, up.z, up.w};
     const float dv[4] = {dn.x, dn.y, dn.z, dn.w};
     float o[4];

@@ -65,22 +65,30 @@ __device__ inline bool contains(const Item *it, int cnt, const Item &q) {
 }
 
 // ------------------------------------------------------------------- runs
-// One wave (all 64 lanes) handles use row s.  iv: kMaxCap intervals of LDS,
-// rr: kMaxRunsRow items of LDS, both private to the wave.
-__device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, const Work &W, int s, Ivl *iv,
-                                Item *rr) {
+// One wave (all 64 lanes) finds the runs of use row s and leaves them in
+// srt sorted by (col, dst).  iv (kMaxCap intervals) and rr (kMaxRunsRow
+// runs) are LDS scratch private to the wave; srt aliases iv.  Returns the
+// run count (0 after a capacity error, which is recorded).
+static_assert(sizeof(Ivl) == sizeof(Run) && kMaxCap == kMaxRunsRow, "sorted runs reuse the interval scratch");
+
+__device__ inline int dev_runs_find(const PlanDev &P, const ArrDev *__restrict__ A, const Work &W, int s, Ivl *iv,
+                                    Run *rr) {
   const int lane = threadIdx.x & 63;
-  const int aidx = P.grp_aidx[P.grp1[s]];
-  const ArrDev &a = A[P.carr[aidx].arr];
-  const int64_t grow = P.grow1[s];
-  const int n = a.cnt[grow];
+  const SliceRec sr = P.srec[s];
+  const ArrDev &a = A[sr.arr];
+  const Ivl *row = a.ivl + sr.grow * (int64_t)a.cap;
   const int W2 = (int)a.n[2];
-  const Ivl *row = a.ivl + grow * (int64_t)a.cap;
-  for (int i = lane; i < n; i += 64) iv[i] = row[i];
+  // the first 64 intervals are read together with the count (the row's
+  // capacity bounds the read)
+  Ivl v0{};
+  if (lane < a.cap) v0 = row[lane];
+  const int n = a.cnt[sr.grow];
+  if (lane < n) iv[lane] = v0;
+  for (int i = 64 + lane; i < n; i += 64) iv[i] = row[i];
   wave_lds_sync();
   int nr = 0;
-  const int sg1 = P.seg0[s] + P.nseg[s];
-  for (int sg = P.seg0[s]; sg < sg1; ++sg) {
+  const int sg1 = sr.seg0 + sr.nseg;
+  for (int sg = sr.seg0; sg < sg1; ++sg) {
     const Seg S = P.useg[sg];
     const uint64_t bit = 1ull << S.dst;
     auto need = [&](int i) -> bool {
@@ -102,7 +110,7 @@ __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, 
         const int c0 = max(iv[i].start, S.c0);
         const int c1 = min((j < n) ? iv[j].start : W2, S.c1);
         const int k = nr + __popcll(m & lanemask_lt());
-        if (k < kMaxRunsRow) rr[k] = Item{src, S.dst, c0, c1, 0, 0, 0, 0};
+        if (k < kMaxRunsRow) rr[k] = Run{src, S.dst, c0, c1};
       }
       nr += __popcll(m);
     }
@@ -112,7 +120,25 @@ __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, 
     nr = 0;
   }
   wave_lds_sync();
-  // storage: the row's own slot, or the spill pool after all slots
+  // rank sort by (col, dst): keys are unique (runs of one dst are disjoint)
+  Run *srt = reinterpret_cast<Run *>(iv);
+  for (int i = lane; i < nr; i += 64) {
+    const Run x = rr[i];
+    int rank = 0;
+    for (int j = 0; j < nr; ++j) {
+      const Run y = rr[j];
+      rank += (y.a0 < x.a0) || (y.a0 == x.a0 && y.dst < x.dst);
+    }
+    srt[rank] = x;
+  }
+  wave_lds_sync();
+  return nr;
+}
+
+// Stores the sorted runs of slice s: the row's own slot, or the spill pool
+// after all slots.
+__device__ inline void dev_runs_store(const PlanDev &P, const Work &W, int s, const Run *srt, int nr) {
+  const int lane = threadIdx.x & 63;
   int off = s * kRunSlot;
   if (nr > kRunSlot) {
     const int64_t pool0 = (int64_t)P.nsl1 * kRunSlot;
@@ -128,21 +154,66 @@ __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, 
     off = __shfl(off, 0);
     if (off < 0) nr = 0;
   }
-  // rank sort by (col, dst): keys are unique (runs of one dst are disjoint)
   for (int i = lane; i < nr; i += 64) {
-    const Item x = rr[i];
-    int rank = 0;
-    for (int j = 0; j < nr; ++j) {
-      const Item y = rr[j];
-      rank += (y.a0 < x.a0) || (y.a0 == x.a0 && y.dst < x.dst);
-    }
-    W.runs[off + rank] = x;
+    const Run x = srt[i];
+    W.runs[off + i] = Item{x.src, x.dst, x.a0, x.a1, 0, 0, 0, 0};
   }
   if (lane == 0) {
     W.roff[s] = nr ? off : 0;
     W.rcnt[s] = nr;
   }
+}
+
+__device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, const Work &W, int s, Ivl *iv,
+                                Run *rr) {
+  const int nr = dev_runs_find(P, A, W, s, iv, rr);
+  dev_runs_store(P, W, s, reinterpret_cast<const Run *>(iv), nr);
   wave_lds_sync();
+}
+
+// Slice s starts a band unless it continues slice s-1 (same group, next
+// position) with an identical sorted run list; cur / prv are the two lists
+// in LDS.  Called by a whole wave.
+__device__ inline bool runs_band_start(const Level &L, int s, const Run *cur, int nc, const Run *prv, int np) {
+  if (s == 0 || L.grp[s] != L.grp[s - 1] || L.pos[s] != L.pos[s - 1] + 1 || nc != np) return true;
+  const int lane = threadIdx.x & 63;
+  bool diff = false;
+  for (int k = lane; k < nc; k += 64) {
+    const Run x = cur[k], y = prv[k];
+    diff |= x.src != y.src || x.dst != y.dst || x.a0 != y.a0 || x.a1 != y.a1;
+  }
+  return __ballot(diff) != 0;
+}
+
+// Band masks from one byte flag per slice (one wave per 64 slices).
+__device__ inline void dev_masks_from_flags(const Level &L, const uint8_t *flag, int c) {
+  const int lane = threadIdx.x & 63;
+  const int q = c * 64 + lane;
+  const uint64_t m = __ballot(q < L.nsl && flag[q] != 0);
+  if (lane == 0) {
+    L.bmask[c] = m;
+    L.bcnt[c] = __popcll(m);
+  }
+}
+
+// Last-workgroup election: every workgroup calls this once after its
+// results are written; returns true in the one workgroup that finishes last,
+// which then sees every other workgroup's writes.  The counter returns to 0.
+__device__ inline bool last_workgroup(int32_t *done) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int prev = atomicAdd(done, 1);
+    s_last = prev == (int)(gridDim.x * gridDim.y * gridDim.z) - 1;
+    if (s_last) {
+      *done = 0;
+      __threadfence();
+    }
+  }
+  __syncthreads();
+  if (s_last) __threadfence();
+  return s_last != 0;
 }
 
 // -------------------------------------------------------------- band flags
@@ -253,35 +324,49 @@ __device__ inline int band_of(const Level &L, int s) {
   return L.bbase[c] + __popcll(L.bmask[c] & ((1ull << (s & 63)) - 1ull));
 }
 
-__device__ inline void dev_heads(const Level &L, int b, int32_t *err) {
+// One wave per band b; lanes take the items of the band's first slice.  An
+// item not continued from the previous (adjacent) slice is a head; its
+// extent is found by walking the following bands while they hold it.  Heads
+// keep the item order and are stored at their items' positions.
+__device__ inline void dev_heads(const Level &L, int b) {
+  const int lane = threadIdx.x & 63;
   const int s0 = L.bandslice[b], s1 = L.bandslice[b + 1];
   const bool adj = s0 > 0 && L.grp[s0 - 1] == L.grp[s0] && L.pos[s0 - 1] + 1 == L.pos[s0];
-  const Item *cur = L.items + L.ioff[s0];
+  const int off = L.ioff[s0];
+  const Item *cur = L.items + off;
   const int cc = L.icnt[s0];
   const Item *prv = adj ? L.items + L.ioff[s0 - 1] : nullptr;
   const int pc = adj ? L.icnt[s0 - 1] : 0;
+  const int p0 = L.pos[s0];
   int nh = 0;
-  for (int k = 0; k < cc; ++k)
-    if (!(adj && contains(prv, pc, cur[k]))) ++nh;
-  // heads are a subset of the band's first slice's items: store them at the
-  // same positions of the head array (no allocation)
-  const int off = L.ioff[s0];
-  (void)err;
-  L.hoff[b] = off;
-  L.hcnt[b] = nh;
-  int h = 0;
-  for (int k = 0; k < cc && h < nh; ++k) {
-    const Item it = cur[k];
-    if (adj && contains(prv, pc, it)) continue;
-    int e = s1;
-    while (e < L.nsl && L.grp[e] == L.grp[e - 1] && L.pos[e] == L.pos[e - 1] + 1 &&
-           contains(L.items + L.ioff[e], L.icnt[e], it))
-      e = L.bandslice[band_of(L, e) + 1];
-    Item o = it;
-    o.pos0 = L.pos[s0];
-    o.pos1 = L.pos[e - 1] + 1;
-    L.heads[off + h] = o;
-    ++h;
+  int64_t vol = 0;
+  for (int base = 0; base < cc; base += 64) {
+    const int k = base + lane;
+    Item it{};
+    bool head = false;
+    if (k < cc) {
+      it = cur[k];
+      head = !(adj && contains(prv, pc, it));
+    }
+    const uint64_t m = __ballot(head);
+    if (head) {
+      int e = s1;
+      while (e < L.nsl && L.grp[e] == L.grp[e - 1] && L.pos[e] == L.pos[e - 1] + 1 &&
+             contains(L.items + L.ioff[e], L.icnt[e], it))
+        e = L.bandslice[band_of(L, e) + 1];
+      it.pos0 = p0;
+      it.pos1 = L.pos[e - 1] + 1;
+      L.heads[off + nh + __popcll(m & lanemask_lt())] = it;
+      vol += (int64_t)(it.pos1 - it.pos0) * (it.a1 - it.a0) * max(1, it.b1 - it.b0);
+    }
+    nh += __popcll(m);
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) vol += __shfl_xor(vol, d);
+  if (lane == 0) {
+    L.hoff[b] = off;
+    L.hcnt[b] = nh;
+    L.hvol[b] = vol;
   }
 }
 
@@ -326,8 +411,7 @@ __device__ inline void dev_compact(const PlanDev &P, const Level &L, const Work 
         by[k] = 0;
         if (b < b1) {
           cn[k] = L.hcnt[b];
-          if (mode != 1)
-            for (int h = 0; h < cn[k]; ++h) by[k] += head_volume(L.heads[L.hoff[b] + h], mode) * ca.esize;
+          if (mode != 1) by[k] = L.hvol[b] * ca.esize;
         }
         sn += cn[k];
         sbyt += by[k];
@@ -458,6 +542,23 @@ __device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ 
   const int aidx = P.gr_aidx[t];
   ArrDev &a = A[P.carr[aidx].arr];
   const int64_t grow = P.gr_row[t];
+  if (P.gr_full[t]) {
+    // the definitions tile the row (touching spans of one device already
+    // merged by the planner): they are the new list
+    const Seg *ds = P.dseg + P.gr_dseg0[t];
+    const int nds = P.gr_ndseg[t];
+    if (nds > a.cap) {
+      if (lane == 0) set_err(W.err, -8);
+      return true;
+    }
+    Ivl *row = a.ivl + grow * (int64_t)a.cap;
+    for (int e = lane; e < nds; e += 64) {
+      const Seg d = ds[e];
+      row[e] = Ivl{d.c0, d.dst, (1ull << d.dst) | ((d.flags & 1) ? (1ull << kHost) : 0ull)};
+    }
+    if (lane == 0) a.cnt[grow] = nds;
+    return true;
+  }
   const int n = a.cnt[grow];
   const int W2 = (int)a.n[2];
   Ivl *row = a.ivl + grow * (int64_t)a.cap;

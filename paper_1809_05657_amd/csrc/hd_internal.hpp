@@ -50,6 +50,20 @@ struct Item {
   int32_t src, dst, a0, a1, b0, b1, pos0, pos1;
 };
 
+// A run found in a use row before sorting: source, destination, columns.
+struct Run {
+  int32_t src, dst, a0, a1;
+};
+
+// One level-1 slice (a use row) as dev_runs reads it: a single record.
+struct SliceRec {
+  int32_t arr;   // runtime array id
+  int32_t seg0;  // first use segment of the row
+  int32_t nseg;
+  int32_t pad;
+  int64_t grow;  // global row (plane * n1 + row)
+};
+
 struct MsgRec {
   int32_t aidx, arr, src, dst;
   int32_t lo[3], hi[3];
@@ -88,6 +102,7 @@ struct Level {
   int32_t *nb;         // [1]
   int32_t *hoff;       // [nsl]
   int32_t *hcnt;       // [nsl]
+  int64_t *hvol;       // [nsl] elements of the band's heads
   Item *heads;         // pool
   int32_t *head_top;   // [1]
   int64_t head_cap;
@@ -116,6 +131,7 @@ struct PlanDev {
   const int32_t *seg0;
   const int32_t *nseg;
   const Seg *useg;
+  const SliceRec *srec;  // [nsl1]
   int32_t ngrp;
   const int32_t *grp_aidx;   // [ngrp]
   const int32_t *grp_plane;  // [ngrp]
@@ -129,6 +145,7 @@ struct PlanDev {
   const int32_t *gr_slice;  // level-1 slice of this row or -1
   const int32_t *gr_dseg0;
   const int32_t *gr_ndseg;
+  const int32_t *gr_full;  // 1: the definitions cover the whole row and there are no holder additions
   const Seg *dseg;
 };
 
@@ -138,7 +155,7 @@ struct Work {
   Item *runs;      // [nsl1 * kRunSlot] row slots, then the spill pool
   int32_t *run_top;  // spill pool top (relative to the pool start)
   int64_t run_cap;
-  int32_t *ovf_cnt;   // GDEF rows left to the large-row path
+  int32_t *ovf_cnt;   // GDEF rows left to the large-row path ([1]: workgroups done)
   int32_t *ovf_list;
   int32_t *goff;   // [ngrp] level-1 output offset per group
   int32_t *gcnt;   // [ngrp]

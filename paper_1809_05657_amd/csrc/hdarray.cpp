@@ -4,7 +4,8 @@
 // cache, and the enqueue of one ApplyKernel on two HIP streams:
 //   meta stream: communication-set derivation (Eq. 1-2) and GDEF update
 //                (Eq. 3-4) — metadata only, overlapping the previous kernel;
-//   data stream: pack, unpack (the wire is the staging buffer on one GPU),
+//   data stream: pack + unpack in one pass (the wire is the staging buffer
+//                on one GPU),
 //                the user kernel over all logical devices in one launch.
 #include <hip/hip_runtime.h>
 
@@ -22,11 +23,13 @@
 #include "hd_internal.hpp"
 
 namespace hd {
-hipError_t launch_runs(const PlanDev &P, const ArrDev *A, const Work &W, hipStream_t s);
-hipError_t launch_level(const Level &L, int32_t *err, hipStream_t s);
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr, int64_t cap,
                           int mode, hipStream_t s);
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
+hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, uint8_t *flag,
+                         int32_t *done, MsgRec *out, MsgHdr *hdr, int64_t cap, int mode, hipStream_t s);
+hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, int32_t *done, MsgRec *out, MsgHdr *hdr,
+                         int64_t cap, hipStream_t s);
 hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
                        int unpack, hipStream_t s);
 int64_t tiles_for(int kind, const WorkBox &B, int esize, int th);
@@ -111,7 +114,7 @@ struct Runtime {
   void *uctx = nullptr;
   int row_cap = 64;
   bool serial = false;  // metadata work on the data stream (measurement aid)
-  int jacobi_rows = 16;
+  int jacobi_rows = 8;
   std::vector<hd_array *> arrays;
   std::vector<Partition> parts;
   std::vector<Kernel> kernels;
@@ -125,6 +128,8 @@ struct Runtime {
   int64_t ws_nsl = 0, ws_ngrp = 0, ws_items = 0;
   uint64_t *bmask = nullptr;
   int32_t *bcnt = nullptr, *bbase = nullptr, *bandslice = nullptr, *hoff = nullptr, *hcnt = nullptr;
+  int64_t *hvol = nullptr;
+  uint8_t *bflag = nullptr;  // band-start flag per slice
   Item *heads = nullptr;
   int32_t *counters = nullptr;  // [0] run_top [1] head_top [2] nb [3] err
   MsgRec *tab[2] = {nullptr, nullptr};
@@ -248,7 +253,7 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   if (const char *e = getenv("HD_SERIAL")) R.serial = atoi(e) != 0;
   if (const char *e = getenv("HD_JACOBI_ROWS")) {
     const int v = atoi(e);
-    if (v == 8 || v == 16 || v == 32 || v == 64) R.jacobi_rows = v;
+    if (v == 4 || v == 8 || v == 16) R.jacobi_rows = v;
   }
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
@@ -269,7 +274,8 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   HIPCK(hipMemset(R.counters, 0, 64));
   R.W.run_top = R.counters + 0;
   R.W.err = R.counters + 3;
-  R.W.ovf_cnt = R.counters + 4;
+  R.W.ovf_cnt = R.counters + 4;  // [4] rows listed, [5] workgroups done
+  // [6], [7]: workgroups done in the level-1 runs and heads kernels
   HIPCK(hipHostMalloc((void **)&R.red_res_host, 64, hipHostMallocDefault));
   R.red_res_dev = dalloc(64);
   R.red_pf = (double *)dalloc(sizeof(double) * kMaxDev * 64 * 4);
@@ -755,6 +761,10 @@ static void free_ws() {
   dfree(R.bandslice);
   dfree(R.hoff);
   dfree(R.hcnt);
+  dfree(R.hvol);
+  R.hvol = nullptr;
+  dfree(R.bflag);
+  R.bflag = nullptr;
   dfree(R.heads);
   dfree(R.W.ovf_list);
   R.W.ovf_list = nullptr;
@@ -805,6 +815,8 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
     R.bandslice = (int32_t *)dalloc(4 * (ns + 1));
     R.hoff = (int32_t *)dalloc(4 * ns);
     R.hcnt = (int32_t *)dalloc(4 * ns);
+    R.hvol = (int64_t *)dalloc(8 * ns);
+    R.bflag = (uint8_t *)dalloc(ns);
     R.heads = (Item *)dalloc(sizeof(Item) * it);
     R.W.ovf_list = (int32_t *)dalloc(4 * ns);
     for (int k = 0; k < 2; ++k) {
@@ -813,7 +825,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
       if (R.hdr[k]) HIPCK(hipMemset(R.hdr[k], 0, sizeof(MsgHdr)));
     }
     if (!R.W.roff || !R.W.rcnt || !R.W.runs || !R.W.goff || !R.W.gcnt || !R.W.l1out || !R.bmask || !R.bcnt ||
-        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
+        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hvol || !R.bflag || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
         !R.hdr[1])
       return fail(HD_ENOMEM);
     HIPCK(hipMemset(R.W.roff, 0, 4 * ns));
@@ -843,7 +855,8 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   std::vector<int32_t> grp1, pos1, seg0, nseg, grp_aidx, grp_plane, grp2, pos2;
   std::vector<int64_t> grow1;
   std::vector<Seg> useg, dseg;
-  std::vector<int32_t> gr_aidx, gr_slice, gr_dseg0, gr_ndseg;
+  std::vector<SliceRec> srec;
+  std::vector<int32_t> gr_aidx, gr_slice, gr_dseg0, gr_ndseg, gr_full;
   std::vector<int64_t> gr_row;
   PlanDev &P = pl->P;
   memset(&P, 0, sizeof(P));
@@ -910,6 +923,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
         ++cnt;
       }
       nseg.push_back(cnt);
+      srec.push_back(SliceRec{(int32_t)a->id, seg0.back(), cnt, 0, row});
       slice_of_row.push_back({row, s});
     }
     C.slice1 = (int32_t)grow1.size();
@@ -933,6 +947,20 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
         ++cnt;
       }
       gr_ndseg.push_back(cnt);
+      // definitions sorted by column that tile [0, n2), no holder additions
+      bool full = cnt > 0 && gr_slice.back() < 0;
+      if (full) {
+        std::vector<Seg> v(dseg.end() - cnt, dseg.end());
+        std::sort(v.begin(), v.end(), [](const Seg &x, const Seg &y) { return x.c0 < y.c0; });
+        int64_t at = 0;
+        for (const Seg &g : v) {
+          if (g.c0 != at) full = false;
+          at = g.c1;
+        }
+        if (at != a->n[2]) full = false;
+        if (full) std::copy(v.begin(), v.end(), dseg.end() - cnt);
+      }
+      gr_full.push_back(full ? 1 : 0);
     }
   }
   P.has3d = has3d;
@@ -949,10 +977,12 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   size_t o_carr = push_blob(blob, carr);
   size_t o_grp1 = push_blob(blob, grp1), o_pos1 = push_blob(blob, pos1), o_grow1 = push_blob(blob, grow1);
   size_t o_seg0 = push_blob(blob, seg0), o_nseg = push_blob(blob, nseg), o_useg = push_blob(blob, useg);
+  size_t o_srec = push_blob(blob, srec);
   size_t o_ga = push_blob(blob, grp_aidx), o_gp = push_blob(blob, grp_plane);
   size_t o_g2 = push_blob(blob, grp2), o_p2 = push_blob(blob, pos2);
   size_t o_gra = push_blob(blob, gr_aidx), o_grr = push_blob(blob, gr_row), o_grs = push_blob(blob, gr_slice);
   size_t o_grd0 = push_blob(blob, gr_dseg0), o_grnd = push_blob(blob, gr_ndseg), o_ds = push_blob(blob, dseg);
+  size_t o_grf = push_blob(blob, gr_full);
   size_t o_wb = (blob.size() + 255) / 256 * 256;
   blob.resize(o_wb + sizeof(WorkBox) * kMaxDev + 16);
   pl->mem = dalloc(blob.size());
@@ -965,6 +995,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   P.seg0 = (const int32_t *)(b + o_seg0);
   P.nseg = (const int32_t *)(b + o_nseg);
   P.useg = (const Seg *)(b + o_useg);
+  P.srec = (const SliceRec *)(b + o_srec);
   P.grp_aidx = (const int32_t *)(b + o_ga);
   P.grp_plane = (const int32_t *)(b + o_gp);
   P.grp2 = (const int32_t *)(b + o_g2);
@@ -975,6 +1006,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   P.gr_dseg0 = (const int32_t *)(b + o_grd0);
   P.gr_ndseg = (const int32_t *)(b + o_grnd);
   P.dseg = (const Seg *)(b + o_ds);
+  P.gr_full = (const int32_t *)(b + o_grf);
   pl->wb = (WorkBox *)(b + o_wb);
   // work boxes are filled by the caller into the host blob first
   pl->nbox = 0;
@@ -1008,6 +1040,7 @@ static Level make_level(int which, const PlanDev &P) {
   L.nb = R.counters + 2;
   L.hoff = R.hoff;
   L.hcnt = R.hcnt;
+  L.hvol = R.hvol;
   L.heads = R.heads;
   L.head_top = R.counters + 1;
   L.head_cap = R.ws_items;
@@ -1079,17 +1112,12 @@ static int enqueue(Plan *pl, const float *coef) {
   // adjoint: the cotangent array is defined by the owners of the work boxes
   // first, so its use-region messages are exactly {(owner(x) -> d, x)}
   if (pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
-  HIPCK(launch_runs(P, R.d_arrs, W, meta));
   Level L1 = make_level(1, P);
-  if (!pl->has3d) {
-    HIPCK(launch_level(L1, W.err, meta));
-    HIPCK(launch_compact(P, L1, W, R.tab[slot], R.hdr[slot], R.ws_items, 0, meta));
-  } else {
-    HIPCK(launch_level(L1, W.err, meta));
-    HIPCK(launch_compact(P, L1, W, R.tab[slot], R.hdr[slot], R.ws_items, 1, meta));
+  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.bflag, R.counters + 6, R.tab[slot], R.hdr[slot], R.ws_items,
+                      pl->has3d ? 1 : 0, meta));
+  if (pl->has3d) {
     Level L2 = make_level(2, P);
-    HIPCK(launch_level(L2, W.err, meta));
-    HIPCK(launch_compact(P, L2, W, R.tab[slot], R.hdr[slot], R.ws_items, 2, meta));
+    HIPCK(launch_level2(P, W, L2, R.counters + 7, R.tab[slot], R.hdr[slot], R.ws_items, meta));
   }
   HIPCK(hipEventRecord(R.ev_cs[slot], meta));
   if (!pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
@@ -1110,12 +1138,10 @@ static int enqueue(Plan *pl, const float *coef) {
     return HD_OK;
   }
   {
+    // pack and unpack in one pass over the staging words (the phase-1 timer
+    // covers both; phase 2 stays empty on this path)
     PhaseTimer tm(1, R.data);
-    HIPCK(launch_pack(R.tab[slot], R.hdr[slot], R.d_arrs, (uint32_t *)R.staging, bw, 0, R.data));
-  }
-  {
-    PhaseTimer tm(2, R.data);
-    HIPCK(launch_pack(R.tab[slot], R.hdr[slot], R.d_arrs, (uint32_t *)R.staging, bw, 1, R.data));
+    HIPCK(launch_pack(R.tab[slot], R.hdr[slot], R.d_arrs, (uint32_t *)R.staging, bw, 2, R.data));
   }
   HIPCK(hipEventRecord(R.ev_free[slot], R.data));
   R.free_pending[slot] = true;
@@ -1808,12 +1834,12 @@ extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
   if (!R.inited || !ids || n <= 0 || reps <= 0) return fail(HD_EINVAL);
   for (int i = 0; i < n; ++i)
     if (ids[i] < 0 || ids[i] >= (int)R.batches.size()) return fail(HD_EINVAL);
-  const int ths[3] = {8, 16, 32}, pws[2] = {1, 4};
+  const int ths[3] = {4, 8, 16}, pws[2] = {1, 4};
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
   float best = 1e30f;
-  int bth = 16, bpw = 1;
+  int bth = 8, bpw = 1;
   for (int th : ths)
     for (int pw : pws) {
       for (int i = 0; i < n; ++i)

@@ -31,12 +31,12 @@ def jacobi_rows(api, A0, B0, ndev=4):
     return A, B, p
 
 
-def jacobi_blocks(api, A0, B0, ndev=16, use_box=False):
-    """Jacobi with a BLOCK partition and 5-point offsets (jacobi_large
-    workload), or a full-box absolute use."""
+def jacobi_blocks(api, A0, B0, ndev=16, use_box=False, kind=BLOCK):
+    """Jacobi with a BLOCK partition (or another kind) and 5-point offsets
+    (jacobi_large workload), or a full-box absolute use."""
     n0, n1 = A0.shape
     A, B = api.create(A0), api.create(B0)
-    p = api.partition(BLOCK, (n0, n1), ndev=ndev)
+    p = api.partition(kind, (n0, n1), ndev=ndev)
     for k, out, inp in (("jacAB", A, B), ("jacBA", B, A)):
         api.kernel(k, K_JACOBI2D)
         if use_box:

@@ -223,6 +223,28 @@ def test_random_programs_parity(hd, seed):
         same_call(rt, orc, [(res[0][i], res[1][i])], f"read {i}")
 
 
+def test_wide_rows_parity(hd):
+    """60 column partitions of a 6 x 900 array: every row has about 118 runs
+    (more than a row's run slot, so the spill pool is used) and about 180
+    GDEF intervals (more boundaries than the register-only update handles,
+    so the LDS path runs), and the definitions tile whole rows."""
+    say("case wide rows 6x900 COL ndev=60 row_cap=256 steps=4")
+    rng = np.random.default_rng(77)
+    A0 = rng.random((6, 900), dtype=np.float32)
+    B0 = rng.random((6, 900), dtype=np.float32)
+    rt, orc = hd.Runtime(row_cap=256), O.Oracle()
+    g = prog.jacobi_blocks(rt, A0, B0, ndev=60, kind=prog.COL)
+    o = prog.jacobi_blocks(orc, A0, B0, ndev=60, kind=prog.COL)
+    for it in range(4):
+        k, gi, oi = ("jacAB", (0, 1), (0, 1)) if it % 2 == 0 else ("jacBA", (1, 0), (1, 0))
+        rt.apply(k, g[2], [g[gi[0]], g[gi[1]]])
+        orc.apply(k, o[2], [o[oi[0]], o[oi[1]]])
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"step {it}")
+        assert len(rt.messages()) == 118
+    for i in range(2):
+        assert np.array_equal(rt.read(g[i], g[2]), orc.read(o[i], o[2]))
+
+
 def test_read_write_reduce_parity(hd):
     say("case read/write/reduce")
     n = 40
