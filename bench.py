@@ -35,14 +35,15 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(name, bytes_alg):
+def committed_traffic(name, kernel):
     """HBM traffic per launch from committed rocprofv3 PMC summaries, or None
-    when absent or taken on another version of the kernel source."""
+    when absent, taken on another version of the kernel source, or on
+    another tile shape of the kernel."""
     p = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_source_hash") != kernel_hash():
+    if d.get("kernel_source_hash") != kernel_hash() or d.get("kernel") != kernel:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -192,6 +193,7 @@ def bench_batched(hd, rt, steps, warmup):
     t_batch = (time.perf_counter() - t0) / steps
     kms, kc = rt.profile_read()["kernel"]
     rt.profile(0)
+    phases = rt.batch_phase_us(ids[(steps - 1) % 2])
     ach = bytes_step / (kms / kc * 1e-3) / 1e9
     return {"metric": METRIC, "value": 1.0 / t_batch, "unit": "steps/s", "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -199,7 +201,9 @@ def bench_batched(hd, rt, steps, warmup):
             "config": {"workload": "batched: 64 arrays, sides log-uniform [512,4096], 2-32 irregular row "
                                    "partitions, 5-point or lower-triangular stencil, ping-pong",
                        "cells": cells, "plain_steps_per_s": 1.0 / t_plain, "batched_over_plain": t_plain / t_batch,
-                       "autotuned_rows": cfg >> 8, "autotuned_pack_words": cfg & 255},
+                       "autotuned_rows": cfg >> 8, "autotuned_pack_words": cfg & 255,
+                       "batch_phases_us": dict(zip(("runs", "band_flags", "band_scan", "heads", "compact",
+                                                    "pack_unpack_gdef", "kernels"), phases))},
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch",
                          "bytes_per_launch": bytes_step, "avg_launch_us": kms / kc * 1e3}}
@@ -274,7 +278,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -339,7 +343,8 @@ def main():
     # those of both: read + write for the pack and again for the unpack
     pk_ms = ph["pack"][0] / max(ph["pack"][1], 1)
     moved = st["last_bytes"]
-    th = int(os.environ.get("HD_JACOBI_ROWS", "0")) or hd.DEFAULT_JACOBI_ROWS
+    kname = "k_jacobi1" if st["stencil_waves"] == 1 else "k_jacobi"
+    kname += f"<{st['stencil_rows']},false>"
     out = {
         "metric": METRIC,
         "value": args.steps / dt,
@@ -358,8 +363,8 @@ def main():
                    "n": n, "partitions": 16, "messages_per_step": st["last_messages"],
                    "halo_bytes_per_step": moved},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic("jacobi2d_8192", bytes_kernel),
-                     "kernel": f"k_jacobi<{th},false>", "bytes_per_launch": bytes_kernel,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic("jacobi2d_8192", kname),
+                     "kernel": kname, "bytes_per_launch": bytes_kernel,
                      "avg_launch_us": avg_kernel_ms * 1e3},
         "step_hbm_frac": bytes_kernel / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "phases_us": {k: (v[0] / max(v[1], 1)) * 1e3 for k, v in ph.items()},

@@ -188,7 +188,8 @@ int hdarray_reduce(hd_array_t *a, void *res, hd_reduce_t op, int part);
 /* Batched step.  Between hdarray_batch_begin() and hdarray_batch_end(),
  * hdarray_apply_kernel() validates and records its call instead of running
  * it.  The recorded calls must touch pairwise distinct arrays and use the
- * built-ins jacobi2d, tri2d or copy.  hdarray_batch_end() returns a batch id;
+ * built-ins jacobi2d, tri2d or copy, with at most 1024 array arguments in
+ * total (HD_EINVAL otherwise).  hdarray_batch_end() returns a batch id;
  * hdarray_batch_run(id) enqueues one execution of every recorded call —
  * communication sets, packs, unpacks, kernels and GDEF updates — as one
  * persistent kernel (phases separated by grid-wide barriers with a bounded
@@ -206,6 +207,14 @@ int hdarray_batch_run(int batch);
  * tile shape does not change any result.  Returns the chosen
  * (rows << 8 | words) or a negative error. */
 int hdarray_batch_autotune(const int *batches, int n, int reps);
+/* Device time of each phase of the last run of a batch, in microseconds, from
+ * clock stamps taken by workgroup 0 at the phase boundaries (a measurement
+ * aid; synchronises).  Phases for 2-D batches: runs, band flags, band scan,
+ * heads, compaction, pack + unpack + GDEF update, user kernels (7); 3-D
+ * batches add band flags, band scan, heads and compaction of the second
+ * stacking level after the first compaction (11).  Writes at most max values
+ * to us and returns their number, or a negative error. */
+int hdarray_batch_phase_us(int batch, double *us, int max);
 
 /* Adjoint of one ApplyKernel of a "stencil3d7" kernel kname on partition
  * part (reverse mode, for differentiation through time steps):
@@ -260,6 +269,8 @@ typedef struct {
   int64_t total_messages;
   int64_t total_bytes;
   int64_t plans_built;     /* distinct (kernel, partition, arrays) plans */
+  int64_t stencil_rows;    /* tile shape of the last Jacobi / triangular launch: */
+  int64_t stencil_waves;   /* rows per tile, waves per workgroup */
 } hd_stats_t;
 int hdarray_get_stats(hd_stats_t *st);
 

@@ -26,7 +26,6 @@ SUM, PROD, MAX, MIN = 0, 1, 2, 3
 K_JACOBI2D, K_COPY, K_MATMUL, K_TRI2D, K_STENCIL3D7 = 1, 2, 3, 4, 5
 BUILTIN_NAMES = {K_JACOBI2D: "jacobi2d", K_COPY: "copy", K_MATMUL: "matmul", K_TRI2D: "tri2d",
                  K_STENCIL3D7: "stencil3d7"}
-DEFAULT_JACOBI_ROWS = 8  # rows per stencil tile when HD_JACOBI_ROWS is unset (runtime default)
 EINVAL, EBOUNDS, ERACE, EKERNEL, ENOMEM, EHIP, ESTATE, ECAPACITY = -1, -2, -3, -4, -5, -6, -7, -8
 MSG_FIELDS = ("arg", "array", "src", "dst", "lo0", "lo1", "lo2", "hi0", "hi1", "hi2", "off", "bytes")
 _TYPE_NAME = {F32: b"float", I32: b"int", F64: b"double"}
@@ -48,7 +47,8 @@ class _Arg(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("calls", C.c_int64), ("last_messages", C.c_int64), ("last_bytes", C.c_int64),
-                ("total_messages", C.c_int64), ("total_bytes", C.c_int64), ("plans_built", C.c_int64)]
+                ("total_messages", C.c_int64), ("total_bytes", C.c_int64), ("plans_built", C.c_int64),
+                ("stencil_rows", C.c_int64), ("stencil_waves", C.c_int64)]
 
 
 class Profile(C.Structure):
@@ -118,6 +118,7 @@ def load():
         "hdarray_batch_end": (C.c_int, []),
         "hdarray_batch_run": (C.c_int, [C.c_int]),
         "hdarray_batch_autotune": (C.c_int, [C.POINTER(C.c_int), C.c_int, C.c_int]),
+        "hdarray_batch_phase_us": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.c_int]),
         "hdarray_profile_read": (C.c_int, [C.POINTER(Profile)]),
     }
     for name, (res, args) in sig.items():
@@ -306,6 +307,11 @@ class Runtime:
 
     def batch_run(self, bid):
         self._ck(self.L.hdarray_batch_run(bid), "batch_run")
+
+    def batch_phase_us(self, batch):
+        buf = (C.c_double * 16)()
+        n = self._ck(self.L.hdarray_batch_phase_us(batch, buf, 16), "batch_phase_us")
+        return [buf[i] for i in range(n)]
 
     def batch_autotune(self, ids, reps=2):
         arr = (C.c_int * len(ids))(*ids)

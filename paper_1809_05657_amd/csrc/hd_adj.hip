@@ -106,13 +106,22 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
   }
 }
 
-// cbar[e] += sum over workgroups (in order) of the partials
-__global__ void k_cbar_final(const double *part, int64_t nblk, double *cbar) {
-  const int e = threadIdx.x;
-  if (e >= 7) return;
-  double s = 0.0;
-  for (int64_t b = 0; b < nblk; ++b) s += part[b * 8 + e];
-  cbar[e] += s;
+// cbar[e] += sum of the workgroup partials, one workgroup per coefficient:
+// thread t sums partials t, t + 256, ... in increasing order, then a
+// pairwise tree over the threads; the order depends only on the count, so
+// the result is reproducible.
+__global__ __launch_bounds__(256) void k_cbar_final(const double *part, int64_t nblk, double *cbar) {
+  __shared__ double s[256];
+  const int e = blockIdx.x, t = threadIdx.x;
+  double v = 0.0;
+  for (int64_t b = t; b < nblk; b += 256) v += part[b * 8 + e];
+  s[t] = v;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (t < h) s[t] = s[t] + s[t + h];
+    __syncthreads();
+  }
+  if (t == 0) cbar[e] += s[0];
 }
 
 // reverse pack: the partial sums at the halo cells of the device that holds
@@ -193,7 +202,7 @@ hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const flo
   a.part = part;
   if (ntiles > 0) {
     hipLaunchKernelGGL(k_s3d_adj, dim3(ntiles), dim3(256), 0, s, a, A);
-    if (cbar) hipLaunchKernelGGL(k_cbar_final, dim3(1), dim3(64), 0, s, part, ntiles, cbar);
+    if (cbar) hipLaunchKernelGGL(k_cbar_final, dim3(7), dim3(256), 0, s, part, ntiles, cbar);
   }
   int grid = (int)((bound_words + 255) / 256);
   if (grid > 4096) grid = 4096;

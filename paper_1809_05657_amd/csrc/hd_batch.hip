@@ -72,35 +72,50 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   unsigned target = 0;
   WaveLds &my = s_lds[wv];
   int32_t *err = B.W.err;
+  int ph = 0;
+  auto stamp = [&]() {
+    if (blockIdx.x == 0 && threadIdx.x == 0) B.clk[ph] = wall_clock64();
+    ++ph;
+  };
+  stamp();
   // runs of every use row
   for (int s = gw; s < B.P.nsl1; s += nw) dev_runs(B.P, B.A, B.W, s, my.r.iv, my.r.rr);
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+  stamp();
   for (int c = gw; c * 64 < B.L1.nsl; c += nw) dev_bandflags(B.L1, c * 64 + lane);
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+  stamp();
   if (blockIdx.x == 0 && B.L1.nsl) dev_bandscan(B.L1);
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+  stamp();
   {
     const int nb = B.L1.nsl ? *B.L1.nb : 0;
     for (int b = gw; b < nb; b += nw) dev_heads(B.L1, b);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+  stamp();
   if (!B.P.has3d) {
     if (blockIdx.x == 0) dev_compact(B.P, B.L1, B.W, B.tab, B.hdr, B.tab_cap, 0);
   } else {
     if (blockIdx.x == 0) dev_compact(B.P, B.L1, B.W, B.tab, B.hdr, B.tab_cap, 1);
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+    stamp();
     for (int c = gw; c * 64 < B.L2.nsl; c += nw) dev_bandflags(B.L2, c * 64 + lane);
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+    stamp();
     if (blockIdx.x == 0 && B.L2.nsl) dev_bandscan(B.L2);
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+    stamp();
     {
       const int nb = B.L2.nsl ? *B.L2.nb : 0;
       for (int b = gw; b < nb; b += nw) dev_heads(B.L2, b);
     }
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+    stamp();
     if (blockIdx.x == 0) dev_compact(B.P, B.L2, B.W, B.tab, B.hdr, B.tab_cap, 2);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+  stamp();
   // pack + unpack in one pass, and the GDEF update (metadata only,
   // independent of the data)
   const int64_t nmsg = B.hdr->nmsg, words = B.hdr->bytes >> 2;
@@ -117,6 +132,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
       if (!dev_gdef_row_fast(B.P, B.A, B.W, t)) dev_gdef_row(B.P, B.A, B.W, t, S, kBatchMaxB);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+  stamp();
   // user kernels: one wave per tile
   for (int64_t t = gw; t < B.ntiles; t += nw) {
     const WorkBox bx = B.wb[find_box(B.wb, B.nbox, t)];
@@ -127,6 +143,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     else if (bx.kind == 2)
       dev_copy_tile(bx, t - bx.tile0, B.A);
   }
+  stamp();
 }
 
 __global__ void k_zero_bar(unsigned *bar) {

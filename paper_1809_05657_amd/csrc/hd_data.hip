@@ -47,7 +47,16 @@ __global__ __launch_bounds__(256) void k_jacobi(const WorkBox *__restrict__ wb, 
   const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
   const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_jacobi_tile<TH, TRI>(B, t - B.tile0, A);
+  dev_jacobi_tile<TH, TRI, true>(B, t - B.tile0, A);
+}
+
+// One wave per workgroup; the tiles of an XCD walk down columns of tiles.
+template <int TH, bool TRI>
+__global__ __launch_bounds__(64) void k_jacobi1(const WorkBox *__restrict__ wb, int nbox,
+                                                const ArrDev *__restrict__ A, int64_t ntiles) {
+  const int64_t t = xcd_remap(blockIdx.x, ntiles);
+  const WorkBox B = wb[find_box(wb, nbox, t)];
+  dev_jacobi_tile<TH, TRI, false>(B, t - B.tile0, A);
 }
 
 __global__ __launch_bounds__(64) void k_copy(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
@@ -175,7 +184,7 @@ int64_t tiles_for(int kind, const WorkBox &B, int esize, int th) {
   return 0;
 }
 
-hipError_t launch_user(int kind, int th, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
+hipError_t launch_user(int kind, int th, int waves, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
                        const float *coef, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   switch (kind) {
@@ -183,10 +192,17 @@ hipError_t launch_user(int kind, int th, const WorkBox *wb, int nbox, const ArrD
     case 5: {
       typedef void (*jk_t)(const WorkBox *, int, const ArrDev *, int64_t);
       const bool tri = kind == 5;
-      jk_t k = tri ? k_jacobi<8, true> : k_jacobi<8, false>;
-      if (th == 4) k = tri ? k_jacobi<4, true> : k_jacobi<4, false>;
-      if (th == 16) k = tri ? k_jacobi<16, true> : k_jacobi<16, false>;
-      hipLaunchKernelGGL(k, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles);
+      if (waves == 4) {
+        jk_t k = tri ? k_jacobi<8, true> : k_jacobi<8, false>;
+        if (th == 4) k = tri ? k_jacobi<4, true> : k_jacobi<4, false>;
+        if (th == 16) k = tri ? k_jacobi<16, true> : k_jacobi<16, false>;
+        hipLaunchKernelGGL(k, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles);
+      } else {
+        jk_t k = tri ? k_jacobi1<8, true> : k_jacobi1<8, false>;
+        if (th == 4) k = tri ? k_jacobi1<4, true> : k_jacobi1<4, false>;
+        if (th == 16) k = tri ? k_jacobi1<16, true> : k_jacobi1<16, false>;
+        hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
+      }
     } break;
     case 2:
       hipLaunchKernelGGL(k_copy, dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);

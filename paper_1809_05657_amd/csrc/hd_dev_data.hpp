@@ -143,14 +143,23 @@ __device__ inline void dev_pack(const MsgRec *__restrict__ M, const MsgHdr *__re
 // ------------------------------------------------------------ jacobi / tri
 // One wave computes a tile of TH rows x 256 columns of one box; each lane
 // owns 4 consecutive columns, the left / right neighbours come from the
-// adjacent lanes (lanes 0 and 63 load the tile's edge columns).  Tiles are
-// numbered along a row of tiles first, so consecutive waves cover
-// consecutive 1 KiB pieces of the same rows.
-template <int TH, bool TRI>
+// adjacent lanes (lanes 0 and 63 load the tile's edge columns).  HF: tiles
+// are numbered along a row of tiles first (consecutive waves cover
+// consecutive 1 KiB pieces of the same rows); otherwise down a column of
+// tiles first (consecutive waves share halo rows).
+template <int TH, bool TRI, bool HF = true>
 __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
   const int lane = threadIdx.x & 63;
-  const int ntx = (B.hi[2] - B.lo[2] + 255) / 256;
-  const int tx = (int)(lt % ntx), ty = (int)(lt / ntx);
+  int tx, ty;
+  if (HF) {
+    const int ntx = (B.hi[2] - B.lo[2] + 255) / 256;
+    tx = (int)(lt % ntx);
+    ty = (int)(lt / ntx);
+  } else {
+    const int nty = (B.hi[1] - B.lo[1] + TH - 1) / TH;
+    ty = (int)(lt % nty);
+    tx = (int)(lt / nty);
+  }
   const int r0 = B.lo[1] + ty * TH;
   const int r1 = min(r0 + TH, B.hi[1]);
   const int c = B.lo[2] + tx * 256 + 4 * lane;

@@ -36,8 +36,12 @@ __device__ inline uint64_t lanemask_lt() {
   return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
+// Orders the LDS accesses of the lanes of one wave: the LDS executes a
+// wave's operations in issue order, so a wavefront-scope fence (which keeps
+// the compiler from moving LDS accesses across it) is enough; a wider scope
+// would also wait for every outstanding global memory operation.
 __device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -65,11 +69,14 @@ __device__ inline bool contains(const Item *it, int cnt, const Item &q) {
 }
 
 // ------------------------------------------------------------------- runs
-// One wave (all 64 lanes) finds the runs of use row s and leaves them in
-// srt sorted by (col, dst).  iv (kMaxCap intervals) and rr (kMaxRunsRow
-// runs) are LDS scratch private to the wave; srt aliases iv.  Returns the
-// run count (0 after a capacity error, which is recorded).
-static_assert(sizeof(Ivl) == sizeof(Run) && kMaxCap == kMaxRunsRow, "sorted runs reuse the interval scratch");
+// One wave (all 64 lanes) finds the runs of use row s and leaves them in rr
+// in discovery order: by use segment (destination, then column; the
+// planner merges each destination's segments of a row, so they are
+// disjoint and sorted), then by column.  That order is a function of the
+// run set alone, so two rows have the same runs iff their rr lists are
+// equal.  iv (at least the row capacity) and rr (kMaxRunsRow runs) are LDS
+// scratch private to the wave.  Returns the run count (0 after a capacity
+// error, which is recorded).
 
 __device__ inline int dev_runs_find(const PlanDev &P, const ArrDev *__restrict__ A, const Work &W, int s, Ivl *iv,
                                     Run *rr) {
@@ -120,24 +127,13 @@ __device__ inline int dev_runs_find(const PlanDev &P, const ArrDev *__restrict__
     nr = 0;
   }
   wave_lds_sync();
-  // rank sort by (col, dst): keys are unique (runs of one dst are disjoint)
-  Run *srt = reinterpret_cast<Run *>(iv);
-  for (int i = lane; i < nr; i += 64) {
-    const Run x = rr[i];
-    int rank = 0;
-    for (int j = 0; j < nr; ++j) {
-      const Run y = rr[j];
-      rank += (y.a0 < x.a0) || (y.a0 == x.a0 && y.dst < x.dst);
-    }
-    srt[rank] = x;
-  }
-  wave_lds_sync();
   return nr;
 }
 
-// Stores the sorted runs of slice s: the row's own slot, or the spill pool
-// after all slots.
-__device__ inline void dev_runs_store(const PlanDev &P, const Work &W, int s, const Run *srt, int nr) {
+// Stores the runs of slice s sorted by (col, dst) (rank sort; the keys are
+// unique because the runs of one destination are disjoint): the row's own
+// slot, or the spill pool after all slots.
+__device__ inline void dev_runs_store(const PlanDev &P, const Work &W, int s, const Run *rr, int nr) {
   const int lane = threadIdx.x & 63;
   int off = s * kRunSlot;
   if (nr > kRunSlot) {
@@ -155,8 +151,13 @@ __device__ inline void dev_runs_store(const PlanDev &P, const Work &W, int s, co
     if (off < 0) nr = 0;
   }
   for (int i = lane; i < nr; i += 64) {
-    const Run x = srt[i];
-    W.runs[off + i] = Item{x.src, x.dst, x.a0, x.a1, 0, 0, 0, 0};
+    const Run x = rr[i];
+    int rank = 0;
+    for (int j = 0; j < nr; ++j) {
+      const Run y = rr[j];
+      rank += (y.a0 < x.a0) || (y.a0 == x.a0 && y.dst < x.dst);
+    }
+    W.runs[off + rank] = Item{x.src, x.dst, x.a0, x.a1, 0, 0, 0, 0};
   }
   if (lane == 0) {
     W.roff[s] = nr ? off : 0;
@@ -167,13 +168,13 @@ __device__ inline void dev_runs_store(const PlanDev &P, const Work &W, int s, co
 __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, const Work &W, int s, Ivl *iv,
                                 Run *rr) {
   const int nr = dev_runs_find(P, A, W, s, iv, rr);
-  dev_runs_store(P, W, s, reinterpret_cast<const Run *>(iv), nr);
+  dev_runs_store(P, W, s, rr, nr);
   wave_lds_sync();
 }
 
 // Slice s starts a band unless it continues slice s-1 (same group, next
-// position) with an identical sorted run list; cur / prv are the two lists
-// in LDS.  Called by a whole wave.
+// position) with an identical run list; cur / prv are the two lists in LDS
+// (discovery order, see dev_runs_find).  Called by a whole wave.
 __device__ inline bool runs_band_start(const Level &L, int s, const Run *cur, int nc, const Run *prv, int np) {
   if (s == 0 || L.grp[s] != L.grp[s - 1] || L.pos[s] != L.pos[s - 1] + 1 || nc != np) return true;
   const int lane = threadIdx.x & 63;
@@ -185,15 +186,22 @@ __device__ inline bool runs_band_start(const Level &L, int s, const Run *cur, in
   return __ballot(diff) != 0;
 }
 
-// Band masks from one byte flag per slice (one wave per 64 slices).
-__device__ inline void dev_masks_from_flags(const Level &L, const uint8_t *flag, int c) {
-  const int lane = threadIdx.x & 63;
-  const int q = c * 64 + lane;
-  const uint64_t m = __ballot(q < L.nsl && flag[q] != 0);
-  if (lane == 0) {
-    L.bmask[c] = m;
-    L.bcnt[c] = __popcll(m);
+// Band mask of chunk c (slices 64c .. 64c+63) from one byte flag per slice,
+// by one thread (the flag array is padded to whole chunks).
+__device__ inline void dev_mask_from_flags(const Level &L, const uint8_t *flag, int c) {
+  const uint64_t *f8 = reinterpret_cast<const uint64_t *>(flag) + 8 * (int64_t)c;
+  uint64_t m = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint64_t v = f8[k];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+      if ((v >> (8 * b)) & 0xffu) m |= 1ull << (8 * k + b);
   }
+  const int valid = L.nsl - 64 * c;
+  if (valid < 64) m &= (1ull << valid) - 1ull;
+  L.bmask[c] = m;
+  L.bcnt[c] = __popcll(m);
 }
 
 // Last-workgroup election: every workgroup calls this once after its
@@ -364,9 +372,12 @@ __device__ inline void dev_heads(const Level &L, int b) {
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) vol += __shfl_xor(vol, d);
   if (lane == 0) {
+    const int g = L.grp[s0];
+    const int j = L.grp_carr ? L.grp_carr[g] : g;
     L.hoff[b] = off;
     L.hcnt[b] = nh;
-    L.hvol[b] = vol;
+    L.bcarr[b] = j;
+    L.hbytes[b] = vol * L.carr[j].esize;
   }
 }
 
@@ -381,103 +392,129 @@ __device__ inline int64_t head_volume(const Item &h, int mode) {
 
 __device__ inline void dev_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr,
                                    int64_t out_cap, int mode) {
-  __shared__ int64_t s_carry_b;
+  // one workgroup: (A) a flat exclusive scan of head counts and bytes over
+  // all bands; (B) the alignment padding at the first band of every
+  // call-array (pack offsets are aligned to the element size), in call-array
+  // order; (C) every band writes its heads at its offsets
+  __shared__ int64_t s_raw[kCompactCarr];  // byte prefix at the call-array's first band, -1: none
+  __shared__ int64_t s_pad[kCompactCarr];  // padding inserted up to and including that call-array
+  __shared__ int64_t s_carry_b, s_total_b;
   __shared__ int s_carry_n;
   const int nt = blockDim.x;
   const int nb = L.nsl ? *L.nb : 0;
+  const int ncarr = P.ncarr < kCompactCarr ? P.ncarr : kCompactCarr;
+  for (int j = threadIdx.x; j < ncarr; j += nt) s_raw[j] = -1;
   if (threadIdx.x == 0) {
     s_carry_b = 0;
     s_carry_n = 0;
+    if (P.ncarr > kCompactCarr) set_err(W.err, -8);
   }
   __syncthreads();
-  for (int j = 0; j < P.ncarr; ++j) {
-    const CallArr ca = P.carr[j];
-    const int sa = mode == 2 ? ca.grp0 : ca.slice0;
-    const int sb = mode == 2 ? ca.grp1 : ca.slice1;
-    if (sa >= sb) continue;
-    const int b0 = band_of(L, sa);
-    const int b1 = sb < L.nsl ? band_of(L, sb) : nb;
-    if (threadIdx.x == 0 && mode != 1) s_carry_b = (s_carry_b + ca.esize - 1) / ca.esize * ca.esize;
+  for (int base = 0; base < nb; base += nt * kScanIt) {
+    int cn[kScanIt];
+    int64_t by[kScanIt];
+    bool first[kScanIt];
+    int jj[kScanIt];
+    int sn = 0;
+    int64_t sbyt = 0;
+#pragma unroll
+    for (int k = 0; k < kScanIt; ++k) {
+      const int b = base + threadIdx.x * kScanIt + k;
+      cn[k] = 0;
+      by[k] = 0;
+      first[k] = false;
+      jj[k] = 0;
+      if (b < nb) {
+        cn[k] = L.hcnt[b];
+        jj[k] = L.bcarr[b];
+        if (mode != 1) by[k] = L.hbytes[b];
+        first[k] = b == 0 || L.bcarr[b - 1] != jj[k];
+      }
+      sn += cn[k];
+      sbyt += by[k];
+    }
+    const int cn0 = s_carry_n;
+    const int64_t cb0 = s_carry_b;
+    int totn;
+    int64_t totb;
+    int exn = block_exscan<int>(sn, &totn) + cn0;
+    int64_t exb = block_exscan<int64_t>(sbyt, &totb) + cb0;
+#pragma unroll
+    for (int k = 0; k < kScanIt; ++k) {
+      const int b = base + threadIdx.x * kScanIt + k;
+      if (b >= nb) break;
+      L.nofs[b] = exn;
+      L.bofs[b] = exb;
+      if (first[k] && jj[k] < kCompactCarr) s_raw[jj[k]] = exb;
+      exn += cn[k];
+      exb += by[k];
+    }
+    if (threadIdx.x == 0) {
+      s_carry_n += totn;
+      s_carry_b += totb;
+    }
     __syncthreads();
-    for (int base = b0; base < b1; base += nt * kScanIt) {
-      int cn[kScanIt];
-      int64_t by[kScanIt];
-      int sn = 0;
-      int64_t sbyt = 0;
-#pragma unroll
-      for (int k = 0; k < kScanIt; ++k) {
-        const int b = base + threadIdx.x * kScanIt + k;
-        cn[k] = 0;
-        by[k] = 0;
-        if (b < b1) {
-          cn[k] = L.hcnt[b];
-          if (mode != 1) by[k] = L.hvol[b] * ca.esize;
-        }
-        sn += cn[k];
-        sbyt += by[k];
+  }
+  if (threadIdx.x == 0) {
+    int64_t pad = 0;
+    for (int j = 0; j < ncarr; ++j) {
+      if (s_raw[j] >= 0 && mode != 1) {
+        const int64_t at = s_raw[j] + pad, e = P.carr[j].esize;
+        pad += (at + e - 1) / e * e - at;
       }
-      const int cn0 = s_carry_n;
-      const int64_t cb0 = s_carry_b;
-      int totn;
-      int64_t totb;
-      int exn = block_exscan<int>(sn, &totn) + cn0;
-      int64_t exb = block_exscan<int64_t>(sbyt, &totb) + cb0;
-#pragma unroll
-      for (int k = 0; k < kScanIt; ++k) {
-        const int b = base + threadIdx.x * kScanIt + k;
-        if (b >= b1) break;
-        const Item *hs = L.heads + L.hoff[b];
-        const int s0 = L.bandslice[b];
-        if (mode == 1) {
-          const int g = L.grp[s0];
-          const bool gstart = s0 == 0 || L.grp[s0 - 1] != g;
-          if (gstart) W.goff[g] = exn;
-          for (int h = 0; h < cn[k]; ++h) {
-            if (exn + h < W.l1_cap) {
-              const Item it = hs[h];
-              // rows of the stacked run become the item's b-range
-              W.l1out[exn + h] = Item{it.src, it.dst, it.a0, it.a1, it.pos0, it.pos1, 0, 0};
-            }
-          }
+      s_pad[j] = pad;
+    }
+    s_total_b = s_carry_b + pad;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += nt) {
+    const int j = L.bcarr[b];
+    const int cnt = L.hcnt[b];
+    int exn = L.nofs[b];
+    const Item *hs = L.heads + L.hoff[b];
+    const int s0 = L.bandslice[b];
+    if (mode == 1) {
+      const int g = L.grp[s0];
+      const bool gstart = s0 == 0 || L.grp[s0 - 1] != g;
+      if (gstart) W.goff[g] = exn;
+      for (int h = 0; h < cnt; ++h) {
+        if (exn + h < W.l1_cap) {
+          const Item it = hs[h];
+          // rows of the stacked run become the item's b-range
+          W.l1out[exn + h] = Item{it.src, it.dst, it.a0, it.a1, it.pos0, it.pos1, 0, 0};
+        }
+      }
+    } else {
+      const CallArr ca = P.carr[j];
+      int64_t ob = L.bofs[b] + (j < kCompactCarr ? s_pad[j] : 0);
+      const int plane = mode == 0 ? P.grp_plane[L.grp[s0]] : 0;
+      for (int h = 0; h < cnt; ++h) {
+        const Item it = hs[h];
+        MsgRec r;
+        r.aidx = j;
+        r.arr = ca.arr;
+        r.src = it.src;
+        r.dst = it.dst;
+        if (mode == 0) {
+          r.lo[0] = plane;
+          r.hi[0] = plane + 1;
+          r.lo[1] = it.pos0;
+          r.hi[1] = it.pos1;
         } else {
-          int64_t ob = exb;
-          for (int h = 0; h < cn[k]; ++h) {
-            const Item it = hs[h];
-            MsgRec r;
-            r.aidx = j;
-            r.arr = ca.arr;
-            r.src = it.src;
-            r.dst = it.dst;
-            if (mode == 0) {
-              const int plane = P.grp_plane[L.grp[s0]];
-              r.lo[0] = plane;
-              r.hi[0] = plane + 1;
-              r.lo[1] = it.pos0;
-              r.hi[1] = it.pos1;
-            } else {
-              r.lo[0] = it.pos0;
-              r.hi[0] = it.pos1;
-              r.lo[1] = it.b0;
-              r.hi[1] = it.b1;
-            }
-            r.lo[2] = it.a0;
-            r.hi[2] = it.a1;
-            r.argpos = ca.argpos;
-            r.esize = ca.esize;
-            r.off = ob;
-            r.bytes = head_volume(it, mode) * ca.esize;
-            ob += r.bytes;
-            if (exn + h < out_cap) out[exn + h] = r;
-          }
+          r.lo[0] = it.pos0;
+          r.hi[0] = it.pos1;
+          r.lo[1] = it.b0;
+          r.hi[1] = it.b1;
         }
-        exn += cn[k];
-        exb += by[k];
+        r.lo[2] = it.a0;
+        r.hi[2] = it.a1;
+        r.argpos = ca.argpos;
+        r.esize = ca.esize;
+        r.off = ob;
+        r.bytes = head_volume(it, mode) * ca.esize;
+        ob += r.bytes;
+        if (exn + h < out_cap) out[exn + h] = r;
       }
-      if (threadIdx.x == 0) {
-        s_carry_n += totn;
-        s_carry_b += totb;
-      }
-      __syncthreads();
     }
   }
   __syncthreads();
@@ -494,7 +531,7 @@ __device__ inline void dev_compact(const PlanDev &P, const Level &L, const Work 
   } else if (threadIdx.x == 0) {
     if (s_carry_n > out_cap) set_err(W.err, -8);
     hdr->nmsg = s_carry_n < out_cap ? s_carry_n : out_cap;
-    hdr->bytes = s_carry_b;
+    hdr->bytes = s_total_b;
     *L.head_top = 0;  // pools are free for the next call
     *W.run_top = 0;
   }
@@ -539,14 +576,14 @@ __device__ inline void gdef_state(int x, int n, int st, int ow, uint64_t ho, con
 // when the row has more than 64 boundaries; the caller then uses dev_gdef_row.
 __device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t) {
   const int lane = threadIdx.x & 63;
-  const int aidx = P.gr_aidx[t];
-  ArrDev &a = A[P.carr[aidx].arr];
-  const int64_t grow = P.gr_row[t];
-  if (P.gr_full[t]) {
+  const GRowRec gr = P.grec[t];
+  ArrDev &a = A[gr.arr];
+  const int64_t grow = gr.grow;
+  if (gr.full) {
     // the definitions tile the row (touching spans of one device already
     // merged by the planner): they are the new list
-    const Seg *ds = P.dseg + P.gr_dseg0[t];
-    const int nds = P.gr_ndseg[t];
+    const Seg *ds = P.dseg + gr.dseg0;
+    const int nds = gr.ndseg;
     if (nds > a.cap) {
       if (lane == 0) set_err(W.err, -8);
       return true;
@@ -562,11 +599,11 @@ __device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ 
   const int n = a.cnt[grow];
   const int W2 = (int)a.n[2];
   Ivl *row = a.ivl + grow * (int64_t)a.cap;
-  const int sl = P.gr_slice[t];
+  const int sl = gr.slice;
   const Item *runs = sl >= 0 ? W.runs + W.roff[sl] : nullptr;
   const int nrun = sl >= 0 ? W.rcnt[sl] : 0;
-  const Seg *ds = P.dseg + P.gr_dseg0[t];
-  const int nds = P.gr_ndseg[t];
+  const Seg *ds = P.dseg + gr.dseg0;
+  const int nds = gr.ndseg;
   const int nb = n + 2 * (nrun + nds);
   if (nb > 64) return false;
   int st = 0x7fffffff, ow = 0;
@@ -626,17 +663,17 @@ struct GdefLds {
 __device__ inline void dev_gdef_row(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t, GdefLds S,
                                     int maxb) {
   const int lane = threadIdx.x & 63;
-  const int aidx = P.gr_aidx[t];
-  ArrDev &a = A[P.carr[aidx].arr];
-  const int64_t grow = P.gr_row[t];
+  const GRowRec gr = P.grec[t];
+  ArrDev &a = A[gr.arr];
+  const int64_t grow = gr.grow;
   const int n = a.cnt[grow];
   const int W2 = (int)a.n[2];
   Ivl *row = a.ivl + grow * (int64_t)a.cap;
-  const int sl = P.gr_slice[t];
+  const int sl = gr.slice;
   const Item *runs = sl >= 0 ? W.runs + W.roff[sl] : nullptr;
   const int nrun = sl >= 0 ? W.rcnt[sl] : 0;
-  const Seg *ds = P.dseg + P.gr_dseg0[t];
-  const int nds = P.gr_ndseg[t];
+  const Seg *ds = P.dseg + gr.dseg0;
+  const int nds = gr.ndseg;
   const int nbnd = n + 2 * (nrun + nds);
   if (nbnd > maxb) {
     if (lane == 0) set_err(W.err, -8);

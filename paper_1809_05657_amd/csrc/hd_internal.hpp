@@ -19,6 +19,7 @@ constexpr int kMaxRunsRow = 256;    // runs one use row may produce
 constexpr int kMaxCallArrays = 8;   // distinct arrays in one ApplyKernel
 constexpr int kMaxBoundaries = 1024;// elementary boundaries of one GDEF row update
 constexpr int kRunSlot = 16;        // runs stored in a use row's own slot; more spill to a pool
+constexpr int kCompactCarr = 1024;  // call-arrays one compaction handles (plain calls: at most 8)
 
 struct Ivl {
   int32_t start;
@@ -64,6 +65,17 @@ struct SliceRec {
   int64_t grow;  // global row (plane * n1 + row)
 };
 
+// One row of a GDEF update as k_gdef reads it: a single record.
+struct GRowRec {
+  int32_t arr;    // runtime array id
+  int32_t slice;  // level-1 slice whose runs add holders, or -1
+  int32_t dseg0;  // first definition segment of the row
+  int32_t ndseg;
+  int64_t grow;   // global row (plane * n1 + row)
+  int32_t full;   // 1: the definitions tile the row and no holders are added
+  int32_t pad;
+};
+
 struct MsgRec {
   int32_t aidx, arr, src, dst;
   int32_t lo[3], hi[3];
@@ -102,7 +114,12 @@ struct Level {
   int32_t *nb;         // [1]
   int32_t *hoff;       // [nsl]
   int32_t *hcnt;       // [nsl]
-  int64_t *hvol;       // [nsl] elements of the band's heads
+  int64_t *hbytes;     // [nsl] bytes of the band's heads
+  int32_t *bcarr;      // [nsl] call-array of the band
+  int32_t *nofs;       // [nsl] compaction: first message of the band
+  int64_t *bofs;       // [nsl] compaction: byte prefix of the band (before padding)
+  const int32_t *grp_carr;  // group -> call-array (level 1); null when groups are call-arrays (level 2)
+  const CallArr *carr;
   Item *heads;         // pool
   int32_t *head_top;   // [1]
   int64_t head_cap;
@@ -140,12 +157,7 @@ struct PlanDev {
   const int32_t *pos2;  // [ngrp] = plane
   // GDEF update rows
   int32_t ngrow;
-  const int32_t *gr_aidx;
-  const int64_t *gr_row;
-  const int32_t *gr_slice;  // level-1 slice of this row or -1
-  const int32_t *gr_dseg0;
-  const int32_t *gr_ndseg;
-  const int32_t *gr_full;  // 1: the definitions cover the whole row and there are no holder additions
+  const GRowRec *grec;  // [ngrow]
   const Seg *dseg;
 };
 
@@ -179,6 +191,7 @@ struct BatchArgs {
   int64_t ntiles;
   unsigned *bar;
   int64_t spin_limit;  // device-clock ticks
+  int64_t *clk;        // device-clock stamps taken by workgroup 0 at each phase boundary
 };
 
 }  // namespace hd

@@ -11,12 +11,13 @@ constexpr int kGdefMaxB = 1024;
 
 // Runs of 4 consecutive use rows per workgroup plus the row before them
 // (fifth wave, only to compare with): each row's band-start flag comes from
-// comparing sorted run lists in LDS.  The last workgroup to finish turns the
-// flags into band masks and scans them (band -> first slice).
+// comparing sorted run lists in LDS.  (No workgroup here waits for the
+// others: a device-wide fence per workgroup costs more than a launch.)
 constexpr int kRfWaves = 5;
+template <int CAP>
 __global__ __launch_bounds__(64 * kRfWaves) void k_runs_flags(PlanDev P, const ArrDev *__restrict__ A, Work W,
-                                                              Level L, uint8_t *flag, int32_t *done) {
-  __shared__ Ivl s_iv[kRfWaves][kMaxCap];
+                                                              Level L, uint8_t *flag) {
+  __shared__ Ivl s_iv[kRfWaves][CAP];
   __shared__ Run s_run[kRfWaves][kMaxRunsRow];
   __shared__ int s_nr[kRfWaves];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -27,35 +28,33 @@ __global__ __launch_bounds__(64 * kRfWaves) void k_runs_flags(PlanDev P, const A
   int nr = 0;
   if (work) {
     nr = dev_runs_find(P, A, W, s, s_iv[wv], s_run[wv]);
-    if (wv < 4) dev_runs_store(P, W, s, reinterpret_cast<const Run *>(s_iv[wv]), nr);
+    if (wv < 4) dev_runs_store(P, W, s, s_run[wv], nr);
   }
   if (lane == 0) s_nr[wv] = nr;
   __syncthreads();
   if (wv < 4 && work) {
     const int pw = wv == 0 ? 4 : wv - 1;
-    const bool st = runs_band_start(L, s, reinterpret_cast<const Run *>(s_iv[wv]), nr,
-                                    reinterpret_cast<const Run *>(s_iv[pw]), s_nr[pw]);
+    const bool st = runs_band_start(L, s, s_run[wv], nr, s_run[pw], s_nr[pw]);
     if (lane == 0) flag[s] = st ? 1 : 0;
   }
-  if (last_workgroup(done)) {
-    const int nch = (L.nsl + 63) / 64;
-    for (int c = wv; c < nch; c += kRfWaves) dev_masks_from_flags(L, flag, c);
-    __syncthreads();
-    dev_bandscan(L);
-  }
+}
+
+// Band masks from the flags, then the band scan (one workgroup).
+__global__ __launch_bounds__(1024) void k_flags_scan(Level L, const uint8_t *flag) {
+  const int nch = (L.nsl + 63) / 64;
+  for (int c = threadIdx.x; c < nch; c += blockDim.x) dev_mask_from_flags(L, flag, c);
+  __syncthreads();
+  dev_bandscan(L);
 }
 
 __global__ __launch_bounds__(256) void k_bandflags(Level L) { dev_bandflags(L, blockIdx.x * blockDim.x + threadIdx.x); }
 
 __global__ __launch_bounds__(1024) void k_bandscan(Level L) { dev_bandscan(L); }
 
-// Heads of every band (one wave per band), then the last workgroup to
-// finish compacts them into the message table (or the level-2 items).
-__global__ __launch_bounds__(256) void k_heads_compact(PlanDev P, Level L, Work W, MsgRec *out, MsgHdr *hdr,
-                                                        int64_t out_cap, int mode, int32_t *done) {
+// Heads of every band, one wave per band.
+__global__ __launch_bounds__(256) void k_heads(Level L) {
   const int nb = *L.nb;
   for (int b = blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += gridDim.x * 4) dev_heads(L, b);
-  if (last_workgroup(done)) dev_compact(P, L, W, out, hdr, out_cap, mode);
 }
 
 __global__ __launch_bounds__(256) void k_compact(PlanDev P, Level L, Work W, MsgRec *out, MsgHdr *hdr,
@@ -64,25 +63,25 @@ __global__ __launch_bounds__(256) void k_compact(PlanDev P, Level L, Work W, Msg
 }
 
 // Rows with at most 64 boundaries are updated register-only, one wave each;
-// larger rows are listed, and the last workgroup to finish updates them with
-// one wave and LDS scratch (such rows are rare), then clears the list.
-__global__ __launch_bounds__(256) void k_gdef(PlanDev P, ArrDev *__restrict__ A, Work W, int32_t *done) {
-  __shared__ Ivl s_iv[kMaxCap];
-  __shared__ int32_t s_b[kGdefMaxB], s_u[kGdefMaxB], s_own[kGdefMaxB];
-  __shared__ uint64_t s_hold[kGdefMaxB];
+// larger rows are listed for k_gdef_large.
+__global__ __launch_bounds__(256) void k_gdef(PlanDev P, ArrDev *__restrict__ A, Work W) {
   const int wv = threadIdx.x >> 6;
   for (int t = blockIdx.x * 4 + wv; t < P.ngrow; t += gridDim.x * 4) {
     if (!dev_gdef_row_fast(P, A, W, t) && (threadIdx.x & 63) == 0) W.ovf_list[atomicAdd(W.ovf_cnt, 1)] = t;
   }
-  if (last_workgroup(done)) {
-    const int cnt = *W.ovf_cnt;
-    if (wv == 0) {
-      GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
-      for (int q = 0; q < cnt; ++q) dev_gdef_row(P, A, W, W.ovf_list[q], S, kGdefMaxB);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *W.ovf_cnt = 0;
-  }
+}
+
+// The listed large rows, one wave each with LDS scratch (such rows are
+// rare, so the grid is small); the last workgroup clears the list.
+constexpr int kGdefLargeGrid = 32;
+__global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict__ A, Work W) {
+  __shared__ Ivl s_iv[kMaxCap];
+  __shared__ int32_t s_b[kGdefMaxB], s_u[kGdefMaxB], s_own[kGdefMaxB];
+  __shared__ uint64_t s_hold[kGdefMaxB];
+  GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
+  const int cnt = *W.ovf_cnt;
+  for (int q = blockIdx.x; q < cnt; q += gridDim.x) dev_gdef_row(P, A, W, W.ovf_list[q], S, kGdefMaxB);
+  if (last_workgroup(W.ovf_cnt + 1)) *W.ovf_cnt = 0;
 }
 
 // Every row starts as one interval [0, n2) owned and held by the host.
@@ -99,28 +98,34 @@ static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr,
                           int64_t cap, int mode, hipStream_t s);
 
-// level 1 in two launches: runs + band flags + band scan, heads + compaction
+// level 1: runs + band flags, band scan, heads, compaction
 hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, uint8_t *flag,
-                         int32_t *done, MsgRec *out, MsgHdr *hdr, int64_t cap, int mode, hipStream_t s) {
+                         MsgRec *out, MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s) {
   if (P.nsl1 == 0) return launch_compact(P, L, W, out, hdr, cap, mode, s);
-  hipLaunchKernelGGL(k_runs_flags, dim3(cdiv(P.nsl1, 4)), dim3(64 * kRfWaves), 0, s, P, A, W, L, flag, done);
+  // LDS for the row's intervals sized to the row capacity (more workgroups
+  // per CU at the default capacity)
+  if (row_cap <= 64)
+    hipLaunchKernelGGL(k_runs_flags<64>, dim3(cdiv(P.nsl1, 4)), dim3(64 * kRfWaves), 0, s, P, A, W, L, flag);
+  else
+    hipLaunchKernelGGL(k_runs_flags<kMaxCap>, dim3(cdiv(P.nsl1, 4)), dim3(64 * kRfWaves), 0, s, P, A, W, L, flag);
+  hipLaunchKernelGGL(k_flags_scan, dim3(1), dim3(1024), 0, s, L, flag);
   int hg = cdiv(L.nsl, 4);
-  if (hg > 256) hg = 256;
-  hipLaunchKernelGGL(k_heads_compact, dim3(hg), dim3(256), 0, s, P, L, W, out, hdr, cap, mode, done + 1);
-  return hipGetLastError();
+  if (hg > 2048) hg = 2048;
+  hipLaunchKernelGGL(k_heads, dim3(hg), dim3(256), 0, s, L);
+  return launch_compact(P, L, W, out, hdr, cap, mode, s);
 }
 
 // level 2 (stacking rectangles across planes): band flags, band scan, then
 // heads + compaction
-hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, int32_t *done, MsgRec *out, MsgHdr *hdr,
-                         int64_t cap, hipStream_t s) {
+hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
+                         hipStream_t s) {
   if (L.nsl == 0) return launch_compact(P, L, W, out, hdr, cap, 2, s);
   hipLaunchKernelGGL(k_bandflags, dim3(cdiv(L.nsl, 256)), dim3(256), 0, s, L);
   hipLaunchKernelGGL(k_bandscan, dim3(1), dim3(1024), 0, s, L);
   int hg = cdiv(L.nsl, 4);
-  if (hg > 256) hg = 256;
-  hipLaunchKernelGGL(k_heads_compact, dim3(hg), dim3(256), 0, s, P, L, W, out, hdr, cap, 2, done);
-  return hipGetLastError();
+  if (hg > 2048) hg = 2048;
+  hipLaunchKernelGGL(k_heads, dim3(hg), dim3(256), 0, s, L);
+  return launch_compact(P, L, W, out, hdr, cap, 2, s);
 }
 
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr,
@@ -139,8 +144,9 @@ hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipSt
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s) {
   if (P.ngrow == 0) return hipSuccess;
   int grid = cdiv(P.ngrow, 4);
-  if (grid > 4096) grid = 4096;
-  hipLaunchKernelGGL(k_gdef, dim3(grid), dim3(256), 0, s, P, A, W, W.ovf_cnt + 1);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_gdef, dim3(grid), dim3(256), 0, s, P, A, W);
+  hipLaunchKernelGGL(k_gdef_large, dim3(kGdefLargeGrid), dim3(64), 0, s, P, A, W);
   return hipGetLastError();
 }
 

@@ -27,13 +27,13 @@ hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRe
                           int mode, hipStream_t s);
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
 hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, uint8_t *flag,
-                         int32_t *done, MsgRec *out, MsgHdr *hdr, int64_t cap, int mode, hipStream_t s);
-hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, int32_t *done, MsgRec *out, MsgHdr *hdr,
-                         int64_t cap, hipStream_t s);
+                         MsgRec *out, MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s);
+hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
+                         hipStream_t s);
 hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
                        int unpack, hipStream_t s);
 int64_t tiles_for(int kind, const WorkBox &B, int esize, int th);
-hipError_t launch_user(int kind, int th, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
+hipError_t launch_user(int kind, int th, int waves, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
                        const float *coef, hipStream_t s);
 hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const ArrDev *A, int arr, double *pf,
                          uint32_t *pi, void *res, hipStream_t s);
@@ -92,8 +92,13 @@ struct Plan {
   int nsl1 = 0, ngrp = 0, ngrow = 0, has3d = 0;
   int64_t stg_bound = 0;  // bytes
   // user kernel
-  int ukind = 0, th = 16;
+  int ukind = 0, th = 8;
   WorkBox *wb = nullptr;
+  // stencil kinds: the work boxes for 4, 8 and 16 rows per tile, and the
+  // key of the tile-shape tuning shared by plans with the same boxes
+  WorkBox *wbj[3] = {nullptr, nullptr, nullptr};
+  int64_t ntj[3] = {0, 0, 0};
+  std::vector<int64_t> tkey;
   // adjoint plans: extended-box tiles and coefficient partials
   bool adjoint = false;
   double *part = nullptr;
@@ -105,6 +110,19 @@ struct CallArray;
 struct RecCall;
 struct Batch;
 
+// Stencil tile shapes tried on real calls (rows per tile, waves per
+// workgroup; one wave walks tiles down the box, four walk along rows), each
+// timed kTuneReps times in interleaved order; the fastest is kept.  The
+// shape never changes a result.
+constexpr int kTuneN = 4, kTuneReps = 2;
+constexpr int kTuneCand[kTuneN][2] = {{8, 1}, {4, 1}, {8, 4}, {4, 4}};
+struct TuneState {
+  int next = 0;
+  bool done = false;
+  int best = 0;
+  hipEvent_t ev[2 * kTuneN * kTuneReps] = {};
+};
+
 struct Runtime {
   bool inited = false;
   int device = 0;
@@ -114,7 +132,9 @@ struct Runtime {
   void *uctx = nullptr;
   int row_cap = 64;
   bool serial = false;  // metadata work on the data stream (measurement aid)
-  int jacobi_rows = 8;
+  int jacobi_rows = 0;   // HD_JACOBI_ROWS / HD_JACOBI_WAVES fix the stencil tile shape;
+  int jacobi_waves = 0;  // otherwise it is tuned per work-box geometry
+  std::map<std::vector<int64_t>, struct TuneState> tunes;
   std::vector<hd_array *> arrays;
   std::vector<Partition> parts;
   std::vector<Kernel> kernels;
@@ -128,7 +148,8 @@ struct Runtime {
   int64_t ws_nsl = 0, ws_ngrp = 0, ws_items = 0;
   uint64_t *bmask = nullptr;
   int32_t *bcnt = nullptr, *bbase = nullptr, *bandslice = nullptr, *hoff = nullptr, *hcnt = nullptr;
-  int64_t *hvol = nullptr;
+  int64_t *hbytes = nullptr, *bofs = nullptr;
+  int32_t *bcarr = nullptr, *nofs = nullptr;
   uint8_t *bflag = nullptr;  // band-start flag per slice
   Item *heads = nullptr;
   int32_t *counters = nullptr;  // [0] run_top [1] head_top [2] nb [3] err
@@ -255,6 +276,10 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
     const int v = atoi(e);
     if (v == 4 || v == 8 || v == 16) R.jacobi_rows = v;
   }
+  if (const char *e = getenv("HD_JACOBI_WAVES")) {
+    const int v = atoi(e);
+    if (v == 1 || v == 4) R.jacobi_waves = v;
+  }
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
   R.device = dev;
@@ -275,7 +300,6 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   R.W.run_top = R.counters + 0;
   R.W.err = R.counters + 3;
   R.W.ovf_cnt = R.counters + 4;  // [4] rows listed, [5] workgroups done
-  // [6], [7]: workgroups done in the level-1 runs and heads kernels
   HIPCK(hipHostMalloc((void **)&R.red_res_host, 64, hipHostMallocDefault));
   R.red_res_dev = dalloc(64);
   R.red_pf = (double *)dalloc(sizeof(double) * kMaxDev * 64 * 4);
@@ -323,6 +347,10 @@ extern "C" void hdarray_exit(void) {
     (void)hipEventDestroy(p.second.second);
   }
   for (hipEvent_t e : R.ev_pool) (void)hipEventDestroy(e);
+  for (auto &kv : R.tunes)
+    for (hipEvent_t e : kv.second.ev)
+      if (e) (void)hipEventDestroy(e);
+  R.tunes.clear();
   (void)hipEventDestroy(R.ev_meta);
   (void)hipEventDestroy(R.ev_data);
   (void)hipStreamDestroy(R.cap);
@@ -761,8 +789,12 @@ static void free_ws() {
   dfree(R.bandslice);
   dfree(R.hoff);
   dfree(R.hcnt);
-  dfree(R.hvol);
-  R.hvol = nullptr;
+  dfree(R.hbytes);
+  dfree(R.bofs);
+  dfree(R.bcarr);
+  dfree(R.nofs);
+  R.hbytes = R.bofs = nullptr;
+  R.bcarr = R.nofs = nullptr;
   dfree(R.bflag);
   R.bflag = nullptr;
   dfree(R.heads);
@@ -815,8 +847,11 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
     R.bandslice = (int32_t *)dalloc(4 * (ns + 1));
     R.hoff = (int32_t *)dalloc(4 * ns);
     R.hcnt = (int32_t *)dalloc(4 * ns);
-    R.hvol = (int64_t *)dalloc(8 * ns);
-    R.bflag = (uint8_t *)dalloc(ns);
+    R.hbytes = (int64_t *)dalloc(8 * ns);
+    R.bofs = (int64_t *)dalloc(8 * ns);
+    R.bcarr = (int32_t *)dalloc(4 * ns);
+    R.nofs = (int32_t *)dalloc(4 * ns);
+    R.bflag = (uint8_t *)dalloc((ns / 64 + 2) * 64);  // whole 64-slice chunks
     R.heads = (Item *)dalloc(sizeof(Item) * it);
     R.W.ovf_list = (int32_t *)dalloc(4 * ns);
     for (int k = 0; k < 2; ++k) {
@@ -825,7 +860,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
       if (R.hdr[k]) HIPCK(hipMemset(R.hdr[k], 0, sizeof(MsgHdr)));
     }
     if (!R.W.roff || !R.W.rcnt || !R.W.runs || !R.W.goff || !R.W.gcnt || !R.W.l1out || !R.bmask || !R.bcnt ||
-        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hvol || !R.bflag || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
+        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hbytes || !R.bofs || !R.bcarr || !R.nofs || !R.bflag || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
         !R.hdr[1])
       return fail(HD_ENOMEM);
     HIPCK(hipMemset(R.W.roff, 0, 4 * ns));
@@ -856,8 +891,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   std::vector<int64_t> grow1;
   std::vector<Seg> useg, dseg;
   std::vector<SliceRec> srec;
-  std::vector<int32_t> gr_aidx, gr_slice, gr_dseg0, gr_ndseg, gr_full;
-  std::vector<int64_t> gr_row;
+  std::vector<GRowRec> grec;
   PlanDev &P = pl->P;
   memset(&P, 0, sizeof(P));
   P.ncarr = (int)cas.size();
@@ -935,20 +969,21 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
       const int64_t ra = a_i < slice_of_row.size() ? slice_of_row[a_i].first : INT64_MAX;
       const int64_t rb = b_i < ds.size() ? ds[b_i].row : INT64_MAX;
       const int64_t row = std::min(ra, rb);
-      gr_aidx.push_back((int32_t)j);
-      gr_row.push_back(row);
-      gr_slice.push_back(ra == row && !ca.no_holders ? slice_of_row[a_i].second : -1);
+      GRowRec g{};
+      g.arr = (int32_t)a->id;
+      g.grow = row;
+      g.slice = ra == row && !ca.no_holders ? slice_of_row[a_i].second : -1;
       if (ra == row) ++a_i;
-      gr_dseg0.push_back((int32_t)dseg.size());
+      g.dseg0 = (int32_t)dseg.size();
       int cnt = 0;
       while (b_i < ds.size() && ds[b_i].row == row) {
         dseg.push_back(Seg{ds[b_i].e, ds[b_i].c0, ds[b_i].c1, ds[b_i].flags});
         ++b_i;
         ++cnt;
       }
-      gr_ndseg.push_back(cnt);
+      g.ndseg = cnt;
       // definitions sorted by column that tile [0, n2), no holder additions
-      bool full = cnt > 0 && gr_slice.back() < 0;
+      bool full = cnt > 0 && g.slice < 0;
       if (full) {
         std::vector<Seg> v(dseg.end() - cnt, dseg.end());
         std::sort(v.begin(), v.end(), [](const Seg &x, const Seg &y) { return x.c0 < y.c0; });
@@ -960,13 +995,14 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
         if (at != a->n[2]) full = false;
         if (full) std::copy(v.begin(), v.end(), dseg.end() - cnt);
       }
-      gr_full.push_back(full ? 1 : 0);
+      g.full = full ? 1 : 0;
+      grec.push_back(g);
     }
   }
   P.has3d = has3d;
   P.nsl1 = (int32_t)grow1.size();
   P.ngrp = (int32_t)grp_aidx.size();
-  P.ngrow = (int32_t)gr_row.size();
+  P.ngrow = (int32_t)grec.size();
   pl->nsl1 = P.nsl1;
   pl->ngrp = P.ngrp;
   pl->ngrow = P.ngrow;
@@ -980,11 +1016,9 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   size_t o_srec = push_blob(blob, srec);
   size_t o_ga = push_blob(blob, grp_aidx), o_gp = push_blob(blob, grp_plane);
   size_t o_g2 = push_blob(blob, grp2), o_p2 = push_blob(blob, pos2);
-  size_t o_gra = push_blob(blob, gr_aidx), o_grr = push_blob(blob, gr_row), o_grs = push_blob(blob, gr_slice);
-  size_t o_grd0 = push_blob(blob, gr_dseg0), o_grnd = push_blob(blob, gr_ndseg), o_ds = push_blob(blob, dseg);
-  size_t o_grf = push_blob(blob, gr_full);
+  size_t o_grec = push_blob(blob, grec), o_ds = push_blob(blob, dseg);
   size_t o_wb = (blob.size() + 255) / 256 * 256;
-  blob.resize(o_wb + sizeof(WorkBox) * kMaxDev + 16);
+  blob.resize(o_wb + sizeof(WorkBox) * 3 * kMaxDev + 16);
   pl->mem = dalloc(blob.size());
   if (!pl->mem) return fail(HD_ENOMEM);
   char *b = (char *)pl->mem;
@@ -1000,14 +1034,10 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   P.grp_plane = (const int32_t *)(b + o_gp);
   P.grp2 = (const int32_t *)(b + o_g2);
   P.pos2 = (const int32_t *)(b + o_p2);
-  P.gr_aidx = (const int32_t *)(b + o_gra);
-  P.gr_row = (const int64_t *)(b + o_grr);
-  P.gr_slice = (const int32_t *)(b + o_grs);
-  P.gr_dseg0 = (const int32_t *)(b + o_grd0);
-  P.gr_ndseg = (const int32_t *)(b + o_grnd);
+  P.grec = (const GRowRec *)(b + o_grec);
   P.dseg = (const Seg *)(b + o_ds);
-  P.gr_full = (const int32_t *)(b + o_grf);
   pl->wb = (WorkBox *)(b + o_wb);
+  for (int k = 0; k < 3; ++k) pl->wbj[k] = pl->wb + k * kMaxDev;
   // work boxes are filled by the caller into the host blob first
   pl->nbox = 0;
   HIPCK(hipMemcpy(pl->mem, blob.data(), blob.size(), hipMemcpyHostToDevice));
@@ -1040,7 +1070,12 @@ static Level make_level(int which, const PlanDev &P) {
   L.nb = R.counters + 2;
   L.hoff = R.hoff;
   L.hcnt = R.hcnt;
-  L.hvol = R.hvol;
+  L.hbytes = R.hbytes;
+  L.bcarr = R.bcarr;
+  L.nofs = R.nofs;
+  L.bofs = R.bofs;
+  L.grp_carr = which == 1 ? P.grp_aidx : nullptr;
+  L.carr = P.carr;
   L.heads = R.heads;
   L.head_top = R.counters + 1;
   L.head_cap = R.ws_items;
@@ -1100,6 +1135,57 @@ extern "C" int hdarray_profile_read(hd_profile_t *out) {
 
 // Enqueues communication (meta: derive; data: pack, unpack) and the GDEF
 // update for a plan; the user kernel (if any) follows on the data stream.
+// Tile shape of a stencil launch: fixed by the environment, or the next
+// candidate of the tuning (with the event pair that times it), or the
+// tuned best.  The tuning reads its events only once they have completed,
+// so it never waits for the GPU.
+static void stencil_shape(Plan *pl, int &th, int &waves, hipEvent_t &e0, hipEvent_t &e1) {
+  e0 = e1 = nullptr;
+  if (R.jacobi_rows || R.jacobi_waves) {
+    th = R.jacobi_rows ? R.jacobi_rows : 8;
+    waves = R.jacobi_waves ? R.jacobi_waves : 1;
+    return;
+  }
+  TuneState &ts = R.tunes[pl->tkey];
+  int c = ts.best;
+  if (!ts.done && ts.next < kTuneN * kTuneReps) {
+    const int slot = ts.next++;
+    c = slot % kTuneN;
+    if (!ts.ev[2 * slot] && hipEventCreate(&ts.ev[2 * slot]) != hipSuccess) ts.ev[2 * slot] = nullptr;
+    if (!ts.ev[2 * slot + 1] && hipEventCreate(&ts.ev[2 * slot + 1]) != hipSuccess) ts.ev[2 * slot + 1] = nullptr;
+    if (ts.ev[2 * slot] && ts.ev[2 * slot + 1]) {
+      e0 = ts.ev[2 * slot];
+      e1 = ts.ev[2 * slot + 1];
+    }
+  } else if (!ts.done) {
+    const int last = 2 * kTuneN * kTuneReps - 1;
+    const bool ready = !ts.ev[last] || hipEventQuery(ts.ev[last]) == hipSuccess;
+    (void)hipGetLastError();  // a not-ready query must not surface as an error of a later call
+    if (ready) {
+      float best = 1e30f;
+      for (int slot = 0; slot < kTuneN * kTuneReps; ++slot) {
+        float ms = 0.f;
+        if (!ts.ev[2 * slot] || !ts.ev[2 * slot + 1] ||
+            hipEventElapsedTime(&ms, ts.ev[2 * slot], ts.ev[2 * slot + 1]) != hipSuccess)
+          continue;
+        if (ms < best) {
+          best = ms;
+          ts.best = slot % kTuneN;
+        }
+      }
+      for (hipEvent_t &e : ts.ev)
+        if (e) {
+          (void)hipEventDestroy(e);
+          e = nullptr;
+        }
+      ts.done = true;
+    }
+    c = ts.best;
+  }
+  th = kTuneCand[c][0];
+  waves = kTuneCand[c][1];
+}
+
 static int enqueue(Plan *pl, const float *coef) {
   const hipStream_t meta = R.serial ? R.data : R.meta;
   const int slot = R.parity;
@@ -1113,11 +1199,11 @@ static int enqueue(Plan *pl, const float *coef) {
   // first, so its use-region messages are exactly {(owner(x) -> d, x)}
   if (pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
   Level L1 = make_level(1, P);
-  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.bflag, R.counters + 6, R.tab[slot], R.hdr[slot], R.ws_items,
-                      pl->has3d ? 1 : 0, meta));
+  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.bflag, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0,
+                      R.row_cap, meta));
   if (pl->has3d) {
     Level L2 = make_level(2, P);
-    HIPCK(launch_level2(P, W, L2, R.counters + 7, R.tab[slot], R.hdr[slot], R.ws_items, meta));
+    HIPCK(launch_level2(P, W, L2, R.tab[slot], R.hdr[slot], R.ws_items, meta));
   }
   HIPCK(hipEventRecord(R.ev_cs[slot], meta));
   if (!pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
@@ -1147,9 +1233,20 @@ static int enqueue(Plan *pl, const float *coef) {
   R.free_pending[slot] = true;
   R.last_tab = slot;
   R.last_batch = -1;
-  if (pl->ukind) {
+  if (pl->ukind == 1 || pl->ukind == 5) {
+    int th = 8, waves = 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    stencil_shape(pl, th, waves, e0, e1);
+    const int q = th == 4 ? 0 : th == 8 ? 1 : 2;
+    R.stats.stencil_rows = th;
+    R.stats.stencil_waves = waves;
     PhaseTimer tm(3, R.data);
-    HIPCK(launch_user(pl->ukind, pl->th, pl->wb, pl->nbox, R.d_arrs, pl->ntiles, coef, R.data));
+    if (e0) HIPCK(hipEventRecord(e0, R.data));
+    HIPCK(launch_user(pl->ukind, th, waves, pl->wbj[q], pl->nbox, R.d_arrs, pl->ntj[q], coef, R.data));
+    if (e1) HIPCK(hipEventRecord(e1, R.data));
+  } else if (pl->ukind) {
+    PhaseTimer tm(3, R.data);
+    HIPCK(launch_user(pl->ukind, pl->th, 1, pl->wb, pl->nbox, R.d_arrs, pl->ntiles, coef, R.data));
   }
   return HD_OK;
 }
@@ -1364,15 +1461,37 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
       return g_last_error;
     }
     pl->ukind = user_kind(k->builtin);
-    pl->th = R.jacobi_rows;
-    int64_t t0 = 0;
-    for (WorkBox &w : wb) {
-      w.tile0 = t0;
-      t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, pl->th);
-    }
     pl->nbox = (int)wb.size();
-    pl->ntiles = t0;
-    if (!wb.empty()) HIPCK(hipMemcpy(pl->wb, wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice));
+    if (pl->ukind == 1 || pl->ukind == 5) {
+      // one set of work boxes per tile height (tile offsets differ)
+      const int ths[3] = {4, 8, 16};
+      for (int q = 0; q < 3; ++q) {
+        int64_t t0 = 0;
+        for (WorkBox &w : wb) {
+          w.tile0 = t0;
+          t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, ths[q]);
+        }
+        pl->ntj[q] = t0;
+        if (!wb.empty()) HIPCK(hipMemcpy(pl->wbj[q], wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice));
+      }
+      pl->th = 8;
+      pl->wb = pl->wbj[1];
+      pl->ntiles = pl->ntj[1];
+      pl->tkey = {pl->ukind, pl->nbox};
+      for (const WorkBox &w : wb)
+        for (int q = 0; q < 3; ++q) {
+          pl->tkey.push_back(w.lo[q]);
+          pl->tkey.push_back(w.hi[q]);
+        }
+    } else {
+      int64_t t0 = 0;
+      for (WorkBox &w : wb) {
+        w.tile0 = t0;
+        t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, pl->th);
+      }
+      pl->ntiles = t0;
+      if (!wb.empty()) HIPCK(hipMemcpy(pl->wb, wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice));
+    }
     R.plans[key] = pl;
     R.stats.plans_built++;
   }
@@ -1746,6 +1865,12 @@ extern "C" int hdarray_batch_end(void) {
       seen.push_back(ca.a->id);
     }
   }
+  size_t ncas = 0;
+  for (RecCall &c : R.rec) ncas += c.cas.size();
+  if (ncas > (size_t)kCompactCarr) {
+    R.rec.clear();
+    return fail(HD_EINVAL);  // more array arguments than one compaction handles
+  }
   for (RecCall &c : R.rec) {
     for (CallArray &ca : c.cas) all.push_back(std::move(ca));
     boxes.insert(boxes.end(), c.boxes.begin(), c.boxes.end());
@@ -1761,7 +1886,7 @@ extern "C" int hdarray_batch_end(void) {
   b->tab_cap = R.ws_items;
   b->tab = (MsgRec *)dalloc(sizeof(MsgRec) * b->tab_cap);
   b->hdr = (MsgHdr *)dalloc(sizeof(MsgHdr));
-  b->bar = (unsigned *)dalloc(256);
+  b->bar = (unsigned *)dalloc(512);  // barrier counter, then 32 phase-clock stamps at byte 256
   b->d_wb = (WorkBox *)dalloc(sizeof(WorkBox) * (boxes.size() + 1));
   if (!b->tab || !b->hdr || !b->bar || !b->d_wb) return fail(HD_ENOMEM);
   HIPCK(hipMemset(b->hdr, 0, sizeof(MsgHdr)));
@@ -1794,6 +1919,7 @@ static int batch_capture(Batch *b) {
   a.ntiles = b->ntiles;
   a.bar = b->bar;
   a.spin_limit = (int64_t)rate_khz * 2000;  // two seconds
+  a.clk = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->bar) + 256);
   HIPCK(hipStreamBeginCapture(R.cap, hipStreamCaptureModeRelaxed));
   hipError_t e = launch_batch(a, b->th, b->pw, b->grid, R.cap);
   hipGraph_t g = nullptr;
@@ -1828,6 +1954,23 @@ extern "C" int hdarray_batch_run(int id) {
   R.last_batch = id;
   R.stats.calls++;
   return HD_OK;
+}
+
+extern "C" int hdarray_batch_phase_us(int id, double *us, int max) {
+  if (!R.inited || !us || max <= 0) return fail(HD_EINVAL);
+  if (id < 0 || id >= (int)R.batches.size() || !R.batches[id] || !R.batches[id]->exec) return fail(HD_EINVAL);
+  const Batch *b = R.batches[id];
+  HIPCK(hipStreamSynchronize(R.data));
+  int64_t clk[32];
+  HIPCK(hipMemcpy(clk, reinterpret_cast<const char *>(b->bar) + 256, sizeof(clk), hipMemcpyDeviceToHost));
+  int dev = 0, rate_khz = 0;
+  HIPCK(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
+    rate_khz = 100000;
+  const int nst = b->pl.P.has3d ? 12 : 8;
+  int n = 0;
+  for (int k = 1; k < nst && n < max; ++k) us[n++] = (double)(clk[k] - clk[k - 1]) * 1e3 / rate_khz;
+  return n;
 }
 
 extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
