@@ -201,9 +201,10 @@ def bench_batched(hd, rt, steps, warmup):
             "config": {"workload": "batched: 64 arrays, sides log-uniform [512,4096], 2-32 irregular row "
                                    "partitions, 5-point or lower-triangular stencil, ping-pong",
                        "cells": cells, "plain_steps_per_s": 1.0 / t_plain, "batched_over_plain": t_plain / t_batch,
-                       "autotuned_rows": cfg >> 8, "autotuned_pack_words": cfg & 255,
-                       "batch_phases_us": dict(zip(("runs", "band_flags", "band_scan", "heads", "compact",
-                                                    "pack_unpack_gdef", "kernels"), phases))},
+                       "autotuned_rows": cfg >> 8, "autotuned_row_first": cfg & 255,
+                       "batch_phases_us": dict(zip(("runs", "band_flags", "band_scan", "heads", "compact_scan",
+                                                    "compact_prefix", "compact_write", "pack_unpack_gdef",
+                                                    "kernels"), phases))},
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch",
                          "bytes_per_launch": bytes_step, "avg_launch_us": kms / kc * 1e3}}

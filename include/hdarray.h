@@ -200,20 +200,22 @@ int hdarray_reduce(hd_array_t *a, void *res, hd_reduce_t op, int part);
 int hdarray_batch_begin(void);
 int hdarray_batch_end(void);
 int hdarray_batch_run(int batch);
-/* Chooses the rows per stencil tile (4, 8, 16) and the words per pack
- * iteration (1, 4) of the given batches by timing each of the 6 candidates
+/* Chooses the rows per stencil tile (4, 8, 16) and the tile order (1: tiles
+ * numbered along rows first, 0: down columns) of the given batches by
+ * timing each of the 6 candidates
  * on `reps` runs of the sequence batches[0..n) after one warm-up run.  These
  * runs are real steps of the program: 6 * (reps + 1) sequences execute.  The
  * tile shape does not change any result.  Returns the chosen
- * (rows << 8 | words) or a negative error. */
+ * (rows << 8 | order) or a negative error. */
 int hdarray_batch_autotune(const int *batches, int n, int reps);
 /* Device time of each phase of the last run of a batch, in microseconds, from
  * clock stamps taken by workgroup 0 at the phase boundaries (a measurement
  * aid; synchronises).  Phases for 2-D batches: runs, band flags, band scan,
- * heads, compaction, pack + unpack + GDEF update, user kernels (7); 3-D
- * batches add band flags, band scan, heads and compaction of the second
- * stacking level after the first compaction (11).  Writes at most max values
- * to us and returns their number, or a negative error. */
+ * heads, compaction (chunk scans, prefixes, writes: 3 phases), pack + unpack
+ * + GDEF update, user kernels (9); 3-D batches insert the first level's
+ * compaction and the second level's band flags, band scan and heads before
+ * the three compaction phases (13).  Writes at most max values to us and
+ * returns their number, or a negative error. */
 int hdarray_batch_phase_us(int batch, double *us, int max);
 
 /* Adjoint of one ApplyKernel of a "stencil3d7" kernel kname on partition

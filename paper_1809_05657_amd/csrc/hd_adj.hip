@@ -27,12 +27,9 @@ struct AdjArgs {
   double *part;       // [gridDim.x][8] coefficient-gradient partials
 };
 
-__device__ inline bool in_box(const WorkBox &B, int i, int j, int k) {
-  return i >= B.lo[0] && i < B.hi[0] && j >= B.lo[1] && j < B.hi[1] && k >= B.lo[2] && k < B.hi[2];
-}
-
-// tiles of the extended box W +- 1 (clipped): one wave per (plane, row) x 256
-// columns, 4 rows per workgroup
+// tiles of the extended box W +- 1 (clipped), marched like the forward
+// kernel: one wave per (row, 256 columns, segment of planes), four rows per
+// workgroup
 __host__ __device__ inline void ext_box(const WorkBox &B, const int64_t *n, int *lo, int *hi) {
   for (int q = 0; q < 3; ++q) {
     lo[q] = B.lo[q] - 1 < 0 ? 0 : B.lo[q] - 1;
@@ -40,54 +37,112 @@ __host__ __device__ inline void ext_box(const WorkBox &B, const int64_t *n, int 
   }
 }
 
+// y is an interior cell of the array inside the work box (one coordinate)
+__device__ inline bool adj_in(int y, int lo, int hi, int n) { return y >= 1 && y <= n - 2 && y >= lo && y < hi; }
+
 __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__restrict__ A) {
   __shared__ double s_red[4][8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double cb[7] = {0, 0, 0, 0, 0, 0, 0};
-  const int64_t t = blockIdx.x;
-  const WorkBox B = a.wb[find_box(a.wb, a.nbox, t)];
-  const ArrDev &ag = A[B.ain], &ao = A[B.aout], &au = A[B.ain2];
-  int lo[3], hi[3];
-  ext_box(B, ag.n, lo, hi);
-  const int h = hi[1] - lo[1], w = hi[2] - lo[2];
-  const int nty = (h + 3) / 4, ntx = (w + 255) / 256;
-  const int64_t lt = t - B.tile0;
-  const int ty = (int)(lt % nty);
-  const int64_t rest = lt / nty;
-  const int tx = (int)(rest % ntx);
-  const int i = lo[0] + (int)(rest / ntx);
-  const int j = lo[1] + ty * 4 + wv;
-  const int N0 = (int)ag.n[0], N1 = (int)ag.n[1], N2 = (int)ag.n[2];
-  const int64_t si = (int64_t)N1 * N2, sj = N2;
-  if (j < hi[1]) {
+  const int64_t nwg = (a.ntiles + 3) >> 2;
+  const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + wv;
+  if (t < a.ntiles) {
+    const WorkBox B = a.wb[find_box(a.wb, a.nbox, t)];
+    const ArrDev &ag = A[B.ain], &ao = A[B.aout], &au = A[B.ain2];
+    int lo[3], hi[3];
+    ext_box(B, ag.n, lo, hi);
+    const int64_t lt = t - B.tile0;
+    const int jrows = hi[1] - lo[1];
+    const int kb = lo[2] & ~3;
+    const int nk = (hi[2] - kb + 255) / 256;
+    const int j = lo[1] + (int)(lt % jrows);
+    const int64_t rest = lt / jrows;
+    const int c = kb + (int)(rest % nk) * 256 + 4 * lane;
+    const int seg = seg_of(B);
+    const int i0 = lo[0] + (int)(rest / nk) * seg;
+    const int i1 = min(i0 + seg, hi[0]);
+    const int N0 = (int)ag.n[0], N1 = (int)ag.n[1], N2 = (int)ag.n[2];
+    const bool vec = (N2 & 3) == 0;
     const float *__restrict__ g1 = reinterpret_cast<const float *>(ag.buf[B.dev]);
     const float *__restrict__ u = reinterpret_cast<const float *>(au.buf[B.dev]);
     float *__restrict__ g0 = reinterpret_cast<float *>(ao.buf[B.dev]);
-    // neighbour y = x - off_e for e = 0..6 with off = (0, -ei, +ei, -ej, +ej, -ek, +ek)
-    const int di[7] = {0, 1, -1, 0, 0, 0, 0}, dj[7] = {0, 0, 0, 1, -1, 0, 0}, dk[7] = {0, 0, 0, 0, 0, 1, -1};
-    const int64_t offs[7] = {0, -si, si, -sj, sj, -1, 1};
-    const int c0 = lo[2] + tx * 256 + 4 * lane;
-#pragma unroll
-    for (int e4 = 0; e4 < 4; ++e4) {
-      const int k = c0 + e4;
-      if (k >= hi[2]) break;
-      const int64_t x = (int64_t)i * si + (int64_t)j * sj + k;
-      float acc = 0.f;
-#pragma unroll
-      for (int e = 0; e < 7; ++e) {
-        const int yi = i + di[e], yj = j + dj[e], yk = k + dk[e];
-        const bool yint = yi >= 1 && yi <= N0 - 2 && yj >= 1 && yj <= N1 - 2 && yk >= 1 && yk <= N2 - 2;
-        if (yint && in_box(B, yi, yj, yk)) acc = __builtin_fmaf(a.cf.c[e], g1[x - offs[e]], acc);
+    const Coef7 &cf = a.cf;
+    // rows of planes i-1 / i / i+1 of du1 (g) and u (w)
+    f4 gpm = ld_rowv(row_ptr(g1, i0 - 1, j, N0, N1, N2), c, N2, vec);
+    RowQ gcu = ld_rowq(row_ptr(g1, i0, j, N0, N1, N2), c, N2, vec, lane);
+    f4 gjm = ld_rowv(row_ptr(g1, i0, j - 1, N0, N1, N2), c, N2, vec);
+    f4 gjp = ld_rowv(row_ptr(g1, i0, j + 1, N0, N1, N2), c, N2, vec);
+    RowQ gpp = ld_rowq(row_ptr(g1, i0 + 1, j, N0, N1, N2), c, N2, vec, lane);
+    f4 wpm = ld_rowv(row_ptr(u, i0 - 1, j, N0, N1, N2), c, N2, vec);
+    RowQ wcu = ld_rowq(row_ptr(u, i0, j, N0, N1, N2), c, N2, vec, lane);
+    f4 wjm = ld_rowv(row_ptr(u, i0, j - 1, N0, N1, N2), c, N2, vec);
+    f4 wjp = ld_rowv(row_ptr(u, i0, j + 1, N0, N1, N2), c, N2, vec);
+    RowQ wpp = ld_rowq(row_ptr(u, i0 + 1, j, N0, N1, N2), c, N2, vec, lane);
+    const bool rj = adj_in(j, B.lo[1], B.hi[1], N1), rjm = adj_in(j - 1, B.lo[1], B.hi[1], N1),
+               rjp = adj_in(j + 1, B.lo[1], B.hi[1], N1);
+    const bool jown = j >= B.lo[1] && j < B.hi[1], jint = j >= 1 && j <= N1 - 2;
+    for (int i = i0; i < i1; ++i) {
+      RowQ gnq{}, wnq{};
+      f4 gnjm{}, gnjp{}, wnjm{}, wnjp{};
+      if (i + 1 < i1) {
+        gnq = ld_rowq(row_ptr(g1, i + 2, j, N0, N1, N2), c, N2, vec, lane);
+        gnjm = ld_rowv(row_ptr(g1, i + 1, j - 1, N0, N1, N2), c, N2, vec);
+        gnjp = ld_rowv(row_ptr(g1, i + 1, j + 1, N0, N1, N2), c, N2, vec);
+        wnq = ld_rowq(row_ptr(u, i + 2, j, N0, N1, N2), c, N2, vec, lane);
+        wnjm = ld_rowv(row_ptr(u, i + 1, j - 1, N0, N1, N2), c, N2, vec);
+        wnjp = ld_rowv(row_ptr(u, i + 1, j + 1, N0, N1, N2), c, N2, vec);
       }
-      const bool xint = i >= 1 && i <= N0 - 2 && j >= 1 && j <= N1 - 2 && k >= 1 && k <= N2 - 2;
-      const bool xown = in_box(B, i, j, k);
-      if (xown && !xint) acc = acc + g1[x];
-      g0[x] = acc;
-      if (xown && xint) {
-        const double gy = (double)g1[x];
+      const float glw = __shfl_up(gcu.v.w, 1), grx = __shfl_down(gcu.v.x, 1);
+      const float wlw = __shfl_up(wcu.v.w, 1), wrx = __shfl_down(wcu.v.x, 1);
+      const float gkl[4] = {lane == 0 ? gcu.l : glw, gcu.v.x, gcu.v.y, gcu.v.z};
+      const float gkr[4] = {gcu.v.y, gcu.v.z, gcu.v.w, lane == 63 ? gcu.r : grx};
+      const float wkl[4] = {lane == 0 ? wcu.l : wlw, wcu.v.x, wcu.v.y, wcu.v.z};
+      const float wkr[4] = {wcu.v.y, wcu.v.z, wcu.v.w, lane == 63 ? wcu.r : wrx};
+      const bool pi = adj_in(i, B.lo[0], B.hi[0], N0), pim = adj_in(i - 1, B.lo[0], B.hi[0], N0),
+                 pip = adj_in(i + 1, B.lo[0], B.hi[0], N0);
+      const bool iown = i >= B.lo[0] && i < B.hi[0], iint = i >= 1 && i <= N0 - 2;
+      float *q = g0 + ((int64_t)i * N1 + j) * N2;
 #pragma unroll
-        for (int e = 0; e < 7; ++e) cb[e] += gy * (double)u[x + offs[e]];
+      for (int e = 0; e < 4; ++e) {
+        const int k = c + e;
+        if (k < lo[2] || k >= hi[2]) continue;
+        const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
+                   kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
+        const float gx = f4at(gcu.v, e);
+        // contributions of the outputs y = x - off_e this device owns
+        float acc = 0.f;
+        if (pi && rj && kk) acc = __builtin_fmaf(cf.c[0], gx, acc);
+        if (pip && rj && kk) acc = __builtin_fmaf(cf.c[1], f4at(gpp.v, e), acc);
+        if (pim && rj && kk) acc = __builtin_fmaf(cf.c[2], f4at(gpm, e), acc);
+        if (pi && rjp && kk) acc = __builtin_fmaf(cf.c[3], f4at(gjp, e), acc);
+        if (pi && rjm && kk) acc = __builtin_fmaf(cf.c[4], f4at(gjm, e), acc);
+        if (pi && rj && kkp) acc = __builtin_fmaf(cf.c[5], gkr[e], acc);
+        if (pi && rj && kkm) acc = __builtin_fmaf(cf.c[6], gkl[e], acc);
+        const bool xown = iown && jown && k >= B.lo[2] && k < B.hi[2];
+        const bool xint = iint && jint && k >= 1 && k <= N2 - 2;
+        if (xown && !xint) acc = acc + gx;
+        q[k] = acc;
+        if (xown && xint) {
+          const double gy = (double)gx;
+          cb[0] += gy * (double)f4at(wcu.v, e);
+          cb[1] += gy * (double)f4at(wpm, e);
+          cb[2] += gy * (double)f4at(wpp.v, e);
+          cb[3] += gy * (double)f4at(wjm, e);
+          cb[4] += gy * (double)f4at(wjp, e);
+          cb[5] += gy * (double)wkl[e];
+          cb[6] += gy * (double)wkr[e];
+        }
       }
+      gpm = gcu.v;
+      gcu = gpp;
+      gpp = gnq;
+      gjm = gnjm;
+      gjp = gnjp;
+      wpm = wcu.v;
+      wcu = wpp;
+      wpp = wnq;
+      wjm = wnjm;
+      wjp = wnjp;
     }
   }
   // fixed-order reduction of the FP64 coefficient partials of this workgroup
@@ -186,9 +241,7 @@ __global__ __launch_bounds__(256) void k_unpack_add(const MsgRec *__restrict__ M
 int64_t adj_tiles(const WorkBox &B, const int64_t *n) {
   int lo[3], hi[3];
   ext_box(B, n, lo, hi);
-  const int64_t d = hi[0] - lo[0], h = hi[1] - lo[1], w = hi[2] - lo[2];
-  if (d <= 0 || h <= 0 || w <= 0) return 0;
-  return d * ((h + 3) / 4) * ((w + 255) / 256);
+  return march_tiles(lo[0], hi[0], lo[1], hi[1], lo[2], hi[2], seg_of(B));
 }
 
 hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const float *coef, double *part,
@@ -201,8 +254,9 @@ hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const flo
   for (int e = 0; e < 7; ++e) a.cf.c[e] = coef[e];
   a.part = part;
   if (ntiles > 0) {
-    hipLaunchKernelGGL(k_s3d_adj, dim3(ntiles), dim3(256), 0, s, a, A);
-    if (cbar) hipLaunchKernelGGL(k_cbar_final, dim3(7), dim3(256), 0, s, part, ntiles, cbar);
+    const int64_t nwg = (ntiles + 3) / 4;
+    hipLaunchKernelGGL(k_s3d_adj, dim3((unsigned)nwg), dim3(256), 0, s, a, A);
+    if (cbar) hipLaunchKernelGGL(k_cbar_final, dim3(7), dim3(256), 0, s, part, nwg, cbar);
   }
   int grid = (int)((bound_words + 255) / 256);
   if (grid > 4096) grid = 4096;

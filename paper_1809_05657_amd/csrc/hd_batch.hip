@@ -3,9 +3,12 @@
 //
 // Phases (the same device functions as the per-call kernels, so results are
 // identical bit for bit), separated by grid-wide barriers:
-//   runs -> band flags -> band scan (block 0) -> heads -> compact (block 0)
-//   [-> level-2 stacking for 3-D arrays] -> pack + GDEF update -> unpack
-//   -> user kernels (Jacobi / triangular / copy tiles of every box).
+//   runs -> band flags -> band scan (block 0) -> heads -> compaction (three
+//   phases: chunk scans, prefixes and padding in block 0, writes)
+//   [3-D arrays: level-1 compaction in block 0, then level-2 stacking]
+//   -> pack + unpack (one pass) with the GDEF update -> user kernels
+//   (Jacobi / triangular / copy tiles of every box; each wave takes a
+//   contiguous range of tiles).
 // The barrier spins with a bounded wait on the device clock: if a barrier
 // does not complete within the limit (workgroups not co-resident), the
 // kernel records an error and every workgroup leaves, so the launch always
@@ -62,15 +65,33 @@ __device__ inline bool grid_sync(unsigned *bar, unsigned nblk, unsigned &target,
   return s_ok != 0;
 }
 
-template <int TH, int PW>
+// the three compaction phases (modes 0 and 2) with their barriers
+__device__ inline bool batch_compact(const BatchArgs &B, const Level &L, int mode, unsigned nblk, unsigned &target,
+                                     int32_t *err, int &ph, int64_t *lds) {
+  dev_compact_p1(L, B.cs, mode);
+  if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) B.clk[ph] = wall_clock64();
+  ++ph;
+  if (blockIdx.x == 0) dev_compact_p2(B.P, L, B.W, B.hdr, B.tab_cap, B.cs, (int)nblk, mode, lds);
+  if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return false;
+  if (blockIdx.x == 0 && threadIdx.x == 0) B.clk[ph] = wall_clock64();
+  ++ph;
+  dev_compact_p3(B.P, L, B.W, B.tab, B.tab_cap, B.cs, mode);
+  return true;
+}
+
+template <int TH, bool HF>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   __shared__ WaveLds s_lds[kBWaves];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const unsigned nblk = gridDim.x;
   const int gw = blockIdx.x * kBWaves + wv, nw = gridDim.x * kBWaves;
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, gs = (int64_t)gridDim.x * blockDim.x;
   unsigned target = 0;
   WaveLds &my = s_lds[wv];
+  // workgroup-wide scratch of the single-workgroup phases (no wave uses its
+  // own scratch at the same time)
+  int64_t *lds = reinterpret_cast<int64_t *>(s_lds);
+  static_assert(sizeof(WaveLds) * kBWaves >= 4 * kCompactCarr * sizeof(int64_t), "compaction scratch");
   int32_t *err = B.W.err;
   int ph = 0;
   auto stamp = [&]() {
@@ -91,13 +112,14 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   {
     const int nb = B.L1.nsl ? *B.L1.nb : 0;
     for (int b = gw; b < nb; b += nw) dev_heads(B.L1, b);
+    dev_compact_reset(B.P, B.cs);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   stamp();
   if (!B.P.has3d) {
-    if (blockIdx.x == 0) dev_compact(B.P, B.L1, B.W, B.tab, B.hdr, B.tab_cap, 0);
+    if (!batch_compact(B, B.L1, 0, nblk, target, err, ph, lds)) return;
   } else {
-    if (blockIdx.x == 0) dev_compact(B.P, B.L1, B.W, B.tab, B.hdr, B.tab_cap, 1);
+    if (blockIdx.x == 0) dev_compact(B.P, B.L1, B.W, B.tab, B.hdr, B.tab_cap, 1, lds);
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
     stamp();
     for (int c = gw; c * 64 < B.L2.nsl; c += nw) dev_bandflags(B.L2, c * 64 + lane);
@@ -109,22 +131,35 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     {
       const int nb = B.L2.nsl ? *B.L2.nb : 0;
       for (int b = gw; b < nb; b += nw) dev_heads(B.L2, b);
+      dev_compact_reset(B.P, B.cs);
     }
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
     stamp();
-    if (blockIdx.x == 0) dev_compact(B.P, B.L2, B.W, B.tab, B.hdr, B.tab_cap, 2);
+    if (!batch_compact(B, B.L2, 2, nblk, target, err, ph, lds)) return;
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   stamp();
   // pack + unpack in one pass, and the GDEF update (metadata only,
   // independent of the data)
-  const int64_t nmsg = B.hdr->nmsg, words = B.hdr->bytes >> 2;
   {
-    int m = 0;
-    for (int64_t q = gt; q * PW < words; q += gs)
-#pragma unroll
-      for (int e = 0; e < PW; ++e)
-        if (q * PW + e < words) dev_pack_word(B.tab, nmsg, B.A, B.stg, 2, q * PW + e, m);
+    // (message, span) pairs per workgroup, as the per-call pack kernel
+    const int64_t nmsg = B.hdr->nmsg, words = B.hdr->bytes >> 2;
+    if (nmsg > 0) {
+      int64_t S = (words + nmsg * 1024 - 1) / (nmsg * 1024);
+      const int64_t smax = (int64_t)nblk / nmsg > 1 ? (int64_t)nblk / nmsg : 1;
+      if (S > smax) S = smax;
+      if (S < 1) S = 1;
+      for (int64_t q = blockIdx.x; q < nmsg * S; q += nblk) {
+        const int64_t m = q / S, sub = q % S;
+        const MsgRec r = B.tab[m];
+        const int64_t nw8 = r.bytes >> 2;
+        const int64_t a0 = nw8 * sub / S, a1 = nw8 * (sub + 1) / S;
+        if (nw8 < (int64_t(1) << 31))
+          dev_pack_span<int32_t>(r, B.A, B.stg, 2, (int32_t)a0, (int32_t)a1);
+        else
+          dev_pack_span<int64_t>(r, B.A, B.stg, 2, a0, a1);
+      }
+    }
   }
   {
     GdefLds S{my.g.iv, my.g.b, my.g.u, my.g.own, my.g.hold};
@@ -133,15 +168,21 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   stamp();
-  // user kernels: one wave per tile
-  for (int64_t t = gw; t < B.ntiles; t += nw) {
-    const WorkBox bx = B.wb[find_box(B.wb, B.nbox, t)];
-    if (bx.kind == 1)
-      dev_jacobi_tile<TH, false>(bx, t - bx.tile0, B.A);
-    else if (bx.kind == 5)
-      dev_jacobi_tile<TH, true>(bx, t - bx.tile0, B.A);
-    else if (bx.kind == 2)
-      dev_copy_tile(bx, t - bx.tile0, B.A);
+  // user kernels: each wave takes a contiguous range of tiles (one box
+  // search, then the box advances with the tile)
+  {
+    const int64_t t0 = B.ntiles * gw / nw, t1 = B.ntiles * (gw + 1) / nw;
+    int bi = t0 < t1 ? find_box(B.wb, B.nbox, t0) : 0;
+    for (int64_t t = t0; t < t1; ++t) {
+      while (bi + 1 < B.nbox && B.wb[bi + 1].tile0 <= t) ++bi;
+      const WorkBox bx = B.wb[bi];
+      if (bx.kind == 1)
+        dev_jacobi_tile<TH, false, HF>(bx, t - bx.tile0, B.A);
+      else if (bx.kind == 5)
+        dev_jacobi_tile<TH, true, HF>(bx, t - bx.tile0, B.A);
+      else if (bx.kind == 2)
+        dev_copy_tile(bx, t - bx.tile0, B.A);
+    }
   }
   stamp();
 }
@@ -152,27 +193,29 @@ __global__ void k_zero_bar(unsigned *bar) {
 
 typedef void (*batch_kernel_t)(BatchArgs);
 
-static batch_kernel_t pick(int th, int pw) {
-  if (th == 4) return pw == 4 ? k_batch<4, 4> : k_batch<4, 1>;
-  if (th == 16) return pw == 4 ? k_batch<16, 4> : k_batch<16, 1>;
-  return pw == 4 ? k_batch<8, 4> : k_batch<8, 1>;
+// th: rows per stencil tile; hf: tiles numbered along rows first
+static batch_kernel_t pick(int th, int hf) {
+  if (th == 4) return hf ? k_batch<4, true> : k_batch<4, false>;
+  if (th == 16) return hf ? k_batch<16, true> : k_batch<16, false>;
+  return hf ? k_batch<8, true> : k_batch<8, false>;
 }
 
-int batch_max_blocks(int th, int pw) {
+int batch_max_blocks(int th, int hf) {
   int dev = 0, ncu = 0, occ = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)pick(th, pw), 256, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)pick(th, hf), 256, 0) != hipSuccess)
     return -1;
   if (occ < 1) occ = 1;
   if (occ > 2) occ = 2;
-  return ncu * occ;
+  // the compaction keeps one chunk per workgroup
+  return ncu * occ < kCompactCarr ? ncu * occ : kCompactCarr;
 }
 
 // the step as two nodes on one stream: zero the barrier, run the batch
-hipError_t launch_batch(const BatchArgs &a, int th, int pw, int grid, hipStream_t s) {
+hipError_t launch_batch(const BatchArgs &a, int th, int hf, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_bar, dim3(1), dim3(64), 0, s, a.bar);
-  hipLaunchKernelGGL(pick(th, pw), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(pick(th, hf), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

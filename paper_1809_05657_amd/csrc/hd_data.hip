@@ -66,11 +66,48 @@ __global__ __launch_bounds__(64) void k_copy(const WorkBox *__restrict__ wb, int
   dev_copy_tile(B, t - B.tile0, A);
 }
 
+// Four waves (four consecutive rows) per workgroup.
 __global__ __launch_bounds__(256) void k_s3d(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
                                              int64_t ntiles, Coef7 cf) {
-  const int64_t t = xcd_remap(blockIdx.x, ntiles);
+  const int64_t nwg = (ntiles + 3) >> 2;
+  const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
+  if (t >= ntiles) return;
   const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_s3d_row(B, t - B.tile0, threadIdx.x >> 6, A, cf);
+  dev_s3d_march(B, t - B.tile0, A, cf);
+}
+
+// ------------------------------------------------------- device-pointer I/O
+// Copies the rows of every box between an external dense full-extent array
+// and the device buffers of array arr (to_ext: buffers -> external).  One
+// wave per row; box tile0 counts rows.
+__global__ __launch_bounds__(256) void k_ext_copy(const WorkBox *__restrict__ wb, int nbox, int64_t rows,
+                                                  const ArrDev *__restrict__ A, int arr, uint32_t *__restrict__ ext,
+                                                  int to_ext) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= rows) return;
+  const WorkBox B = wb[find_box(wb, nbox, r)];
+  const ArrDev &a = A[arr];
+  const int64_t lr = r - B.tile0;
+  const int h = B.hi[1] - B.lo[1];
+  const int64_t p = B.lo[0] + lr / h, q = B.lo[1] + lr % h;
+  const int k = a.esize >> 2;
+  const int64_t base = ((p * a.n[1] + q) * a.n[2] + B.lo[2]) * k;
+  const int64_t words = (int64_t)(B.hi[2] - B.lo[2]) * k;
+  uint32_t *buf = reinterpret_cast<uint32_t *>(a.buf[B.dev]);
+  if (to_ext) {
+    for (int64_t w = lane; w < words; w += 64) ext[base + w] = buf[base + w];
+  } else {
+    for (int64_t w = lane; w < words; w += 64) buf[base + w] = ext[base + w];
+  }
+}
+
+hipError_t launch_ext_copy(const WorkBox *wb, int nbox, int64_t rows, const ArrDev *A, int arr, void *ext, int to_ext,
+                           hipStream_t s) {
+  if (rows <= 0 || nbox <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ext_copy, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, wb, nbox, rows, A, arr,
+                     reinterpret_cast<uint32_t *>(ext), to_ext);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ reduce
@@ -210,7 +247,7 @@ hipError_t launch_user(int kind, int th, int waves, const WorkBox *wb, int nbox,
     case 3: {
       Coef7 c;
       for (int e = 0; e < 7; ++e) c.c[e] = coef ? coef[e] : 0.f;
-      hipLaunchKernelGGL(k_s3d, dim3(ntiles), dim3(256), 0, s, wb, nbox, A, ntiles, c);
+      hipLaunchKernelGGL(k_s3d, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles, c);
     } break;
     case 4:
       return launch_mm(wb, nbox, A, ntiles, s);

@@ -275,54 +275,145 @@ __host__ __device__ inline int64_t copy_tiles(const WorkBox &B, int esize) {
   return d * ((h + 15) / 16) * ((w * (esize / 4) + 255) / 256);
 }
 
-// -------------------------------------------------------------- stencil3d7
-// One wave: one (plane, row) x 256 columns; tile = 4 consecutive rows.
-__device__ inline void dev_s3d_row(const WorkBox &B, int64_t lt, int wv, const ArrDev *__restrict__ A,
-                                   const Coef7 &cf) {
+// ------------------------------------------------------------- stencil3d
+// One wave computes one row (j) of 256 columns (4 per lane) over a segment of
+// B.seg planes (kS3dSeg unless set), marching in i: the rows of planes i-1, i, i+1 stay in
+// registers, so each plane of the input is read from memory about once; the
+// next plane's rows are requested before the current plane is computed.
+// Four consecutive rows per workgroup share their j-neighbour rows in cache.
+constexpr int kS3dSeg = 32;
+
+// Four consecutive elements of a row at columns [c, c + 4) (zeros outside
+// the row); vec: rows are 16-byte aligned and c is a multiple of 4.
+__device__ inline f4 ld_row4(const float *__restrict__ row, int c, int n2, bool vec) {
+  f4 x = {0.f, 0.f, 0.f, 0.f};
+  if (vec) {
+    if (c < n2) x = *reinterpret_cast<const f4 *>(row + c);
+  } else {
+    if (c >= 0 && c < n2) x.x = row[c];
+    if (c + 1 >= 0 && c + 1 < n2) x.y = row[c + 1];
+    if (c + 2 >= 0 && c + 2 < n2) x.z = row[c + 2];
+    if (c + 3 >= 0 && c + 3 < n2) x.w = row[c + 3];
+  }
+  return x;
+}
+
+// Row (i, j) of a full-extent array, or null outside the array.
+__device__ inline const float *row_ptr(const float *__restrict__ u, int i, int j, int n0, int n1, int n2) {
+  if (i < 0 || i >= n0 || j < 0 || j >= n1) return nullptr;
+  return u + ((int64_t)i * n1 + j) * n2;
+}
+
+// A row chunk with its left / right neighbour columns (valid in lanes 0 / 63).
+struct RowQ {
+  f4 v;
+  float l, r;
+};
+
+__device__ inline RowQ ld_rowq(const float *__restrict__ row, int c, int n2, bool vec, int lane) {
+  RowQ q;
+  q.v = {0.f, 0.f, 0.f, 0.f};
+  q.l = q.r = 0.f;
+  if (!row) return q;
+  q.v = ld_row4(row, c, n2, vec);
+  if (lane == 0 && c >= 1 && c - 1 < n2) q.l = row[c - 1];
+  if (lane == 63 && c + 4 >= 0 && c + 4 < n2) q.r = row[c + 4];
+  return q;
+}
+
+__device__ inline f4 ld_rowv(const float *__restrict__ row, int c, int n2, bool vec) {
+  if (!row) return f4{0.f, 0.f, 0.f, 0.f};
+  return ld_row4(row, c, n2, vec);
+}
+
+__device__ inline float f4at(const f4 &v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+
+// Tiles of a box for the marching kernels: rows x 256-column chunks x plane
+// segments, rows fastest.  Columns start at the box's low column rounded
+// down to a multiple of 4.
+__host__ __device__ inline int seg_of(const WorkBox &B) { return B.seg > 0 ? B.seg : kS3dSeg; }
+
+__host__ __device__ inline int64_t march_tiles(int lo0, int hi0, int lo1, int hi1, int lo2, int hi2, int seg) {
+  if (hi0 <= lo0 || hi1 <= lo1 || hi2 <= lo2) return 0;
+  const int64_t kb = lo2 & ~3;
+  return (int64_t)((hi0 - lo0 + seg - 1) / seg) * ((hi2 - kb + 255) / 256) * (hi1 - lo1);
+}
+
+__host__ __device__ inline int64_t s3d_tiles(const WorkBox &B) {
+  return march_tiles(B.lo[0], B.hi[0], B.lo[1], B.hi[1], B.lo[2], B.hi[2], seg_of(B));
+}
+
+__device__ inline void dev_s3d_march(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef7 &cf) {
   const int lane = threadIdx.x & 63;
-  const int h = B.hi[1] - B.lo[1];
-  const int w = B.hi[2] - B.lo[2];
-  const int nty = (h + 3) / 4, ntx = (w + 255) / 256;
-  const int ty = (int)(lt % nty);
-  const int64_t rest = lt / nty;
-  const int tx = (int)(rest % ntx);
-  const int i = B.lo[0] + (int)(rest / ntx);
-  const int j = B.lo[1] + ty * 4 + wv;
-  if (j >= B.hi[1]) return;
+  const int jrows = B.hi[1] - B.lo[1];
+  const int kb = B.lo[2] & ~3;
+  const int nk = (B.hi[2] - kb + 255) / 256;
+  const int j = B.lo[1] + (int)(lt % jrows);
+  const int64_t rest = lt / jrows;
+  const int c = kb + (int)(rest % nk) * 256 + 4 * lane;
+  const int seg = seg_of(B);
+  const int i0 = B.lo[0] + (int)(rest / nk) * seg;
+  const int i1 = min(i0 + seg, B.hi[0]);
   const ArrDev &ai = A[B.ain];
   const float *__restrict__ u = reinterpret_cast<const float *>(ai.buf[B.dev]);
   float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
   const int N0 = (int)ai.n[0], N1 = (int)ai.n[1], N2 = (int)ai.n[2];
-  const int64_t si = (int64_t)N1 * N2, sj = N2;
-  const int c = B.lo[2] + tx * 256 + 4 * lane;
-  const int64_t x0 = (int64_t)i * si + (int64_t)j * sj;
-  const bool rowint = i >= 1 && i <= N0 - 2 && j >= 1 && j <= N1 - 2;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int k = c + e;
-    if (k >= B.hi[2]) break;
-    const int64_t x = x0 + k;
-    float r;
-    if (rowint && k >= 1 && k <= N2 - 2) {
-      float acc = cf.c[0] * u[x];
-      acc = __builtin_fmaf(cf.c[1], u[x - si], acc);
-      acc = __builtin_fmaf(cf.c[2], u[x + si], acc);
-      acc = __builtin_fmaf(cf.c[3], u[x - sj], acc);
-      acc = __builtin_fmaf(cf.c[4], u[x + sj], acc);
-      acc = __builtin_fmaf(cf.c[5], u[x - 1], acc);
-      acc = __builtin_fmaf(cf.c[6], u[x + 1], acc);
-      r = acc;
-    } else {
-      r = u[x];
+  const bool vec = (N2 & 3) == 0;
+  const bool jint = j >= 1 && j <= N1 - 2;
+  // planes i-1 (row j), i (rows j-1, j, j+1), i+1 (row j)
+  f4 pm = ld_rowv(row_ptr(u, i0 - 1, j, N0, N1, N2), c, N2, vec);
+  RowQ cu = ld_rowq(row_ptr(u, i0, j, N0, N1, N2), c, N2, vec, lane);
+  f4 jm = ld_rowv(row_ptr(u, i0, j - 1, N0, N1, N2), c, N2, vec);
+  f4 jp = ld_rowv(row_ptr(u, i0, j + 1, N0, N1, N2), c, N2, vec);
+  RowQ pp = ld_rowq(row_ptr(u, i0 + 1, j, N0, N1, N2), c, N2, vec, lane);
+  for (int i = i0; i < i1; ++i) {
+    // the next plane's rows, requested before this plane is computed
+    RowQ nq{};
+    f4 njm{}, njp{};
+    const bool more = i + 1 < i1;
+    if (more) {
+      nq = ld_rowq(row_ptr(u, i + 2, j, N0, N1, N2), c, N2, vec, lane);
+      njm = ld_rowv(row_ptr(u, i + 1, j - 1, N0, N1, N2), c, N2, vec);
+      njp = ld_rowv(row_ptr(u, i + 1, j + 1, N0, N1, N2), c, N2, vec);
     }
-    out[x] = r;
+    const float lw = __shfl_up(cu.v.w, 1), rx = __shfl_down(cu.v.x, 1);
+    const float kl[4] = {lane == 0 ? cu.l : lw, cu.v.x, cu.v.y, cu.v.z};
+    const float kr[4] = {cu.v.y, cu.v.z, cu.v.w, lane == 63 ? cu.r : rx};
+    const bool iint = jint && i >= 1 && i <= N0 - 2;
+    float o[4];
+    bool wr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = c + e;
+      wr[e] = k >= B.lo[2] && k < B.hi[2];
+      const float x = f4at(cu.v, e);
+      if (iint && k >= 1 && k <= N2 - 2) {
+        float acc = cf.c[0] * x;
+        acc = __builtin_fmaf(cf.c[1], f4at(pm, e), acc);
+        acc = __builtin_fmaf(cf.c[2], f4at(pp.v, e), acc);
+        acc = __builtin_fmaf(cf.c[3], f4at(jm, e), acc);
+        acc = __builtin_fmaf(cf.c[4], f4at(jp, e), acc);
+        acc = __builtin_fmaf(cf.c[5], kl[e], acc);
+        acc = __builtin_fmaf(cf.c[6], kr[e], acc);
+        o[e] = acc;
+      } else {
+        o[e] = x;
+      }
+    }
+    float *q = out + ((int64_t)i * N1 + j) * N2 + c;
+    if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
+      __builtin_nontemporal_store(f4{o[0], o[1], o[2], o[3]}, reinterpret_cast<f4 *>(q));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (wr[e]) q[e] = o[e];
+    }
+    pm = cu.v;
+    cu = pp;
+    pp = nq;
+    jm = njm;
+    jp = njp;
   }
-}
-
-__host__ __device__ inline int64_t s3d_tiles(const WorkBox &B) {
-  const int64_t d = B.hi[0] - B.lo[0], h = B.hi[1] - B.lo[1], w = B.hi[2] - B.lo[2];
-  if (d <= 0 || h <= 0 || w <= 0) return 0;
-  return d * ((h + 3) / 4) * ((w + 255) / 256);
 }
 
 }  // namespace hd

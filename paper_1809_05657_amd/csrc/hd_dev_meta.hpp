@@ -172,38 +172,6 @@ __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, 
   wave_lds_sync();
 }
 
-// Slice s starts a band unless it continues slice s-1 (same group, next
-// position) with an identical run list; cur / prv are the two lists in LDS
-// (discovery order, see dev_runs_find).  Called by a whole wave.
-__device__ inline bool runs_band_start(const Level &L, int s, const Run *cur, int nc, const Run *prv, int np) {
-  if (s == 0 || L.grp[s] != L.grp[s - 1] || L.pos[s] != L.pos[s - 1] + 1 || nc != np) return true;
-  const int lane = threadIdx.x & 63;
-  bool diff = false;
-  for (int k = lane; k < nc; k += 64) {
-    const Run x = cur[k], y = prv[k];
-    diff |= x.src != y.src || x.dst != y.dst || x.a0 != y.a0 || x.a1 != y.a1;
-  }
-  return __ballot(diff) != 0;
-}
-
-// Band mask of chunk c (slices 64c .. 64c+63) from one byte flag per slice,
-// by one thread (the flag array is padded to whole chunks).
-__device__ inline void dev_mask_from_flags(const Level &L, const uint8_t *flag, int c) {
-  const uint64_t *f8 = reinterpret_cast<const uint64_t *>(flag) + 8 * (int64_t)c;
-  uint64_t m = 0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint64_t v = f8[k];
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-      if ((v >> (8 * b)) & 0xffu) m |= 1ull << (8 * k + b);
-  }
-  const int valid = L.nsl - 64 * c;
-  if (valid < 64) m &= (1ull << valid) - 1ull;
-  L.bmask[c] = m;
-  L.bcnt[c] = __popcll(m);
-}
-
 // Last-workgroup election: every workgroup calls this once after its
 // results are written; returns true in the one workgroup that finishes last,
 // which then sees every other workgroup's writes.  The counter returns to 0.
@@ -390,14 +358,67 @@ __device__ inline int64_t head_volume(const Item &h, int mode) {
   return (int64_t)(h.pos1 - h.pos0) * (h.b1 - h.b0) * (h.a1 - h.a0);
 }
 
+// Writes the heads of band b as messages (modes 0, 2) starting at message
+// exn and byte offset ob, or as level-2 items (mode 1) starting at exn.
+__device__ inline void compact_band(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, int64_t out_cap,
+                                    int mode, int b, int exn, int64_t ob) {
+  const int j = L.bcarr[b];
+  const int cnt = L.hcnt[b];
+  const Item *hs = L.heads + L.hoff[b];
+  const int s0 = L.bandslice[b];
+  if (mode == 1) {
+    const int g = L.grp[s0];
+    const bool gstart = s0 == 0 || L.grp[s0 - 1] != g;
+    if (gstart) W.goff[g] = exn;
+    for (int h = 0; h < cnt; ++h) {
+      if (exn + h < W.l1_cap) {
+        const Item it = hs[h];
+        // rows of the stacked run become the item's b-range
+        W.l1out[exn + h] = Item{it.src, it.dst, it.a0, it.a1, it.pos0, it.pos1, 0, 0};
+      }
+    }
+    return;
+  }
+  const CallArr ca = P.carr[j];
+  const int plane = mode == 0 ? P.grp_plane[L.grp[s0]] : 0;
+  for (int h = 0; h < cnt; ++h) {
+    const Item it = hs[h];
+    MsgRec r;
+    r.aidx = j;
+    r.arr = ca.arr;
+    r.src = it.src;
+    r.dst = it.dst;
+    if (mode == 0) {
+      r.lo[0] = plane;
+      r.hi[0] = plane + 1;
+      r.lo[1] = it.pos0;
+      r.hi[1] = it.pos1;
+    } else {
+      r.lo[0] = it.pos0;
+      r.hi[0] = it.pos1;
+      r.lo[1] = it.b0;
+      r.hi[1] = it.b1;
+    }
+    r.lo[2] = it.a0;
+    r.hi[2] = it.a1;
+    r.argpos = ca.argpos;
+    r.esize = ca.esize;
+    r.off = ob;
+    r.bytes = head_volume(it, mode) * ca.esize;
+    ob += r.bytes;
+    if (exn + h < out_cap) out[exn + h] = r;
+  }
+}
+
+// lds: 2 * kCompactCarr int64 of LDS scratch
 __device__ inline void dev_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr,
-                                   int64_t out_cap, int mode) {
+                                   int64_t out_cap, int mode, int64_t *lds) {
   // one workgroup: (A) a flat exclusive scan of head counts and bytes over
   // all bands; (B) the alignment padding at the first band of every
   // call-array (pack offsets are aligned to the element size), in call-array
   // order; (C) every band writes its heads at its offsets
-  __shared__ int64_t s_raw[kCompactCarr];  // byte prefix at the call-array's first band, -1: none
-  __shared__ int64_t s_pad[kCompactCarr];  // padding inserted up to and including that call-array
+  int64_t *s_raw = lds;                 // byte prefix at the call-array's first band, -1: none
+  int64_t *s_pad = lds + kCompactCarr;  // padding inserted up to and including that call-array
   __shared__ int64_t s_carry_b, s_total_b;
   __shared__ int s_carry_n;
   const int nt = blockDim.x;
@@ -469,53 +490,7 @@ __device__ inline void dev_compact(const PlanDev &P, const Level &L, const Work 
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += nt) {
     const int j = L.bcarr[b];
-    const int cnt = L.hcnt[b];
-    int exn = L.nofs[b];
-    const Item *hs = L.heads + L.hoff[b];
-    const int s0 = L.bandslice[b];
-    if (mode == 1) {
-      const int g = L.grp[s0];
-      const bool gstart = s0 == 0 || L.grp[s0 - 1] != g;
-      if (gstart) W.goff[g] = exn;
-      for (int h = 0; h < cnt; ++h) {
-        if (exn + h < W.l1_cap) {
-          const Item it = hs[h];
-          // rows of the stacked run become the item's b-range
-          W.l1out[exn + h] = Item{it.src, it.dst, it.a0, it.a1, it.pos0, it.pos1, 0, 0};
-        }
-      }
-    } else {
-      const CallArr ca = P.carr[j];
-      int64_t ob = L.bofs[b] + (j < kCompactCarr ? s_pad[j] : 0);
-      const int plane = mode == 0 ? P.grp_plane[L.grp[s0]] : 0;
-      for (int h = 0; h < cnt; ++h) {
-        const Item it = hs[h];
-        MsgRec r;
-        r.aidx = j;
-        r.arr = ca.arr;
-        r.src = it.src;
-        r.dst = it.dst;
-        if (mode == 0) {
-          r.lo[0] = plane;
-          r.hi[0] = plane + 1;
-          r.lo[1] = it.pos0;
-          r.hi[1] = it.pos1;
-        } else {
-          r.lo[0] = it.pos0;
-          r.hi[0] = it.pos1;
-          r.lo[1] = it.b0;
-          r.hi[1] = it.b1;
-        }
-        r.lo[2] = it.a0;
-        r.hi[2] = it.a1;
-        r.argpos = ca.argpos;
-        r.esize = ca.esize;
-        r.off = ob;
-        r.bytes = head_volume(it, mode) * ca.esize;
-        ob += r.bytes;
-        if (exn + h < out_cap) out[exn + h] = r;
-      }
-    }
+    compact_band(P, L, W, out, out_cap, mode, b, L.nofs[b], L.bofs[b] + (j < kCompactCarr ? s_pad[j] : 0));
   }
   __syncthreads();
   if (mode == 1) {
@@ -536,6 +511,160 @@ __device__ inline void dev_compact(const PlanDev &P, const Level &L, const Work 
     *W.run_top = 0;
   }
   __syncthreads();
+}
+
+// Compaction by all workgroups of a persistent launch (modes 0 and 2), in
+// three phases separated by grid barriers.  cs: scratch of 6 * kCompactCarr
+// int64: chunk totals (count, bytes), chunk prefixes (count, bytes), and per
+// call-array the local byte prefix of its first band and that band's chunk
+// (-1: no band; reset by dev_compact_reset before the heads phase).
+// Workgroup w owns bands [nb * w / G, nb * (w + 1) / G), G <= kCompactCarr.
+struct CScratch {
+  int64_t *tot_n, *tot_b, *pre_n, *pre_b, *first_b, *first_c;
+  __device__ CScratch(int64_t *cs)
+      : tot_n(cs), tot_b(cs + kCompactCarr), pre_n(cs + 2 * kCompactCarr), pre_b(cs + 3 * kCompactCarr),
+        first_b(cs + 4 * kCompactCarr), first_c(cs + 5 * kCompactCarr) {}
+};
+
+__device__ inline void dev_compact_reset(const PlanDev &P, int64_t *cs) {
+  CScratch c(cs);
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kCompactCarr; j += gridDim.x * blockDim.x) c.first_c[j] = -1;
+}
+
+// phase 1: scan of the workgroup's own chunk of bands
+__device__ inline void dev_compact_p1(const Level &L, int64_t *cs, int mode) {
+  CScratch c(cs);
+  __shared__ int64_t s_cb;
+  __shared__ int s_cn;
+  const int nb = L.nsl ? *L.nb : 0;
+  const int G = gridDim.x, w = blockIdx.x, nt = blockDim.x;
+  const int b0 = (int)((int64_t)nb * w / G), b1 = (int)((int64_t)nb * (w + 1) / G);
+  if (threadIdx.x == 0) {
+    s_cb = 0;
+    s_cn = 0;
+  }
+  __syncthreads();
+  for (int base = b0; base < b1; base += nt) {
+    const int b = base + threadIdx.x;
+    int cn = 0;
+    int64_t by = 0;
+    int j = -1;
+    bool first = false;
+    if (b < b1) {
+      cn = L.hcnt[b];
+      j = L.bcarr[b];
+      by = mode != 1 ? L.hbytes[b] : 0;
+      first = b == 0 || L.bcarr[b - 1] != j;
+    }
+    int tn;
+    int64_t tb;
+    const int exn = block_exscan<int>(cn, &tn) + s_cn;
+    const int64_t exb = block_exscan<int64_t>(by, &tb) + s_cb;
+    if (b < b1) {
+      L.nofs[b] = exn;
+      L.bofs[b] = exb;
+      if (first && j < kCompactCarr) {
+        c.first_b[j] = exb;
+        c.first_c[j] = w;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_cn += tn;
+      s_cb += tb;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    c.tot_n[w] = s_cn;
+    c.tot_b[w] = s_cb;
+  }
+}
+
+// phase 2 (one workgroup): chunk prefixes, padding per call-array, totals
+// lds: 4 * kCompactCarr int64 of LDS scratch
+__device__ inline void dev_compact_p2(const PlanDev &P, const Level &L, const Work &W, MsgHdr *hdr, int64_t out_cap,
+                                      int64_t *cs, int nchunk, int mode, int64_t *lds) {
+  // all threads load into LDS and scan; one thread walks the call-arrays in
+  // order over LDS values only
+  int64_t *s_n = lds, *s_b = lds + kCompactCarr, *s_at = lds + 2 * kCompactCarr, *s_e = lds + 3 * kCompactCarr;
+  __shared__ int64_t s_tn, s_tb;
+  CScratch c(cs);
+  const int nt = blockDim.x;
+  const int ncarr = P.ncarr < kCompactCarr ? P.ncarr : kCompactCarr;
+  for (int w = threadIdx.x; w < nchunk; w += nt) {
+    s_n[w] = c.tot_n[w];
+    s_b[w] = c.tot_b[w];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    // one wave scans the chunk totals in place (inclusive per 64, carried)
+    int64_t cn = 0, cb = 0;
+    for (int base = 0; base < nchunk; base += 64) {
+      const int w = base + (int)threadIdx.x;
+      int64_t xn = w < nchunk ? s_n[w] : 0, xb = w < nchunk ? s_b[w] : 0;
+      const int64_t vn = xn, vb = xb;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int64_t yn = __shfl_up(xn, d), yb = __shfl_up(xb, d);
+        if ((int)threadIdx.x >= d) {
+          xn += yn;
+          xb += yb;
+        }
+      }
+      if (w < nchunk) {
+        c.pre_n[w] = cn + xn - vn;
+        c.pre_b[w] = cb + xb - vb;
+      }
+      cn += __shfl(xn, 63);
+      cb += __shfl(xb, 63);
+    }
+    if (threadIdx.x == 0) {
+      s_tn = cn;
+      s_tb = cb;
+    }
+  }
+  __syncthreads();
+  // raw byte position of every call-array's first band (-1: no band)
+  for (int j = threadIdx.x; j < ncarr; j += nt) {
+    const int64_t fc = c.first_c[j];
+    s_at[j] = fc >= 0 ? c.first_b[j] + c.pre_b[fc] : -1;
+    s_e[j] = P.carr[j].esize;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t pad = 0;
+    for (int j = 0; j < ncarr; ++j) {
+      if (s_at[j] >= 0 && mode != 1) {
+        const int64_t at = s_at[j] + pad, e = s_e[j];
+        pad += (at + e - 1) / e * e - at;
+      }
+      s_at[j] = pad;  // the padding of the call-arrays up to j, for the bands of j
+    }
+    const int64_t n = s_tn;
+    if (P.ncarr > kCompactCarr || n > out_cap) set_err(W.err, -8);
+    hdr->nmsg = n < out_cap ? n : out_cap;
+    hdr->bytes = s_tb + pad;
+    *L.head_top = 0;
+    *W.run_top = 0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < ncarr; j += nt) c.first_b[j] = s_at[j];
+}
+
+// phase 3: every workgroup writes the messages of its chunk
+__device__ inline void dev_compact_p3(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, int64_t out_cap,
+                                      int64_t *cs, int mode) {
+  CScratch c(cs);
+  const int nb = L.nsl ? *L.nb : 0;
+  const int G = gridDim.x, w = blockIdx.x;
+  const int b0 = (int)((int64_t)nb * w / G), b1 = (int)((int64_t)nb * (w + 1) / G);
+  const int64_t pn = c.pre_n[w], pb = c.pre_b[w];
+  for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
+    const int j = L.bcarr[b];
+    compact_band(P, L, W, out, out_cap, mode, b, (int)(L.nofs[b] + pn),
+                 L.bofs[b] + pb + (j < kCompactCarr ? c.first_b[j] : 0));
+  }
 }
 
 // --------------------------------------------------------------- GDEF row

@@ -133,6 +133,8 @@ struct WorkBox {
   int32_t lo[3], hi[3];
   int32_t aout, ain, ain2, cidx;  // cidx: coefficient set of the box
   int64_t tile0;  // first tile index of this box in the launch
+  int32_t seg;    // 3-D stencil kernels: planes marched by one wave
+  int32_t pad;
 };
 
 // Per-call constant data uploaded once per plan.
@@ -192,6 +194,7 @@ struct BatchArgs {
   unsigned *bar;
   int64_t spin_limit;  // device-clock ticks
   int64_t *clk;        // device-clock stamps taken by workgroup 0 at each phase boundary
+  int64_t *cs;         // compaction scratch, 6 * kCompactCarr
 };
 
 }  // namespace hd

@@ -26,21 +26,23 @@ namespace hd {
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr, int64_t cap,
                           int mode, hipStream_t s);
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
-hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, uint8_t *flag,
-                         MsgRec *out, MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s);
+hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, MsgRec *out,
+                         MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s);
 hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
                          hipStream_t s);
 hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
                        int unpack, hipStream_t s);
 int64_t tiles_for(int kind, const WorkBox &B, int esize, int th);
+hipError_t launch_ext_copy(const WorkBox *wb, int nbox, int64_t rows, const ArrDev *A, int arr, void *ext,
+                           int to_ext, hipStream_t s);
 hipError_t launch_user(int kind, int th, int waves, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
                        const float *coef, hipStream_t s);
 hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const ArrDev *A, int arr, double *pf,
                          uint32_t *pi, void *res, hipStream_t s);
 hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipStream_t s);
 int reduce_blocks();
-int batch_max_blocks(int th, int pw);
-hipError_t launch_batch(const BatchArgs &a, int th, int pw, int grid, hipStream_t s);
+int batch_max_blocks(int th, int hf);
+hipError_t launch_batch(const BatchArgs &a, int th, int hf, int grid, hipStream_t s);
 int64_t adj_tiles(const WorkBox &B, const int64_t *n);
 hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const float *coef, double *part,
                           double *cbar, const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg,
@@ -99,6 +101,10 @@ struct Plan {
   WorkBox *wbj[3] = {nullptr, nullptr, nullptr};
   int64_t ntj[3] = {0, 0, 0};
   std::vector<int64_t> tkey;
+  // device-pointer Write / Read plans: the partition's regions as boxes whose
+  // tile0 counts rows (in the third box slot, unused by those plans)
+  int xn = -1;
+  int64_t xrows = 0;
   // adjoint plans: extended-box tiles and coefficient partials
   bool adjoint = false;
   double *part = nullptr;
@@ -134,6 +140,7 @@ struct Runtime {
   bool serial = false;  // metadata work on the data stream (measurement aid)
   int jacobi_rows = 0;   // HD_JACOBI_ROWS / HD_JACOBI_WAVES fix the stencil tile shape;
   int jacobi_waves = 0;  // otherwise it is tuned per work-box geometry
+  int s3d_seg = 0;       // planes per wave of the 3-D stencil kernels (0: default)
   std::map<std::vector<int64_t>, struct TuneState> tunes;
   std::vector<hd_array *> arrays;
   std::vector<Partition> parts;
@@ -150,9 +157,9 @@ struct Runtime {
   int32_t *bcnt = nullptr, *bbase = nullptr, *bandslice = nullptr, *hoff = nullptr, *hcnt = nullptr;
   int64_t *hbytes = nullptr, *bofs = nullptr;
   int32_t *bcarr = nullptr, *nofs = nullptr;
-  uint8_t *bflag = nullptr;  // band-start flag per slice
   Item *heads = nullptr;
   int32_t *counters = nullptr;  // [0] run_top [1] head_top [2] nb [3] err
+  int64_t *cscratch = nullptr;  // compaction scratch of the batched kernel
   MsgRec *tab[2] = {nullptr, nullptr};
   MsgHdr *hdr[2] = {nullptr, nullptr};
   hipEvent_t ev_cs[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
@@ -276,6 +283,10 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
     const int v = atoi(e);
     if (v == 4 || v == 8 || v == 16) R.jacobi_rows = v;
   }
+  if (const char *e = getenv("HD_S3D_SEG")) {
+    const int v = atoi(e);
+    if (v >= 1 && v <= 4096) R.s3d_seg = v;
+  }
   if (const char *e = getenv("HD_JACOBI_WAVES")) {
     const int v = atoi(e);
     if (v == 1 || v == 4) R.jacobi_waves = v;
@@ -295,6 +306,8 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   R.h_arrs.assign(R.arr_cap, ArrDev{});
   R.d_arrs = (ArrDev *)dalloc(sizeof(ArrDev) * R.arr_cap);
   R.counters = (int32_t *)dalloc(64);
+  R.cscratch = (int64_t *)dalloc(sizeof(int64_t) * 6 * kCompactCarr);
+  if (!R.cscratch) return fail(HD_ENOMEM);
   if (!R.d_arrs || !R.counters) return fail(HD_ENOMEM);
   HIPCK(hipMemset(R.counters, 0, 64));
   R.W.run_top = R.counters + 0;
@@ -334,6 +347,7 @@ extern "C" void hdarray_exit(void) {
   free_ws();
   dfree(R.d_arrs);
   dfree(R.counters);
+  dfree(R.cscratch);
   dfree(R.red_res_dev);
   dfree(R.red_pf);
   dfree(R.red_pi);
@@ -795,8 +809,6 @@ static void free_ws() {
   dfree(R.nofs);
   R.hbytes = R.bofs = nullptr;
   R.bcarr = R.nofs = nullptr;
-  dfree(R.bflag);
-  R.bflag = nullptr;
   dfree(R.heads);
   dfree(R.W.ovf_list);
   R.W.ovf_list = nullptr;
@@ -851,7 +863,6 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
     R.bofs = (int64_t *)dalloc(8 * ns);
     R.bcarr = (int32_t *)dalloc(4 * ns);
     R.nofs = (int32_t *)dalloc(4 * ns);
-    R.bflag = (uint8_t *)dalloc((ns / 64 + 2) * 64);  // whole 64-slice chunks
     R.heads = (Item *)dalloc(sizeof(Item) * it);
     R.W.ovf_list = (int32_t *)dalloc(4 * ns);
     for (int k = 0; k < 2; ++k) {
@@ -860,7 +871,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
       if (R.hdr[k]) HIPCK(hipMemset(R.hdr[k], 0, sizeof(MsgHdr)));
     }
     if (!R.W.roff || !R.W.rcnt || !R.W.runs || !R.W.goff || !R.W.gcnt || !R.W.l1out || !R.bmask || !R.bcnt ||
-        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hbytes || !R.bofs || !R.bcarr || !R.nofs || !R.bflag || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
+        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hbytes || !R.bofs || !R.bcarr || !R.nofs || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
         !R.hdr[1])
       return fail(HD_ENOMEM);
     HIPCK(hipMemset(R.W.roff, 0, 4 * ns));
@@ -1199,8 +1210,8 @@ static int enqueue(Plan *pl, const float *coef) {
   // first, so its use-region messages are exactly {(owner(x) -> d, x)}
   if (pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
   Level L1 = make_level(1, P);
-  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.bflag, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0,
-                      R.row_cap, meta));
+  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0, R.row_cap,
+                      meta));
   if (pl->has3d) {
     Level L2 = make_level(2, P);
     HIPCK(launch_level2(P, W, L2, R.tab[slot], R.hdr[slot], R.ws_items, meta));
@@ -1486,6 +1497,7 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
     } else {
       int64_t t0 = 0;
       for (WorkBox &w : wb) {
+        w.seg = R.s3d_seg;
         w.tile0 = t0;
         t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, pl->th);
       }
@@ -1779,7 +1791,7 @@ struct Batch {
   std::vector<WorkBox> boxes;
   WorkBox *d_wb = nullptr;
   int64_t ntiles = 0;
-  int th = 16, pw = 1, grid = 0;
+  int th = 16, hf = 1, grid = 0;
   MsgRec *tab = nullptr;
   MsgHdr *hdr = nullptr;
   int64_t tab_cap = 0;
@@ -1787,7 +1799,7 @@ struct Batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t epoch = -1;
-  int gth = 0, gpw = 0;
+  int gth = 0, ghf = 0;
 };
 
 static void drop_graph(Batch *b) {
@@ -1825,7 +1837,7 @@ static void last_table(MsgRec **tab, MsgHdr **hdr) {
   }
 }
 
-static int batch_config(Batch *b, int th, int pw) {
+static int batch_config(Batch *b, int th, int hf) {
   int64_t t0 = 0;
   for (WorkBox &w : b->boxes) {
     w.tile0 = t0;
@@ -1836,8 +1848,8 @@ static int batch_config(Batch *b, int th, int pw) {
   if (!b->boxes.empty())
     HIPCK(hipMemcpy(b->d_wb, b->boxes.data(), sizeof(WorkBox) * b->boxes.size(), hipMemcpyHostToDevice));
   b->th = th;
-  b->pw = pw;
-  b->grid = batch_max_blocks(th, pw);
+  b->hf = hf;
+  b->grid = batch_max_blocks(th, hf);
   if (b->grid <= 0) return fail(HD_EHIP);
   return HD_OK;
 }
@@ -1920,8 +1932,9 @@ static int batch_capture(Batch *b) {
   a.bar = b->bar;
   a.spin_limit = (int64_t)rate_khz * 2000;  // two seconds
   a.clk = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->bar) + 256);
+  a.cs = R.cscratch;
   HIPCK(hipStreamBeginCapture(R.cap, hipStreamCaptureModeRelaxed));
-  hipError_t e = launch_batch(a, b->th, b->pw, b->grid, R.cap);
+  hipError_t e = launch_batch(a, b->th, b->hf, b->grid, R.cap);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(R.cap, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -1932,7 +1945,7 @@ static int batch_capture(Batch *b) {
   HIPCK(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
   b->epoch = R.ws_epoch;
   b->gth = b->th;
-  b->gpw = b->pw;
+  b->ghf = b->hf;
   return HD_OK;
 }
 
@@ -1940,7 +1953,7 @@ extern "C" int hdarray_batch_run(int id) {
   if (!R.inited || R.recording) return fail(HD_ESTATE);
   if (id < 0 || id >= (int)R.batches.size() || !R.batches[id]) return fail(HD_EINVAL);
   Batch *b = R.batches[id];
-  if (!b->exec || b->epoch != R.ws_epoch || b->gth != b->th || b->gpw != b->pw)
+  if (!b->exec || b->epoch != R.ws_epoch || b->gth != b->th || b->ghf != b->hf)
     if (batch_capture(b) != HD_OK) return g_last_error;
   // ordered after the metadata work of earlier calls, and before later ones
   HIPCK(hipEventRecord(R.ev_meta, R.meta));
@@ -1967,7 +1980,7 @@ extern "C" int hdarray_batch_phase_us(int id, double *us, int max) {
   HIPCK(hipGetDevice(&dev));
   if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
     rate_khz = 100000;
-  const int nst = b->pl.P.has3d ? 12 : 8;
+  const int nst = b->pl.P.has3d ? 14 : 10;
   int n = 0;
   for (int k = 1; k < nst && n < max; ++k) us[n++] = (double)(clk[k] - clk[k - 1]) * 1e3 / rate_khz;
   return n;
@@ -1977,16 +1990,16 @@ extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
   if (!R.inited || !ids || n <= 0 || reps <= 0) return fail(HD_EINVAL);
   for (int i = 0; i < n; ++i)
     if (ids[i] < 0 || ids[i] >= (int)R.batches.size()) return fail(HD_EINVAL);
-  const int ths[3] = {4, 8, 16}, pws[2] = {1, 4};
+  const int ths[3] = {4, 8, 16}, hfs[2] = {0, 1};  // rows per tile x tile order (1: along rows)
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
   float best = 1e30f;
-  int bth = 8, bpw = 1;
+  int bth = 8, bhf = 0;
   for (int th : ths)
-    for (int pw : pws) {
+    for (int hf : hfs) {
       for (int i = 0; i < n; ++i)
-        if (batch_config(R.batches[ids[i]], th, pw) != HD_OK) return g_last_error;
+        if (batch_config(R.batches[ids[i]], th, hf) != HD_OK) return g_last_error;
       for (int i = 0; i < n; ++i)
         if (hdarray_batch_run(ids[i]) != HD_OK) return g_last_error;
       HIPCK(hipEventRecord(e0, R.data));
@@ -2000,16 +2013,16 @@ extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
       if (ms < best) {
         best = ms;
         bth = th;
-        bpw = pw;
+        bhf = hf;
       }
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   for (int i = 0; i < n; ++i)
-    if (batch_config(R.batches[ids[i]], bth, bpw) != HD_OK) return g_last_error;
+    if (batch_config(R.batches[ids[i]], bth, bhf) != HD_OK) return g_last_error;
   int rc = hdarray_sync();
   if (rc != HD_OK) return rc;
-  return (bth << 8) | bpw;
+  return (bth << 8) | bhf;
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -2067,6 +2080,7 @@ extern "C" int hdarray_apply_adjoint(const char *kname, int part, hd_array_t *di
     }
     int64_t t0 = 0;
     for (WorkBox &w : wb) {
+      w.seg = R.s3d_seg;
       w.tile0 = t0;
       t0 += adj_tiles(w, u->n);
     }
@@ -2084,24 +2098,41 @@ extern "C" int hdarray_apply_adjoint(const char *kname, int part, hd_array_t *di
   return enqueue(pl, coef);
 }
 
+// The partition's regions of a as boxes for k_ext_copy (built once per plan).
+static int ext_boxes(Plan *pl, int part, hd_array *a) {
+  if (pl->xn >= 0) return HD_OK;
+  const Partition &pt = R.parts[part];
+  std::vector<WorkBox> v;
+  int64_t rows = 0;
+  for (int d = 0; d < pt.ndev; ++d) {
+    if (part_dev_empty(pt, d)) continue;
+    WorkBox w{};
+    w.dev = d;
+    w.aout = w.ain = a->id;
+    for (int q = 0; q < 3; ++q) {
+      w.lo[q] = (int32_t)pt.lo[d][q];
+      w.hi[q] = (int32_t)pt.hi[d][q];
+    }
+    w.tile0 = rows;
+    rows += (int64_t)(w.hi[0] - w.lo[0]) * (w.hi[1] - w.lo[1]);
+    v.push_back(w);
+  }
+  WorkBox *dst = pl->wbj[2];
+  if (!v.empty()) HIPCK(hipMemcpy(dst, v.data(), sizeof(WorkBox) * v.size(), hipMemcpyHostToDevice));
+  pl->xn = (int)v.size();
+  pl->xrows = rows;
+  return HD_OK;
+}
+
 extern "C" int hdarray_write_device(hd_array_t *ah, const void *dptr, int part) {
   if (!R.inited) return fail(HD_ESTATE);
   hd_array *a = get_arr(ah);
   if (!a || !dptr) return fail(HD_EINVAL);
   Plan *pl = io_plan(3, part, a);
   if (!pl) return g_last_error;
-  const Partition &pt = R.parts[part];
-  const size_t es = a->esize;
-  for (int d = 0; d < pt.ndev; ++d) {
-    if (part_dev_empty(pt, d)) continue;
-    const int64_t *lo = pt.lo[d], *hi = pt.hi[d];
-    for (int64_t p = lo[0]; p < hi[0]; ++p) {
-      const size_t base = ((size_t)p * a->n[1] + lo[1]) * a->n[2] + lo[2];
-      const size_t pitch = a->n[2] * es, w = (hi[2] - lo[2]) * es, rows = hi[1] - lo[1];
-      HIPCK(hipMemcpy2DAsync(a->buf[d] + base * es, pitch, (const char *)dptr + base * es, pitch, w, rows,
-                             hipMemcpyDeviceToDevice, R.data));
-    }
-  }
+  if (ext_boxes(pl, part, a) != HD_OK) return g_last_error;
+  // every device's region in one launch (rows of the regions, in device order)
+  HIPCK(launch_ext_copy(pl->wbj[2], pl->xn, pl->xrows, R.d_arrs, a->id, const_cast<void *>(dptr), 0, R.data));
   HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, R.meta));
   return HD_OK;
 }
@@ -2113,17 +2144,7 @@ extern "C" int hdarray_read_device(hd_array_t *ah, void *dptr, int part) {
   Plan *pl = io_plan(1, part, a);
   if (!pl) return g_last_error;
   if (enqueue(pl, nullptr) != HD_OK) return g_last_error;
-  const Partition &pt = R.parts[part];
-  const size_t es = a->esize;
-  for (int d = 0; d < pt.ndev; ++d) {
-    if (part_dev_empty(pt, d)) continue;
-    const int64_t *lo = pt.lo[d], *hi = pt.hi[d];
-    for (int64_t p = lo[0]; p < hi[0]; ++p) {
-      const size_t base = ((size_t)p * a->n[1] + lo[1]) * a->n[2] + lo[2];
-      const size_t pitch = a->n[2] * es, w = (hi[2] - lo[2]) * es, rows = hi[1] - lo[1];
-      HIPCK(hipMemcpy2DAsync((char *)dptr + base * es, pitch, a->buf[d] + base * es, pitch, w, rows,
-                             hipMemcpyDeviceToDevice, R.data));
-    }
-  }
+  if (ext_boxes(pl, part, a) != HD_OK) return g_last_error;
+  HIPCK(launch_ext_copy(pl->wbj[2], pl->xn, pl->xrows, R.d_arrs, a->id, dptr, 1, R.data));
   return HD_OK;
 }
