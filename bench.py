@@ -25,7 +25,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "ApplyKernel steps/s + pack/unpack GB/s (% HBM peak), plain vs batched/adjoint"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1809_05657_amd/csrc/hd_data.hip", "paper_1809_05657_amd/csrc/hd_dev_data.hpp"]
+KERNEL_SOURCES = ["paper_1809_05657_amd/csrc/hd_jacobi.hip", "paper_1809_05657_amd/csrc/hd_dev_jacobi.hpp",
+                  "paper_1809_05657_amd/csrc/hd_dev_common.hpp"]
 
 
 def kernel_hash():
@@ -43,9 +44,9 @@ def committed_traffic(name, kernel):
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_source_hash") != kernel_hash() or d.get("kernel") != kernel:
+    if d.get("kernel_source_hash") != kernel_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
 def setup_jacobi_large(rt, hd, n):

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhdarray.so")
-SOURCES = ["hd_meta.hip", "hd_data.hip", "hd_mm.hip", "hd_batch.hip", "hd_adj.hip", "hdarray.cpp"]
+SOURCES = ["hd_meta.hip", "hd_data.hip", "hd_jacobi.hip", "hd_mm.hip", "hd_batch.hip", "hd_adj.hip", "hdarray.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

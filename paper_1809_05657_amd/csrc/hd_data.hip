@@ -12,6 +12,8 @@ namespace hd {
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 int64_t mm_tiles(const int32_t *lo, const int32_t *hi);
 hipError_t launch_mm(const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles, hipStream_t s);
+hipError_t launch_jacobi(bool tri, int th, int waves, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
+                         hipStream_t s);
 
 // Pack / unpack (mode 0 / 1) or both in one pass (mode 2).  Every message is
 // cut into S equal spans (S from the average message size, so that the
@@ -39,26 +41,6 @@ __global__ __launch_bounds__(256) void k_pack(const MsgRec *__restrict__ M, cons
   }
 }
 
-// Four waves per workgroup, one tile each (4 x 256 columns of the same rows).
-template <int TH, bool TRI>
-__global__ __launch_bounds__(256) void k_jacobi(const WorkBox *__restrict__ wb, int nbox,
-                                                const ArrDev *__restrict__ A, int64_t ntiles) {
-  const int64_t nwg = (ntiles + 3) >> 2;
-  const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
-  if (t >= ntiles) return;
-  const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_jacobi_tile<TH, TRI, true>(B, t - B.tile0, A);
-}
-
-// One wave per workgroup; the tiles of an XCD walk down columns of tiles.
-template <int TH, bool TRI>
-__global__ __launch_bounds__(64) void k_jacobi1(const WorkBox *__restrict__ wb, int nbox,
-                                                const ArrDev *__restrict__ A, int64_t ntiles) {
-  const int64_t t = xcd_remap(blockIdx.x, ntiles);
-  const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_jacobi_tile<TH, TRI, false>(B, t - B.tile0, A);
-}
-
 __global__ __launch_bounds__(64) void k_copy(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
                                              int64_t ntiles) {
   const int64_t t = xcd_remap(blockIdx.x, ntiles);
@@ -73,7 +55,10 @@ __global__ __launch_bounds__(256) void k_s3d(const WorkBox *__restrict__ wb, int
   const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
   const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_s3d_march(B, t - B.tile0, A, cf);
+  if (B.seg > 0)
+    dev_s3d_march(B, t - B.tile0, A, cf);
+  else
+    dev_s3d_plane<kS3dRows>(B, t - B.tile0, A, cf);
 }
 
 // ------------------------------------------------------- device-pointer I/O
@@ -226,21 +211,8 @@ hipError_t launch_user(int kind, int th, int waves, const WorkBox *wb, int nbox,
   if (ntiles <= 0) return hipSuccess;
   switch (kind) {
     case 1:
-    case 5: {
-      typedef void (*jk_t)(const WorkBox *, int, const ArrDev *, int64_t);
-      const bool tri = kind == 5;
-      if (waves == 4) {
-        jk_t k = tri ? k_jacobi<8, true> : k_jacobi<8, false>;
-        if (th == 4) k = tri ? k_jacobi<4, true> : k_jacobi<4, false>;
-        if (th == 16) k = tri ? k_jacobi<16, true> : k_jacobi<16, false>;
-        hipLaunchKernelGGL(k, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles);
-      } else {
-        jk_t k = tri ? k_jacobi1<8, true> : k_jacobi1<8, false>;
-        if (th == 4) k = tri ? k_jacobi1<4, true> : k_jacobi1<4, false>;
-        if (th == 16) k = tri ? k_jacobi1<16, true> : k_jacobi1<16, false>;
-        hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
-      }
-    } break;
+    case 5:
+      return launch_jacobi(kind == 5, th, waves, wb, nbox, A, ntiles, s);
     case 2:
       hipLaunchKernelGGL(k_copy, dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
       break;

@@ -16,36 +16,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-#include "hd_internal.hpp"
+#include "hd_dev_common.hpp"
+#include "hd_dev_jacobi.hpp"
 
 namespace hd {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-struct Coef7 {
-  float c[7];
-};
-
-// Flat tile index so that each XCD (workgroups are dealt round-robin over the
-// 8 XCDs) walks a contiguous range of tiles: neighbouring tiles, which share
-// halo rows, then hit the same L2.
-__device__ inline int64_t xcd_remap(int64_t bid, int64_t ntiles) {
-  const int64_t q = ntiles >> 3, r = ntiles & 7;
-  const int64_t x = bid & 7, k = bid >> 3;
-  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
-
-__device__ inline int find_box(const WorkBox *__restrict__ wb, int nbox, int64_t t) {
-  int lo = 0, hi = nbox - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (wb[mid].tile0 <= t)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
 
 // ------------------------------------------------------------ pack / unpack
 __device__ inline int find_msg(const MsgRec *__restrict__ M, int64_t n, int64_t byteoff) {
@@ -140,104 +114,6 @@ __device__ inline void dev_pack(const MsgRec *__restrict__ M, const MsgHdr *__re
   for (int64_t w = first; w < words; w += stride) dev_pack_word(M, n, A, stg, unpack, w, m);
 }
 
-// ------------------------------------------------------------ jacobi / tri
-// One wave computes a tile of TH rows x 256 columns of one box; each lane
-// owns 4 consecutive columns, the left / right neighbours come from the
-// adjacent lanes (lanes 0 and 63 load the tile's edge columns).  HF: tiles
-// are numbered along a row of tiles first (consecutive waves cover
-// consecutive 1 KiB pieces of the same rows); otherwise down a column of
-// tiles first (consecutive waves share halo rows).
-template <int TH, bool TRI, bool HF = true>
-__device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
-  const int lane = threadIdx.x & 63;
-  int tx, ty;
-  if (HF) {
-    const int ntx = (B.hi[2] - B.lo[2] + 255) / 256;
-    tx = (int)(lt % ntx);
-    ty = (int)(lt / ntx);
-  } else {
-    const int nty = (B.hi[1] - B.lo[1] + TH - 1) / TH;
-    ty = (int)(lt % nty);
-    tx = (int)(lt / nty);
-  }
-  const int r0 = B.lo[1] + ty * TH;
-  const int r1 = min(r0 + TH, B.hi[1]);
-  const int c = B.lo[2] + tx * 256 + 4 * lane;
-  const ArrDev &ai = A[B.ain];
-  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
-  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
-  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
-  const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
-  f4 v[TH + 2];
-  float Lh[TH + 2], Rh[TH + 2];
-#pragma unroll
-  for (int k = 0; k < TH + 2; ++k) {
-    const int r = r0 - 1 + k;
-    f4 x = {0.f, 0.f, 0.f, 0.f};
-    float l = 0.f, rr = 0.f;
-    if (r >= 0 && r < N1 && r <= r1) {
-      const float *p = in + (int64_t)r * N2;
-      if (vec && c + 4 <= N2) {
-        x = *reinterpret_cast<const f4 *>(p + c);
-      } else {
-        if (c < N2) x.x = p[c];
-        if (c + 1 < N2) x.y = p[c + 1];
-        if (c + 2 < N2) x.z = p[c + 2];
-        if (c + 3 < N2) x.w = p[c + 3];
-      }
-      if (lane == 0 && c >= 1 && c - 1 < N2) l = p[c - 1];
-      if (lane == 63 && c + 4 < N2) rr = p[c + 4];
-    }
-    const float lw = __shfl_up(x.w, 1);
-    const float rx = __shfl_down(x.x, 1);
-    Lh[k] = lane == 0 ? l : lw;
-    Rh[k] = lane == 63 ? rr : rx;
-    v[k] = x;
-  }
-#pragma unroll
-  for (int k = 1; k <= TH; ++k) {
-    const int i = r0 + k - 1;
-    if (i >= r1) break;
-    const f4 up = v[k - 1], cu = v[k], dn = v[k + 1];
-    const float cv[6] = {Lh[k], cu.x, cu.y, cu.z, cu.w, Rh[k]};
-    const float uv[4] = {up.x, up.y, up.z, up.w};
-    const float dv[4] = {dn.x, dn.y, dn.z, dn.w};
-    float o[4];
-    bool wr[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int j = c + e;
-      bool interior, write = j < B.hi[2];
-      if (TRI) {
-        write = write && j <= i;
-        interior = j >= 1 && j < i && i <= N1 - 2;
-      } else {
-        interior = i >= 1 && i <= N1 - 2 && j >= 1 && j <= N2 - 2;
-      }
-      float s = cv[e] + cv[e + 2];
-      s = s + uv[e];
-      s = s + dv[e];
-      o[e] = interior ? s * 0.25f : cv[e + 1];
-      wr[e] = write;
-    }
-    float *q = out + (int64_t)i * N2 + c;
-    if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
-      f4 ov = {o[0], o[1], o[2], o[3]};
-      __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q));
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (wr[e]) q[e] = o[e];
-    }
-  }
-}
-
-__host__ __device__ inline int64_t jacobi_tiles(const WorkBox &B, int th) {
-  const int64_t h = B.hi[1] - B.lo[1], w = B.hi[2] - B.lo[2];
-  if (h <= 0 || w <= 0 || B.hi[0] <= B.lo[0]) return 0;
-  return ((h + th - 1) / th) * ((w + 255) / 256);
-}
-
 // --------------------------------------------------------------------- copy
 // One wave: 16 rows x 256 words of one plane of the box.
 __device__ inline void dev_copy_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
@@ -276,12 +152,15 @@ __host__ __device__ inline int64_t copy_tiles(const WorkBox &B, int esize) {
 }
 
 // ------------------------------------------------------------- stencil3d
-// One wave computes one row (j) of 256 columns (4 per lane) over a segment of
-// B.seg planes (kS3dSeg unless set), marching in i: the rows of planes i-1, i, i+1 stay in
-// registers, so each plane of the input is read from memory about once; the
-// next plane's rows are requested before the current plane is computed.
-// Four consecutive rows per workgroup share their j-neighbour rows in cache.
-constexpr int kS3dSeg = 32;
+// Two tile forms.  Plane tiles (default): one wave computes kS3dRows rows x
+// 256 columns (4 per lane) of one plane and issues all its row loads at once
+// (rows j-1 .. j+kS3dRows of plane i, rows j .. of planes i-1 and i+1);
+// tiles are numbered rows first, then columns, then planes, so a box is
+// swept plane by plane and the neighbour planes are still in cache.
+// Marching tiles (B.seg > 0 planes per wave): one wave computes one row over
+// a segment of planes, keeping planes i-1, i, i+1 in registers and
+// requesting the next plane's rows before computing the current one.
+constexpr int kS3dRows = 4;
 
 // Four consecutive elements of a row at columns [c, c + 4) (zeros outside
 // the row); vec: rows are 16-byte aligned and c is a multiple of 4.
@@ -328,19 +207,100 @@ __device__ inline f4 ld_rowv(const float *__restrict__ row, int c, int n2, bool 
 
 __device__ inline float f4at(const f4 &v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
 
-// Tiles of a box for the marching kernels: rows x 256-column chunks x plane
-// segments, rows fastest.  Columns start at the box's low column rounded
-// down to a multiple of 4.
-__host__ __device__ inline int seg_of(const WorkBox &B) { return B.seg > 0 ? B.seg : kS3dSeg; }
-
-__host__ __device__ inline int64_t march_tiles(int lo0, int hi0, int lo1, int hi1, int lo2, int hi2, int seg) {
+// Tiles of a box: marching (seg > 0: rows x 256-column chunks x plane
+// segments) or plane tiles (seg == 0: groups of `rows` rows x 256-column
+// chunks x planes), rows fastest.  Columns start at the box's low column
+// rounded down to a multiple of 4.
+__host__ __device__ inline int64_t s3d_box_tiles(int lo0, int hi0, int lo1, int hi1, int lo2, int hi2, int seg,
+                                                 int rows) {
   if (hi0 <= lo0 || hi1 <= lo1 || hi2 <= lo2) return 0;
-  const int64_t kb = lo2 & ~3;
-  return (int64_t)((hi0 - lo0 + seg - 1) / seg) * ((hi2 - kb + 255) / 256) * (hi1 - lo1);
+  const int64_t kb = lo2 & ~3, nk = (hi2 - kb + 255) / 256;
+  if (seg > 0) return (int64_t)((hi0 - lo0 + seg - 1) / seg) * nk * (hi1 - lo1);
+  return (int64_t)(hi0 - lo0) * nk * ((hi1 - lo1 + rows - 1) / rows);
 }
 
 __host__ __device__ inline int64_t s3d_tiles(const WorkBox &B) {
-  return march_tiles(B.lo[0], B.hi[0], B.lo[1], B.hi[1], B.lo[2], B.hi[2], seg_of(B));
+  return s3d_box_tiles(B.lo[0], B.hi[0], B.lo[1], B.hi[1], B.lo[2], B.hi[2], B.seg, kS3dRows);
+}
+
+// One 7-point update (interior) or copy (boundary) of element e of a lane's
+// four columns; nb: i-1, i+1, j-1, j+1, k-1, k+1 neighbours.
+__device__ inline float s3d_point(const Coef7 &cf, float x, float im, float ip, float jm, float jp, float km,
+                                  float kp) {
+  float acc = cf.c[0] * x;
+  acc = __builtin_fmaf(cf.c[1], im, acc);
+  acc = __builtin_fmaf(cf.c[2], ip, acc);
+  acc = __builtin_fmaf(cf.c[3], jm, acc);
+  acc = __builtin_fmaf(cf.c[4], jp, acc);
+  acc = __builtin_fmaf(cf.c[5], km, acc);
+  acc = __builtin_fmaf(cf.c[6], kp, acc);
+  return acc;
+}
+
+template <int TH>
+__device__ inline void dev_s3d_plane(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef7 &cf) {
+  const int lane = threadIdx.x & 63;
+  const int kb = B.lo[2] & ~3;
+  const int nk = (B.hi[2] - kb + 255) / 256;
+  const int nj = (B.hi[1] - B.lo[1] + TH - 1) / TH;
+  const int j0 = B.lo[1] + (int)(lt % nj) * TH;
+  const int64_t rest = lt / nj;
+  const int c = kb + (int)(rest % nk) * 256 + 4 * lane;
+  const int i = B.lo[0] + (int)(rest / nk);
+  const int j1 = min(j0 + TH, B.hi[1]);
+  const ArrDev &ai = A[B.ain];
+  const float *__restrict__ u = reinterpret_cast<const float *>(ai.buf[B.dev]);
+  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  const int N0 = (int)ai.n[0], N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const bool vec = (N2 & 3) == 0;
+  f4 cr[TH + 2], pm[TH], pp[TH];
+  float cl[TH], crt[TH];
+#pragma unroll
+  for (int q = 0; q < TH + 2; ++q) {
+    const int r = j0 - 1 + q;
+    const bool own = q >= 1 && r < j1;
+    cr[q] = (r <= j1) ? ld_rowv(row_ptr(u, i, r, N0, N1, N2), c, N2, vec) : f4{0.f, 0.f, 0.f, 0.f};
+    if (own) {
+      const float *row = row_ptr(u, i, r, N0, N1, N2);
+      cl[q - 1] = (lane == 0 && c >= 1) ? row[c - 1] : 0.f;
+      crt[q - 1] = (lane == 63 && c + 4 < N2) ? row[c + 4] : 0.f;
+      pm[q - 1] = ld_rowv(row_ptr(u, i - 1, r, N0, N1, N2), c, N2, vec);
+      pp[q - 1] = ld_rowv(row_ptr(u, i + 1, r, N0, N1, N2), c, N2, vec);
+    } else if (q >= 1 && q <= TH) {
+      cl[q - 1] = crt[q - 1] = 0.f;
+      pm[q - 1] = pp[q - 1] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+  const bool iint = i >= 1 && i <= N0 - 2;
+#pragma unroll
+  for (int q = 0; q < TH; ++q) {
+    const int j = j0 + q;
+    const f4 cu = cr[q + 1];
+    const float lw = __shfl_up(cu.w, 1), rx = __shfl_down(cu.x, 1);
+    if (j >= j1) continue;
+    const float kl[4] = {lane == 0 ? cl[q] : lw, cu.x, cu.y, cu.z};
+    const float kr[4] = {cu.y, cu.z, cu.w, lane == 63 ? crt[q] : rx};
+    const bool rint = iint && j >= 1 && j <= N1 - 2;
+    float o[4];
+    bool wr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = c + e;
+      wr[e] = k >= B.lo[2] && k < B.hi[2];
+      const float x = f4at(cu, e);
+      o[e] = (rint && k >= 1 && k <= N2 - 2)
+                 ? s3d_point(cf, x, f4at(pm[q], e), f4at(pp[q], e), f4at(cr[q], e), f4at(cr[q + 2], e), kl[e], kr[e])
+                 : x;
+    }
+    float *dst = out + ((int64_t)i * N1 + j) * N2 + c;
+    if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
+      __builtin_nontemporal_store(f4{o[0], o[1], o[2], o[3]}, reinterpret_cast<f4 *>(dst));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (wr[e]) dst[e] = o[e];
+    }
+  }
 }
 
 __device__ inline void dev_s3d_march(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef7 &cf) {
@@ -351,7 +311,7 @@ __device__ inline void dev_s3d_march(const WorkBox &B, int64_t lt, const ArrDev 
   const int j = B.lo[1] + (int)(lt % jrows);
   const int64_t rest = lt / jrows;
   const int c = kb + (int)(rest % nk) * 256 + 4 * lane;
-  const int seg = seg_of(B);
+  const int seg = B.seg;
   const int i0 = B.lo[0] + (int)(rest / nk) * seg;
   const int i1 = min(i0 + seg, B.hi[0]);
   const ArrDev &ai = A[B.ain];

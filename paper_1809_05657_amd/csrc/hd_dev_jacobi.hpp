@@ -1,0 +1,110 @@
+// hd_dev_jacobi.hpp — the 2-D 5-point Jacobi / lower-triangular tile
+// (Sec. 5.1 formula: A[i][j] = (((B[i][j-1] + B[i][j+1]) + B[i-1][j]) +
+// B[i+1][j]) / 4 on interior cells, A = B on the array boundary), shared by
+// the per-call kernels (hd_jacobi.hip) and the persistent batched kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hd_dev_common.hpp"
+
+namespace hd {
+
+// ------------------------------------------------------------ jacobi / tri
+// One wave computes a tile of TH rows x 256 columns of one box; each lane
+// owns 4 consecutive columns, the left / right neighbours come from the
+// adjacent lanes (lanes 0 and 63 load the tile's edge columns).  HF: tiles
+// are numbered along a row of tiles first (consecutive waves cover
+// consecutive 1 KiB pieces of the same rows); otherwise down a column of
+// tiles first (consecutive waves share halo rows).
+template <int TH, bool TRI, bool HF = true>
+__device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
+  const int lane = threadIdx.x & 63;
+  int tx, ty;
+  if (HF) {
+    const int ntx = (B.hi[2] - B.lo[2] + 255) / 256;
+    tx = (int)(lt % ntx);
+    ty = (int)(lt / ntx);
+  } else {
+    const int nty = (B.hi[1] - B.lo[1] + TH - 1) / TH;
+    ty = (int)(lt % nty);
+    tx = (int)(lt / nty);
+  }
+  const int r0 = B.lo[1] + ty * TH;
+  const int r1 = min(r0 + TH, B.hi[1]);
+  const int c = B.lo[2] + tx * 256 + 4 * lane;
+  const ArrDev &ai = A[B.ain];
+  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
+  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
+  f4 v[TH + 2];
+  float Lh[TH + 2], Rh[TH + 2];
+#pragma unroll
+  for (int k = 0; k < TH + 2; ++k) {
+    const int r = r0 - 1 + k;
+    f4 x = {0.f, 0.f, 0.f, 0.f};
+    float l = 0.f, rr = 0.f;
+    if (r >= 0 && r < N1 && r <= r1) {
+      const float *p = in + (int64_t)r * N2;
+      if (vec && c + 4 <= N2) {
+        x = *reinterpret_cast<const f4 *>(p + c);
+      } else {
+        if (c < N2) x.x = p[c];
+        if (c + 1 < N2) x.y = p[c + 1];
+        if (c + 2 < N2) x.z = p[c + 2];
+        if (c + 3 < N2) x.w = p[c + 3];
+      }
+      if (lane == 0 && c >= 1 && c - 1 < N2) l = p[c - 1];
+      if (lane == 63 && c + 4 < N2) rr = p[c + 4];
+    }
+    const float lw = __shfl_up(x.w, 1);
+    const float rx = __shfl_down(x.x, 1);
+    Lh[k] = lane == 0 ? l : lw;
+    Rh[k] = lane == 63 ? rr : rx;
+    v[k] = x;
+  }
+#pragma unroll
+  for (int k = 1; k <= TH; ++k) {
+    const int i = r0 + k - 1;
+    if (i >= r1) break;
+    const f4 up = v[k - 1], cu = v[k], dn = v[k + 1];
+    const float cv[6] = {Lh[k], cu.x, cu.y, cu.z, cu.w, Rh[k]};
+    const float uv[4] = {up.x, up.y, up.z, up.w};
+    const float dv[4] = {dn.x, dn.y, dn.z, dn.w};
+    float o[4];
+    bool wr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = c + e;
+      bool interior, write = j < B.hi[2];
+      if (TRI) {
+        write = write && j <= i;
+        interior = j >= 1 && j < i && i <= N1 - 2;
+      } else {
+        interior = i >= 1 && i <= N1 - 2 && j >= 1 && j <= N2 - 2;
+      }
+      float s = cv[e] + cv[e + 2];
+      s = s + uv[e];
+      s = s + dv[e];
+      o[e] = interior ? s * 0.25f : cv[e + 1];
+      wr[e] = write;
+    }
+    float *q = out + (int64_t)i * N2 + c;
+    if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
+      f4 ov = {o[0], o[1], o[2], o[3]};
+      __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (wr[e]) q[e] = o[e];
+    }
+  }
+}
+
+__host__ __device__ inline int64_t jacobi_tiles(const WorkBox &B, int th) {
+  const int64_t h = B.hi[1] - B.lo[1], w = B.hi[2] - B.lo[2];
+  if (h <= 0 || w <= 0 || B.hi[0] <= B.lo[0]) return 0;
+  return ((h + th - 1) / th) * ((w + 255) / 256);
+}
+
+}  // namespace hd

@@ -172,6 +172,39 @@ __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, 
   wave_lds_sync();
 }
 
+// Slice s starts a band unless it continues slice s-1 (same group, next
+// position) with the same runs; cur / prv are the two run lists in LDS, in
+// discovery order (a function of the run set, see dev_runs_find).  Called
+// by a whole wave.
+__device__ inline bool runs_band_start(const Level &L, int s, const Run *cur, int nc, const Run *prv, int np) {
+  if (s == 0 || L.grp[s] != L.grp[s - 1] || L.pos[s] != L.pos[s - 1] + 1 || nc != np) return true;
+  const int lane = threadIdx.x & 63;
+  bool diff = false;
+  for (int k = lane; k < nc; k += 64) {
+    const Run x = cur[k], y = prv[k];
+    diff |= x.src != y.src || x.dst != y.dst || x.a0 != y.a0 || x.a1 != y.a1;
+  }
+  return __ballot(diff) != 0;
+}
+
+// Band mask of chunk c (slices 64c .. 64c+63) from one byte flag per slice,
+// by one thread (the flag array is padded to whole chunks).
+__device__ inline void dev_mask_from_flags(const Level &L, const uint8_t *flag, int c) {
+  const uint64_t *f8 = reinterpret_cast<const uint64_t *>(flag) + 8 * (int64_t)c;
+  uint64_t m = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint64_t v = f8[k];
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+      if ((v >> (8 * b)) & 0xffu) m |= 1ull << (8 * k + b);
+  }
+  const int valid = L.nsl - 64 * c;
+  if (valid < 64) m &= (1ull << valid) - 1ull;
+  L.bmask[c] = m;
+  L.bcnt[c] = __popcll(m);
+}
+
 // Last-workgroup election: every workgroup calls this once after its
 // results are written; returns true in the one workgroup that finishes last,
 // which then sees every other workgroup's writes.  The counter returns to 0.

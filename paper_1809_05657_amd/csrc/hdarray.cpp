@@ -26,8 +26,8 @@ namespace hd {
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr, int64_t cap,
                           int mode, hipStream_t s);
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
-hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, MsgRec *out,
-                         MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s);
+hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, uint8_t *flag,
+                         MsgRec *out, MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s);
 hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
                          hipStream_t s);
 hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
@@ -157,6 +157,7 @@ struct Runtime {
   int32_t *bcnt = nullptr, *bbase = nullptr, *bandslice = nullptr, *hoff = nullptr, *hcnt = nullptr;
   int64_t *hbytes = nullptr, *bofs = nullptr;
   int32_t *bcarr = nullptr, *nofs = nullptr;
+  uint8_t *bflag = nullptr;  // band-start flag per level-1 slice (whole 64-slice chunks)
   Item *heads = nullptr;
   int32_t *counters = nullptr;  // [0] run_top [1] head_top [2] nb [3] err
   int64_t *cscratch = nullptr;  // compaction scratch of the batched kernel
@@ -809,6 +810,8 @@ static void free_ws() {
   dfree(R.nofs);
   R.hbytes = R.bofs = nullptr;
   R.bcarr = R.nofs = nullptr;
+  dfree(R.bflag);
+  R.bflag = nullptr;
   dfree(R.heads);
   dfree(R.W.ovf_list);
   R.W.ovf_list = nullptr;
@@ -863,6 +866,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
     R.bofs = (int64_t *)dalloc(8 * ns);
     R.bcarr = (int32_t *)dalloc(4 * ns);
     R.nofs = (int32_t *)dalloc(4 * ns);
+    R.bflag = (uint8_t *)dalloc((ns / 64 + 2) * 64);
     R.heads = (Item *)dalloc(sizeof(Item) * it);
     R.W.ovf_list = (int32_t *)dalloc(4 * ns);
     for (int k = 0; k < 2; ++k) {
@@ -871,7 +875,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
       if (R.hdr[k]) HIPCK(hipMemset(R.hdr[k], 0, sizeof(MsgHdr)));
     }
     if (!R.W.roff || !R.W.rcnt || !R.W.runs || !R.W.goff || !R.W.gcnt || !R.W.l1out || !R.bmask || !R.bcnt ||
-        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hbytes || !R.bofs || !R.bcarr || !R.nofs || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
+        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hbytes || !R.bofs || !R.bcarr || !R.nofs || !R.bflag || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
         !R.hdr[1])
       return fail(HD_ENOMEM);
     HIPCK(hipMemset(R.W.roff, 0, 4 * ns));
@@ -1210,8 +1214,8 @@ static int enqueue(Plan *pl, const float *coef) {
   // first, so its use-region messages are exactly {(owner(x) -> d, x)}
   if (pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
   Level L1 = make_level(1, P);
-  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0, R.row_cap,
-                      meta));
+  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.bflag, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0,
+                      R.row_cap, meta));
   if (pl->has3d) {
     Level L2 = make_level(2, P);
     HIPCK(launch_level2(P, W, L2, R.tab[slot], R.hdr[slot], R.ws_items, meta));
