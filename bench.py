@@ -128,7 +128,7 @@ def bench_matmul(hd, rt, steps, warmup):
     flops = 2.0 * n ** 3
     tf = flops / (kms / kc * 1e-3) / 1e12
     moved = st["last_bytes"]
-    pk, up = first["pack"][0], first["unpack"][0]
+    pk = first["pack"][0]
     return {"metric": METRIC, "value": steps / dt, "unit": "steps/s", "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": dt * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -137,9 +137,131 @@ def bench_matmul(hd, rt, steps, warmup):
                        "first_step_bytes": moved, "first_step_ms": sum(v[0] for v in first.values())},
             "roofline": {"bound": "mfma", "achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
                          "traffic": None, "kernel": "k_mm_mfma", "avg_launch_us": kms / kc * 1e3},
-            "pack_unpack": {"bytes": moved, "pack_GBps": 2 * moved / (pk * 1e-3) / 1e9 if pk else None,
-                            "unpack_GBps": 2 * moved / (up * 1e-3) / 1e9 if up else None,
-                            "frac_hbm": (2 * moved / (pk * 1e-3) / 1e9) / HBM_PEAK_GBS if pk else None}}
+            "pack_unpack": {"bytes": moved, "fused_pass_us": pk * 1e3,
+                            "GBps": 4 * moved / (pk * 1e-3) / 1e9 if pk else None,
+                            "frac_hbm": (4 * moved / (pk * 1e-3) / 1e9) / HBM_PEAK_GBS if pk else None}}
+
+
+def bench_2mm(hd, rt, steps, warmup):
+    """2MM (Sec. 5.1): D = A.B then E = C.D, 4096^2 fp32, 8 partitions, ROW
+    and then COL; one iteration = both products.  Reports iterations/s and
+    the bytes moved per iteration under each partitioning."""
+    from workloads import matmul_inputs
+    n, P = 4096, 8
+    a0, b0 = matmul_inputs(n, 3)
+    c0, _ = matmul_inputs(n, 6)
+    res = {}
+    for name, lay in (("row", hd.ROW), ("col", hd.COL)):
+        A, B, Cm = rt.create(a0), rt.create(b0), rt.create(c0)
+        D, E = rt.create(shape=(n, n)), rt.create(shape=(n, n))
+        p = rt.partition(lay, (n, n), ndev=P)
+        k1, k2 = f"mm1_{name}", f"mm2_{name}"
+        for k in (k1, k2):
+            rt.kernel(k, hd.K_MATMUL)
+            rt.set_offsets(k, 0, 0, [(0, "*")])
+            rt.set_offsets(k, 1, 0, [("*", 0)])
+            rt.set_offsets(k, 2, 1, [(0, 0)])
+        for X, x0 in ((A, a0), (B, b0), (Cm, c0)):
+            rt.write(X, x0, p)
+        rt.sync()
+        moved = []
+
+        def it(track):
+            for k, args in ((k1, [A, B, D]), (k2, [Cm, D, E])):
+                rt.apply(k, p, args)
+                if track:
+                    rt.sync()
+                    moved.append(rt.stats()["last_bytes"])
+
+        it(True)
+        it(True)
+        for _ in range(warmup):
+            it(False)
+        rt.sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            it(False)
+        rt.sync()
+        dt = time.perf_counter() - t0
+        res[name] = {"iterations_per_s": steps / dt, "ms_per_iteration": dt * 1e3 / steps,
+                     "first_iteration_bytes": moved[0] + moved[1], "steady_iteration_bytes": moved[2] + moved[3],
+                     "tflops": 2 * 2.0 * n ** 3 * steps / dt / 1e12}
+    r, c = res["row"], res["col"]
+    vol = lambda d, k: d["first_iteration_bytes"] + (k - 1) * d["steady_iteration_bytes"]
+    return {"metric": "2mm iterations/s", "value": r["iterations_per_s"], "unit": "iterations/s", "n_gpus": 1,
+            "steps": steps, "warmup": warmup, "ms_per_step": r["ms_per_iteration"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"2mm: D=A.B, E=C.D, {n}x{n} fp32 U[-1,1), {P} partitions, GEMM clauses; "
+                                   "value = ROW partitions", "n": n, "partitions": P},
+            "row": r, "col": c,
+            "volume_ratio_row_over_col_100_iterations": vol(r, 100) / vol(c, 100)}
+
+
+def bench_conv2d(hd, rt, steps, warmup):
+    """conv2d: the 3 x 3 convolution of Sec. 5.1 on 8192^2 fp32, 16 devices
+    (4 x 4 blocks), use = the 3 x 3 window, def = own block.  Ping-pong
+    steps (A = conv(B), B = conv(A)) exchange 48 strips and 36 corner cells
+    every step; the paper's form (A = conv(B) repeated, B never redefined)
+    communicates once and is timed second."""
+    from workloads import CONV9_WEIGHTS, jacobi_inputs
+    n = 8192
+    A0, B0 = jacobi_inputs(n, 2)
+    A, B = rt.create(A0), rt.create(B0)
+    p = rt.partition(hd.BLOCK, (n, n), ndev=16)
+    offs = [(di, dj) for di in (-1, 0, 1) for dj in (-1, 0, 1)]
+    for k in ("convAB", "convBA"):
+        rt.kernel(k, hd.K_CONV2D9)
+        rt.set_offsets(k, 1, 0, offs)
+        rt.set_offsets(k, 0, 1, [(0, 0)])
+    rt.write(A, A0, p)
+    rt.write(B, B0, p)
+    del A0, B0
+    w = [float(x) for x in CONV9_WEIGHTS]
+
+    def pp(i):
+        if i % 2 == 0:
+            rt.apply("convAB", p, [A, B], w)
+        else:
+            rt.apply("convBA", p, [B, A], w)
+
+    for i in range(warmup):
+        pp(i)
+    rt.sync()
+    rt.profile(1 << 3)
+    rt.profile_read()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        pp(warmup + i)
+    rt.sync()
+    dt = time.perf_counter() - t0
+    kms, kcnt = rt.profile_read()["kernel"]
+    rt.profile(0)
+    st = rt.stats()
+    # the paper's form: B fixed, so only the first of these calls moves data
+    for _ in range(3):
+        rt.apply("convAB", p, [A, B], w)
+    rt.sync()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        rt.apply("convAB", p, [A, B], w)
+    rt.sync()
+    dt1 = time.perf_counter() - t1
+    st1 = rt.stats()
+    byts = 2 * 4 * n * n
+    avg_ms = kms / max(kcnt, 1)
+    ach = byts / (avg_ms * 1e-3) / 1e9
+    kname = ("k_conv1" if st["stencil_waves"] == 1 else "k_conv") + f"<{st['stencil_rows']}>"
+    return {"metric": "conv2d steps/s", "value": steps / dt, "unit": "steps/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": dt * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"conv2d: 3x3 convolution {n}x{n} fp32, 16 logical devices (4x4 blocks), "
+                                   "use = 3x3 window, def = own block, ping-pong", "n": n, "partitions": 16,
+                       "messages_per_step": st["last_messages"], "halo_bytes_per_step": st["last_bytes"]},
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": kname, "bytes_per_launch": byts,
+                         "avg_launch_us": avg_ms * 1e3},
+            "paper_form": {"steps_per_s": steps / dt1, "ms_per_step": dt1 * 1e3 / steps,
+                           "messages_last_step": st1["last_messages"]}}
 
 
 def bench_batched(hd, rt, steps, warmup):
@@ -285,7 +407,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="jacobi_large",
-                    choices=["jacobi_large", "matmul", "batched", "stencil3d", "copy_calib"])
+                    choices=["jacobi_large", "matmul", "2mm", "conv2d", "batched", "stencil3d", "copy_calib"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs the ApplyKernel path on one GPU only (the logical devices are "
@@ -299,7 +421,7 @@ def main():
     stream = torch.cuda.current_stream()
     rt = hd.Runtime(stream=stream.cuda_stream)
     if args.workload != "jacobi_large":
-        fn = {"matmul": bench_matmul, "batched": bench_batched, "stencil3d": bench_stencil3d,
+        fn = {"matmul": bench_matmul, "2mm": bench_2mm, "conv2d": bench_conv2d, "batched": bench_batched, "stencil3d": bench_stencil3d,
               "copy_calib": bench_copy_calib}[args.workload]
         out = fn(hd, rt, args.steps, args.warmup)
         rt.close()
@@ -337,6 +459,27 @@ def main():
     ph = rt.profile_read()
     rt.profile(0)
     st = rt.stats()
+    # the same steps with the plan cache on (Sec. 4.2): reported beside the
+    # headline, which derives the communication sets on every step
+    rt.set_plan_cache(True)
+    base = args.warmup + args.steps + 20
+    for i in range(10):
+        step(base + i)
+    rt.sync()
+    h0 = rt.stats()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        step(base + 10 + i)
+    rt.sync()
+    dtc = time.perf_counter() - t1
+    h1 = rt.stats()
+    rt.profile(0xF)
+    for i in range(20):
+        step(base + 10 + args.steps + i)
+    rt.sync()
+    phc = rt.profile_read()
+    rt.profile(0)
+    rt.set_plan_cache(False)
     ms_step = dt * 1e3 / args.steps
     bytes_kernel = 2 * 4 * n * n  # read B once, write A once per step
     avg_kernel_ms = kms / max(kcnt, 1)
@@ -372,6 +515,10 @@ def main():
         "phases_us": {k: (v[0] / max(v[1], 1)) * 1e3 for k, v in ph.items()},
         "pack_unpack": {"bytes": moved, "fused_pass_us": pk_ms * 1e3,
                         "GBps": 4 * moved / max(pk_ms * 1e-3, 1e-12) / 1e9},
+        "plan_cache": {"steps_per_s": args.steps / dtc, "ms_per_step": dtc * 1e3 / args.steps,
+                       "hits": h1["cache_hits"] - h0["cache_hits"],
+                       "misses": h1["cache_misses"] - h0["cache_misses"],
+                       "phases_us": {k: (v[0] / max(v[1], 1)) * 1e3 for k, v in phc.items()}},
     }
     rt.close()
     if not args.no_cpu_baseline:

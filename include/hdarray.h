@@ -89,8 +89,13 @@ typedef struct {
  * 4..256, default 64; a row needing more intervals raises HD_ECAPACITY).
  * Environment, read here: HD_SERIAL=1 runs the communication-set
  * derivation and GDEF update on the data stream instead of overlapping
- * them (a measurement aid); HD_JACOBI_ROWS=4|8|16 sets the rows per tile of
- * the Jacobi / triangular kernels of later plans (default 8).  Returns the HIP device id (>= 0) or a negative error. */
+ * them (a measurement aid); HD_JACOBI_ROWS=4|8|16 and HD_JACOBI_WAVES=1|4
+ * fix the rows per tile and waves per workgroup of the Jacobi / triangular
+ * kernels of later plans (by default the runtime times the four shapes
+ * {4, 8 rows} x {1, 4 waves} on the first calls of each work-box geometry
+ * and keeps the fastest; no shape changes a result); HD_S3D_SEG=N makes the
+ * 3-D stencil kernels march each row through N planes instead of using
+ * plane tiles.  Returns the HIP device id (>= 0) or a negative error. */
 int hdarray_init(int argc, char **argv, const char *kpath, const char *dpath);
 
 /* HDArrayExit: waits for the GPU, frees every array, plan and buffer. */
@@ -128,8 +133,13 @@ int hdarray_partition_manual(int dim, int ndev, const int64_t *lo, const int64_t
 int hdarray_partition_region(int part, int dev, int64_t *lo3, int64_t *hi3);
 
 /* Kernel table entry (replaces the frontend's file M, Sec. 4.1).  builtin is
- * one of "jacobi2d", "copy", "matmul", "tri2d", "stencil3d7".  Argument
- * order: jacobi2d/tri2d/copy/stencil3d7 (out, in), matmul (A, B, C). */
+ * one of "jacobi2d", "copy", "matmul", "tri2d", "stencil3d7", "conv2d9".
+ * Argument order: jacobi2d/tri2d/copy/stencil3d7/conv2d9 (out, in), matmul
+ * (A, B, C).  stencil3d7 takes 7 float scalars after the arrays (centre,
+ * -i, +i, -j, +j, -k, +k); conv2d9 (the 8-neighbour convolution of
+ * Sec. 5.1) takes 9: the 3 x 3 weights row by row, out[i][j] = the
+ * first-rounded product w0*in[i-1][j-1] followed by one fused multiply-add
+ * per further window cell in the same order, boundary cells copied. */
 int hdarray_register_kernel(const char *kname, const char *builtin);
 
 /* use / def offset clauses (Table 1): noff offsets, each given as 3 int32
@@ -273,8 +283,22 @@ typedef struct {
   int64_t plans_built;     /* distinct (kernel, partition, arrays) plans */
   int64_t stencil_rows;    /* tile shape of the last Jacobi / triangular launch: */
   int64_t stencil_waves;   /* rows per tile, waves per workgroup */
+  int64_t cache_hits;      /* plan-cache calls that reused a message table */
+  int64_t cache_misses;    /* plan-cache calls that derived one */
 } hd_stats_t;
 int hdarray_get_stats(hd_stats_t *st);
+
+/* Plan cache (Sec. 4.2; off by default).  With it on, an ApplyKernel call
+ * whose arrays all have the GDEF that the call's plan last derived its
+ * communication under reuses that plan's message table and runs: the
+ * derivation is skipped and only the GDEF update and the data path run.
+ * GDEF equality is decided exactly on the host: each array keeps the list
+ * of plan updates applied to it since a call that defined all of it without
+ * using it, and equal lists give equal GDEF; an array with no such call
+ * behind it (or a list longer than 8) never hits.  Each plan gets its own
+ * table and run buffers (the workspace's size) on its first cached call.
+ * Results equal those with the cache off.  HD_ESTATE before hdarray_init. */
+int hdarray_set_plan_cache(int on);
 
 /* Per-phase device timing with HIP events recorded on the stream each phase
  * runs on (opt-in; adds an event pair per timed phase and call).  enable is a

@@ -27,7 +27,7 @@ STAR = -(2 ** 31)
 F32, I32, F64 = 0, 1, 2
 ROW, COL, BLOCK = 0, 1, 2
 SUM, PROD, MAX, MIN = 0, 1, 2, 3
-K_JACOBI2D, K_COPY, K_MATMUL, K_TRI2D, K_STENCIL3D7 = 1, 2, 3, 4, 5
+K_JACOBI2D, K_COPY, K_MATMUL, K_TRI2D, K_STENCIL3D7, K_CONV2D9 = 1, 2, 3, 4, 5, 6
 EINVAL, EBOUNDS, ERACE, EKERNEL, ENOMEM, ESTATE, ECOHERENCE = -1, -2, -3, -4, -5, -7, -9
 MSG_FIELDS = ("arg", "array", "src", "dst", "lo0", "lo1", "lo2", "hi0", "hi1", "hi2", "off", "bytes")
 

@@ -428,7 +428,7 @@ int orc_part_region(orc_ctx *c, int part, int dev, int64_t *lo3, int64_t *hi3) {
 
 /* ----------------------------------------------------------------- kernels */
 int orc_kernel(orc_ctx *c, const char *name, int builtin) {
-  if (builtin < ORC_K_JACOBI2D || builtin > ORC_K_STENCIL3D7) return ORC_EKERNEL;
+  if (builtin < ORC_K_JACOBI2D || builtin > ORC_K_CONV2D9) return ORC_EKERNEL;
   for (int i = 0; i < c->nk; i++)
     if (!strcmp(c->kn[i].name, name)) return ORC_EINVAL;
   if (c->nk == c->capk) {
@@ -842,6 +842,9 @@ static int kspec(int builtin, kspec_t *s) {
     case ORC_K_STENCIL3D7:
       s->nargs = 2, s->out = 0, s->nin = 1, s->in[0] = 1, s->dim = 3, s->nscal = 7;
       return 1;
+    case ORC_K_CONV2D9:
+      s->nargs = 2, s->out = 0, s->nin = 1, s->in[0] = 1, s->dim = 2, s->nscal = 9;
+      return 1;
   }
   return 0;
 }
@@ -855,8 +858,8 @@ typedef struct {
   uint64_t bit;
   int64_t bad;
   arr_t *ain0, *ain1, *aout;
-  float cf[7];
-  double cfd[7];
+  float cf[9];
+  double cfd[9];
 } keval_t;
 
 #define RD(t, x) ((t)->h0 && !((t)->h0[(x)] & (t)->bit) ? ((t)->bad++, 0) : 0)
@@ -943,6 +946,42 @@ static void eval_s3d_cell(keval_t *t, int64_t i, int64_t j, int64_t k) {
   }
 }
 
+/* 2-D convolution with the eight neighbours of Sec. 5.1 (weights given by
+ * the caller): out[i][j] = sum over the 3 x 3 window of w[3(di+1)+(dj+1)] *
+ * in[i+di][j+dj], the window taken row by row (di = -1, 0, 1, and inside
+ * a row dj = -1, 0, 1): the first product rounded, then one fused
+ * multiply-add per further cell.  Cells on the array boundary are copied. */
+static void eval_conv_cell(keval_t *t, int64_t i, int64_t j) {
+  int64_t nr = t->aout->n[1], nc = t->aout->n[2];
+  int64_t x = i * nc + j;
+  int interior = i >= 1 && i <= nr - 2 && j >= 1 && j <= nc - 2;
+  if (!interior) {
+    RD(t, x);
+    if (t->out) memcpy(t->out + 4 * x, t->in0 + 4 * x, 4);
+    if (t->outd) t->outd[x] = t->in0d[x];
+    return;
+  }
+  for (int di = -1; di <= 1; di++)
+    for (int dj = -1; dj <= 1; dj++) RD(t, x + di * nc + dj);
+  if (t->out) {
+    float acc = 0.0f;
+    int w = 0;
+    for (int di = -1; di <= 1; di++)
+      for (int dj = -1; dj <= 1; dj++, w++) {
+        float v = ldf(t->in0, x + di * nc + dj);
+        acc = w == 0 ? t->cf[0] * v : fmaf(t->cf[w], v, acc);
+      }
+    stf(t->out, x, acc);
+  }
+  if (t->outd) {
+    double acc = 0.0;
+    int w = 0;
+    for (int di = -1; di <= 1; di++)
+      for (int dj = -1; dj <= 1; dj++, w++) acc += t->cfd[w] * t->in0d[x + di * nc + dj];
+    t->outd[x] = acc;
+  }
+}
+
 /* GEMM of Sec. 3.2 with alpha = 1, beta = 0: C[i][j] = sum_k A[i][k]*B[k][j],
  * FP32 accumulation in k order. */
 static void eval_mm_cell(keval_t *t, int64_t i, int64_t j) {
@@ -980,6 +1019,9 @@ static void eval_region(keval_t *t, int builtin, const int64_t *lo, const int64_
             break;
           case ORC_K_STENCIL3D7:
             eval_s3d_cell(t, p, r, q);
+            break;
+          case ORC_K_CONV2D9:
+            eval_conv_cell(t, r, q);
             break;
           case ORC_K_MATMUL:
             eval_mm_cell(t, r, q);
@@ -1072,6 +1114,7 @@ int orc_apply(orc_ctx *c, int k, int part, int nargs, const int *arrs, int nscal
     case ORC_K_JACOBI2D:
     case ORC_K_COPY:
     case ORC_K_STENCIL3D7:
+    case ORC_K_CONV2D9:
       if (memcmp(A[0]->n, A[1]->n, sizeof(A[0]->n)) || A[0]->esize != A[1]->esize) return ORC_EINVAL;
       if (kn->builtin != ORC_K_COPY && A[1]->type != ORC_F32) return ORC_EINVAL;
       break;
@@ -1150,7 +1193,7 @@ int orc_apply(orc_ctx *c, int k, int part, int nargs, const int *arrs, int nscal
     t.aout = ao;
     t.ain0 = A[ks.in[0]];
     t.ain1 = ks.nin > 1 ? A[ks.in[1]] : NULL;
-    for (int i = 0; i < 7 && i < nscal; i++) {
+    for (int i = 0; i < 9 && i < nscal; i++) {
       t.cf[i] = (float)scal[i];
       t.cfd[i] = (double)(float)scal[i];
     }

@@ -42,7 +42,7 @@
 enum { ORC_F32 = 0, ORC_I32 = 1, ORC_F64 = 2 };
 enum { ORC_ROW = 0, ORC_COL = 1, ORC_BLOCK = 2 };
 enum { ORC_SUM = 0, ORC_PROD = 1, ORC_MAX = 2, ORC_MIN = 3 };
-enum { ORC_K_JACOBI2D = 1, ORC_K_COPY = 2, ORC_K_MATMUL = 3, ORC_K_TRI2D = 4, ORC_K_STENCIL3D7 = 5 };
+enum { ORC_K_JACOBI2D = 1, ORC_K_COPY = 2, ORC_K_MATMUL = 3, ORC_K_TRI2D = 4, ORC_K_STENCIL3D7 = 5, ORC_K_CONV2D9 = 6 };
 
 /* one message record: 12 int64 */
 enum { ORC_MSG_ARG = 0, ORC_MSG_ARRAY, ORC_MSG_SRC, ORC_MSG_DST, ORC_MSG_LO0, ORC_MSG_LO1, ORC_MSG_LO2,

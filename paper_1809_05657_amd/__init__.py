@@ -23,9 +23,9 @@ STAR = -(2 ** 31)
 F32, I32, F64 = 0, 1, 2
 ROW, COL, BLOCK = 0, 1, 2
 SUM, PROD, MAX, MIN = 0, 1, 2, 3
-K_JACOBI2D, K_COPY, K_MATMUL, K_TRI2D, K_STENCIL3D7 = 1, 2, 3, 4, 5
+K_JACOBI2D, K_COPY, K_MATMUL, K_TRI2D, K_STENCIL3D7, K_CONV2D9 = 1, 2, 3, 4, 5, 6
 BUILTIN_NAMES = {K_JACOBI2D: "jacobi2d", K_COPY: "copy", K_MATMUL: "matmul", K_TRI2D: "tri2d",
-                 K_STENCIL3D7: "stencil3d7"}
+                 K_STENCIL3D7: "stencil3d7", K_CONV2D9: "conv2d9"}
 EINVAL, EBOUNDS, ERACE, EKERNEL, ENOMEM, EHIP, ESTATE, ECAPACITY = -1, -2, -3, -4, -5, -6, -7, -8
 MSG_FIELDS = ("arg", "array", "src", "dst", "lo0", "lo1", "lo2", "hi0", "hi1", "hi2", "off", "bytes")
 _TYPE_NAME = {F32: b"float", I32: b"int", F64: b"double"}
@@ -48,7 +48,8 @@ class _Arg(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("calls", C.c_int64), ("last_messages", C.c_int64), ("last_bytes", C.c_int64),
                 ("total_messages", C.c_int64), ("total_bytes", C.c_int64), ("plans_built", C.c_int64),
-                ("stencil_rows", C.c_int64), ("stencil_waves", C.c_int64)]
+                ("stencil_rows", C.c_int64), ("stencil_waves", C.c_int64),
+                ("cache_hits", C.c_int64), ("cache_misses", C.c_int64)]
 
 
 class Profile(C.Structure):
@@ -111,6 +112,7 @@ def load():
         "hdarray_debug_device_buffer": (C.c_int, [P, C.c_int, P]),
         "hdarray_device_ptr": (P, [P, C.c_int]),
         "hdarray_profile": (C.c_int, [C.c_int]),
+        "hdarray_set_plan_cache": (C.c_int, [C.c_int]),
         "hdarray_apply_adjoint": (C.c_int, [C.c_char_p, C.c_int, P, P, P, C.POINTER(C.c_float), P]),
         "hdarray_write_device": (C.c_int, [P, P, C.c_int]),
         "hdarray_read_device": (C.c_int, [P, P, C.c_int]),
@@ -316,6 +318,11 @@ class Runtime:
     def batch_autotune(self, ids, reps=2):
         arr = (C.c_int * len(ids))(*ids)
         return self._ck(self.L.hdarray_batch_autotune(arr, len(ids), reps), "batch_autotune")
+
+    def set_plan_cache(self, on=True):
+        """Reuse a plan's message table while its arrays' GDEF is unchanged
+        (Sec. 4.2); off by default."""
+        self._ck(self.L.hdarray_set_plan_cache(int(bool(on))), "set_plan_cache")
 
     def profile(self, enable=True):
         self._ck(self.L.hdarray_profile(int(enable)), "profile")

@@ -27,9 +27,9 @@ struct AdjArgs {
   double *part;       // [gridDim.x][8] coefficient-gradient partials
 };
 
-// tiles of the extended box W +- 1 (clipped), like the forward kernel:
-// plane tiles of kAdjRows rows, or (B.seg > 0) one wave per (row, 256
-// columns, segment of planes) marching; four waves per workgroup
+// tiles of the extended box W +- 1 (clipped), marched like the forward
+// kernel: one wave per (row, 256 columns, segment of planes), four rows per
+// workgroup
 __host__ __device__ inline void ext_box(const WorkBox &B, const int64_t *n, int *lo, int *hi) {
   for (int q = 0; q < 3; ++q) {
     lo[q] = B.lo[q] - 1 < 0 ? 0 : B.lo[q] - 1;
@@ -58,106 +58,13 @@ __device__ inline float adj_elem(const Coef7 &cf, bool pi, bool pim, bool pip, b
   return acc;
 }
 
-constexpr int kAdjRows = 2;
-
-// Plane tile of the adjoint: kAdjRows rows x 256 columns of plane i of the
-// extended box; du1 and u rows loaded at once (see dev_s3d_plane).
-__device__ inline void adj_plane(const AdjArgs &a, const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A,
-                                 double *cb) {
-  constexpr int TH = kAdjRows;
-  const int lane = threadIdx.x & 63;
-  const ArrDev &ag = A[B.ain], &ao = A[B.aout], &au = A[B.ain2];
-  int lo[3], hi[3];
-  ext_box(B, ag.n, lo, hi);
-  const int kb = lo[2] & ~3;
-  const int nk = (hi[2] - kb + 255) / 256;
-  const int nj = (hi[1] - lo[1] + TH - 1) / TH;
-  const int j0 = lo[1] + (int)(lt % nj) * TH;
-  const int64_t rest = lt / nj;
-  const int c = kb + (int)(rest % nk) * 256 + 4 * lane;
-  const int i = lo[0] + (int)(rest / nk);
-  const int j1 = min(j0 + TH, hi[1]);
-  const int N0 = (int)ag.n[0], N1 = (int)ag.n[1], N2 = (int)ag.n[2];
-  const bool vec = (N2 & 3) == 0;
-  const float *__restrict__ g1 = reinterpret_cast<const float *>(ag.buf[B.dev]);
-  const float *__restrict__ u = reinterpret_cast<const float *>(au.buf[B.dev]);
-  float *__restrict__ g0 = reinterpret_cast<float *>(ao.buf[B.dev]);
-  const Coef7 &cf = a.cf;
-  f4 gr[TH + 2], wr[TH + 2], gm[TH], gp[TH], wm[TH], wp[TH];
-  float gl[TH], grt[TH], wl[TH], wrt[TH];
-#pragma unroll
-  for (int q = 0; q < TH + 2; ++q) {
-    const int r = j0 - 1 + q;
-    const bool need = r <= j1;
-    gr[q] = need ? ld_rowv(row_ptr(g1, i, r, N0, N1, N2), c, N2, vec) : f4{0.f, 0.f, 0.f, 0.f};
-    wr[q] = need ? ld_rowv(row_ptr(u, i, r, N0, N1, N2), c, N2, vec) : f4{0.f, 0.f, 0.f, 0.f};
-    if (q >= 1 && q <= TH) {
-      const bool own = r < j1;
-      const float *grow = own ? row_ptr(g1, i, r, N0, N1, N2) : nullptr;
-      const float *wrow = own ? row_ptr(u, i, r, N0, N1, N2) : nullptr;
-      gl[q - 1] = (grow && lane == 0 && c >= 1) ? grow[c - 1] : 0.f;
-      grt[q - 1] = (grow && lane == 63 && c + 4 < N2) ? grow[c + 4] : 0.f;
-      wl[q - 1] = (wrow && lane == 0 && c >= 1) ? wrow[c - 1] : 0.f;
-      wrt[q - 1] = (wrow && lane == 63 && c + 4 < N2) ? wrow[c + 4] : 0.f;
-      gm[q - 1] = own ? ld_rowv(row_ptr(g1, i - 1, r, N0, N1, N2), c, N2, vec) : f4{0.f, 0.f, 0.f, 0.f};
-      gp[q - 1] = own ? ld_rowv(row_ptr(g1, i + 1, r, N0, N1, N2), c, N2, vec) : f4{0.f, 0.f, 0.f, 0.f};
-      wm[q - 1] = own ? ld_rowv(row_ptr(u, i - 1, r, N0, N1, N2), c, N2, vec) : f4{0.f, 0.f, 0.f, 0.f};
-      wp[q - 1] = own ? ld_rowv(row_ptr(u, i + 1, r, N0, N1, N2), c, N2, vec) : f4{0.f, 0.f, 0.f, 0.f};
-    }
-  }
-  const bool pi = adj_in(i, B.lo[0], B.hi[0], N0), pim = adj_in(i - 1, B.lo[0], B.hi[0], N0),
-             pip = adj_in(i + 1, B.lo[0], B.hi[0], N0);
-  const bool iown = i >= B.lo[0] && i < B.hi[0], iint = i >= 1 && i <= N0 - 2;
-#pragma unroll
-  for (int q = 0; q < TH; ++q) {
-    const int j = j0 + q;
-    const f4 gc = gr[q + 1], wc = wr[q + 1];
-    const float glw = __shfl_up(gc.w, 1), grx = __shfl_down(gc.x, 1);
-    const float wlw = __shfl_up(wc.w, 1), wrx = __shfl_down(wc.x, 1);
-    if (j >= j1) continue;
-    const float gkm[4] = {lane == 0 ? gl[q] : glw, gc.x, gc.y, gc.z};
-    const float gkp[4] = {gc.y, gc.z, gc.w, lane == 63 ? grt[q] : grx};
-    const float wkm[4] = {lane == 0 ? wl[q] : wlw, wc.x, wc.y, wc.z};
-    const float wkp[4] = {wc.y, wc.z, wc.w, lane == 63 ? wrt[q] : wrx};
-    const bool rj = adj_in(j, B.lo[1], B.hi[1], N1), rjm = adj_in(j - 1, B.lo[1], B.hi[1], N1),
-               rjp = adj_in(j + 1, B.lo[1], B.hi[1], N1);
-    const bool jown = j >= B.lo[1] && j < B.hi[1], jint = j >= 1 && j <= N1 - 2;
-    float *dst = g0 + ((int64_t)i * N1 + j) * N2;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int k = c + e;
-      if (k < lo[2] || k >= hi[2]) continue;
-      const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
-                 kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
-      const bool xown = iown && jown && k >= B.lo[2] && k < B.hi[2];
-      const bool xint = iint && jint && k >= 1 && k <= N2 - 2;
-      const float gx = f4at(gc, e);
-      dst[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gx, f4at(gp[q], e), f4at(gm[q], e),
-                        f4at(gr[q + 2], e), f4at(gr[q], e), gkp[e], gkm[e], xown, xint);
-      if (xown && xint) {
-        const double gy = (double)gx;
-        cb[0] += gy * (double)f4at(wc, e);
-        cb[1] += gy * (double)f4at(wm[q], e);
-        cb[2] += gy * (double)f4at(wp[q], e);
-        cb[3] += gy * (double)f4at(wr[q], e);
-        cb[4] += gy * (double)f4at(wr[q + 2], e);
-        cb[5] += gy * (double)wkm[e];
-        cb[6] += gy * (double)wkp[e];
-      }
-    }
-  }
-}
-
 __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__restrict__ A) {
   __shared__ double s_red[4][8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double cb[7] = {0, 0, 0, 0, 0, 0, 0};
   const int64_t nwg = (a.ntiles + 3) >> 2;
   const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + wv;
-  if (t < a.ntiles && a.wb[find_box(a.wb, a.nbox, t)].seg == 0) {
-    const WorkBox B = a.wb[find_box(a.wb, a.nbox, t)];
-    adj_plane(a, B, t - B.tile0, A, cb);
-  } else if (t < a.ntiles) {
+  if (t < a.ntiles) {
     const WorkBox B = a.wb[find_box(a.wb, a.nbox, t)];
     const ArrDev &ag = A[B.ain], &ao = A[B.aout], &au = A[B.ain2];
     int lo[3], hi[3];
@@ -169,7 +76,7 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
     const int j = lo[1] + (int)(lt % jrows);
     const int64_t rest = lt / jrows;
     const int c = kb + (int)(rest % nk) * 256 + 4 * lane;
-    const int seg = B.seg;
+    const int seg = seg_of(B);
     const int i0 = lo[0] + (int)(rest / nk) * seg;
     const int i1 = min(i0 + seg, hi[0]);
     const int N0 = (int)ag.n[0], N1 = (int)ag.n[1], N2 = (int)ag.n[2];
@@ -220,19 +127,10 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
         const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
                    kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
         const float gx = f4at(gcu.v, e);
-        // contributions of the outputs y = x - off_e this device owns
-        float acc = 0.f;
-        if (pi && rj && kk) acc = __builtin_fmaf(cf.c[0], gx, acc);
-        if (pip && rj && kk) acc = __builtin_fmaf(cf.c[1], f4at(gpp.v, e), acc);
-        if (pim && rj && kk) acc = __builtin_fmaf(cf.c[2], f4at(gpm, e), acc);
-        if (pi && rjp && kk) acc = __builtin_fmaf(cf.c[3], f4at(gjp, e), acc);
-        if (pi && rjm && kk) acc = __builtin_fmaf(cf.c[4], f4at(gjm, e), acc);
-        if (pi && rj && kkp) acc = __builtin_fmaf(cf.c[5], gkr[e], acc);
-        if (pi && rj && kkm) acc = __builtin_fmaf(cf.c[6], gkl[e], acc);
         const bool xown = iown && jown && k >= B.lo[2] && k < B.hi[2];
         const bool xint = iint && jint && k >= 1 && k <= N2 - 2;
-        if (xown && !xint) acc = acc + gx;
-        q[k] = acc;
+        q[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gx, f4at(gpp.v, e), f4at(gpm, e), f4at(gjp, e),
+                        f4at(gjm, e), gkr[e], gkl[e], xown, xint);
         if (xown && xint) {
           const double gy = (double)gx;
           cb[0] += gy * (double)f4at(wcu.v, e);
@@ -352,7 +250,7 @@ __global__ __launch_bounds__(256) void k_unpack_add(const MsgRec *__restrict__ M
 int64_t adj_tiles(const WorkBox &B, const int64_t *n) {
   int lo[3], hi[3];
   ext_box(B, n, lo, hi);
-  return s3d_box_tiles(lo[0], hi[0], lo[1], hi[1], lo[2], hi[2], B.seg, kAdjRows);
+  return march_tiles(lo[0], hi[0], lo[1], hi[1], lo[2], hi[2], seg_of(B));
 }
 
 hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const float *coef, double *part,

@@ -33,9 +33,13 @@ struct GdefLdsB {
   int32_t b[kBatchMaxB], u[kBatchMaxB], own[kBatchMaxB];
   uint64_t hold[kBatchMaxB];
 };
+struct HeadsLds {
+  Item p[kHeadLds], w[kHeadLds];
+};
 union WaveLds {
   RunsLds r;
   GdefLdsB g;
+  HeadsLds h;
 };
 
 // Grid barrier on a monotonically increasing counter (zeroed before the
@@ -111,7 +115,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   stamp();
   {
     const int nb = B.L1.nsl ? *B.L1.nb : 0;
-    for (int b = gw; b < nb; b += nw) dev_heads(B.L1, b);
+    for (int b = gw; b < nb; b += nw) dev_heads(B.L1, b, nb, my.h.p, my.h.w);
     dev_compact_reset(B.P, B.cs);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     stamp();
     {
       const int nb = B.L2.nsl ? *B.L2.nb : 0;
-      for (int b = gw; b < nb; b += nw) dev_heads(B.L2, b);
+      for (int b = gw; b < nb; b += nw) dev_heads(B.L2, b, nb, my.h.p, my.h.w);
       dev_compact_reset(B.P, B.cs);
     }
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;

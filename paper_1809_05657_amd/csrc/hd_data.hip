@@ -14,6 +14,8 @@ int64_t mm_tiles(const int32_t *lo, const int32_t *hi);
 hipError_t launch_mm(const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles, hipStream_t s);
 hipError_t launch_jacobi(bool tri, int th, int waves, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
                          hipStream_t s);
+hipError_t launch_conv(int th, int waves, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
+                       const float *coef, hipStream_t s);
 
 // Pack / unpack (mode 0 / 1) or both in one pass (mode 2).  Every message is
 // cut into S equal spans (S from the average message size, so that the
@@ -55,10 +57,7 @@ __global__ __launch_bounds__(256) void k_s3d(const WorkBox *__restrict__ wb, int
   const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
   if (t >= ntiles) return;
   const WorkBox B = wb[find_box(wb, nbox, t)];
-  if (B.seg > 0)
-    dev_s3d_march(B, t - B.tile0, A, cf);
-  else
-    dev_s3d_plane<kS3dRows>(B, t - B.tile0, A, cf);
+  dev_s3d_march(B, t - B.tile0, A, cf);
 }
 
 // ------------------------------------------------------- device-pointer I/O
@@ -195,6 +194,7 @@ int64_t tiles_for(int kind, const WorkBox &B, int esize, int th) {
   switch (kind) {
     case 1:
     case 5:
+    case 6:
       return jacobi_tiles(B, th);
     case 2:
       return copy_tiles(B, esize);
@@ -213,6 +213,8 @@ hipError_t launch_user(int kind, int th, int waves, const WorkBox *wb, int nbox,
     case 1:
     case 5:
       return launch_jacobi(kind == 5, th, waves, wb, nbox, A, ntiles, s);
+    case 6:
+      return launch_conv(th, waves, wb, nbox, A, ntiles, coef, s);
     case 2:
       hipLaunchKernelGGL(k_copy, dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
       break;

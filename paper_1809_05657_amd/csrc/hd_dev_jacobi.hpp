@@ -1,7 +1,8 @@
 // hd_dev_jacobi.hpp — the 2-D 5-point Jacobi / lower-triangular tile
 // (Sec. 5.1 formula: A[i][j] = (((B[i][j-1] + B[i][j+1]) + B[i-1][j]) +
 // B[i+1][j]) / 4 on interior cells, A = B on the array boundary), shared by
-// the per-call kernels (hd_jacobi.hip) and the persistent batched kernel.
+// the per-call kernels (hd_jacobi.hip) and the persistent batched kernel,
+// and the 3 x 3 convolution tile on the same tiling.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -16,10 +17,8 @@ namespace hd {
 // are numbered along a row of tiles first (consecutive waves cover
 // consecutive 1 KiB pieces of the same rows); otherwise down a column of
 // tiles first (consecutive waves share halo rows).
-template <int TH, bool TRI, bool HF = true>
-__device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
-  const int lane = threadIdx.x & 63;
-  int tx, ty;
+template <int TH, bool HF>
+__device__ inline void tile_pos(const WorkBox &B, int64_t lt, int &tx, int &ty) {
   if (HF) {
     const int ntx = (B.hi[2] - B.lo[2] + 255) / 256;
     tx = (int)(lt % ntx);
@@ -29,16 +28,15 @@ __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDe
     ty = (int)(lt % nty);
     tx = (int)(lt / nty);
   }
-  const int r0 = B.lo[1] + ty * TH;
-  const int r1 = min(r0 + TH, B.hi[1]);
-  const int c = B.lo[2] + tx * 256 + 4 * lane;
-  const ArrDev &ai = A[B.ain];
-  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
-  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
-  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
-  const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
-  f4 v[TH + 2];
-  float Lh[TH + 2], Rh[TH + 2];
+}
+
+// Rows r0-1 .. r0+TH of the lane's 4 columns (rows past r1 or outside the
+// array read as zero and are never used), with the left / right neighbour
+// column of each row.
+template <int TH>
+__device__ inline void load_rows(const float *__restrict__ in, int r0, int r1, int c, int N1, int N2, bool vec,
+                                 f4 *v, float *Lh, float *Rh) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < TH + 2; ++k) {
     const int r = r0 - 1 + k;
@@ -63,6 +61,37 @@ __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDe
     Rh[k] = lane == 63 ? rr : rx;
     v[k] = x;
   }
+}
+
+__device__ inline void store4(float *q, const float *o, const bool *wr, bool vec) {
+  if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
+    f4 ov = {o[0], o[1], o[2], o[3]};
+    __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q));
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (wr[e]) q[e] = o[e];
+  }
+}
+
+template <int TH, bool TRI, bool HF = true>
+__device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
+  const int lane = threadIdx.x & 63;
+  int tx, ty;
+  tile_pos<TH, HF>(B, lt, tx, ty);
+  const int r0 = B.lo[1] + ty * TH;
+  const int r1 = min(r0 + TH, B.hi[1]);
+  // triangular kernel: a tile entirely above the diagonal writes nothing
+  if (TRI && B.lo[2] + tx * 256 > r1 - 1) return;
+  const int c = B.lo[2] + tx * 256 + 4 * lane;
+  const ArrDev &ai = A[B.ain];
+  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
+  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
+  f4 v[TH + 2];
+  float Lh[TH + 2], Rh[TH + 2];
+  load_rows<TH>(in, r0, r1, c, N1, N2, vec, v, Lh, Rh);
 #pragma unroll
   for (int k = 1; k <= TH; ++k) {
     const int i = r0 + k - 1;
@@ -89,15 +118,62 @@ __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDe
       o[e] = interior ? s * 0.25f : cv[e + 1];
       wr[e] = write;
     }
-    float *q = out + (int64_t)i * N2 + c;
-    if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
-      f4 ov = {o[0], o[1], o[2], o[3]};
-      __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q));
-    } else {
+    store4(out + (int64_t)i * N2 + c, o, wr, vec);
+  }
+}
+
+// ------------------------------------------------------------ convolution
+// 2-D convolution with the eight neighbours (Sec. 5.1), weights w[0..8] over
+// the 3 x 3 window row by row: the first product rounded, then one fused
+// multiply-add per further cell in the same order; the array boundary is
+// copied.  Same tiles as the Jacobi kernel.
+struct Coef9 {
+  float w[9];
+};
+
+template <int TH, bool HF = true>
+__device__ inline void dev_conv_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef9 &W) {
+  const int lane = threadIdx.x & 63;
+  int tx, ty;
+  tile_pos<TH, HF>(B, lt, tx, ty);
+  const int r0 = B.lo[1] + ty * TH;
+  const int r1 = min(r0 + TH, B.hi[1]);
+  const int c = B.lo[2] + tx * 256 + 4 * lane;
+  const ArrDev &ai = A[B.ain];
+  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
+  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
+  f4 v[TH + 2];
+  float Lh[TH + 2], Rh[TH + 2];
+  load_rows<TH>(in, r0, r1, c, N1, N2, vec, v, Lh, Rh);
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (wr[e]) q[e] = o[e];
+  for (int k = 1; k <= TH; ++k) {
+    const int i = r0 + k - 1;
+    if (i >= r1) break;
+    const f4 up = v[k - 1], cu = v[k], dn = v[k + 1];
+    const float row[3][6] = {{Lh[k - 1], up.x, up.y, up.z, up.w, Rh[k - 1]},
+                             {Lh[k], cu.x, cu.y, cu.z, cu.w, Rh[k]},
+                             {Lh[k + 1], dn.x, dn.y, dn.z, dn.w, Rh[k + 1]}};
+    float o[4];
+    bool wr[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = c + e;
+      const bool interior = i >= 1 && i <= N1 - 2 && j >= 1 && j <= N2 - 2;
+      float acc = W.w[0] * row[0][e];
+      acc = __builtin_fmaf(W.w[1], row[0][e + 1], acc);
+      acc = __builtin_fmaf(W.w[2], row[0][e + 2], acc);
+      acc = __builtin_fmaf(W.w[3], row[1][e], acc);
+      acc = __builtin_fmaf(W.w[4], row[1][e + 1], acc);
+      acc = __builtin_fmaf(W.w[5], row[1][e + 2], acc);
+      acc = __builtin_fmaf(W.w[6], row[2][e], acc);
+      acc = __builtin_fmaf(W.w[7], row[2][e + 1], acc);
+      acc = __builtin_fmaf(W.w[8], row[2][e + 2], acc);
+      o[e] = interior ? acc : row[1][e + 1];
+      wr[e] = j < B.hi[2];
     }
+    store4(out + (int64_t)i * N2 + c, o, wr, vec);
   }
 }
 

@@ -172,39 +172,6 @@ __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, 
   wave_lds_sync();
 }
 
-// Slice s starts a band unless it continues slice s-1 (same group, next
-// position) with the same runs; cur / prv are the two run lists in LDS, in
-// discovery order (a function of the run set, see dev_runs_find).  Called
-// by a whole wave.
-__device__ inline bool runs_band_start(const Level &L, int s, const Run *cur, int nc, const Run *prv, int np) {
-  if (s == 0 || L.grp[s] != L.grp[s - 1] || L.pos[s] != L.pos[s - 1] + 1 || nc != np) return true;
-  const int lane = threadIdx.x & 63;
-  bool diff = false;
-  for (int k = lane; k < nc; k += 64) {
-    const Run x = cur[k], y = prv[k];
-    diff |= x.src != y.src || x.dst != y.dst || x.a0 != y.a0 || x.a1 != y.a1;
-  }
-  return __ballot(diff) != 0;
-}
-
-// Band mask of chunk c (slices 64c .. 64c+63) from one byte flag per slice,
-// by one thread (the flag array is padded to whole chunks).
-__device__ inline void dev_mask_from_flags(const Level &L, const uint8_t *flag, int c) {
-  const uint64_t *f8 = reinterpret_cast<const uint64_t *>(flag) + 8 * (int64_t)c;
-  uint64_t m = 0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint64_t v = f8[k];
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-      if ((v >> (8 * b)) & 0xffu) m |= 1ull << (8 * k + b);
-  }
-  const int valid = L.nsl - 64 * c;
-  if (valid < 64) m &= (1ull << valid) - 1ull;
-  L.bmask[c] = m;
-  L.bcnt[c] = __popcll(m);
-}
-
 // Last-workgroup election: every workgroup calls this once after its
 // results are written; returns true in the one workgroup that finishes last,
 // which then sees every other workgroup's writes.  The counter returns to 0.
@@ -230,20 +197,27 @@ __device__ inline bool last_workgroup(int32_t *done) {
 __device__ inline void dev_bandflags(const Level &L, int s) {
   bool st = false;
   if (s < L.nsl) {
-    if (s == 0 || L.grp[s] != L.grp[s - 1] || L.pos[s] != L.pos[s - 1] + 1) {
+    if (s == 0) {
       st = true;
     } else {
-      const int c = L.icnt[s];
-      if (c != L.icnt[s - 1]) {
-        st = true;
-      } else {
-        const Item *x = L.items + L.ioff[s];
-        const Item *y = L.items + L.ioff[s - 1];
-        for (int k = 0; k < c; ++k)
-          if (!item_eq(x[k], y[k])) {
-            st = true;
-            break;
+      // every index is read in one round; the item lists are compared four
+      // pairs at a time (loads issued together)
+      const int g0 = L.grp[s], g1 = L.grp[s - 1], p0 = L.pos[s], p1 = L.pos[s - 1];
+      const int c = L.icnt[s], cp = L.icnt[s - 1];
+      const Item *x = L.items + L.ioff[s];
+      const Item *y = L.items + L.ioff[s - 1];
+      st = g0 != g1 || p0 != p1 + 1 || c != cp;
+      for (int k = 0; k < c && !st; k += 4) {
+        Item xa[4], ya[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k + q < c) {
+            xa[q] = x[k + q];
+            ya[q] = y[k + q];
           }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k + q < c && !item_eq(xa[q], ya[q])) st = true;
       }
     }
   }
@@ -333,11 +307,23 @@ __device__ inline int band_of(const Level &L, int s) {
   return L.bbase[c] + __popcll(L.bmask[c] & ((1ull << (s & 63)) - 1ull));
 }
 
-// One wave per band b; lanes take the items of the band's first slice.  An
-// item not continued from the previous (adjacent) slice is a head; its
-// extent is found by walking the following bands while they hold it.  Heads
-// keep the item order and are stored at their items' positions.
-__device__ inline void dev_heads(const Level &L, int b) {
+// One wave per band b (nb bands); lanes take the items of the band's first
+// slice.  An item not continued from the previous (adjacent) slice is a
+// head; its extent is found by walking the following bands while their
+// first slice holds it: the wave walks all its heads together, band by
+// band, reading each band's items once into LDS (sp: the previous slice,
+// sw: the band being walked; kHeadLds items each, larger lists are searched
+// in global memory).  Heads keep the item order and are stored at their
+// items' positions.
+constexpr int kHeadLds = 128;
+
+__device__ inline void lds_items(Item *dst, const Item *src, int cnt) {
+  const int lane = threadIdx.x & 63;
+  if (cnt <= kHeadLds)
+    for (int k = lane; k < cnt; k += 64) dst[k] = src[k];
+}
+
+__device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *sw) {
   const int lane = threadIdx.x & 63;
   const int s0 = L.bandslice[b], s1 = L.bandslice[b + 1];
   const bool adj = s0 > 0 && L.grp[s0 - 1] == L.grp[s0] && L.pos[s0 - 1] + 1 == L.pos[s0];
@@ -347,6 +333,8 @@ __device__ inline void dev_heads(const Level &L, int b) {
   const Item *prv = adj ? L.items + L.ioff[s0 - 1] : nullptr;
   const int pc = adj ? L.icnt[s0 - 1] : 0;
   const int p0 = L.pos[s0];
+  lds_items(sp, prv, pc);
+  wave_lds_sync();
   int nh = 0;
   int64_t vol = 0;
   for (int base = 0; base < cc; base += 64) {
@@ -355,14 +343,27 @@ __device__ inline void dev_heads(const Level &L, int b) {
     bool head = false;
     if (k < cc) {
       it = cur[k];
-      head = !(adj && contains(prv, pc, it));
+      head = !(adj && (pc <= kHeadLds ? contains(sp, pc, it) : contains(prv, pc, it)));
     }
     const uint64_t m = __ballot(head);
+    int e = s1;
+    bool go = head;
+    for (int bb = b + 1; __ballot(go) != 0ull; ++bb) {
+      const int t0 = bb < nb ? L.bandslice[bb] : L.nsl;
+      if (!(bb < nb && t0 < L.nsl && L.grp[t0] == L.grp[t0 - 1] && L.pos[t0] == L.pos[t0 - 1] + 1)) break;
+      const int tc = L.icnt[t0];
+      const Item *ti = L.items + L.ioff[t0];
+      wave_lds_sync();
+      lds_items(sw, ti, tc);
+      wave_lds_sync();
+      if (go) {
+        if (tc <= kHeadLds ? contains(sw, tc, it) : contains(ti, tc, it))
+          e = L.bandslice[bb + 1];
+        else
+          go = false;
+      }
+    }
     if (head) {
-      int e = s1;
-      while (e < L.nsl && L.grp[e] == L.grp[e - 1] && L.pos[e] == L.pos[e - 1] + 1 &&
-             contains(L.items + L.ioff[e], L.icnt[e], it))
-        e = L.bandslice[band_of(L, e) + 1];
       it.pos0 = p0;
       it.pos1 = L.pos[e - 1] + 1;
       L.heads[off + nh + __popcll(m & lanemask_lt())] = it;
@@ -370,6 +371,7 @@ __device__ inline void dev_heads(const Level &L, int b) {
     }
     nh += __popcll(m);
   }
+  wave_lds_sync();
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) vol += __shfl_xor(vol, d);
   if (lane == 0) {

@@ -14,45 +14,31 @@ namespace hd {
 
 constexpr int kGdefMaxB = 1024;
 
-// One wave per use row: the runs of the row, sorted, into the row's slot,
-// and its band-start flag: the wave also finds the runs of the row before
-// (when it is the adjacent row of the same plane) and compares the lists,
-// so no later pass has to read the stored runs back.
+// One wave per use row: the runs of the row, sorted, into the row's slot.
 template <int CAP>
-__global__ __launch_bounds__(64) void k_runs(PlanDev P, const ArrDev *__restrict__ A, Work W, Level L,
-                                             uint8_t *flag) {
+__global__ __launch_bounds__(64) void k_runs(PlanDev P, const ArrDev *__restrict__ A, Work W) {
   __shared__ Ivl s_iv[CAP];
-  __shared__ Run s_run[kMaxRunsRow], s_prv[kMaxRunsRow];
+  __shared__ Run s_run[kMaxRunsRow];
   const int s = blockIdx.x;
   if (s >= P.nsl1) return;
-  int np = 0;
-  const bool adj = s > 0 && L.grp[s] == L.grp[s - 1] && L.pos[s] == L.pos[s - 1] + 1;
-  if (adj) np = dev_runs_find(P, A, W, s - 1, s_iv, s_prv);
   const int nr = dev_runs_find(P, A, W, s, s_iv, s_run);
-  const bool st = runs_band_start(L, s, s_run, nr, s_prv, np);
-  if (threadIdx.x == 0) flag[s] = st ? 1 : 0;
   dev_runs_store(P, W, s, s_run, nr);
 }
 
 // One wave per 64 slices: band-start flags from the stored items -> chunk
-// masks (second stacking level).
+// masks.
 __global__ __launch_bounds__(64) void k_bandflags(Level L) { dev_bandflags(L, blockIdx.x * 64 + threadIdx.x); }
 
-// One wave: exclusive scan of the band counts, band -> first slice.
-__global__ __launch_bounds__(64) void k_bandscan(Level L) { dev_bandscan(L); }
-
-// One wave: chunk masks from the flags k_runs wrote, then the band scan.
-__global__ __launch_bounds__(64) void k_flags_scan(Level L, const uint8_t *flag) {
-  const int nch = (L.nsl + 63) / 64;
-  for (int c = threadIdx.x; c < nch; c += 64) dev_mask_from_flags(L, flag, c);
-  __syncthreads();
-  dev_bandscan(L);
-}
+// One workgroup (one wave for small levels): exclusive scan of the band
+// counts, band -> first slice.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_bandscan(Level L) { dev_bandscan(L); }
 
 // Heads of every band, one wave per band.
 __global__ __launch_bounds__(64) void k_heads(Level L) {
+  __shared__ Item s_p[kHeadLds], s_w[kHeadLds];
   const int nb = *L.nb;
-  for (int b = blockIdx.x; b < nb; b += gridDim.x) dev_heads(L, b);
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) dev_heads(L, b, nb, s_p, s_w);
 }
 
 // One wave: the message table (or the level-2 items).
@@ -117,29 +103,33 @@ static void launch_heads(const Level &L, hipStream_t s) {
   hipLaunchKernelGGL(k_heads, dim3(hg), dim3(64), 0, s, L);
 }
 
-// level 1: runs + band flags, band scan, heads, compaction (mode 0: the
+static void launch_bands(const Level &L, hipStream_t s) {
+  hipLaunchKernelGGL(k_bandflags, dim3(cdiv(L.nsl, 64)), dim3(64), 0, s, L);
+  if (L.nsl <= 8192)
+    hipLaunchKernelGGL(k_bandscan<64>, dim3(1), dim3(64), 0, s, L);
+  else
+    hipLaunchKernelGGL(k_bandscan<1024>, dim3(1), dim3(1024), 0, s, L);
+  launch_heads(L, s);
+}
+
+// level 1: runs, band flags, band scan, heads, compaction (mode 0: the
 // final messages; mode 1: the level-2 items of 3-D arrays)
-hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, uint8_t *flag,
-                         MsgRec *out, MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s) {
+hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, MsgRec *out,
+                         MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s) {
   if (P.nsl1 == 0) return launch_compact(P, L, W, out, hdr, cap, mode, s);
   // LDS for the row's intervals sized to the row capacity
   if (row_cap <= 64)
-    hipLaunchKernelGGL(k_runs<64>, dim3(P.nsl1), dim3(64), 0, s, P, A, W, L, flag);
+    hipLaunchKernelGGL(k_runs<64>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
   else
-    hipLaunchKernelGGL(k_runs<kMaxCap>, dim3(P.nsl1), dim3(64), 0, s, P, A, W, L, flag);
-  hipLaunchKernelGGL(k_flags_scan, dim3(1), dim3(64), 0, s, L, flag);
-  launch_heads(L, s);
+    hipLaunchKernelGGL(k_runs<kMaxCap>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
+  launch_bands(L, s);
   return launch_compact(P, L, W, out, hdr, cap, mode, s);
 }
 
 // level 2 (rectangles of consecutive planes stacked into boxes)
 hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
                          hipStream_t s) {
-  if (L.nsl > 0) {
-    hipLaunchKernelGGL(k_bandflags, dim3(cdiv(L.nsl, 64)), dim3(64), 0, s, L);
-    hipLaunchKernelGGL(k_bandscan, dim3(1), dim3(64), 0, s, L);
-    launch_heads(L, s);
-  }
+  if (L.nsl > 0) launch_bands(L, s);
   return launch_compact(P, L, W, out, hdr, cap, 2, s);
 }
 

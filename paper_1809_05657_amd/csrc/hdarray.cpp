@@ -26,8 +26,8 @@ namespace hd {
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr, int64_t cap,
                           int mode, hipStream_t s);
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
-hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, uint8_t *flag,
-                         MsgRec *out, MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s);
+hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, MsgRec *out,
+                         MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s);
 hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
                          hipStream_t s);
 hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
@@ -72,6 +72,12 @@ struct hd_array {
   Ivl *ivl;
   int32_t *cnt;
   int cap;
+  // GDEF history since the last call that defined the whole array (no use
+  // of it in that call): (plan id, call-array) pairs; empty + hist_ok false
+  // when unknown.  Equal histories mean equal GDEF (the update is a
+  // deterministic function of the state before and the plan).
+  std::vector<uint64_t> hist;
+  bool hist_ok = false;
 };
 
 struct Partition {
@@ -81,7 +87,7 @@ struct Partition {
 
 struct Kernel {
   std::string name;
-  int builtin;  // 1 jacobi2d, 2 copy, 3 stencil3d7, 4 matmul, 5 tri2d
+  int builtin;  // 1 jacobi2d, 2 copy, 3 stencil3d7, 4 matmul, 5 tri2d, 6 conv2d9
   int noff[8][2];
   int32_t off[8][2][64][3];
   std::map<std::tuple<int, int, int, int>, std::vector<Shape>> abs;  // (part, arr, dev, uod)
@@ -105,6 +111,21 @@ struct Plan {
   // tile0 counts rows (in the third box slot, unused by those plans)
   int xn = -1;
   int64_t xrows = 0;
+  // plan cache (Sec. 4.2): per call-array the array id and whether the call
+  // defines the whole array without using it; the plan's own message table
+  // and runs, and the GDEF histories they were derived under
+  uint64_t uid = 0;
+  bool apply = false;
+  std::vector<int> ca_arr;
+  std::vector<char> ca_full;
+  int64_t pcap = 0;
+  MsgRec *ptab = nullptr;
+  MsgHdr *phdr = nullptr;
+  Item *pruns = nullptr;
+  int32_t *proff = nullptr, *prcnt = nullptr;
+  hipEvent_t ev_ready = nullptr, ev_used = nullptr;
+  bool used_pending = false, have = false;
+  std::vector<uint64_t> last_key;
   // adjoint plans: extended-box tiles and coefficient partials
   bool adjoint = false;
   double *part = nullptr;
@@ -157,7 +178,6 @@ struct Runtime {
   int32_t *bcnt = nullptr, *bbase = nullptr, *bandslice = nullptr, *hoff = nullptr, *hcnt = nullptr;
   int64_t *hbytes = nullptr, *bofs = nullptr;
   int32_t *bcarr = nullptr, *nofs = nullptr;
-  uint8_t *bflag = nullptr;  // band-start flag per level-1 slice (whole 64-slice chunks)
   Item *heads = nullptr;
   int32_t *counters = nullptr;  // [0] run_top [1] head_top [2] nb [3] err
   int64_t *cscratch = nullptr;  // compaction scratch of the batched kernel
@@ -166,6 +186,10 @@ struct Runtime {
   hipEvent_t ev_cs[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
   bool free_pending[2] = {false, false};
   int parity = 0, last_tab = -1;
+  MsgRec *last_ptab = nullptr;  // plan-owned table of the last call (plan cache on)
+  MsgHdr *last_phdr = nullptr;
+  bool plan_cache = false;
+  uint64_t next_uid = 1;
   char *staging = nullptr;
   int64_t staging_cap = 0;
   double *red_pf = nullptr;
@@ -324,12 +348,14 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
 
 static void free_ws();
 static void free_batches();
+static void free_plan_buffers(Plan *pl);
 
 extern "C" void hdarray_exit(void) {
   if (!R.inited) return;
   (void)hipStreamSynchronize(R.meta);
   (void)hipStreamSynchronize(R.data);
   for (auto &kv : R.plans) {
+    free_plan_buffers(kv.second);
     dfree(kv.second->mem);
     dfree(kv.second->part);
     delete kv.second;
@@ -622,6 +648,8 @@ extern "C" int hdarray_register_kernel(const char *kname, const char *builtin) {
     b = 4;
   else if (!strcmp(builtin, "tri2d"))
     b = 5;
+  else if (!strcmp(builtin, "conv2d9"))
+    b = 6;
   else
     return fail(HD_EKERNEL);
   if (R.kidx.count(kname)) return fail(HD_EINVAL);
@@ -810,8 +838,6 @@ static void free_ws() {
   dfree(R.nofs);
   R.hbytes = R.bofs = nullptr;
   R.bcarr = R.nofs = nullptr;
-  dfree(R.bflag);
-  R.bflag = nullptr;
   dfree(R.heads);
   dfree(R.W.ovf_list);
   R.W.ovf_list = nullptr;
@@ -866,7 +892,6 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
     R.bofs = (int64_t *)dalloc(8 * ns);
     R.bcarr = (int32_t *)dalloc(4 * ns);
     R.nofs = (int32_t *)dalloc(4 * ns);
-    R.bflag = (uint8_t *)dalloc((ns / 64 + 2) * 64);
     R.heads = (Item *)dalloc(sizeof(Item) * it);
     R.W.ovf_list = (int32_t *)dalloc(4 * ns);
     for (int k = 0; k < 2; ++k) {
@@ -875,7 +900,7 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
       if (R.hdr[k]) HIPCK(hipMemset(R.hdr[k], 0, sizeof(MsgHdr)));
     }
     if (!R.W.roff || !R.W.rcnt || !R.W.runs || !R.W.goff || !R.W.gcnt || !R.W.l1out || !R.bmask || !R.bcnt ||
-        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hbytes || !R.bofs || !R.bcarr || !R.nofs || !R.bflag || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
+        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hbytes || !R.bofs || !R.bcarr || !R.nofs || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
         !R.hdr[1])
       return fail(HD_ENOMEM);
     HIPCK(hipMemset(R.W.roff, 0, 4 * ns));
@@ -909,6 +934,9 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   std::vector<GRowRec> grec;
   PlanDev &P = pl->P;
   memset(&P, 0, sizeof(P));
+  pl->ca_arr.clear();
+  pl->ca_full.clear();
+  pl->uid = R.next_uid++;
   P.ncarr = (int)cas.size();
   int64_t stg = 0;
   int has3d = 0;
@@ -979,6 +1007,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
     C.grp1 = (int32_t)grp_aidx.size();
     stg += 16;
     // GDEF rows: rows with use or def spans
+    const size_t grec0 = grec.size();
     size_t a_i = 0, b_i = 0;
     while (a_i < slice_of_row.size() || b_i < ds.size()) {
       const int64_t ra = a_i < slice_of_row.size() ? slice_of_row[a_i].first : INT64_MAX;
@@ -1013,6 +1042,12 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
       g.full = full ? 1 : 0;
       grec.push_back(g);
     }
+    // a call that defines every row of the array whole and does not use it
+    // leaves a GDEF that does not depend on the one before (plan cache)
+    int64_t nfull = 0;
+    for (size_t q = grec0; q < grec.size(); ++q) nfull += grec[q].full;
+    pl->ca_arr.push_back(a->id);
+    pl->ca_full.push_back(C.slice1 == C.slice0 && nfull == a->n[0] * a->n[1] ? 1 : 0);
   }
   P.has3d = has3d;
   P.nsl1 = (int32_t)grow1.size();
@@ -1125,6 +1160,12 @@ struct PhaseTimer {
   }
 };
 
+extern "C" int hdarray_set_plan_cache(int on) {
+  if (!R.inited) return fail(HD_ESTATE);
+  R.plan_cache = on != 0;
+  return HD_OK;
+}
+
 extern "C" int hdarray_profile(int enable) {
   R.prof = enable;
   return HD_OK;
@@ -1201,7 +1242,133 @@ static void stencil_shape(Plan *pl, int &th, int &waves, hipEvent_t &e0, hipEven
   waves = kTuneCand[c][1];
 }
 
+// ------------------------------------------------------------ plan cache
+// Sec. 4.2: when the GDEF of every array of a call is the one the plan's
+// last derivation saw, the communication sets are the same, so the plan's
+// message table and runs are reused and only the GDEF update runs.  GDEF
+// equality is decided on the host, exactly: each array keeps the list of
+// (plan, call-array) updates since a call that defined all of it without
+// using it; equal lists give equal GDEF.
+static std::vector<uint64_t> plan_key(const Plan *pl) {
+  std::vector<uint64_t> k;
+  for (int id : pl->ca_arr) {
+    const hd_array *a = R.arrays[id];
+    if (!a || !a->hist_ok) return {};
+    k.insert(k.end(), a->hist.begin(), a->hist.end());
+    k.push_back(~0ull);
+  }
+  return k;
+}
+
+static void advance_hist(const Plan *pl) {
+  for (size_t j = 0; j < pl->ca_arr.size(); ++j) {
+    hd_array *a = R.arrays[pl->ca_arr[j]];
+    const uint64_t tag = (pl->uid << 10) | j;
+    if (pl->ca_full[j]) {
+      a->hist.assign(1, tag);
+      a->hist_ok = true;
+    } else if (a->hist_ok) {
+      if (a->hist.size() >= 8) {
+        a->hist.clear();
+        a->hist_ok = false;
+      } else {
+        a->hist.push_back(tag);
+      }
+    }
+  }
+}
+
+// the plan's own table, runs and events (allocated on its first cached call)
+static int plan_buffers(Plan *pl) {
+  if (pl->ptab) return HD_OK;
+  pl->pcap = R.ws_items;
+  pl->ptab = (MsgRec *)dalloc(sizeof(MsgRec) * pl->pcap);
+  pl->phdr = (MsgHdr *)dalloc(sizeof(MsgHdr));
+  pl->pruns = (Item *)dalloc(sizeof(Item) * pl->pcap);
+  pl->proff = (int32_t *)dalloc(4 * ((int64_t)pl->nsl1 + 1));
+  pl->prcnt = (int32_t *)dalloc(4 * ((int64_t)pl->nsl1 + 1));
+  if (!pl->ptab || !pl->phdr || !pl->pruns || !pl->proff || !pl->prcnt) return fail(HD_ENOMEM);
+  HIPCK(hipMemset(pl->phdr, 0, sizeof(MsgHdr)));
+  HIPCK(hipEventCreateWithFlags(&pl->ev_ready, hipEventDisableTiming));
+  HIPCK(hipEventCreateWithFlags(&pl->ev_used, hipEventDisableTiming));
+  return HD_OK;
+}
+
+static void free_plan_buffers(Plan *pl) {
+  dfree(pl->ptab);
+  dfree(pl->phdr);
+  dfree(pl->pruns);
+  dfree(pl->proff);
+  dfree(pl->prcnt);
+  if (pl->ev_ready) (void)hipEventDestroy(pl->ev_ready);
+  if (pl->ev_used) (void)hipEventDestroy(pl->ev_used);
+  pl->ptab = nullptr;
+  pl->phdr = nullptr;
+  pl->pruns = nullptr;
+  pl->proff = pl->prcnt = nullptr;
+  pl->ev_ready = pl->ev_used = nullptr;
+}
+
+static int enqueue_user(Plan *pl, const float *coef);
+
+// A plain call with the plan cache on: derivation (on a miss) into the
+// plan's own buffers, GDEF update from the plan's runs, pack from the
+// plan's table.
+static int enqueue_cached(Plan *pl, const float *coef) {
+  const hipStream_t meta = R.serial ? R.data : R.meta;
+  if (plan_buffers(pl) != HD_OK) return g_last_error;
+  const std::vector<uint64_t> key = plan_key(pl);
+  const bool hit = pl->have && !key.empty() && key == pl->last_key;
+  const PlanDev &P = pl->P;
+  Work W = R.W;
+  W.runs = pl->pruns;
+  W.roff = pl->proff;
+  W.rcnt = pl->prcnt;
+  W.run_cap = pl->pcap;
+  {
+    PhaseTimer tm(0, meta);
+    if (!hit) {
+      // the data stream must be done with the table of this plan's last call
+      if (pl->used_pending) HIPCK(hipStreamWaitEvent(meta, pl->ev_used, 0));
+      Level L1 = make_level(1, P);
+      L1.ioff = W.roff;
+      L1.icnt = W.rcnt;
+      L1.items = W.runs;
+      HIPCK(launch_level1(P, R.d_arrs, W, L1, pl->ptab, pl->phdr, pl->pcap, pl->has3d ? 1 : 0, R.row_cap, meta));
+      if (pl->has3d) {
+        Level L2 = make_level(2, P);
+        HIPCK(launch_level2(P, W, L2, pl->ptab, pl->phdr, pl->pcap, meta));
+      }
+      HIPCK(hipEventRecord(pl->ev_ready, meta));
+      R.stats.cache_misses++;
+    } else {
+      R.stats.cache_hits++;
+    }
+    HIPCK(launch_gdef(P, R.d_arrs, W, meta));
+  }
+  pl->last_key = key;
+  pl->have = !key.empty();
+  advance_hist(pl);
+  HIPCK(hipStreamWaitEvent(R.data, pl->ev_ready, 0));
+  {
+    PhaseTimer tm(1, R.data);
+    HIPCK(launch_pack(pl->ptab, pl->phdr, R.d_arrs, (uint32_t *)R.staging, pl->stg_bound / 4 + 1, 2, R.data));
+  }
+  HIPCK(hipEventRecord(pl->ev_used, R.data));
+  pl->used_pending = true;
+  R.last_ptab = pl->ptab;
+  R.last_phdr = pl->phdr;
+  R.last_tab = -1;
+  R.last_batch = -1;
+  return enqueue_user(pl, coef);
+}
+
 static int enqueue(Plan *pl, const float *coef) {
+  if (pl->apply && !pl->adjoint && R.plan_cache) return enqueue_cached(pl, coef);
+  // every plan's GDEF update is a function of the plan and the GDEF before it
+  advance_hist(pl);
+  R.last_ptab = nullptr;
+  R.last_phdr = nullptr;
   const hipStream_t meta = R.serial ? R.data : R.meta;
   const int slot = R.parity;
   R.parity ^= 1;
@@ -1214,8 +1381,8 @@ static int enqueue(Plan *pl, const float *coef) {
   // first, so its use-region messages are exactly {(owner(x) -> d, x)}
   if (pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
   Level L1 = make_level(1, P);
-  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.bflag, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0,
-                      R.row_cap, meta));
+  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0, R.row_cap,
+                      meta));
   if (pl->has3d) {
     Level L2 = make_level(2, P);
     HIPCK(launch_level2(P, W, L2, R.tab[slot], R.hdr[slot], R.ws_items, meta));
@@ -1248,7 +1415,12 @@ static int enqueue(Plan *pl, const float *coef) {
   R.free_pending[slot] = true;
   R.last_tab = slot;
   R.last_batch = -1;
-  if (pl->ukind == 1 || pl->ukind == 5) {
+  return enqueue_user(pl, coef);
+}
+
+// the user kernel of a call, on the data stream
+static int enqueue_user(Plan *pl, const float *coef) {
+  if (pl->ukind == 1 || pl->ukind == 5 || pl->ukind == 6) {
     int th = 8, waves = 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     stencil_shape(pl, th, waves, e0, e1);
@@ -1285,6 +1457,9 @@ static bool kspec(int b, KSpec &s) {
       return true;
     case 4:
       s = KSpec{3, 2, 2, {0, 1}, 2, 0};
+      return true;
+    case 6:
+      s = KSpec{2, 0, 1, {1, 0}, 2, 9};
       return true;
   }
   return false;
@@ -1338,6 +1513,7 @@ static int user_kind(int builtin) {
     case 3: return 3;
     case 4: return 4;
     case 5: return 5;
+    case 6: return 6;
   }
   return 0;
 }
@@ -1434,6 +1610,7 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
     case 1:
     case 2:
     case 3:
+    case 6:
       if (memcmp(A[0]->n, A[1]->n, sizeof(A[0]->n)) || A[0]->esize != A[1]->esize) return fail(HD_EINVAL);
       if (k->builtin != 2 && A[1]->type != 0) return fail(HD_EINVAL);
       break;
@@ -1449,8 +1626,8 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
   for (int d = 0; d < pt.ndev; ++d)
     for (int j = 0; j < 3; ++j)
       if (pt.hi[d][j] > ao->n[j]) return fail(HD_EBOUNDS);
-  float coef[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int e = 0; e < 7 && e < (int)sc.size(); ++e) coef[e] = (float)sc[e];
+  float coef[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int e = 0; e < 9 && e < (int)sc.size(); ++e) coef[e] = (float)sc[e];
   if (R.recording) {
     if (k->builtin != 1 && k->builtin != 2 && k->builtin != 5) return fail(HD_EINVAL);
     RecCall rc;
@@ -1476,8 +1653,9 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
       return g_last_error;
     }
     pl->ukind = user_kind(k->builtin);
+    pl->apply = true;
     pl->nbox = (int)wb.size();
-    if (pl->ukind == 1 || pl->ukind == 5) {
+    if (pl->ukind == 1 || pl->ukind == 5 || pl->ukind == 6) {
       // one set of work boxes per tile height (tile offsets differ)
       const int ths[3] = {4, 8, 16};
       for (int q = 0; q < 3; ++q) {
@@ -1634,6 +1812,7 @@ extern "C" int hdarray_write(hd_array_t *ah, const void *uA, int part) {
   // communication (the plan has no use rows)
   pl->ukind = 0;
   HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, R.meta));
+  advance_hist(pl);
   return HD_OK;
 }
 
@@ -1835,6 +2014,9 @@ static void last_table(MsgRec **tab, MsgHdr **hdr) {
   if (R.last_batch >= 0 && R.last_batch < (int)R.batches.size()) {
     *tab = R.batches[R.last_batch]->tab;
     *hdr = R.batches[R.last_batch]->hdr;
+  } else if (R.last_ptab) {
+    *tab = R.last_ptab;
+    *hdr = R.last_phdr;
   } else if (R.last_tab >= 0) {
     *tab = R.tab[R.last_tab];
     *hdr = R.hdr[R.last_tab];
@@ -1968,6 +2150,9 @@ extern "C" int hdarray_batch_run(int id) {
   }
   HIPCK(hipEventRecord(R.ev_data, R.data));
   HIPCK(hipStreamWaitEvent(R.meta, R.ev_data, 0));
+  advance_hist(&b->pl);
+  R.last_ptab = nullptr;
+  R.last_phdr = nullptr;
   R.last_batch = id;
   R.stats.calls++;
   return HD_OK;
@@ -2138,6 +2323,7 @@ extern "C" int hdarray_write_device(hd_array_t *ah, const void *dptr, int part) 
   // every device's region in one launch (rows of the regions, in device order)
   HIPCK(launch_ext_copy(pl->wbj[2], pl->xn, pl->xrows, R.d_arrs, a->id, const_cast<void *>(dptr), 0, R.data));
   HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, R.meta));
+  advance_hist(pl);
   return HD_OK;
 }
 

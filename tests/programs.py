@@ -2,11 +2,11 @@
 runtime (both expose create / partition / kernel / set_offsets /
 set_absolute / set_trapezoid / apply / write / read / reduce / messages /
 pack / gdef with the same meaning).  Builtin ids: 1 jacobi2d, 2 copy,
-3 matmul, 4 tri2d, 5 stencil3d7; kinds: 0 ROW, 1 COL, 2 BLOCK."""
+3 matmul, 4 tri2d, 5 stencil3d7, 6 conv2d9; kinds: 0 ROW, 1 COL, 2 BLOCK."""
 import numpy as np
 
 ROW, COL, BLOCK = 0, 1, 2
-K_JACOBI2D, K_COPY, K_MATMUL, K_TRI2D, K_STENCIL3D7 = 1, 2, 3, 4, 5
+K_JACOBI2D, K_COPY, K_MATMUL, K_TRI2D, K_STENCIL3D7, K_CONV2D9 = 1, 2, 3, 4, 5, 6
 S3D_OFFSETS = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
 J2D_OFFSETS = [(0, 0), (0, -1), (0, 1), (-1, 0), (1, 0)]
 
@@ -127,3 +127,40 @@ def batched_arrays(api, inst, seed=4):
         api.write(B, B0, p)
         out.append((A, B, p, m["kind"]))
     return out
+
+
+def mm2(api, a0, b0, c0, P, layout=ROW):
+    """Sec. 5.1 2MM: D = A x B, then E = C x D, both with the GEMM clauses
+    use(X,(0,*)) use(Y,(*,0)) def(Z,(0,0)); ROW or COL partitions of the
+    n x n work region (the partition argument is the only change)."""
+    n = a0.shape[0]
+    A, B, Cm = api.create(a0), api.create(b0), api.create(c0)
+    D, E = api.create(shape=(n, n)), api.create(shape=(n, n))
+    p = api.partition(layout, (n, n), ndev=P)
+    for k in ("mm1", "mm2"):
+        api.kernel(k, K_MATMUL)
+        api.set_offsets(k, 0, 0, [(0, "*")])
+        api.set_offsets(k, 1, 0, [("*", 0)])
+        api.set_offsets(k, 2, 1, [(0, 0)])
+    for X, x0 in ((A, a0), (B, b0), (Cm, c0)):
+        api.write(X, x0, p)
+    return A, B, Cm, D, E, p
+
+
+CONV_OFFSETS = [(di, dj) for di in (-1, 0, 1) for dj in (-1, 0, 1)]
+
+
+def conv2d(api, f0, ndev=16, kind=BLOCK):
+    """Sec. 5.1 Convolution: 3 x 3 window (the eight neighbours and the
+    centre) as use offsets, def = own block; convAB reads B into A, convBA
+    reads A into B."""
+    n0, n1 = f0.shape
+    A, B = api.create(np.zeros_like(f0)), api.create(f0)
+    p = api.partition(kind, (n0, n1), ndev=ndev)
+    for k in ("convAB", "convBA"):
+        api.kernel(k, K_CONV2D9)
+        api.set_offsets(k, 1, 0, CONV_OFFSETS)
+        api.set_offsets(k, 0, 1, [(0, 0)])
+    api.write(A, np.zeros_like(f0), p)
+    api.write(B, f0, p)
+    return A, B, p

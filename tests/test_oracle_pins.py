@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 from tests import canon
-from workloads import S3D_COEFFS, jacobi_inputs
+from workloads import CONV9_WEIGHTS, S3D_COEFFS, jacobi_inputs
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -440,6 +440,83 @@ def test_stencil3d_closed_forms():
     f = np.full((n, n, n), 3.5, np.float32)
     _, u, _, _ = _s3d_once(f, cexact)
     assert np.array_equal(u, f)
+
+
+CONV_OFFSETS = [(di, dj) for di in (-1, 0, 1) for dj in (-1, 0, 1)]
+
+
+def _conv_once(f, w, ndev=4, kind=None):
+    o = O.Oracle()
+    n0, n1 = f.shape
+    A, B = o.create(np.zeros_like(f)), o.create(f)
+    p = o.partition(O.BLOCK if kind is None else kind, f.shape, ndev=ndev)
+    o.kernel("conv", O.K_CONV2D9)
+    o.set_offsets("conv", 1, 0, CONV_OFFSETS)
+    o.set_offsets("conv", 0, 1, [(0, 0)])
+    o.write(A, np.zeros_like(f), p)
+    o.write(B, f, p)
+    o.apply("conv", p, [A, B], [float(x) for x in w])
+    ms = o.messages()
+    assert o.bad_reads() == 0
+    return o, o.read(A, p), o.truth64(A), ms, (A, B, p)
+
+
+def test_conv2d_closed_forms():
+    """3 x 3 convolution (the eight-neighbour kernel of Sec. 5.1): a unit
+    impulse reproduces the weights at the mirrored window positions exactly
+    (catches a transposed or mirrored window and a dropped term); a linear
+    field along each axis gives sum(w) f + (far-side minus near-side weights)
+    in FP64; dyadic weights summing to one keep a constant field exactly;
+    boundary cells are copied; a 2 x 2 block grid exchanges 8 strips and
+    4 corner cells."""
+    w = [float(x) for x in CONV9_WEIGHTS]
+    n = 14
+    f = np.zeros((n, n), np.float32)
+    r, c = 6, 7
+    f[r, c] = 1.0
+    _, u, _, ms, _ = _conv_once(f, w)
+    want = np.zeros_like(f)
+    for k, (di, dj) in enumerate(CONV_OFFSETS):
+        want[r - di, c - dj] = np.float32(w[k])
+    want[0, :], want[-1, :], want[:, 0], want[:, -1] = f[0, :], f[-1, :], f[:, 0], f[:, -1]
+    assert np.array_equal(u, want)
+    # 2 x 2 blocks: each device receives two strips and one corner cell
+    assert len(ms) == 8 + 4
+    assert sorted(int(m[11]) for m in ms)[:4] == [4, 4, 4, 4]
+    w64 = np.array(CONV9_WEIGHTS, dtype=np.float64).reshape(3, 3)
+    ii = np.indices((n, n)).astype(np.float64)
+    for axis in (0, 1):
+        g = ii[axis] + 1.0
+        _, _, u64, _, _ = _conv_once(g.astype(np.float32), w)
+        lo, hi = (w64[0, :].sum(), w64[2, :].sum()) if axis == 0 else (w64[:, 0].sum(), w64[:, 2].sum())
+        want = g.copy()
+        want[1:-1, 1:-1] = (w64.sum() * g + (hi - lo))[1:-1, 1:-1]
+        assert np.allclose(u64, want, rtol=0, atol=1e-12)
+    dy = [1 / 16, 1 / 8, 1 / 16, 1 / 8, 1 / 4, 1 / 8, 1 / 16, 1 / 8, 1 / 16]
+    f = np.full((n, 11), 2.75, np.float32)
+    _, u, _, _, _ = _conv_once(f, dy, ndev=3, kind=O.ROW)
+    assert np.array_equal(u, f)
+
+
+def test_conv2d_fp32_within_bound_and_comm_once():
+    """FP32 run vs the FP64 run within the error bound of a 9-term
+    multiply-add chain; repeated calls with the input never redefined move
+    their halo once (Table 3's Convolution row)."""
+    w = [float(x) for x in CONV9_WEIGHTS]
+    rng = np.random.default_rng(21)
+    f = rng.random((40, 37), dtype=np.float32)
+    o, u, u64, ms, (A, B, p) = _conv_once(f, w, ndev=6)
+    aw = np.abs(np.array(CONV9_WEIGHTS, dtype=np.float64))
+    mag = np.zeros_like(u64)
+    fa = np.abs(f.astype(np.float64))
+    for k, (di, dj) in enumerate(CONV_OFFSETS):
+        mag[1:-1, 1:-1] += aw[k] * fa[1 + di:f.shape[0] - 1 + di, 1 + dj:f.shape[1] - 1 + dj]
+    gamma = 9 * 2.0 ** -24 / (1 - 9 * 2.0 ** -24)
+    assert np.all(np.abs(u - u64) <= gamma * mag)
+    assert len(ms) > 0
+    for _ in range(2):
+        o.apply("conv", p, [A, B], w)
+        assert len(o.messages()) == 0
 
 
 def test_s3d_adjoint_fp64_dot_product_and_fd():

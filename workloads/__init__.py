@@ -30,6 +30,11 @@ STENCIL3D = dict(name="stencil3d", n=512, n_small=32, ndev=8, T=64, ckpt=8, seed
 # adjoint shows up as an error.
 S3D_COEFFS = np.array([0.28, 0.06, 0.14, 0.09, 0.11, 0.07, 0.13], dtype=np.float32)
 
+# 3 x 3 convolution weights (row by row over the window), rounded to fp32;
+# no two are equal and the sum is 0.95 < 1, so a transposed or mirrored
+# window and a dropped term all change the result.
+CONV9_WEIGHTS = np.array([0.03, 0.12, 0.05, 0.10, 0.31, 0.08, 0.06, 0.11, 0.09], dtype=np.float32)
+
 
 def uniform01(shape, rng):
     """U[0,1) fp32 (multiples of 2^-24, no subnormals)."""
