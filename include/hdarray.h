@@ -89,13 +89,14 @@ typedef struct {
  * 4..256, default 64; a row needing more intervals raises HD_ECAPACITY).
  * Environment, read here: HD_SERIAL=1 runs the communication-set
  * derivation and GDEF update on the data stream instead of overlapping
- * them (a measurement aid); HD_JACOBI_ROWS=4|8|16 and HD_JACOBI_WAVES=1|4
- * fix the rows per tile and waves per workgroup of the Jacobi / triangular
- * kernels of later plans (by default the runtime times the four shapes
- * {4, 8 rows} x {1, 4 waves} on the first calls of each work-box geometry
- * and keeps the fastest; no shape changes a result); HD_S3D_SEG=N makes the
- * 3-D stencil kernels march each row through N planes instead of using
- * plane tiles.  Returns the HIP device id (>= 0) or a negative error. */
+ * them (a measurement aid); HD_JACOBI_ROWS=4|8|16|32|64, HD_JACOBI_WAVES=1|4
+ * and HD_JACOBI_ORDER=0|1 fix the tile shape of the 2-D stencil kernels as
+ * hdarray_set_stencil_shape does; HD_S3D_SEG=N sets the number of planes
+ * each row of the 3-D stencil kernels marches through (default 32);
+ * HD_EVENT_SCOPE=system makes the runtime's inter-stream events use HIP's
+ * default system-scope release instead of a device-scope one (a
+ * measurement aid).  Returns the HIP device id (>= 0) or a negative
+ * error. */
 int hdarray_init(int argc, char **argv, const char *kpath, const char *dpath);
 
 /* HDArrayExit: waits for the GPU, frees every array, plan and buffer. */
@@ -285,8 +286,21 @@ typedef struct {
   int64_t stencil_waves;   /* rows per tile, waves per workgroup */
   int64_t cache_hits;      /* plan-cache calls that reused a message table */
   int64_t cache_misses;    /* plan-cache calls that derived one */
+  int64_t stencil_order;   /* tile order of the last stencil launch (1 along rows, 0 down columns) */
 } hd_stats_t;
 int hdarray_get_stats(hd_stats_t *st);
+
+/* Tile shape of the 2-D stencil kernels (jacobi2d, tri2d, conv2d9) for
+ * later calls: rows = 4, 8 or 16 rows per tile with waves = 1 (one wave per
+ * workgroup) or 4 (four tiles of the same rows per workgroup); order = 1:
+ * consecutive tiles of an XCD run along a row of tiles, 0: down a column of
+ * tiles (one-wave shapes only; four waves always run along rows).  rows =
+ * 32 or 64 selects tall strips of that many rows, one wave each, streaming
+ * through an 8-row register window (waves and order ignored).  (0, 0, any)
+ * restores the default: the runtime times candidate shapes on the first
+ * calls of each work-box geometry and keeps the fastest.  No shape changes
+ * a result.  HD_EINVAL for other values, HD_ESTATE before init. */
+int hdarray_set_stencil_shape(int rows, int waves, int order);
 
 /* Plan cache (Sec. 4.2; off by default).  With it on, an ApplyKernel call
  * whose arrays all have the GDEF that the call's plan last derived its

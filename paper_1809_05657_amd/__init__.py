@@ -49,7 +49,7 @@ class Stats(C.Structure):
     _fields_ = [("calls", C.c_int64), ("last_messages", C.c_int64), ("last_bytes", C.c_int64),
                 ("total_messages", C.c_int64), ("total_bytes", C.c_int64), ("plans_built", C.c_int64),
                 ("stencil_rows", C.c_int64), ("stencil_waves", C.c_int64),
-                ("cache_hits", C.c_int64), ("cache_misses", C.c_int64)]
+                ("cache_hits", C.c_int64), ("cache_misses", C.c_int64), ("stencil_order", C.c_int64)]
 
 
 class Profile(C.Structure):
@@ -113,6 +113,7 @@ def load():
         "hdarray_device_ptr": (P, [P, C.c_int]),
         "hdarray_profile": (C.c_int, [C.c_int]),
         "hdarray_set_plan_cache": (C.c_int, [C.c_int]),
+        "hdarray_set_stencil_shape": (C.c_int, [C.c_int, C.c_int, C.c_int]),
         "hdarray_apply_adjoint": (C.c_int, [C.c_char_p, C.c_int, P, P, P, C.POINTER(C.c_float), P]),
         "hdarray_write_device": (C.c_int, [P, P, C.c_int]),
         "hdarray_read_device": (C.c_int, [P, P, C.c_int]),
@@ -318,6 +319,12 @@ class Runtime:
     def batch_autotune(self, ids, reps=2):
         arr = (C.c_int * len(ids))(*ids)
         return self._ck(self.L.hdarray_batch_autotune(arr, len(ids), reps), "batch_autotune")
+
+    def set_stencil_shape(self, rows=0, waves=0, order=1):
+        """Fix the 2-D stencil tile shape (rows 4/8/16 with waves 1/4 and
+        tile order 1 along rows / 0 down columns, or strips of 32/64 rows);
+        (0, 0) restores timing-based selection."""
+        self._ck(self.L.hdarray_set_stencil_shape(int(rows), int(waves), int(order)), "set_stencil_shape")
 
     def set_plan_cache(self, on=True):
         """Reuse a plan's message table while its arrays' GDEF is unchanged

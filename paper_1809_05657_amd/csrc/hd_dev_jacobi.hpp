@@ -30,37 +30,41 @@ __device__ inline void tile_pos(const WorkBox &B, int64_t lt, int &tx, int &ty) 
   }
 }
 
+// One row of the lane's 4 columns with its left / right neighbour column
+// (zero when the row is outside the array or past rlim; such rows are never
+// used).  Called by whole waves (the neighbours come from adjacent lanes).
+__device__ inline void load_row(const float *__restrict__ in, int r, int rlim, int c, int N1, int N2, bool vec,
+                                f4 &v, float &Lh, float &Rh) {
+  const int lane = threadIdx.x & 63;
+  f4 x = {0.f, 0.f, 0.f, 0.f};
+  float l = 0.f, rr = 0.f;
+  if (r >= 0 && r < N1 && r <= rlim) {
+    const float *p = in + (int64_t)r * N2;
+    if (vec && c + 4 <= N2) {
+      x = *reinterpret_cast<const f4 *>(p + c);
+    } else {
+      if (c < N2) x.x = p[c];
+      if (c + 1 < N2) x.y = p[c + 1];
+      if (c + 2 < N2) x.z = p[c + 2];
+      if (c + 3 < N2) x.w = p[c + 3];
+    }
+    if (lane == 0 && c >= 1 && c - 1 < N2) l = p[c - 1];
+    if (lane == 63 && c + 4 < N2) rr = p[c + 4];
+  }
+  const float lw = __shfl_up(x.w, 1);
+  const float rx = __shfl_down(x.x, 1);
+  Lh = lane == 0 ? l : lw;
+  Rh = lane == 63 ? rr : rx;
+  v = x;
+}
+
 // Rows r0-1 .. r0+TH of the lane's 4 columns (rows past r1 or outside the
-// array read as zero and are never used), with the left / right neighbour
-// column of each row.
+// array read as zero and are never used).
 template <int TH>
 __device__ inline void load_rows(const float *__restrict__ in, int r0, int r1, int c, int N1, int N2, bool vec,
                                  f4 *v, float *Lh, float *Rh) {
-  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int k = 0; k < TH + 2; ++k) {
-    const int r = r0 - 1 + k;
-    f4 x = {0.f, 0.f, 0.f, 0.f};
-    float l = 0.f, rr = 0.f;
-    if (r >= 0 && r < N1 && r <= r1) {
-      const float *p = in + (int64_t)r * N2;
-      if (vec && c + 4 <= N2) {
-        x = *reinterpret_cast<const f4 *>(p + c);
-      } else {
-        if (c < N2) x.x = p[c];
-        if (c + 1 < N2) x.y = p[c + 1];
-        if (c + 2 < N2) x.z = p[c + 2];
-        if (c + 3 < N2) x.w = p[c + 3];
-      }
-      if (lane == 0 && c >= 1 && c - 1 < N2) l = p[c - 1];
-      if (lane == 63 && c + 4 < N2) rr = p[c + 4];
-    }
-    const float lw = __shfl_up(x.w, 1);
-    const float rx = __shfl_down(x.x, 1);
-    Lh[k] = lane == 0 ? l : lw;
-    Rh[k] = lane == 63 ? rr : rx;
-    v[k] = x;
-  }
+  for (int k = 0; k < TH + 2; ++k) load_row(in, r0 - 1 + k, r1, c, N1, N2, vec, v[k], Lh[k], Rh[k]);
 }
 
 __device__ inline void store4(float *q, const float *o, const bool *wr, bool vec) {
@@ -174,6 +178,108 @@ __device__ inline void dev_conv_tile(const WorkBox &B, int64_t lt, const ArrDev 
       wr[e] = j < B.hi[2];
     }
     store4(out + (int64_t)i * N2 + c, o, wr, vec);
+  }
+}
+
+// ---------------------------------------------------------------- strips
+// Tall strips (TS rows x 256 columns, one wave): the rows stream through a
+// register window in chunks of C rows, the next chunk's loads issued before
+// the current chunk is computed, so each input row is read once per strip
+// (plus two halo rows per strip) with a small register footprint.
+// OP: 0 Jacobi, 1 lower-triangular Jacobi, 2 3 x 3 convolution (weights W).
+template <int OP>
+__device__ inline void strip_row(int i, int c, int N1, int N2, const WorkBox &B, const f4 &up, const f4 &cu,
+                                 const f4 &dn, float Lu, float Ru, float Lc, float Rc, float Ld, float Rd,
+                                 const Coef9 &W, float *__restrict__ out, bool vec) {
+  float o[4];
+  bool wr[4];
+  const float cv[6] = {Lc, cu.x, cu.y, cu.z, cu.w, Rc};
+  if (OP == 2) {
+    const float uv[6] = {Lu, up.x, up.y, up.z, up.w, Ru};
+    const float dv[6] = {Ld, dn.x, dn.y, dn.z, dn.w, Rd};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = c + e;
+      const bool interior = i >= 1 && i <= N1 - 2 && j >= 1 && j <= N2 - 2;
+      float acc = W.w[0] * uv[e];
+      acc = __builtin_fmaf(W.w[1], uv[e + 1], acc);
+      acc = __builtin_fmaf(W.w[2], uv[e + 2], acc);
+      acc = __builtin_fmaf(W.w[3], cv[e], acc);
+      acc = __builtin_fmaf(W.w[4], cv[e + 1], acc);
+      acc = __builtin_fmaf(W.w[5], cv[e + 2], acc);
+      acc = __builtin_fmaf(W.w[6], dv[e], acc);
+      acc = __builtin_fmaf(W.w[7], dv[e + 1], acc);
+      acc = __builtin_fmaf(W.w[8], dv[e + 2], acc);
+      o[e] = interior ? acc : cv[e + 1];
+      wr[e] = j < B.hi[2];
+    }
+  } else {
+    const float uv[4] = {up.x, up.y, up.z, up.w};
+    const float dv[4] = {dn.x, dn.y, dn.z, dn.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = c + e;
+      bool interior, write = j < B.hi[2];
+      if (OP == 1) {
+        write = write && j <= i;
+        interior = j >= 1 && j < i && i <= N1 - 2;
+      } else {
+        interior = i >= 1 && i <= N1 - 2 && j >= 1 && j <= N2 - 2;
+      }
+      float s = cv[e] + cv[e + 2];
+      s = s + uv[e];
+      s = s + dv[e];
+      o[e] = interior ? s * 0.25f : cv[e + 1];
+      wr[e] = write;
+    }
+  }
+  store4(out + (int64_t)i * N2 + c, o, wr, vec);
+}
+
+template <int TS, int C, int OP, bool HF>
+__device__ inline void dev_strip(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef9 &W) {
+  const int lane = threadIdx.x & 63;
+  int tx, ty;
+  tile_pos<TS, HF>(B, lt, tx, ty);
+  const int r0 = B.lo[1] + ty * TS;
+  const int r1 = min(r0 + TS, B.hi[1]);
+  if (OP == 1 && B.lo[2] + tx * 256 > r1 - 1) return;
+  const int c = B.lo[2] + tx * 256 + 4 * lane;
+  const ArrDev &ai = A[B.ain];
+  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
+  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
+  // window: rows base-1 .. base+C
+  f4 v[C + 2];
+  float L[C + 2], R[C + 2];
+  load_rows<C>(in, r0, r1, c, N1, N2, vec, v, L, R);
+  for (int base = r0; base < r1; base += C) {
+    f4 nv[C];
+    float nL[C], nR[C];
+    if (base + C < r1) {
+#pragma unroll
+      for (int k = 0; k < C; ++k) load_row(in, base + C + 1 + k, r1, c, N1, N2, vec, nv[k], nL[k], nR[k]);
+    }
+#pragma unroll
+    for (int k = 1; k <= C; ++k) {
+      const int i = base + k - 1;
+      if (i >= r1) break;
+      strip_row<OP>(i, c, N1, N2, B, v[k - 1], v[k], v[k + 1], L[k - 1], R[k - 1], L[k], R[k], L[k + 1], R[k + 1], W,
+                    out, vec);
+    }
+    v[0] = v[C];
+    v[1] = v[C + 1];
+    L[0] = L[C];
+    L[1] = L[C + 1];
+    R[0] = R[C];
+    R[1] = R[C + 1];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      v[k + 2] = nv[k];
+      L[k + 2] = nL[k];
+      R[k + 2] = nR[k];
+    }
   }
 }
 

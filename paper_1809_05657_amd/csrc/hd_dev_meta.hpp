@@ -47,6 +47,9 @@ __device__ inline void wave_lds_sync() {
 
 __device__ inline void set_err(int32_t *err, int code) { atomicCAS(err, 0, code); }
 
+// Value of v in lane l (l the same in every lane).
+__device__ inline int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
 __device__ inline bool item_eq(const Item &x, const Item &y) {
   return x.src == y.src && x.dst == y.dst && x.a0 == y.a0 && x.a1 == y.a1 && x.b0 == y.b0 && x.b1 == y.b1;
 }
@@ -86,40 +89,49 @@ __device__ inline int dev_runs_find(const PlanDev &P, const ArrDev *__restrict__
   const Ivl *row = a.ivl + sr.grow * (int64_t)a.cap;
   const int W2 = (int)a.n[2];
   // the first 64 intervals are read together with the count (the row's
-  // capacity bounds the read)
+  // capacity bounds the read) and with the first 64 use segments (one per
+  // lane, read back with lane reads)
   Ivl v0{};
   if (lane < a.cap) v0 = row[lane];
+  Seg mine{0, 0, 0, 0};
+  if (lane < sr.nseg) mine = P.useg[sr.seg0 + lane];
   const int n = a.cnt[sr.grow];
   if (lane < n) iv[lane] = v0;
   for (int i = 64 + lane; i < n; i += 64) iv[i] = row[i];
   wave_lds_sync();
   int nr = 0;
-  const int sg1 = sr.seg0 + sr.nseg;
-  for (int sg = sr.seg0; sg < sg1; ++sg) {
-    const Seg S = P.useg[sg];
-    const uint64_t bit = 1ull << S.dst;
-    auto need = [&](int i) -> bool {
-      const int st = iv[i].start, en = (i + 1 < n) ? iv[i + 1].start : W2;
-      return max(st, S.c0) < min(en, S.c1) && !(iv[i].holders & bit);
-    };
-    for (int base = 0; base < n; base += 64) {
-      const int i = base + lane;
-      bool start = false;
-      int src = 0;
-      if (i < n) {
-        src = iv[i].owner;
-        start = need(i) && !(i > 0 && iv[i - 1].owner == src && need(i - 1));
+  for (int sb = 0; sb < sr.nseg; sb += 64) {
+    if (sb > 0) {
+      mine = Seg{0, 0, 0, 0};
+      if (sb + lane < sr.nseg) mine = P.useg[sr.seg0 + sb + lane];
+    }
+    const int sn = min(64, sr.nseg - sb);
+    for (int q = 0; q < sn; ++q) {
+      const int sdst = lane_read(mine.dst, q), sc0 = lane_read(mine.c0, q), sc1 = lane_read(mine.c1, q);
+      const uint64_t bit = 1ull << sdst;
+      auto need = [&](int i) -> bool {
+        const int st = iv[i].start, en = (i + 1 < n) ? iv[i + 1].start : W2;
+        return max(st, sc0) < min(en, sc1) && !(iv[i].holders & bit);
+      };
+      for (int base = 0; base < n; base += 64) {
+        const int i = base + lane;
+        bool start = false;
+        int src = 0;
+        if (i < n) {
+          src = iv[i].owner;
+          start = need(i) && !(i > 0 && iv[i - 1].owner == src && need(i - 1));
+        }
+        const uint64_t m = __ballot(start);
+        if (start) {
+          int j = i + 1;
+          while (j < n && iv[j].owner == src && need(j)) ++j;
+          const int c0 = max(iv[i].start, sc0);
+          const int c1 = min((j < n) ? iv[j].start : W2, sc1);
+          const int k = nr + __popcll(m & lanemask_lt());
+          if (k < kMaxRunsRow) rr[k] = Run{src, sdst, c0, c1};
+        }
+        nr += __popcll(m);
       }
-      const uint64_t m = __ballot(start);
-      if (start) {
-        int j = i + 1;
-        while (j < n && iv[j].owner == src && need(j)) ++j;
-        const int c0 = max(iv[i].start, S.c0);
-        const int c1 = min((j < n) ? iv[j].start : W2, S.c1);
-        const int k = nr + __popcll(m & lanemask_lt());
-        if (k < kMaxRunsRow) rr[k] = Run{src, S.dst, c0, c1};
-      }
-      nr += __popcll(m);
     }
   }
   if (nr > kMaxRunsRow) {
@@ -333,6 +345,20 @@ __device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *
   const Item *prv = adj ? L.items + L.ioff[s0 - 1] : nullptr;
   const int pc = adj ? L.icnt[s0 - 1] : 0;
   const int p0 = L.pos[s0];
+  // the next 64 bands, one per lane: does the band continue the slice before
+  // it (same group, next position), its first slice's item count and
+  // offset, and the slice after it; read back with lane reads in the walk
+  const int bl = b + 1 + lane;
+  int n_cont = 0, n_tc = 0, n_to = 0, n_end = L.nsl;
+  if (bl < nb) {
+    const int t0 = L.bandslice[bl];
+    n_end = L.bandslice[bl + 1];
+    if (t0 < L.nsl) {
+      n_cont = L.grp[t0] == L.grp[t0 - 1] && L.pos[t0] == L.pos[t0 - 1] + 1;
+      n_tc = L.icnt[t0];
+      n_to = L.ioff[t0];
+    }
+  }
   lds_items(sp, prv, pc);
   wave_lds_sync();
   int nh = 0;
@@ -349,16 +375,28 @@ __device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *
     int e = s1;
     bool go = head;
     for (int bb = b + 1; __ballot(go) != 0ull; ++bb) {
-      const int t0 = bb < nb ? L.bandslice[bb] : L.nsl;
-      if (!(bb < nb && t0 < L.nsl && L.grp[t0] == L.grp[t0 - 1] && L.pos[t0] == L.pos[t0 - 1] + 1)) break;
-      const int tc = L.icnt[t0];
-      const Item *ti = L.items + L.ioff[t0];
+      const int q = bb - b - 1;
+      int cont, tc, toff, tend;
+      if (q < 64) {
+        cont = lane_read(n_cont, q);
+        tc = lane_read(n_tc, q);
+        toff = lane_read(n_to, q);
+        tend = lane_read(n_end, q);
+      } else {
+        const int t0 = bb < nb ? L.bandslice[bb] : L.nsl;
+        cont = bb < nb && t0 < L.nsl && L.grp[t0] == L.grp[t0 - 1] && L.pos[t0] == L.pos[t0 - 1] + 1;
+        tc = cont ? L.icnt[t0] : 0;
+        toff = cont ? L.ioff[t0] : 0;
+        tend = cont ? L.bandslice[bb + 1] : L.nsl;
+      }
+      if (!cont) break;
+      const Item *ti = L.items + toff;
       wave_lds_sync();
       lds_items(sw, ti, tc);
       wave_lds_sync();
       if (go) {
         if (tc <= kHeadLds ? contains(sw, tc, it) : contains(ti, tc, it))
-          e = L.bandslice[bb + 1];
+          e = tend;
         else
           go = false;
       }
@@ -709,8 +747,15 @@ __device__ inline void dev_compact_p3(const PlanDev &P, const Level &L, const Wo
 // the wave: iv[kMaxCap], b[maxb], u[maxb], own[maxb], hold[maxb].
 // State of the elementary segment starting at x: old interval (lanes 0..n-1
 // hold the old list), then holder additions, then definitions.
-__device__ inline void gdef_state(int x, int n, int st, int ow, uint64_t ho, const Item *runs, int nrun,
-                                  const Seg *ds, int nds, int &own, uint64_t &hol) {
+// Runs and definitions of the row sit one per lane (lane e: run e, def e);
+// the loops read them with lane reads, so no global load is serialised.
+struct RowEdits {
+  int nrun, ra0, ra1, rdst;
+  int nds, dc0, dc1, ddst, dfl;
+};
+
+__device__ inline void gdef_state(int x, int n, int st, int ow, uint64_t ho, const RowEdits &E, int &own,
+                                  uint64_t &hol) {
   // last interval with start <= x (old starts in lanes 0..n-1, start[0] = 0);
   // binary lifting with every lane active at every shuffle
   int lo = 0;
@@ -722,15 +767,15 @@ __device__ inline void gdef_state(int x, int n, int st, int ow, uint64_t ho, con
   }
   own = __shfl(ow, lo);
   hol = __shfl(ho, lo);
-  for (int e = 0; e < nrun; ++e) {
-    const Item r = runs[e];
-    if (r.a0 <= x && x < r.a1) hol |= 1ull << r.dst;
+  for (int e = 0; e < E.nrun; ++e) {
+    const int a0 = lane_read(E.ra0, e), a1 = lane_read(E.ra1, e), d = lane_read(E.rdst, e);
+    if (a0 <= x && x < a1) hol |= 1ull << d;
   }
-  for (int e = 0; e < nds; ++e) {
-    const Seg d = ds[e];
-    if (d.c0 <= x && x < d.c1) {
-      own = d.dst;
-      hol = (1ull << d.dst) | ((d.flags & 1) ? (1ull << kHost) : 0ull);
+  for (int e = 0; e < E.nds; ++e) {
+    const int c0 = lane_read(E.dc0, e), c1 = lane_read(E.dc1, e), d = lane_read(E.ddst, e);
+    if (c0 <= x && x < c1) {
+      own = d;
+      hol = (1ull << d) | ((lane_read(E.dfl, e) & 1) ? (1ull << kHost) : 0ull);
     }
   }
 }
@@ -778,34 +823,53 @@ __device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ 
     ow = v.owner;
     ho = v.holders;
   }
+  // edits one per lane
+  RowEdits E{nrun, 0, 0, 0, nds, 0, 0, 0, 0};
+  if (lane < nrun) {
+    const Item r = runs[lane];
+    E.ra0 = r.a0;
+    E.ra1 = r.a1;
+    E.rdst = r.dst;
+  }
+  if (lane < nds) {
+    const Seg d = ds[lane];
+    E.dc0 = d.c0;
+    E.dc1 = d.c1;
+    E.ddst = d.dst;
+    E.dfl = d.flags;
+  }
+  // boundaries: old starts, then run ends, then definition ends (an end at
+  // the row's width is the wrap to 0, already a start)
+  // (every lane takes part in the shuffles; the source lanes are in range)
+  const int er = ((lane - n) >> 1) & 63, ed = ((lane - n - 2 * nrun) >> 1) & 63;
+  const int a0 = __shfl(E.ra0, er), a1 = __shfl(E.ra1, er);
+  const int c0 = __shfl(E.dc0, ed), c1 = __shfl(E.dc1, ed);
   int b = 0x7fffffff;
   if (lane < n) {
     b = st;
   } else if (lane < n + 2 * nrun) {
-    const Item r = runs[(lane - n) >> 1];
-    b = ((lane - n) & 1) ? (r.a1 < W2 ? r.a1 : 0) : r.a0;
+    b = ((lane - n) & 1) ? (a1 < W2 ? a1 : 0) : a0;
   } else if (lane < nb) {
-    const Seg d = ds[(lane - n - 2 * nrun) >> 1];
-    b = ((lane - n - 2 * nrun) & 1) ? (d.c1 < W2 ? d.c1 : 0) : d.c0;
+    b = ((lane - n - 2 * nrun) & 1) ? (c1 < W2 ? c1 : 0) : c0;
   }
   // first occurrence of each value, and its predecessor value
   bool first = lane < nb;
   int pv = -1;
   for (int j = 0; j < nb; ++j) {
-    const int y = __shfl(b, j);
+    const int y = lane_read(b, j);
     if (j < lane && y == b) first = false;
     if (y < b && y > pv) pv = y;
   }
   int own = 0, pown = 0;
   uint64_t hol = 0, phol = 0;
   // both calls are made by every lane (they contain shuffles)
-  gdef_state(first ? b : 0, n, st, ow, ho, runs, nrun, ds, nds, own, hol);
-  gdef_state(pv < 0 ? 0 : pv, n, st, ow, ho, runs, nrun, ds, nds, pown, phol);
+  gdef_state(first ? b : 0, n, st, ow, ho, E, own, hol);
+  gdef_state(pv < 0 ? 0 : pv, n, st, ow, ho, E, pown, phol);
   const bool keep = first && (pv < 0 || own != pown || hol != phol);
   int idx = 0;
   for (int j = 0; j < nb; ++j) {
-    const int y = __shfl(b, j);
-    const int kj = __shfl((int)keep, j);
+    const int y = lane_read(b, j);
+    const int kj = lane_read((int)keep, j);
     if (kj && y < b) ++idx;
   }
   const int nn = __popcll(__ballot(keep));

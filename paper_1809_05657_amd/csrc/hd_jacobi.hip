@@ -21,27 +21,53 @@ __global__ __launch_bounds__(256) void k_jacobi(const WorkBox *__restrict__ wb, 
   dev_jacobi_tile<TH, TRI, true>(B, t - B.tile0, A);
 }
 
-// One wave per workgroup; the tiles of an XCD walk down columns of tiles.
-template <int TH, bool TRI>
+// One wave per workgroup; the tiles of an XCD walk along rows of tiles (HF)
+// or down columns of tiles.
+template <int TH, bool TRI, bool HF>
 __global__ __launch_bounds__(64) void k_jacobi1(const WorkBox *__restrict__ wb, int nbox,
                                                 const ArrDev *__restrict__ A, int64_t ntiles) {
   const int64_t t = xcd_remap(blockIdx.x, ntiles);
   const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_jacobi_tile<TH, TRI, false>(B, t - B.tile0, A);
+  dev_jacobi_tile<TH, TRI, HF>(B, t - B.tile0, A);
 }
 
-hipError_t launch_jacobi(bool tri, int th, int waves, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
-                         hipStream_t s) {
+// Tall strips (32 or 64 rows, one wave each) streaming through a register
+// window of 8 rows; the strips of an XCD walk down columns.
+template <int TS, int OP>
+__global__ __launch_bounds__(64) void k_strip(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
+                                              int64_t ntiles, Coef9 w) {
+  const int64_t t = xcd_remap(blockIdx.x, ntiles);
+  const WorkBox B = wb[find_box(wb, nbox, t)];
+  dev_strip<TS, 8, OP, false>(B, t - B.tile0, A, w);
+}
+
+static hipError_t launch_strip(int op, int th, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
+                               const Coef9 &w, hipStream_t s) {
+  typedef void (*sk_t)(const WorkBox *, int, const ArrDev *, int64_t, Coef9);
+  sk_t k = th == 64 ? (op == 0 ? k_strip<64, 0> : op == 1 ? k_strip<64, 1> : k_strip<64, 2>)
+                    : (op == 0 ? k_strip<32, 0> : op == 1 ? k_strip<32, 1> : k_strip<32, 2>);
+  hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(64), 0, s, wb, nbox, A, ntiles, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi(bool tri, int th, int waves, int order, const WorkBox *wb, int nbox, const ArrDev *A,
+                         int64_t ntiles, hipStream_t s) {
   typedef void (*jk_t)(const WorkBox *, int, const ArrDev *, int64_t);
+  if (th >= 32) return launch_strip(tri ? 1 : 0, th, wb, nbox, A, ntiles, Coef9{}, s);
   if (waves == 4) {
     jk_t k = tri ? k_jacobi<8, true> : k_jacobi<8, false>;
     if (th == 4) k = tri ? k_jacobi<4, true> : k_jacobi<4, false>;
     if (th == 16) k = tri ? k_jacobi<16, true> : k_jacobi<16, false>;
     hipLaunchKernelGGL(k, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles);
+  } else if (order) {
+    jk_t k = tri ? k_jacobi1<8, true, true> : k_jacobi1<8, false, true>;
+    if (th == 4) k = tri ? k_jacobi1<4, true, true> : k_jacobi1<4, false, true>;
+    if (th == 16) k = tri ? k_jacobi1<16, true, true> : k_jacobi1<16, false, true>;
+    hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
   } else {
-    jk_t k = tri ? k_jacobi1<8, true> : k_jacobi1<8, false>;
-    if (th == 4) k = tri ? k_jacobi1<4, true> : k_jacobi1<4, false>;
-    if (th == 16) k = tri ? k_jacobi1<16, true> : k_jacobi1<16, false>;
+    jk_t k = tri ? k_jacobi1<8, true, false> : k_jacobi1<8, false, false>;
+    if (th == 4) k = tri ? k_jacobi1<4, true, false> : k_jacobi1<4, false, false>;
+    if (th == 16) k = tri ? k_jacobi1<16, true, false> : k_jacobi1<16, false, false>;
     hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
   }
   return hipGetLastError();
@@ -58,24 +84,28 @@ __global__ __launch_bounds__(256) void k_conv(const WorkBox *__restrict__ wb, in
   dev_conv_tile<TH, true>(B, t - B.tile0, A, w);
 }
 
-template <int TH>
+template <int TH, bool HF>
 __global__ __launch_bounds__(64) void k_conv1(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
                                               int64_t ntiles, Coef9 w) {
   const int64_t t = xcd_remap(blockIdx.x, ntiles);
   const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_conv_tile<TH, false>(B, t - B.tile0, A, w);
+  dev_conv_tile<TH, HF>(B, t - B.tile0, A, w);
 }
 
-hipError_t launch_conv(int th, int waves, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
+hipError_t launch_conv(int th, int waves, int order, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
                        const float *coef, hipStream_t s) {
   typedef void (*ck_t)(const WorkBox *, int, const ArrDev *, int64_t, Coef9);
   Coef9 w;
   for (int e = 0; e < 9; ++e) w.w[e] = coef ? coef[e] : 0.f;
+  if (th >= 32) return launch_strip(2, th, wb, nbox, A, ntiles, w, s);
   if (waves == 4) {
     ck_t k = th == 4 ? k_conv<4> : th == 16 ? k_conv<16> : k_conv<8>;
     hipLaunchKernelGGL(k, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles, w);
+  } else if (order) {
+    ck_t k = th == 4 ? k_conv1<4, true> : th == 16 ? k_conv1<16, true> : k_conv1<8, true>;
+    hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(64), 0, s, wb, nbox, A, ntiles, w);
   } else {
-    ck_t k = th == 4 ? k_conv1<4> : th == 16 ? k_conv1<16> : k_conv1<8>;
+    ck_t k = th == 4 ? k_conv1<4, false> : th == 16 ? k_conv1<16, false> : k_conv1<8, false>;
     hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(64), 0, s, wb, nbox, A, ntiles, w);
   }
   return hipGetLastError();

@@ -55,24 +55,28 @@ __global__ __launch_bounds__(1024) void k_compact_wg(PlanDev P, Level L, Work W,
 }
 
 // Rows with at most 64 boundaries are updated register-only, one wave each;
-// larger rows are listed for k_gdef_large.
-__global__ __launch_bounds__(64) void k_gdef(PlanDev P, ArrDev *__restrict__ A, Work W) {
+// larger rows are listed (count in *cnt) for k_gdef_large.
+__global__ __launch_bounds__(64) void k_gdef(PlanDev P, ArrDev *__restrict__ A, Work W, int32_t *cnt) {
   for (int t = blockIdx.x; t < P.ngrow; t += gridDim.x) {
-    if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list[atomicAdd(W.ovf_cnt, 1)] = t;
+    if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list[atomicAdd(cnt, 1)] = t;
   }
 }
 
 // The listed large rows, one wave each with LDS scratch (such rows are
-// rare, so the grid is small); the last workgroup clears the list.
+// rare, so the grid is small).  Two list counters alternate between calls:
+// this launch clears the other one, which the previous launch (finished,
+// same stream) read and the next k_gdef appends to, so no workgroup has to
+// wait for the others before a counter is reset.
 constexpr int kGdefLargeGrid = 32;
-__global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict__ A, Work W) {
+__global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict__ A, Work W, const int32_t *cnt,
+                                                   int32_t *other) {
   __shared__ Ivl s_iv[kMaxCap];
   __shared__ int32_t s_b[kGdefMaxB], s_u[kGdefMaxB], s_own[kGdefMaxB];
   __shared__ uint64_t s_hold[kGdefMaxB];
   GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
-  const int cnt = *W.ovf_cnt;
-  for (int q = blockIdx.x; q < cnt; q += gridDim.x) dev_gdef_row(P, A, W, W.ovf_list[q], S, kGdefMaxB);
-  if (last_workgroup(W.ovf_cnt + 1)) *W.ovf_cnt = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
+  const int n = *cnt;
+  for (int q = blockIdx.x; q < n; q += gridDim.x) dev_gdef_row(P, A, W, W.ovf_list[q], S, kGdefMaxB);
 }
 
 // Every row starts as one interval [0, n2) owned and held by the host.
@@ -112,18 +116,30 @@ static void launch_bands(const Level &L, hipStream_t s) {
   launch_heads(L, s);
 }
 
-// level 1: runs, band flags, band scan, heads, compaction (mode 0: the
-// final messages; mode 1: the level-2 items of 3-D arrays)
-hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, MsgRec *out,
-                         MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s) {
-  if (P.nsl1 == 0) return launch_compact(P, L, W, out, hdr, cap, mode, s);
+// level 1: runs (the only step that reads GDEF), then band flags, band
+// scan, heads, compaction (mode 0: the final messages; mode 1: the level-2
+// items of 3-D arrays)
+hipError_t launch_runs(const PlanDev &P, const ArrDev *A, const Work &W, int row_cap, hipStream_t s) {
+  if (P.nsl1 == 0) return hipSuccess;
   // LDS for the row's intervals sized to the row capacity
   if (row_cap <= 64)
     hipLaunchKernelGGL(k_runs<64>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
   else
     hipLaunchKernelGGL(k_runs<kMaxCap>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
-  launch_bands(L, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_level1_tail(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
+                              int mode, hipStream_t s) {
+  if (P.nsl1 > 0) launch_bands(L, s);
   return launch_compact(P, L, W, out, hdr, cap, mode, s);
+}
+
+hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, MsgRec *out,
+                         MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s) {
+  const hipError_t e = launch_runs(P, A, W, row_cap, s);
+  if (e != hipSuccess) return e;
+  return launch_level1_tail(P, W, L, out, hdr, cap, mode, s);
 }
 
 // level 2 (rectangles of consecutive planes stacked into boxes)
@@ -140,11 +156,18 @@ hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipSt
   return hipGetLastError();
 }
 
+// Every GDEF update of the runtime goes through here, in stream order (the
+// meta stream waits for the second internal stream before it launches
+// another), so the counter parity alternates launch by launch.
+static int g_ovf_parity = 0;
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s) {
   if (P.ngrow == 0) return hipSuccess;
+  const int p = g_ovf_parity;
+  g_ovf_parity ^= 1;
+  int32_t *cur = W.ovf_cnt + p, *other = W.ovf_cnt + (1 - p);
   const int grid = P.ngrow < (1 << 20) ? P.ngrow : (1 << 20);
-  hipLaunchKernelGGL(k_gdef, dim3(grid), dim3(64), 0, s, P, A, W);
-  hipLaunchKernelGGL(k_gdef_large, dim3(kGdefLargeGrid), dim3(64), 0, s, P, A, W);
+  hipLaunchKernelGGL(k_gdef, dim3(grid), dim3(64), 0, s, P, A, W, cur);
+  hipLaunchKernelGGL(k_gdef_large, dim3(kGdefLargeGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur, other);
   return hipGetLastError();
 }
 

@@ -26,6 +26,9 @@ namespace hd {
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr, int64_t cap,
                           int mode, hipStream_t s);
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
+hipError_t launch_runs(const PlanDev &P, const ArrDev *A, const Work &W, int row_cap, hipStream_t s);
+hipError_t launch_level1_tail(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
+                              int mode, hipStream_t s);
 hipError_t launch_level1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L, MsgRec *out,
                          MsgHdr *hdr, int64_t cap, int mode, int row_cap, hipStream_t s);
 hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
@@ -35,8 +38,8 @@ hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32
 int64_t tiles_for(int kind, const WorkBox &B, int esize, int th);
 hipError_t launch_ext_copy(const WorkBox *wb, int nbox, int64_t rows, const ArrDev *A, int arr, void *ext,
                            int to_ext, hipStream_t s);
-hipError_t launch_user(int kind, int th, int waves, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
-                       const float *coef, hipStream_t s);
+hipError_t launch_user(int kind, int th, int waves, int order, const WorkBox *wb, int nbox, const ArrDev *A,
+                       int64_t ntiles, const float *coef, hipStream_t s);
 hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const ArrDev *A, int arr, double *pf,
                          uint32_t *pi, void *res, hipStream_t s);
 hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipStream_t s);
@@ -104,8 +107,8 @@ struct Plan {
   WorkBox *wb = nullptr;
   // stencil kinds: the work boxes for 4, 8 and 16 rows per tile, and the
   // key of the tile-shape tuning shared by plans with the same boxes
-  WorkBox *wbj[3] = {nullptr, nullptr, nullptr};
-  int64_t ntj[3] = {0, 0, 0};
+  WorkBox *wbj[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t ntj[5] = {0, 0, 0, 0, 0};
   std::vector<int64_t> tkey;
   // device-pointer Write / Read plans: the partition's regions as boxes whose
   // tile0 counts rows (in the third box slot, unused by those plans)
@@ -142,7 +145,8 @@ struct Batch;
 // timed kTuneReps times in interleaved order; the fastest is kept.  The
 // shape never changes a result.
 constexpr int kTuneN = 4, kTuneReps = 2;
-constexpr int kTuneCand[kTuneN][2] = {{8, 1}, {4, 1}, {8, 4}, {4, 4}};
+// (rows per tile, waves per workgroup, order: 1 along rows, 0 down columns)
+constexpr int kTuneCand[kTuneN][3] = {{4, 1, 1}, {8, 1, 1}, {4, 4, 1}, {4, 1, 0}};
 struct TuneState {
   int next = 0;
   bool done = false;
@@ -159,6 +163,7 @@ struct Runtime {
   void *uctx = nullptr;
   int row_cap = 64;
   bool serial = false;  // metadata work on the data stream (measurement aid)
+  int jacobi_order = 1;  // with a fixed shape: 1 tiles along rows, 0 down columns
   int jacobi_rows = 0;   // HD_JACOBI_ROWS / HD_JACOBI_WAVES fix the stencil tile shape;
   int jacobi_waves = 0;  // otherwise it is tuned per work-box geometry
   int s3d_seg = 0;       // planes per wave of the 3-D stencil kernels (0: default)
@@ -205,6 +210,12 @@ struct Runtime {
   int last_batch = -1;
   hipEvent_t ev_meta = nullptr, ev_data = nullptr;
   hipStream_t cap = nullptr;
+  // GDEF updates run on a second internal stream beside the rest of the
+  // derivation (they need only its runs)
+  hipStream_t meta2 = nullptr;
+  hipEvent_t ev_runs = nullptr, ev_gdef = nullptr;
+  bool system_events = false;
+  unsigned sync_ev = 0, time_ev = 0;
   double *adj_cbar = nullptr;
   // opt-in phase timing
   int prof = 0;  // bit p: time phase p
@@ -306,7 +317,7 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   if (const char *e = getenv("HD_SERIAL")) R.serial = atoi(e) != 0;
   if (const char *e = getenv("HD_JACOBI_ROWS")) {
     const int v = atoi(e);
-    if (v == 4 || v == 8 || v == 16) R.jacobi_rows = v;
+    if (v == 4 || v == 8 || v == 16 || v == 32 || v == 64) R.jacobi_rows = v;
   }
   if (const char *e = getenv("HD_S3D_SEG")) {
     const int v = atoi(e);
@@ -316,16 +327,26 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
     const int v = atoi(e);
     if (v == 1 || v == 4) R.jacobi_waves = v;
   }
+  if (const char *e = getenv("HD_JACOBI_ORDER")) R.jacobi_order = atoi(e) != 0;
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
   R.device = dev;
   HIPCK(hipStreamCreateWithFlags(&R.meta, hipStreamNonBlocking));
   HIPCK(hipStreamCreateWithFlags(&R.cap, hipStreamNonBlocking));
-  HIPCK(hipEventCreateWithFlags(&R.ev_meta, hipEventDisableTiming));
-  HIPCK(hipEventCreateWithFlags(&R.ev_data, hipEventDisableTiming));
+  HIPCK(hipStreamCreateWithFlags(&R.meta2, hipStreamNonBlocking));
+  // events order work between the runtime's streams on this one device, so
+  // a device-scope release is enough (the default system-scope one also
+  // writes caches back for the host); timing events need no fence at all
+  if (const char *e = getenv("HD_EVENT_SCOPE")) R.system_events = !strcmp(e, "system");
+  R.sync_ev = hipEventDisableTiming | (R.system_events ? 0u : (unsigned)hipEventReleaseToDevice);
+  R.time_ev = R.system_events ? 0u : (unsigned)hipEventDisableSystemFence;
+  HIPCK(hipEventCreateWithFlags(&R.ev_runs, R.sync_ev));
+  HIPCK(hipEventCreateWithFlags(&R.ev_gdef, R.sync_ev));
+  HIPCK(hipEventCreateWithFlags(&R.ev_meta, R.sync_ev));
+  HIPCK(hipEventCreateWithFlags(&R.ev_data, R.sync_ev));
   for (int k = 0; k < 2; ++k) {
-    HIPCK(hipEventCreateWithFlags(&R.ev_cs[k], hipEventDisableTiming));
-    HIPCK(hipEventCreateWithFlags(&R.ev_free[k], hipEventDisableTiming));
+    HIPCK(hipEventCreateWithFlags(&R.ev_cs[k], R.sync_ev));
+    HIPCK(hipEventCreateWithFlags(&R.ev_free[k], R.sync_ev));
   }
   R.arr_cap = 4096;
   R.h_arrs.assign(R.arr_cap, ArrDev{});
@@ -337,7 +358,7 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   HIPCK(hipMemset(R.counters, 0, 64));
   R.W.run_top = R.counters + 0;
   R.W.err = R.counters + 3;
-  R.W.ovf_cnt = R.counters + 4;  // [4] rows listed, [5] workgroups done
+  R.W.ovf_cnt = R.counters + 4;  // [4], [5]: rows listed for the large-row GDEF update, alternating
   HIPCK(hipHostMalloc((void **)&R.red_res_host, 64, hipHostMallocDefault));
   R.red_res_dev = dalloc(64);
   R.red_pf = (double *)dalloc(sizeof(double) * kMaxDev * 64 * 4);
@@ -353,6 +374,7 @@ static void free_plan_buffers(Plan *pl);
 extern "C" void hdarray_exit(void) {
   if (!R.inited) return;
   (void)hipStreamSynchronize(R.meta);
+  (void)hipStreamSynchronize(R.meta2);
   (void)hipStreamSynchronize(R.data);
   for (auto &kv : R.plans) {
     free_plan_buffers(kv.second);
@@ -394,7 +416,10 @@ extern "C" void hdarray_exit(void) {
   R.tunes.clear();
   (void)hipEventDestroy(R.ev_meta);
   (void)hipEventDestroy(R.ev_data);
+  (void)hipEventDestroy(R.ev_runs);
+  (void)hipEventDestroy(R.ev_gdef);
   (void)hipStreamDestroy(R.cap);
+  (void)hipStreamDestroy(R.meta2);
   (void)hipStreamDestroy(R.meta);
   hd_alloc_fn ua = R.ualloc;
   hd_free_fn uf = R.ufree;
@@ -1068,7 +1093,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   size_t o_g2 = push_blob(blob, grp2), o_p2 = push_blob(blob, pos2);
   size_t o_grec = push_blob(blob, grec), o_ds = push_blob(blob, dseg);
   size_t o_wb = (blob.size() + 255) / 256 * 256;
-  blob.resize(o_wb + sizeof(WorkBox) * 3 * kMaxDev + 16);
+  blob.resize(o_wb + sizeof(WorkBox) * 5 * kMaxDev + 16);
   pl->mem = dalloc(blob.size());
   if (!pl->mem) return fail(HD_ENOMEM);
   char *b = (char *)pl->mem;
@@ -1087,7 +1112,7 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   P.grec = (const GRowRec *)(b + o_grec);
   P.dseg = (const Seg *)(b + o_ds);
   pl->wb = (WorkBox *)(b + o_wb);
-  for (int k = 0; k < 3; ++k) pl->wbj[k] = pl->wb + k * kMaxDev;
+  for (int k = 0; k < 5; ++k) pl->wbj[k] = pl->wb + k * kMaxDev;
   // work boxes are filled by the caller into the host blob first
   pl->nbox = 0;
   HIPCK(hipMemcpy(pl->mem, blob.data(), blob.size(), hipMemcpyHostToDevice));
@@ -1139,7 +1164,7 @@ static hipEvent_t prof_event() {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, R.time_ev) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -1159,6 +1184,17 @@ struct PhaseTimer {
     R.prof_pending.push_back({phase, {a, b}});
   }
 };
+
+extern "C" int hdarray_set_stencil_shape(int rows, int waves, int order) {
+  if (!R.inited) return fail(HD_ESTATE);
+  if (!(rows == 0 || rows == 4 || rows == 8 || rows == 16 || rows == 32 || rows == 64)) return fail(HD_EINVAL);
+  if (!(waves == 0 || waves == 1 || waves == 4)) return fail(HD_EINVAL);
+  if (order != 0 && order != 1) return fail(HD_EINVAL);
+  R.jacobi_rows = rows;
+  R.jacobi_waves = waves;
+  R.jacobi_order = order;
+  return HD_OK;
+}
 
 extern "C" int hdarray_set_plan_cache(int on) {
   if (!R.inited) return fail(HD_ESTATE);
@@ -1195,11 +1231,12 @@ extern "C" int hdarray_profile_read(hd_profile_t *out) {
 // candidate of the tuning (with the event pair that times it), or the
 // tuned best.  The tuning reads its events only once they have completed,
 // so it never waits for the GPU.
-static void stencil_shape(Plan *pl, int &th, int &waves, hipEvent_t &e0, hipEvent_t &e1) {
+static void stencil_shape(Plan *pl, int &th, int &waves, int &order, hipEvent_t &e0, hipEvent_t &e1) {
   e0 = e1 = nullptr;
   if (R.jacobi_rows || R.jacobi_waves) {
-    th = R.jacobi_rows ? R.jacobi_rows : 8;
+    th = R.jacobi_rows ? R.jacobi_rows : 4;
     waves = R.jacobi_waves ? R.jacobi_waves : 1;
+    order = waves == 4 ? 1 : R.jacobi_order;
     return;
   }
   TuneState &ts = R.tunes[pl->tkey];
@@ -1207,8 +1244,10 @@ static void stencil_shape(Plan *pl, int &th, int &waves, hipEvent_t &e0, hipEven
   if (!ts.done && ts.next < kTuneN * kTuneReps) {
     const int slot = ts.next++;
     c = slot % kTuneN;
-    if (!ts.ev[2 * slot] && hipEventCreate(&ts.ev[2 * slot]) != hipSuccess) ts.ev[2 * slot] = nullptr;
-    if (!ts.ev[2 * slot + 1] && hipEventCreate(&ts.ev[2 * slot + 1]) != hipSuccess) ts.ev[2 * slot + 1] = nullptr;
+    if (!ts.ev[2 * slot] && hipEventCreateWithFlags(&ts.ev[2 * slot], R.time_ev) != hipSuccess)
+      ts.ev[2 * slot] = nullptr;
+    if (!ts.ev[2 * slot + 1] && hipEventCreateWithFlags(&ts.ev[2 * slot + 1], R.time_ev) != hipSuccess)
+      ts.ev[2 * slot + 1] = nullptr;
     if (ts.ev[2 * slot] && ts.ev[2 * slot + 1]) {
       e0 = ts.ev[2 * slot];
       e1 = ts.ev[2 * slot + 1];
@@ -1240,6 +1279,7 @@ static void stencil_shape(Plan *pl, int &th, int &waves, hipEvent_t &e0, hipEven
   }
   th = kTuneCand[c][0];
   waves = kTuneCand[c][1];
+  order = kTuneCand[c][2];
 }
 
 // ------------------------------------------------------------ plan cache
@@ -1289,8 +1329,8 @@ static int plan_buffers(Plan *pl) {
   pl->prcnt = (int32_t *)dalloc(4 * ((int64_t)pl->nsl1 + 1));
   if (!pl->ptab || !pl->phdr || !pl->pruns || !pl->proff || !pl->prcnt) return fail(HD_ENOMEM);
   HIPCK(hipMemset(pl->phdr, 0, sizeof(MsgHdr)));
-  HIPCK(hipEventCreateWithFlags(&pl->ev_ready, hipEventDisableTiming));
-  HIPCK(hipEventCreateWithFlags(&pl->ev_used, hipEventDisableTiming));
+  HIPCK(hipEventCreateWithFlags(&pl->ev_ready, R.sync_ev));
+  HIPCK(hipEventCreateWithFlags(&pl->ev_used, R.sync_ev));
   return HD_OK;
 }
 
@@ -1310,6 +1350,32 @@ static void free_plan_buffers(Plan *pl) {
 }
 
 static int enqueue_user(Plan *pl, const float *coef);
+
+// Communication-set derivation and GDEF update of one call.  Only the runs
+// read GDEF, so once they are found the GDEF update (which needs nothing
+// else) runs on the second internal stream beside the rest of the
+// derivation; the meta stream then waits for it, so the next call's runs
+// see the updated GDEF.  ev_table (optional) marks the message table done.
+static hipError_t derive_and_update(const PlanDev &P, const Work &W, const Level &L1, MsgRec *tab, MsgHdr *hdr,
+                                    int64_t cap, int has3d, hipStream_t meta, hipEvent_t ev_table = nullptr) {
+  hipError_t e = launch_runs(P, R.d_arrs, W, R.row_cap, meta);
+  if (e != hipSuccess) return e;
+  const bool fork = meta != R.data;
+  if (fork) {
+    if ((e = hipEventRecord(R.ev_runs, meta)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(R.meta2, R.ev_runs, 0)) != hipSuccess) return e;
+    if ((e = launch_gdef(P, R.d_arrs, W, R.meta2)) != hipSuccess) return e;
+    if ((e = hipEventRecord(R.ev_gdef, R.meta2)) != hipSuccess) return e;
+  }
+  if ((e = launch_level1_tail(P, W, L1, tab, hdr, cap, has3d ? 1 : 0, meta)) != hipSuccess) return e;
+  if (has3d) {
+    Level L2 = make_level(2, P);
+    if ((e = launch_level2(P, W, L2, tab, hdr, cap, meta)) != hipSuccess) return e;
+  }
+  if (ev_table && (e = hipEventRecord(ev_table, meta)) != hipSuccess) return e;
+  if (fork) return hipStreamWaitEvent(meta, R.ev_gdef, 0);
+  return launch_gdef(P, R.d_arrs, W, meta);
+}
 
 // A plain call with the plan cache on: derivation (on a miss) into the
 // plan's own buffers, GDEF update from the plan's runs, pack from the
@@ -1334,17 +1400,12 @@ static int enqueue_cached(Plan *pl, const float *coef) {
       L1.ioff = W.roff;
       L1.icnt = W.rcnt;
       L1.items = W.runs;
-      HIPCK(launch_level1(P, R.d_arrs, W, L1, pl->ptab, pl->phdr, pl->pcap, pl->has3d ? 1 : 0, R.row_cap, meta));
-      if (pl->has3d) {
-        Level L2 = make_level(2, P);
-        HIPCK(launch_level2(P, W, L2, pl->ptab, pl->phdr, pl->pcap, meta));
-      }
-      HIPCK(hipEventRecord(pl->ev_ready, meta));
+      HIPCK(derive_and_update(P, W, L1, pl->ptab, pl->phdr, pl->pcap, pl->has3d, meta, pl->ev_ready));
       R.stats.cache_misses++;
     } else {
+      HIPCK(launch_gdef(P, R.d_arrs, W, meta));
       R.stats.cache_hits++;
     }
-    HIPCK(launch_gdef(P, R.d_arrs, W, meta));
   }
   pl->last_key = key;
   pl->have = !key.empty();
@@ -1379,16 +1440,19 @@ static int enqueue(Plan *pl, const float *coef) {
   PhaseTimer tm(0, meta);
   // adjoint: the cotangent array is defined by the owners of the work boxes
   // first, so its use-region messages are exactly {(owner(x) -> d, x)}
-  if (pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
   Level L1 = make_level(1, P);
-  HIPCK(launch_level1(P, R.d_arrs, W, L1, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0, R.row_cap,
-                      meta));
-  if (pl->has3d) {
-    Level L2 = make_level(2, P);
-    HIPCK(launch_level2(P, W, L2, R.tab[slot], R.hdr[slot], R.ws_items, meta));
+  if (pl->adjoint) {
+    HIPCK(launch_gdef(P, R.d_arrs, W, meta));
+    HIPCK(launch_level1(P, R.d_arrs, W, L1, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0, R.row_cap,
+                        meta));
+    if (pl->has3d) {
+      Level L2 = make_level(2, P);
+      HIPCK(launch_level2(P, W, L2, R.tab[slot], R.hdr[slot], R.ws_items, meta));
+    }
+    HIPCK(hipEventRecord(R.ev_cs[slot], meta));
+  } else {
+    HIPCK(derive_and_update(P, W, L1, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d, meta, R.ev_cs[slot]));
   }
-  HIPCK(hipEventRecord(R.ev_cs[slot], meta));
-  if (!pl->adjoint) HIPCK(launch_gdef(P, R.d_arrs, W, meta));
   }
   // data stream
   HIPCK(hipStreamWaitEvent(R.data, R.ev_cs[slot], 0));
@@ -1421,19 +1485,20 @@ static int enqueue(Plan *pl, const float *coef) {
 // the user kernel of a call, on the data stream
 static int enqueue_user(Plan *pl, const float *coef) {
   if (pl->ukind == 1 || pl->ukind == 5 || pl->ukind == 6) {
-    int th = 8, waves = 1;
+    int th = 8, waves = 1, order = 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    stencil_shape(pl, th, waves, e0, e1);
-    const int q = th == 4 ? 0 : th == 8 ? 1 : 2;
+    stencil_shape(pl, th, waves, order, e0, e1);
+    const int q = th == 4 ? 0 : th == 8 ? 1 : th == 16 ? 2 : th == 32 ? 3 : 4;
     R.stats.stencil_rows = th;
     R.stats.stencil_waves = waves;
+    R.stats.stencil_order = order;
     PhaseTimer tm(3, R.data);
     if (e0) HIPCK(hipEventRecord(e0, R.data));
-    HIPCK(launch_user(pl->ukind, th, waves, pl->wbj[q], pl->nbox, R.d_arrs, pl->ntj[q], coef, R.data));
+    HIPCK(launch_user(pl->ukind, th, waves, order, pl->wbj[q], pl->nbox, R.d_arrs, pl->ntj[q], coef, R.data));
     if (e1) HIPCK(hipEventRecord(e1, R.data));
   } else if (pl->ukind) {
     PhaseTimer tm(3, R.data);
-    HIPCK(launch_user(pl->ukind, pl->th, 1, pl->wb, pl->nbox, R.d_arrs, pl->ntiles, coef, R.data));
+    HIPCK(launch_user(pl->ukind, pl->th, 1, 1, pl->wb, pl->nbox, R.d_arrs, pl->ntiles, coef, R.data));
   }
   return HD_OK;
 }
@@ -1657,8 +1722,8 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
     pl->nbox = (int)wb.size();
     if (pl->ukind == 1 || pl->ukind == 5 || pl->ukind == 6) {
       // one set of work boxes per tile height (tile offsets differ)
-      const int ths[3] = {4, 8, 16};
-      for (int q = 0; q < 3; ++q) {
+      const int ths[5] = {4, 8, 16, 32, 64};
+      for (int q = 0; q < 5; ++q) {
         int64_t t0 = 0;
         for (WorkBox &w : wb) {
           w.tile0 = t0;

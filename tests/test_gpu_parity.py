@@ -149,6 +149,59 @@ def test_conv2d_parity(hd, n0, n1, ndev, kind):
     assert orc.bad_reads() == 0
 
 
+@pytest.mark.parametrize("rows,waves,order", [(4, 1, 1), (8, 1, 1), (16, 1, 1), (4, 1, 0), (8, 1, 0), (16, 1, 0),
+                                               (4, 4, 1), (8, 4, 1), (16, 4, 1), (32, 0, 1), (64, 0, 1)])
+def test_stencil_shapes_parity(hd, rows, waves, order):
+    """Every 2-D stencil tile shape (tiles of 4/8/16 rows with one or four
+    waves in either tile order, tall strips of 32/64 rows) gives the
+    oracle's bits for Jacobi,
+    lower-triangular Jacobi and the 3 x 3 convolution, on sizes with ragged
+    tails in both dimensions and strips longer than some boxes."""
+    say(f"case stencil shape rows={rows} waves={waves} order={order}")
+    rng = np.random.default_rng(rows * 10 + waves + 100 * order)
+    w = [float(x) for x in CONV9_WEIGHTS]
+    # Jacobi, BLOCK 8 with full-box use
+    A0 = rng.random((150, 530), dtype=np.float32)
+    B0 = rng.random((150, 530), dtype=np.float32)
+    rt, orc = hd.Runtime(), O.Oracle()
+    rt.set_stencil_shape(rows, waves, order)
+    g = prog.jacobi_blocks(rt, A0, B0, 8, True)
+    o = prog.jacobi_blocks(orc, A0, B0, 8, True)
+    for it in range(3):
+        k, ag, ao = ("jacAB", [g[0], g[1]], [o[0], o[1]]) if it % 2 == 0 else ("jacBA", [g[1], g[0]], [o[1], o[0]])
+        rt.apply(k, g[2], ag)
+        orc.apply(k, o[2], ao)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"jacobi step {it}")
+        st = rt.stats()
+        assert st["stencil_rows"] == rows
+        assert rows >= 32 or (st["stencil_waves"] == waves and st["stencil_order"] == (1 if waves == 4 else order))
+    assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+    # triangular on irregular row splits
+    T0, U0 = jacobi_inputs(150, 9)
+    rt, orc = hd.Runtime(), O.Oracle()
+    rt.set_stencil_shape(rows, waves, order)
+    g = prog.tri(rt, T0, U0, [0, 1, 40, 41, 97, 150])
+    o = prog.tri(orc, T0, U0, [0, 1, 40, 41, 97, 150])
+    for it in range(3):
+        k, ag, ao = ("triAB", [g[0], g[1]], [o[0], o[1]]) if it % 2 == 0 else ("triBA", [g[1], g[0]], [o[1], o[0]])
+        rt.apply(k, g[2], ag)
+        orc.apply(k, o[2], ao)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"tri step {it}")
+    assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+    # convolution, COL 5 with unaligned column blocks
+    f0 = rng.random((75, 613), dtype=np.float32)
+    rt, orc = hd.Runtime(), O.Oracle()
+    rt.set_stencil_shape(rows, waves, order)
+    g = prog.conv2d(rt, f0, 5, prog.COL)
+    o = prog.conv2d(orc, f0, 5, prog.COL)
+    for it in range(3):
+        k, gi = ("convAB", (0, 1)) if it % 2 == 0 else ("convBA", (1, 0))
+        rt.apply(k, g[2], [g[gi[0]], g[gi[1]]], w)
+        orc.apply(k, o[2], [o[gi[0]], o[gi[1]]], w)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"conv step {it}")
+    assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+
+
 @pytest.mark.parametrize("n,P", [(64, 4), (96, 3)])
 def test_gemm_parity(hd, n, P):
     """Listings 2-3 GEMM: the gather of B (first call), then no messages;
