@@ -416,7 +416,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="jacobi_large",
                     choices=["jacobi_large", "matmul", "2mm", "conv2d", "batched", "stencil3d", "copy_calib"])
