@@ -317,12 +317,14 @@ int hdarray_set_plan_cache(int on);
 /* Per-phase device timing with HIP events recorded on the stream each phase
  * runs on (opt-in; adds an event pair per timed phase and call).  enable is a
  * bit mask over the phases (bit p times phase p, 0 disables).  Phases:
- * 0 communication-set derivation + GDEF update (internal stream), 1 pack,
- * 2 unpack, 3 user kernel (data stream).  hdarray_profile_read
+ * 0 communication-set derivation + GDEF update (internal stream), 1 pack
+ * (with the unpack in the same pass), 2 unpack (when separate), 3 user
+ * kernel, 4 adjoint step (reverse pack, adjoint kernel, scatter-add; data
+ * stream).  hdarray_profile_read
  * synchronises, adds up the elapsed times since the last read and resets. */
 typedef struct {
-  double ms[4];
-  int64_t count[4];
+  double ms[5];
+  int64_t count[5];
 } hd_profile_t;
 int hdarray_profile(int enable);
 int hdarray_profile_read(hd_profile_t *out);

@@ -53,10 +53,10 @@ class Stats(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("ms", C.c_double * 4), ("count", C.c_int64 * 4)]
+    _fields_ = [("ms", C.c_double * 5), ("count", C.c_int64 * 5)]
 
 
-PHASES = ("derive+gdef", "pack", "unpack", "kernel")
+PHASES = ("derive+gdef", "pack", "unpack", "kernel", "adjoint")
 _lib = None
 _TORCH_CB = None
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -337,7 +337,7 @@ class Runtime:
     def profile_read(self):
         pr = Profile()
         self._ck(self.L.hdarray_profile_read(C.byref(pr)), "profile_read")
-        return {PHASES[i]: (pr.ms[i], pr.count[i]) for i in range(4)}
+        return {PHASES[i]: (pr.ms[i], pr.count[i]) for i in range(len(PHASES))}
 
     # -- parity dumps ------------------------------------------------------------
     def messages(self):

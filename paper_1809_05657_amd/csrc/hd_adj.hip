@@ -29,7 +29,9 @@ struct AdjArgs {
 
 // tiles of the extended box W +- 1 (clipped), marched like the forward
 // kernel: one wave per (row, 256 columns, segment of planes), four rows per
-// workgroup
+// workgroup.  The column tiles cover the box's own columns; the extended
+// column on either side is one extra cell of lane 0 / lane 63 (it gets a
+// contribution from its one neighbour inside the box only).
 __host__ __device__ inline void ext_box(const WorkBox &B, const int64_t *n, int *lo, int *hi) {
   for (int q = 0; q < 3; ++q) {
     lo[q] = B.lo[q] - 1 < 0 ? 0 : B.lo[q] - 1;
@@ -71,11 +73,15 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
     ext_box(B, ag.n, lo, hi);
     const int64_t lt = t - B.tile0;
     const int jrows = hi[1] - lo[1];
-    const int kb = lo[2] & ~3;
-    const int nk = (hi[2] - kb + 255) / 256;
+    const int kb = B.lo[2] & ~3;
+    const int nk = (B.hi[2] - kb + 255) / 256;
     const int j = lo[1] + (int)(lt % jrows);
     const int64_t rest = lt / jrows;
-    const int c = kb + (int)(rest % nk) * 256 + 4 * lane;
+    const int tk = (int)(rest % nk);
+    const int c = kb + tk * 256 + 4 * lane;
+    // extended columns outside the column tiles
+    const bool xl = lane == 0 && tk == 0 && lo[2] < kb;
+    const bool xr = lane == 63 && tk == nk - 1 && hi[2] > kb + nk * 256;
     const int seg = seg_of(B);
     const int i0 = lo[0] + (int)(rest / nk) * seg;
     const int i1 = min(i0 + seg, hi[0]);
@@ -141,6 +147,23 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
           cb[5] += gy * (double)wkl[e];
           cb[6] += gy * (double)wkr[e];
         }
+      }
+      // the extended column next to the box: only the term of its neighbour
+      // inside the box can be nonzero (every other term needs the cell itself
+      // inside the box), so the values it does not read are passed as zero
+      if (xl) {
+        const int k = c - 1;
+        const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
+                   kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
+        q[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gcu.l, 0.f, 0.f, 0.f, 0.f, gcu.v.x, 0.f, false,
+                        false);
+      }
+      if (xr) {
+        const int k = c + 4;
+        const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
+                   kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
+        q[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gcu.r, 0.f, 0.f, 0.f, 0.f, 0.f, gcu.v.w, false,
+                        false);
       }
       gpm = gcu.v;
       gcu = gpp;
@@ -250,7 +273,7 @@ __global__ __launch_bounds__(256) void k_unpack_add(const MsgRec *__restrict__ M
 int64_t adj_tiles(const WorkBox &B, const int64_t *n) {
   int lo[3], hi[3];
   ext_box(B, n, lo, hi);
-  return march_tiles(lo[0], hi[0], lo[1], hi[1], lo[2], hi[2], seg_of(B));
+  return march_tiles(lo[0], hi[0], lo[1], hi[1], B.lo[2], B.hi[2], seg_of(B));
 }
 
 hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const float *coef, double *part,

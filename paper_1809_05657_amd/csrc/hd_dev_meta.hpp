@@ -788,55 +788,47 @@ __device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ 
   const GRowRec gr = P.grec[t];
   ArrDev &a = A[gr.arr];
   const int64_t grow = gr.grow;
+  Ivl *row = a.ivl + grow * (int64_t)a.cap;
+  const Seg *ds = P.dseg + gr.dseg0;
+  const int nds = gr.ndseg;
+  const int sl = gr.slice;
+  // every load that depends only on the row record is issued at once: the
+  // count, the first 64 old intervals (the row's capacity bounds the read),
+  // the run location and the first 64 definitions
+  Ivl v{0x7fffffff, 0, 0ull};
+  if (!gr.full && lane < a.cap) v = row[lane];
+  const int n = gr.full ? 0 : a.cnt[grow];
+  const int nrun = sl >= 0 ? W.rcnt[sl] : 0;
+  const int roff = sl >= 0 ? W.roff[sl] : 0;
+  Seg d{0, 0, 0, 0};
+  if (lane < nds) d = ds[lane];
   if (gr.full) {
     // the definitions tile the row (touching spans of one device already
     // merged by the planner): they are the new list
-    const Seg *ds = P.dseg + gr.dseg0;
-    const int nds = gr.ndseg;
     if (nds > a.cap) {
       if (lane == 0) set_err(W.err, -8);
       return true;
     }
-    Ivl *row = a.ivl + grow * (int64_t)a.cap;
     for (int e = lane; e < nds; e += 64) {
-      const Seg d = ds[e];
-      row[e] = Ivl{d.c0, d.dst, (1ull << d.dst) | ((d.flags & 1) ? (1ull << kHost) : 0ull)};
+      const Seg de = e < 64 ? d : ds[e];
+      row[e] = Ivl{de.c0, de.dst, (1ull << de.dst) | ((de.flags & 1) ? (1ull << kHost) : 0ull)};
     }
     if (lane == 0) a.cnt[grow] = nds;
     return true;
   }
-  const int n = a.cnt[grow];
   const int W2 = (int)a.n[2];
-  Ivl *row = a.ivl + grow * (int64_t)a.cap;
-  const int sl = gr.slice;
-  const Item *runs = sl >= 0 ? W.runs + W.roff[sl] : nullptr;
-  const int nrun = sl >= 0 ? W.rcnt[sl] : 0;
-  const Seg *ds = P.dseg + gr.dseg0;
-  const int nds = gr.ndseg;
   const int nb = n + 2 * (nrun + nds);
   if (nb > 64) return false;
-  int st = 0x7fffffff, ow = 0;
-  uint64_t ho = 0;
-  if (lane < n) {
-    const Ivl v = row[lane];
-    st = v.start;
-    ow = v.owner;
-    ho = v.holders;
-  }
+  const int st = lane < n ? v.start : 0x7fffffff;
+  const int ow = lane < n ? v.owner : 0;
+  const uint64_t ho = lane < n ? v.holders : 0ull;
   // edits one per lane
-  RowEdits E{nrun, 0, 0, 0, nds, 0, 0, 0, 0};
+  RowEdits E{nrun, 0, 0, 0, nds, d.c0, d.c1, d.dst, d.flags};
   if (lane < nrun) {
-    const Item r = runs[lane];
+    const Item r = W.runs[roff + lane];
     E.ra0 = r.a0;
     E.ra1 = r.a1;
     E.rdst = r.dst;
-  }
-  if (lane < nds) {
-    const Seg d = ds[lane];
-    E.dc0 = d.c0;
-    E.dc1 = d.c1;
-    E.ddst = d.dst;
-    E.dfl = d.flags;
   }
   // boundaries: old starts, then run ends, then definition ends (an end at
   // the row's width is the wrap to 0, already a start)

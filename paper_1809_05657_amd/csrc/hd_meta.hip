@@ -48,7 +48,7 @@ __global__ __launch_bounds__(64) void k_compact(PlanDev P, Level L, Work W, MsgR
   dev_compact(P, L, W, out, hdr, out_cap, mode, s);
 }
 
-__global__ __launch_bounds__(1024) void k_compact_wg(PlanDev P, Level L, Work W, MsgRec *out, MsgHdr *hdr,
+__global__ __launch_bounds__(256) void k_compact_wg(PlanDev P, Level L, Work W, MsgRec *out, MsgHdr *hdr,
                                                      int64_t out_cap, int mode) {
   __shared__ int64_t s[2 * kCompactCarr];
   dev_compact(P, L, W, out, hdr, out_cap, mode, s);
@@ -94,11 +94,11 @@ hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRe
                           int64_t cap, int mode, hipStream_t s) {
   // one wave for tables of a few thousand bands at most; a full workgroup
   // when the level has many slices (and so possibly many bands)
-  const int nt = L.nsl <= 8192 ? 64 : 1024;
+  const int nt = L.nsl <= 8192 ? 64 : 256;
   if (nt == 64)
     hipLaunchKernelGGL(k_compact, dim3(1), dim3(64), 0, s, P, L, W, out, hdr, cap, mode);
   else
-    hipLaunchKernelGGL(k_compact_wg, dim3(1), dim3(1024), 0, s, P, L, W, out, hdr, cap, mode);
+    hipLaunchKernelGGL(k_compact_wg, dim3(1), dim3(256), 0, s, P, L, W, out, hdr, cap, mode);
   return hipGetLastError();
 }
 
@@ -112,7 +112,7 @@ static void launch_bands(const Level &L, hipStream_t s) {
   if (L.nsl <= 8192)
     hipLaunchKernelGGL(k_bandscan<64>, dim3(1), dim3(64), 0, s, L);
   else
-    hipLaunchKernelGGL(k_bandscan<1024>, dim3(1), dim3(1024), 0, s, L);
+    hipLaunchKernelGGL(k_bandscan<256>, dim3(1), dim3(256), 0, s, L);
   launch_heads(L, s);
 }
 

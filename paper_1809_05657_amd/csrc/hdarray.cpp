@@ -1459,7 +1459,7 @@ static int enqueue(Plan *pl, const float *coef) {
   const int64_t bw = pl->stg_bound / 4 + 1;
   if (pl->adjoint) {
     {
-      PhaseTimer tm(3, R.data);
+      PhaseTimer tm(4, R.data);
       HIPCK(launch_adjoint(pl->wb, pl->nbox, pl->ntiles, coef, pl->part, R.adj_cbar, R.tab[slot], R.hdr[slot],
                            R.d_arrs, (uint32_t *)R.staging, bw, R.data));
     }

@@ -150,3 +150,29 @@ def test_reverse_messages_parity(env):
     assert len(mg) == len(mo) > 0
     cols = [2, 3, 4, 5, 6, 7, 8, 9, 10, 11]
     assert np.array_equal(mg[:, cols], mo[:, cols])
+
+
+@pytest.mark.parametrize("shape", [(6, 6, 512), (5, 7, 600), (9, 33, 70)])
+def test_adjoint_wide_rows(env, shape):
+    """Boxes 256 columns wide (the extended column right of the box falls
+    just past the last column tile), wider than one tile, and narrow boxes
+    with unaligned starts: gradient and coefficient gradients against the
+    FP64 CPU adjoint."""
+    hdm, ag, torch = env
+    T, ck = 4, 2
+    say(f"case adjoint wide rows {shape} T={T}")
+    rng = np.random.default_rng(sum(shape))
+    u0 = rng.random(shape, dtype=np.float32)
+    w = rng.random(shape, dtype=np.float32)
+    coef = [float(c) for c in S3D_COEFFS]
+    rt = hdm.Runtime()
+    solver = ag.Stencil3D(rt, shape, ndev=8, T=T, ckpt=ck)
+    dev = torch.device("cuda:0")
+    solver.forward(torch.from_numpy(u0).to(dev), coef)
+    g0, cb = solver.backward(torch.from_numpy(w).to(dev))
+    g0 = g0.cpu().numpy().astype(np.float64)
+    cb = cb.cpu().numpy()
+    c64 = np.array(S3D_COEFFS, dtype=np.float64)
+    g64, gc64 = O.s3d_adjoint64(u0.astype(np.float64), c64, T, w.astype(np.float64))
+    assert np.linalg.norm(g0 - g64) / np.linalg.norm(g64) <= 1e-4
+    assert np.all(np.abs(cb - gc64) <= 1e-4 * np.abs(gc64))
