@@ -142,6 +142,93 @@ __device__ inline int dev_runs_find(const PlanDev &P, const ArrDev *__restrict__
   return nr;
 }
 
+// One use row per lane, for rows with at most kLaneIvl intervals, kLaneSeg
+// use segments and kRunSlot runs (the common case: a few owners per row):
+// the intervals sit in registers, the runs are found in the same order as
+// by the wave (by segment, then column; consecutive needed intervals of one
+// owner merge), staged in the lane's own column of lr ([4 * kRunSlot][64]:
+// src, dst, a0, a1) and stored rank-sorted by (col, dst) into the row's
+// slot, exactly as the wave stores them.  Returns false, writing nothing,
+// for any other row.
+constexpr int kLaneIvl = 8, kLaneSeg = 8;
+__device__ inline bool dev_runs_lane(const PlanDev &P, const ArrDev *__restrict__ A, const Work &W, int s,
+                                     int32_t *lr) {
+  const int lane = threadIdx.x & 63;
+  const SliceRec sr = P.srec[s];
+  const ArrDev &a = A[sr.arr];
+  const int n = a.cnt[sr.grow];
+  if (n > kLaneIvl || sr.nseg > kLaneSeg) return false;
+  const Ivl *row = a.ivl + sr.grow * (int64_t)a.cap;
+  const int W2 = (int)a.n[2];
+  int st[kLaneIvl + 1], ow[kLaneIvl];
+  uint64_t ho[kLaneIvl];
+#pragma unroll
+  for (int i = 0; i < kLaneIvl; ++i) {
+    st[i] = W2;
+    ow[i] = -1;
+    ho[i] = ~0ull;
+    if (i < n) {
+      const Ivl v = row[i];
+      st[i] = v.start;
+      ow[i] = v.owner;
+      ho[i] = v.holders;
+    }
+  }
+  st[kLaneIvl] = W2;
+  int nr = 0;
+  bool over = false;
+  auto emit = [&](int src, int dst, int a0, int a1) {
+    if (nr < kRunSlot) {
+      lr[(4 * nr + 0) * 64 + lane] = src;
+      lr[(4 * nr + 1) * 64 + lane] = dst;
+      lr[(4 * nr + 2) * 64 + lane] = a0;
+      lr[(4 * nr + 3) * 64 + lane] = a1;
+    } else {
+      over = true;
+    }
+    ++nr;
+  };
+#pragma unroll
+  for (int q = 0; q < kLaneSeg; ++q) {
+    if (q < sr.nseg) {
+      const Seg S = P.useg[sr.seg0 + q];
+      const uint64_t bit = 1ull << S.dst;
+      int cs = -1, c0 = 0, c1 = 0;
+#pragma unroll
+      for (int i = 0; i < kLaneIvl; ++i) {
+        const int en = st[i + 1];
+        const bool nd = i < n && max(st[i], S.c0) < min(en, S.c1) && !(ho[i] & bit);
+        if (nd && cs == ow[i]) {
+          c1 = min(en, S.c1);
+        } else {
+          if (cs >= 0) emit(cs, S.dst, c0, c1);
+          cs = -1;
+          if (nd) {
+            cs = ow[i];
+            c0 = max(st[i], S.c0);
+            c1 = min(en, S.c1);
+          }
+        }
+      }
+      if (cs >= 0) emit(cs, S.dst, c0, c1);
+    }
+  }
+  if (over) return false;
+  const int off = s * kRunSlot;
+  for (int i = 0; i < nr; ++i) {
+    const int xa = lr[(4 * i + 2) * 64 + lane], xd = lr[(4 * i + 1) * 64 + lane];
+    int rank = 0;
+    for (int j = 0; j < nr; ++j) {
+      const int ya = lr[(4 * j + 2) * 64 + lane], yd = lr[(4 * j + 1) * 64 + lane];
+      rank += (ya < xa) || (ya == xa && yd < xd);
+    }
+    W.runs[off + rank] = Item{lr[(4 * i) * 64 + lane], xd, xa, lr[(4 * i + 3) * 64 + lane], 0, 0, 0, 0};
+  }
+  W.roff[s] = nr ? off : 0;
+  W.rcnt[s] = nr;
+  return true;
+}
+
 // Stores the runs of slice s sorted by (col, dst) (rank sort; the keys are
 // unique because the runs of one destination are disjoint): the row's own
 // slot, or the spill pool after all slots.
@@ -783,6 +870,25 @@ __device__ inline void gdef_state(int x, int n, int st, int ow, uint64_t ho, con
 // Register-only update of one row (one wave, no LDS): every boundary of the
 // old list and of the edits sits in one lane.  Returns false (row untouched)
 // when the row has more than 64 boundaries; the caller then uses dev_gdef_row.
+// A row the definitions tile (touching spans of one device already merged by
+// the planner): the definitions are the new list.  One lane per row.
+__device__ inline void dev_gdef_full_lane(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t) {
+  const GRowRec gr = P.grec[t];
+  const ArrDev &a = A[gr.arr];
+  const int nds = gr.ndseg;
+  if (nds > a.cap) {
+    set_err(W.err, -8);
+    return;
+  }
+  Ivl *row = a.ivl + gr.grow * (int64_t)a.cap;
+  const Seg *ds = P.dseg + gr.dseg0;
+  for (int e = 0; e < nds; ++e) {
+    const Seg d = ds[e];
+    row[e] = Ivl{d.c0, d.dst, (1ull << d.dst) | ((d.flags & 1) ? (1ull << kHost) : 0ull)};
+  }
+  a.cnt[gr.grow] = nds;
+}
+
 __device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t) {
   const int lane = threadIdx.x & 63;
   const GRowRec gr = P.grec[t];

@@ -157,8 +157,9 @@ struct PlanDev {
   // level 2 (3-D arrays): slices = groups
   const int32_t *grp2;  // [ngrp] = aidx
   const int32_t *pos2;  // [ngrp] = plane
-  // GDEF update rows
+  // GDEF update rows: the ngfull rows the definitions tile come first
   int32_t ngrow;
+  int32_t ngfull;
   const GRowRec *grec;  // [ngrow]
   const Seg *dseg;
 };

@@ -14,15 +14,25 @@ namespace hd {
 
 constexpr int kGdefMaxB = 1024;
 
-// One wave per use row: the runs of the row, sorted, into the row's slot.
+// 64 use rows per one-wave workgroup: rows with few intervals, segments
+// and runs one per lane; the wave then takes the other rows of its 64 one
+// at a time.  The runs of each row, sorted, go to the row's slot.
 template <int CAP>
 __global__ __launch_bounds__(64) void k_runs(PlanDev P, const ArrDev *__restrict__ A, Work W) {
   __shared__ Ivl s_iv[CAP];
   __shared__ Run s_run[kMaxRunsRow];
-  const int s = blockIdx.x;
-  if (s >= P.nsl1) return;
-  const int nr = dev_runs_find(P, A, W, s, s_iv, s_run);
-  dev_runs_store(P, W, s, s_run, nr);
+  __shared__ int32_t s_lr[4 * kRunSlot * 64];
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  const bool done = s >= P.nsl1 || dev_runs_lane(P, A, W, s, s_lr);
+  uint64_t left = __ballot(!done);
+  while (left) {
+    const int l = __ffsll((unsigned long long)left) - 1;
+    left &= left - 1;
+    const int r = blockIdx.x * 64 + l;
+    const int nr = dev_runs_find(P, A, W, r, s_iv, s_run);
+    dev_runs_store(P, W, r, s_run, nr);
+    wave_lds_sync();
+  }
 }
 
 // One wave per 64 slices: band-start flags from the stored items -> chunk
@@ -54,10 +64,18 @@ __global__ __launch_bounds__(256) void k_compact_wg(PlanDev P, Level L, Work W, 
   dev_compact(P, L, W, out, hdr, out_cap, mode, s);
 }
 
-// Rows with at most 64 boundaries are updated register-only, one wave each;
-// larger rows are listed (count in *cnt) for k_gdef_large.
-__global__ __launch_bounds__(64) void k_gdef(PlanDev P, ArrDev *__restrict__ A, Work W, int32_t *cnt) {
-  for (int t = blockIdx.x; t < P.ngrow; t += gridDim.x) {
+// The first nfw workgroups copy the rows the definitions tile, one lane
+// per row; in the others, rows with at most 64 boundaries are updated
+// register-only, one wave each, and larger rows are listed (count in *cnt)
+// for k_gdef_large.
+__global__ __launch_bounds__(64) void k_gdef(PlanDev P, ArrDev *__restrict__ A, Work W, int32_t *cnt, int nfw) {
+  if ((int)blockIdx.x < nfw) {
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t < P.ngfull) dev_gdef_full_lane(P, A, W, t);
+    return;
+  }
+  const int g = (int)gridDim.x - nfw;
+  for (int t = P.ngfull + (int)blockIdx.x - nfw; t < P.ngrow; t += g) {
     if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list[atomicAdd(cnt, 1)] = t;
   }
 }
@@ -123,9 +141,9 @@ hipError_t launch_runs(const PlanDev &P, const ArrDev *A, const Work &W, int row
   if (P.nsl1 == 0) return hipSuccess;
   // LDS for the row's intervals sized to the row capacity
   if (row_cap <= 64)
-    hipLaunchKernelGGL(k_runs<64>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
+    hipLaunchKernelGGL(k_runs<64>, dim3(cdiv(P.nsl1, 64)), dim3(64), 0, s, P, A, W);
   else
-    hipLaunchKernelGGL(k_runs<kMaxCap>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
+    hipLaunchKernelGGL(k_runs<kMaxCap>, dim3(cdiv(P.nsl1, 64)), dim3(64), 0, s, P, A, W);
   return hipGetLastError();
 }
 
@@ -165,8 +183,10 @@ hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s
   const int p = g_ovf_parity;
   g_ovf_parity ^= 1;
   int32_t *cur = W.ovf_cnt + p, *other = W.ovf_cnt + (1 - p);
-  const int grid = P.ngrow < (1 << 20) ? P.ngrow : (1 << 20);
-  hipLaunchKernelGGL(k_gdef, dim3(grid), dim3(64), 0, s, P, A, W, cur);
+  const int nfw = cdiv(P.ngfull, 64);
+  const int rest = P.ngrow - P.ngfull;
+  const int grid = nfw + (rest < (1 << 20) ? rest : (1 << 20));
+  hipLaunchKernelGGL(k_gdef, dim3(grid), dim3(64), 0, s, P, A, W, cur, nfw);
   hipLaunchKernelGGL(k_gdef_large, dim3(kGdefLargeGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur, other);
   return hipGetLastError();
 }

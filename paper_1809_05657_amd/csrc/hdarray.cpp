@@ -1077,7 +1077,12 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   P.has3d = has3d;
   P.nsl1 = (int32_t)grow1.size();
   P.ngrp = (int32_t)grp_aidx.size();
+  // rows the definitions tile first (their update is a plain copy, one lane
+  // per row); the order of the other rows is kept
+  std::stable_partition(grec.begin(), grec.end(), [](const GRowRec &g) { return g.full != 0; });
   P.ngrow = (int32_t)grec.size();
+  P.ngfull = 0;
+  for (const GRowRec &g : grec) P.ngfull += g.full ? 1 : 0;
   pl->nsl1 = P.nsl1;
   pl->ngrp = P.ngrp;
   pl->ngrow = P.ngrow;
