@@ -205,9 +205,12 @@ int hdarray_reduce(hd_array_t *a, void *res, hd_reduce_t op, int part);
  * communication sets, packs, unpacks, kernels and GDEF updates — as one
  * persistent kernel (phases separated by grid-wide barriers with a bounded
  * wait) replayed from a HIP graph.  Results are bit-identical to running the
- * calls one by one.  A barrier that times out (workgroups not co-resident)
- * makes the launch exit early; the next synchronising call then returns
- * HD_EHIP. */
+ * calls one by one.  Within a batch a use row may produce at most 64 runs
+ * and a GDEF row update at most 256 interval boundaries (the per-workgroup
+ * scratch is kept small so that four workgroups share a CU); beyond that the
+ * next synchronising call returns HD_ECAPACITY.  A barrier that times out
+ * (workgroups not co-resident) makes the launch exit early; the next
+ * synchronising call then returns HD_EHIP. */
 int hdarray_batch_begin(void);
 int hdarray_batch_end(void);
 int hdarray_batch_run(int batch);

@@ -7,8 +7,8 @@
 //   phases: chunk scans, prefixes and padding in block 0, writes)
 //   [3-D arrays: level-1 compaction in block 0, then level-2 stacking]
 //   -> pack + unpack (one pass) with the GDEF update -> user kernels
-//   (Jacobi / triangular / copy tiles of every box; each wave takes a
-//   contiguous range of tiles).
+//   (Jacobi / triangular / copy tiles of every box, dealt round-robin over
+//   the waves).
 // The barrier spins with a bounded wait on the device clock: if a barrier
 // does not complete within the limit (workgroups not co-resident), the
 // kernel records an error and every workgroup leaves, so the launch always
@@ -21,12 +21,18 @@
 namespace hd {
 
 constexpr int kBWaves = 4;
-constexpr int kBatchMaxB = 512;  // boundaries of one GDEF row update in a batch
+// per-wave scratch of a batch, smaller than the per-call kernels' so that
+// four workgroups fit a CU: boundaries of one GDEF row update, runs of one
+// use row, items of a band held in LDS (longer lists are searched in global
+// memory; more boundaries or runs than this raise HD_ECAPACITY)
+constexpr int kBatchMaxB = 256;
+constexpr int kBatchRuns = 64;
+constexpr int kBatchHeads = 64;
 
 // per-wave LDS: union of the runs scratch and the GDEF scratch
 struct RunsLds {
   Ivl iv[kMaxCap];
-  Run rr[kMaxRunsRow];
+  Run rr[kBatchRuns];
 };
 struct GdefLdsB {
   Ivl iv[kMaxCap];
@@ -34,12 +40,18 @@ struct GdefLdsB {
   uint64_t hold[kBatchMaxB];
 };
 struct HeadsLds {
-  Item p[kHeadLds], w[kHeadLds];
+  Item p[kBatchHeads], w[kBatchHeads];
+};
+// runs of up to 8 per row found one row per lane
+constexpr int kBatchLaneRuns = 8;
+struct LaneRunsLds {
+  int32_t lr[4 * kBatchLaneRuns * 64];
 };
 union WaveLds {
   RunsLds r;
   GdefLdsB g;
   HeadsLds h;
+  LaneRunsLds l;
 };
 
 // Grid barrier on a monotonically increasing counter (zeroed before the
@@ -103,8 +115,19 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     ++ph;
   };
   stamp();
-  // runs of every use row
-  for (int s = gw; s < B.P.nsl1; s += nw) dev_runs(B.P, B.A, B.W, s, my.r.iv, my.r.rr);
+  // runs of every use row: 64 rows per wave, one per lane where the row is
+  // simple, the others by the whole wave
+  for (int c = gw; c * 64 < B.P.nsl1; c += nw) {
+    const int s = c * 64 + lane;
+    const bool done = s >= B.P.nsl1 || dev_runs_lane<kBatchLaneRuns>(B.P, B.A, B.W, s, my.l.lr);
+    uint64_t left = __ballot(!done);
+    wave_lds_sync();
+    while (left) {
+      const int l = __ffsll((unsigned long long)left) - 1;
+      left &= left - 1;
+      dev_runs(B.P, B.A, B.W, c * 64 + l, my.r.iv, my.r.rr, kBatchRuns);
+    }
+  }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   stamp();
   for (int c = gw; c * 64 < B.L1.nsl; c += nw) dev_bandflags(B.L1, c * 64 + lane);
@@ -115,7 +138,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   stamp();
   {
     const int nb = B.L1.nsl ? *B.L1.nb : 0;
-    for (int b = gw; b < nb; b += nw) dev_heads(B.L1, b, nb, my.h.p, my.h.w);
+    for (int b = gw; b < nb; b += nw) dev_heads(B.L1, b, nb, my.h.p, my.h.w, kBatchHeads);
     dev_compact_reset(B.P, B.cs);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
@@ -134,7 +157,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     stamp();
     {
       const int nb = B.L2.nsl ? *B.L2.nb : 0;
-      for (int b = gw; b < nb; b += nw) dev_heads(B.L2, b, nb, my.h.p, my.h.w);
+      for (int b = gw; b < nb; b += nw) dev_heads(B.L2, b, nb, my.h.p, my.h.w, kBatchHeads);
       dev_compact_reset(B.P, B.cs);
     }
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
@@ -166,20 +189,23 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     }
   }
   {
+    // rows the definitions tile: one lane per row; the others one wave per row
+    for (int c = gw; c * 64 < B.P.ngfull; c += nw) {
+      const int t = c * 64 + lane;
+      if (t < B.P.ngfull) dev_gdef_full_lane(B.P, B.A, B.W, t);
+    }
     GdefLds S{my.g.iv, my.g.b, my.g.u, my.g.own, my.g.hold};
-    for (int t = gw; t < B.P.ngrow; t += nw)
+    for (int t = B.P.ngfull + gw; t < B.P.ngrow; t += nw)
       if (!dev_gdef_row_fast(B.P, B.A, B.W, t)) dev_gdef_row(B.P, B.A, B.W, t, S, kBatchMaxB);
   }
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   stamp();
-  // user kernels: each wave takes a contiguous range of tiles (one box
-  // search, then the box advances with the tile)
+  // user kernels: the tiles are dealt round-robin over the waves (four
+  // consecutive tiles per workgroup), so the waves running together cover
+  // neighbouring tiles, as the waves of a per-call launch do
   {
-    const int64_t t0 = B.ntiles * gw / nw, t1 = B.ntiles * (gw + 1) / nw;
-    int bi = t0 < t1 ? find_box(B.wb, B.nbox, t0) : 0;
-    for (int64_t t = t0; t < t1; ++t) {
-      while (bi + 1 < B.nbox && B.wb[bi + 1].tile0 <= t) ++bi;
-      const WorkBox bx = B.wb[bi];
+    for (int64_t t = gw; t < B.ntiles; t += nw) {
+      const WorkBox bx = B.wb[find_box(B.wb, B.nbox, t)];
       if (bx.kind == 1)
         dev_jacobi_tile<TH, false, HF>(bx, t - bx.tile0, B.A);
       else if (bx.kind == 5)
@@ -211,7 +237,7 @@ int batch_max_blocks(int th, int hf) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)pick(th, hf), 256, 0) != hipSuccess)
     return -1;
   if (occ < 1) occ = 1;
-  if (occ > 2) occ = 2;
+  if (occ > 4) occ = 4;
   // the compaction keeps one chunk per workgroup
   return ncu * occ < kCompactCarr ? ncu * occ : kCompactCarr;
 }

@@ -77,12 +77,12 @@ __device__ inline bool contains(const Item *it, int cnt, const Item &q) {
 // planner merges each destination's segments of a row, so they are
 // disjoint and sorted), then by column.  That order is a function of the
 // run set alone, so two rows have the same runs iff their rr lists are
-// equal.  iv (at least the row capacity) and rr (kMaxRunsRow runs) are LDS
+// equal.  iv (at least the row capacity) and rr (maxr runs) are LDS
 // scratch private to the wave.  Returns the run count (0 after a capacity
 // error, which is recorded).
 
 __device__ inline int dev_runs_find(const PlanDev &P, const ArrDev *__restrict__ A, const Work &W, int s, Ivl *iv,
-                                    Run *rr) {
+                                    Run *rr, int maxr = kMaxRunsRow) {
   const int lane = threadIdx.x & 63;
   const SliceRec sr = P.srec[s];
   const ArrDev &a = A[sr.arr];
@@ -128,13 +128,13 @@ __device__ inline int dev_runs_find(const PlanDev &P, const ArrDev *__restrict__
           const int c0 = max(iv[i].start, sc0);
           const int c1 = min((j < n) ? iv[j].start : W2, sc1);
           const int k = nr + __popcll(m & lanemask_lt());
-          if (k < kMaxRunsRow) rr[k] = Run{src, sdst, c0, c1};
+          if (k < maxr) rr[k] = Run{src, sdst, c0, c1};
         }
         nr += __popcll(m);
       }
     }
   }
-  if (nr > kMaxRunsRow) {
+  if (nr > maxr) {
     if (lane == 0) set_err(W.err, -8);
     nr = 0;
   }
@@ -143,16 +143,18 @@ __device__ inline int dev_runs_find(const PlanDev &P, const ArrDev *__restrict__
 }
 
 // One use row per lane, for rows with at most kLaneIvl intervals, kLaneSeg
-// use segments and kRunSlot runs (the common case: a few owners per row):
-// the intervals sit in registers, the runs are found in the same order as
-// by the wave (by segment, then column; consecutive needed intervals of one
-// owner merge), staged in the lane's own column of lr ([4 * kRunSlot][64]:
-// src, dst, a0, a1) and stored rank-sorted by (col, dst) into the row's
-// slot, exactly as the wave stores them.  Returns false, writing nothing,
-// for any other row.
+// use segments and LR runs (LR <= kRunSlot; the common case: a few owners
+// per row): the intervals sit in registers, the runs are found in the same
+// order as by the wave (by segment, then column; consecutive needed
+// intervals of one owner merge), staged in the lane's own column of lr
+// ([4 * LR][64]: src, dst, a0, a1) and stored rank-sorted by (col, dst) into
+// the row's slot, exactly as the wave stores them.  Returns false, writing
+// nothing, for any other row.
 constexpr int kLaneIvl = 8, kLaneSeg = 8;
+template <int LR = kRunSlot>
 __device__ inline bool dev_runs_lane(const PlanDev &P, const ArrDev *__restrict__ A, const Work &W, int s,
                                      int32_t *lr) {
+  static_assert(LR <= kRunSlot, "runs beyond the row's slot take the wave path");
   const int lane = threadIdx.x & 63;
   const SliceRec sr = P.srec[s];
   const ArrDev &a = A[sr.arr];
@@ -178,7 +180,7 @@ __device__ inline bool dev_runs_lane(const PlanDev &P, const ArrDev *__restrict_
   int nr = 0;
   bool over = false;
   auto emit = [&](int src, int dst, int a0, int a1) {
-    if (nr < kRunSlot) {
+    if (nr < LR) {
       lr[(4 * nr + 0) * 64 + lane] = src;
       lr[(4 * nr + 1) * 64 + lane] = dst;
       lr[(4 * nr + 2) * 64 + lane] = a0;
@@ -265,8 +267,8 @@ __device__ inline void dev_runs_store(const PlanDev &P, const Work &W, int s, co
 }
 
 __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, const Work &W, int s, Ivl *iv,
-                                Run *rr) {
-  const int nr = dev_runs_find(P, A, W, s, iv, rr);
+                                Run *rr, int maxr = kMaxRunsRow) {
+  const int nr = dev_runs_find(P, A, W, s, iv, rr, maxr);
   dev_runs_store(P, W, s, rr, nr);
   wave_lds_sync();
 }
@@ -411,18 +413,18 @@ __device__ inline int band_of(const Level &L, int s) {
 // head; its extent is found by walking the following bands while their
 // first slice holds it: the wave walks all its heads together, band by
 // band, reading each band's items once into LDS (sp: the previous slice,
-// sw: the band being walked; kHeadLds items each, larger lists are searched
-// in global memory).  Heads keep the item order and are stored at their
-// items' positions.
+// sw: the band being walked; hcap items each, larger lists are searched in
+// global memory).  Heads keep the item order and are stored at their items'
+// positions.
 constexpr int kHeadLds = 128;
 
-__device__ inline void lds_items(Item *dst, const Item *src, int cnt) {
+__device__ inline void lds_items(Item *dst, const Item *src, int cnt, int hcap) {
   const int lane = threadIdx.x & 63;
-  if (cnt <= kHeadLds)
+  if (cnt <= hcap)
     for (int k = lane; k < cnt; k += 64) dst[k] = src[k];
 }
 
-__device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *sw) {
+__device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *sw, int hcap = kHeadLds) {
   const int lane = threadIdx.x & 63;
   const int s0 = L.bandslice[b], s1 = L.bandslice[b + 1];
   const bool adj = s0 > 0 && L.grp[s0 - 1] == L.grp[s0] && L.pos[s0 - 1] + 1 == L.pos[s0];
@@ -446,7 +448,7 @@ __device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *
       n_to = L.ioff[t0];
     }
   }
-  lds_items(sp, prv, pc);
+  lds_items(sp, prv, pc, hcap);
   wave_lds_sync();
   int nh = 0;
   int64_t vol = 0;
@@ -456,7 +458,7 @@ __device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *
     bool head = false;
     if (k < cc) {
       it = cur[k];
-      head = !(adj && (pc <= kHeadLds ? contains(sp, pc, it) : contains(prv, pc, it)));
+      head = !(adj && (pc <= hcap ? contains(sp, pc, it) : contains(prv, pc, it)));
     }
     const uint64_t m = __ballot(head);
     int e = s1;
@@ -479,10 +481,10 @@ __device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *
       if (!cont) break;
       const Item *ti = L.items + toff;
       wave_lds_sync();
-      lds_items(sw, ti, tc);
+      lds_items(sw, ti, tc, hcap);
       wave_lds_sync();
       if (go) {
-        if (tc <= kHeadLds ? contains(sw, tc, it) : contains(ti, tc, it))
+        if (tc <= hcap ? contains(sw, tc, it) : contains(ti, tc, it))
           e = tend;
         else
           go = false;

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(64) void k_runs(PlanDev P, const ArrDev *__restrict
   __shared__ Run s_run[kMaxRunsRow];
   __shared__ int32_t s_lr[4 * kRunSlot * 64];
   const int s = blockIdx.x * 64 + threadIdx.x;
-  const bool done = s >= P.nsl1 || dev_runs_lane(P, A, W, s, s_lr);
+  const bool done = s >= P.nsl1 || dev_runs_lane<kRunSlot>(P, A, W, s, s_lr);
   uint64_t left = __ballot(!done);
   while (left) {
     const int l = __ffsll((unsigned long long)left) - 1;
