@@ -78,6 +78,71 @@ __device__ inline void store4(float *q, const float *o, const bool *wr, bool vec
   }
 }
 
+// ------------------------------------------------- unaligned rows (coalesced)
+// When a row cannot be read as float4 (row length or box start not a
+// multiple of 4), lane l takes columns tc + 64 e + l (e = 0..3) instead of
+// four consecutive ones, so every load and store covers 256 consecutive
+// bytes.  A cell's left / right neighbours come from the adjacent lane, from
+// lane 63 / 0 of the neighbouring group, or from the tile's edge columns.
+struct RowI {
+  float x[4], l[4], r[4];
+};
+
+__device__ inline RowI load_row_i(const float *__restrict__ in, int r, int rlim, int tc, int N1, int N2) {
+  const int lane = threadIdx.x & 63;
+  RowI q;
+  float el = 0.f, er = 0.f;
+  const bool ok = r >= 0 && r < N1 && r <= rlim;
+  const float *p = in + (int64_t)r * N2;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int col = tc + 64 * e + lane;
+    q.x[e] = ok && col < N2 ? p[col] : 0.f;
+  }
+  if (ok && lane == 0 && tc >= 1) el = p[tc - 1];
+  if (ok && lane == 63 && tc + 256 < N2) er = p[tc + 256];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float up = __shfl_up(q.x[e], 1), dn = __shfl_down(q.x[e], 1);
+    float prev = el, next = er;
+    if (e > 0) prev = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.x[e > 0 ? e - 1 : 0]), 63));
+    if (e < 3) next = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.x[e < 3 ? e + 1 : 3]), 0));
+    q.l[e] = lane > 0 ? up : prev;
+    q.r[e] = lane < 63 ? dn : next;
+  }
+  return q;
+}
+
+template <int TH, bool TRI, bool HF>
+__device__ inline void dev_jacobi_tile_i(const WorkBox &B, int tx, int r0, int r1, const float *__restrict__ in,
+                                         float *__restrict__ out, int N1, int N2) {
+  const int lane = threadIdx.x & 63;
+  const int tc = B.lo[2] + tx * 256;
+  RowI v[TH + 2];
+#pragma unroll
+  for (int k = 0; k < TH + 2; ++k) v[k] = load_row_i(in, r0 - 1 + k, r1, tc, N1, N2);
+#pragma unroll
+  for (int k = 1; k <= TH; ++k) {
+    const int i = r0 + k - 1;
+    if (i >= r1) break;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = tc + 64 * e + lane;
+      bool interior, write = j < B.hi[2];
+      if (TRI) {
+        write = write && j <= i;
+        interior = j >= 1 && j < i && i <= N1 - 2;
+      } else {
+        interior = i >= 1 && i <= N1 - 2 && j >= 1 && j <= N2 - 2;
+      }
+      float s = v[k].l[e] + v[k].r[e];
+      s = s + v[k - 1].x[e];
+      s = s + v[k + 1].x[e];
+      if (write) out[(int64_t)i * N2 + j] = interior ? s * 0.25f : v[k].x[e];
+    }
+  }
+}
+
 template <int TH, bool TRI, bool HF = true>
 __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A) {
   const int lane = threadIdx.x & 63;
@@ -93,6 +158,10 @@ __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDe
   float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
   const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
   const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
+  if (!vec) {
+    dev_jacobi_tile_i<TH, TRI, HF>(B, tx, r0, r1, in, out, N1, N2);
+    return;
+  }
   f4 v[TH + 2];
   float Lh[TH + 2], Rh[TH + 2];
   load_rows<TH>(in, r0, r1, c, N1, N2, vec, v, Lh, Rh);
