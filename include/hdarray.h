@@ -94,8 +94,9 @@ typedef struct {
  * hdarray_set_stencil_shape does; HD_S3D_SEG=N sets the number of planes
  * each row of the 3-D stencil kernels marches through (default 32);
  * HD_EVENT_SCOPE=system makes the runtime's inter-stream events use HIP's
- * default system-scope release instead of a device-scope one (a
- * measurement aid).  Returns the HIP device id (>= 0) or a negative
+ * default system-scope release instead of a device-scope one, and
+ * HD_RUNS_WAVE_MAX=N finds the runs of levels with fewer than N use rows
+ * with one wave per row instead of one lane per row (measurement aids).  Returns the HIP device id (>= 0) or a negative
  * error. */
 int hdarray_init(int argc, char **argv, const char *kpath, const char *dpath);
 

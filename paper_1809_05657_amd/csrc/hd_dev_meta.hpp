@@ -273,26 +273,6 @@ __device__ inline void dev_runs(const PlanDev &P, const ArrDev *__restrict__ A, 
   wave_lds_sync();
 }
 
-// Last-workgroup election: every workgroup calls this once after its
-// results are written; returns true in the one workgroup that finishes last,
-// which then sees every other workgroup's writes.  The counter returns to 0.
-__device__ inline bool last_workgroup(int32_t *done) {
-  __shared__ int s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int prev = atomicAdd(done, 1);
-    s_last = prev == (int)(gridDim.x * gridDim.y * gridDim.z) - 1;
-    if (s_last) {
-      *done = 0;
-      __threadfence();
-    }
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last != 0;
-}
-
 // -------------------------------------------------------------- band flags
 // Called by whole waves; s = 64 * chunk + lane.
 __device__ inline void dev_bandflags(const Level &L, int s) {

@@ -14,6 +14,17 @@ namespace hd {
 
 constexpr int kGdefMaxB = 1024;
 
+// One wave per use row (a measurement alternative; see launch_runs).
+template <int CAP>
+__global__ __launch_bounds__(64) void k_runs_wave(PlanDev P, const ArrDev *__restrict__ A, Work W) {
+  __shared__ Ivl s_iv[CAP];
+  __shared__ Run s_run[kMaxRunsRow];
+  const int s = blockIdx.x;
+  if (s >= P.nsl1) return;
+  const int nr = dev_runs_find(P, A, W, s, s_iv, s_run);
+  dev_runs_store(P, W, s, s_run, nr);
+}
+
 // 64 use rows per one-wave workgroup: rows with few intervals, segments
 // and runs one per lane; the wave then takes the other rows of its 64 one
 // at a time.  The runs of each row, sorted, go to the row's slot.
@@ -137,13 +148,26 @@ static void launch_bands(const Level &L, hipStream_t s) {
 // level 1: runs (the only step that reads GDEF), then band flags, band
 // scan, heads, compaction (mode 0: the final messages; mode 1: the level-2
 // items of 3-D arrays)
+// Levels of fewer use rows than g_runs_wave_max use one wave per row.  A
+// wave per row finishes the runs sooner on its own (25 vs 70 us on the
+// 8192-row Jacobi level next to the stencil kernel), but its many small
+// workgroups slow the stencil kernel they overlap more than that gains, so
+// the default (0) is the lane form everywhere.
+int g_runs_wave_max = 0;
+
 hipError_t launch_runs(const PlanDev &P, const ArrDev *A, const Work &W, int row_cap, hipStream_t s) {
   if (P.nsl1 == 0) return hipSuccess;
   // LDS for the row's intervals sized to the row capacity
-  if (row_cap <= 64)
+  if (P.nsl1 < g_runs_wave_max) {
+    if (row_cap <= 64)
+      hipLaunchKernelGGL(k_runs_wave<64>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
+    else
+      hipLaunchKernelGGL(k_runs_wave<kMaxCap>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
+  } else if (row_cap <= 64) {
     hipLaunchKernelGGL(k_runs<64>, dim3(cdiv(P.nsl1, 64)), dim3(64), 0, s, P, A, W);
-  else
+  } else {
     hipLaunchKernelGGL(k_runs<kMaxCap>, dim3(cdiv(P.nsl1, 64)), dim3(64), 0, s, P, A, W);
+  }
   return hipGetLastError();
 }
 

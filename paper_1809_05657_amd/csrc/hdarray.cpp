@@ -26,6 +26,7 @@ namespace hd {
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr, int64_t cap,
                           int mode, hipStream_t s);
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
+extern int g_runs_wave_max;
 hipError_t launch_runs(const PlanDev &P, const ArrDev *A, const Work &W, int row_cap, hipStream_t s);
 hipError_t launch_level1_tail(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
                               int mode, hipStream_t s);
@@ -328,6 +329,8 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
     if (v == 1 || v == 4) R.jacobi_waves = v;
   }
   if (const char *e = getenv("HD_JACOBI_ORDER")) R.jacobi_order = atoi(e) != 0;
+  g_runs_wave_max = 0;
+  if (const char *e = getenv("HD_RUNS_WAVE_MAX")) g_runs_wave_max = atoi(e);
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
   R.device = dev;

@@ -312,6 +312,69 @@ def test_random_programs_parity(hd, seed):
         same_call(rt, orc, [(res[0][i], res[1][i])], f"read {i}")
 
 
+@pytest.mark.parametrize("case", ["rows2d", "rows3d"])
+def test_many_rows_parity(hd, case):
+    """Levels with more than 32768 use rows, where the runs are found one
+    row per lane (with the wave taking the rows that do not fit): a tall
+    2-D array with column partitions, and a 3-D array of many rows."""
+    rng = np.random.default_rng(91)
+    rt, orc = hd.Runtime(), O.Oracle()
+    if case == "rows2d":
+        say("case many rows 40000x24 COL ndev=3")
+        A0 = rng.random((40000, 24), dtype=np.float32)
+        B0 = rng.random((40000, 24), dtype=np.float32)
+        g = prog.jacobi_blocks(rt, A0, B0, 3, kind=prog.COL)
+        o = prog.jacobi_blocks(orc, A0, B0, 3, kind=prog.COL)
+        names = ("jacAB", "jacBA")
+        coef = None
+    else:
+        say("case many rows 3-D (40, 1000, 12) ndev=8")
+        u0 = rng.random((40, 1000, 12), dtype=np.float32)
+        g = prog.stencil3d(rt, u0, 8)
+        o = prog.stencil3d(orc, u0, 8)
+        names = ("s3dUV", "s3dVU")
+        coef = [float(c) for c in S3D_COEFFS]
+    for it in range(3):
+        k, gi = (names[0], (0, 1)) if it % 2 == 0 else (names[1], (1, 0))
+        args = [] if coef is None else [coef]
+        rt.apply(k, g[2], [g[gi[0]], g[gi[1]]], *args)
+        orc.apply(k, o[2], [o[gi[0]], o[gi[1]]], *args)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"step {it}")
+    assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+
+
+def test_runs_wave_form_parity(hd):
+    """The one-wave-per-use-row form of the runs kernel (selected for small
+    levels through HD_RUNS_WAVE_MAX) gives the same messages and GDEF."""
+    say("case runs wave form (HD_RUNS_WAVE_MAX) block 130x520 ndev=8 and 3-D 12^3")
+    os.environ["HD_RUNS_WAVE_MAX"] = "1000000"
+    try:
+        rng = np.random.default_rng(17)
+        A0 = rng.random((130, 520), dtype=np.float32)
+        B0 = rng.random((130, 520), dtype=np.float32)
+        rt, orc = hd.Runtime(), O.Oracle()
+        g = prog.jacobi_blocks(rt, A0, B0, 8, True)
+        o = prog.jacobi_blocks(orc, A0, B0, 8, True)
+        for it in range(3):
+            k, gi = ("jacAB", (0, 1)) if it % 2 == 0 else ("jacBA", (1, 0))
+            rt.apply(k, g[2], [g[gi[0]], g[gi[1]]])
+            orc.apply(k, o[2], [o[gi[0]], o[gi[1]]])
+            same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"2-D step {it}")
+        u0 = rng.random((12, 12, 12), dtype=np.float32)
+        coef = [float(c) for c in S3D_COEFFS]
+        rt, orc = hd.Runtime(), O.Oracle()
+        g = prog.stencil3d(rt, u0, 8)
+        o = prog.stencil3d(orc, u0, 8)
+        for it in range(3):
+            k, gi = ("s3dUV", (0, 1)) if it % 2 == 0 else ("s3dVU", (1, 0))
+            rt.apply(k, g[2], [g[gi[0]], g[gi[1]]], coef)
+            orc.apply(k, o[2], [o[gi[0]], o[gi[1]]], coef)
+            same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"3-D step {it}")
+    finally:
+        del os.environ["HD_RUNS_WAVE_MAX"]
+        hd.Runtime()  # back to the default form for later tests
+
+
 def test_wide_rows_parity(hd):
     """60 column partitions of a 6 x 900 array: every row has about 118 runs
     (more than a row's run slot, so the spill pool is used) and about 180
