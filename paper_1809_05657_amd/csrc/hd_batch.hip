@@ -56,16 +56,20 @@ union WaveLds {
 
 // Grid barrier on a monotonically increasing counter (zeroed before the
 // launch).  Returns false if the run was abandoned (timeout or earlier error).
+// One thread per workgroup arrives with a release increment (after the
+// workgroup barrier, so it publishes the whole workgroup's writes), polls
+// with relaxed loads and then takes one acquire fence: an acquire on every
+// poll would invalidate the XCD's L2 once per poll, slowing every other
+// workgroup on it.
 __device__ inline bool grid_sync(unsigned *bar, unsigned nblk, unsigned &target, int32_t *err, int64_t limit) {
   __shared__ int s_ok;
   __syncthreads();
   target += nblk;
   if (threadIdx.x == 0) {
-    __threadfence();
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     const int64_t t0 = wall_clock64();
     int ok = 1;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == -9 ||
           wall_clock64() - t0 > limit) {
         atomicCAS(err, 0, -9);
@@ -74,11 +78,28 @@ __device__ inline bool grid_sync(unsigned *bar, unsigned nblk, unsigned &target,
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
   return s_ok != 0;
+}
+
+// Wave-uniform reads of data the launch never writes, through the constant
+// (address space 4) path.
+__device__ inline int32_t load_int_const(const int32_t *p, int64_t i) {
+  typedef const __attribute__((address_space(4))) int32_t cint;
+  return ((cint *)p)[i];
+}
+__device__ inline WorkBox load_box_const(const WorkBox *wb, int i) {
+  typedef const __attribute__((address_space(4))) int32_t cint;
+  static_assert(sizeof(WorkBox) % 4 == 0, "box words");
+  cint *p = (cint *)(wb + i);
+  WorkBox b;
+  int32_t *q = reinterpret_cast<int32_t *>(&b);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(WorkBox) / 4); ++k) q[k] = p[k];
+  return b;
 }
 
 // the three compaction phases (modes 0 and 2) with their barriers
@@ -202,10 +223,16 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   stamp();
   // user kernels: the tiles are dealt round-robin over the waves (four
   // consecutive tiles per workgroup), so the waves running together cover
-  // neighbouring tiles, as the waves of a per-call launch do
+  // neighbouring tiles, as the waves of a per-call launch do.  The tile's
+  // box comes from the per-tile table and the box table, both read-only in
+  // this launch, with wave-uniform indices: loads through the constant
+  // cache, which do not wait for the previous tile's stores (a search over
+  // the boxes with vector loads cost about ten dependent round trips per
+  // tile).
   {
-    for (int64_t t = gw; t < B.ntiles; t += nw) {
-      const WorkBox bx = B.wb[find_box(B.wb, B.nbox, t)];
+    const int ugw = __builtin_amdgcn_readfirstlane(gw);
+    for (int64_t t = ugw; t < B.ntiles; t += nw) {
+      const WorkBox bx = load_box_const(B.wb, load_int_const(B.tbox, t));
       if (bx.kind == 1)
         dev_jacobi_tile<TH, false, HF>(bx, t - bx.tile0, B.A);
       else if (bx.kind == 5)

@@ -190,6 +190,7 @@ struct BatchArgs {
   int64_t tab_cap;
   uint32_t *stg;
   const WorkBox *wb;
+  const int32_t *tbox;  // box index of every tile
   int nbox;
   int64_t ntiles;
   unsigned *bar;

@@ -2046,6 +2046,8 @@ struct Batch {
   Plan pl;
   std::vector<WorkBox> boxes;
   WorkBox *d_wb = nullptr;
+  int32_t *d_tbox = nullptr;  // box of every tile (sized for the smallest tile height)
+  int64_t tbox_cap = 0;
   int64_t ntiles = 0;
   int th = 16, hf = 1, grid = 0;
   MsgRec *tab = nullptr;
@@ -2071,6 +2073,7 @@ static void free_batches() {
     drop_graph(b);
     dfree(b->pl.mem);
     dfree(b->d_wb);
+    dfree(b->d_tbox);
     dfree(b->tab);
     dfree(b->hdr);
     dfree(b->bar);
@@ -2103,9 +2106,16 @@ static int batch_config(Batch *b, int th, int hf) {
     t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, th);
   }
   b->ntiles = t0;
+  if (t0 > b->tbox_cap) return fail(HD_EINVAL);
+  std::vector<int32_t> tb((size_t)t0);
+  for (size_t i = 0; i < b->boxes.size(); ++i) {
+    const int64_t e = i + 1 < b->boxes.size() ? b->boxes[i + 1].tile0 : t0;
+    std::fill(tb.begin() + b->boxes[i].tile0, tb.begin() + e, (int32_t)i);
+  }
   HIPCK(hipStreamSynchronize(R.data));
   if (!b->boxes.empty())
     HIPCK(hipMemcpy(b->d_wb, b->boxes.data(), sizeof(WorkBox) * b->boxes.size(), hipMemcpyHostToDevice));
+  if (t0 > 0) HIPCK(hipMemcpy(b->d_tbox, tb.data(), sizeof(int32_t) * t0, hipMemcpyHostToDevice));
   b->th = th;
   b->hf = hf;
   b->grid = batch_max_blocks(th, hf);
@@ -2159,7 +2169,15 @@ extern "C" int hdarray_batch_end(void) {
   b->hdr = (MsgHdr *)dalloc(sizeof(MsgHdr));
   b->bar = (unsigned *)dalloc(512);  // barrier counter, then 32 phase-clock stamps at byte 256
   b->d_wb = (WorkBox *)dalloc(sizeof(WorkBox) * (boxes.size() + 1));
-  if (!b->tab || !b->hdr || !b->bar || !b->d_wb) return fail(HD_ENOMEM);
+  // the tile -> box table, sized for the largest tile count of the tile
+  // heights the batch may be configured with
+  for (int th : {4, 8, 16}) {
+    int64_t nt = 0;
+    for (const WorkBox &w : boxes) nt += tiles_for(w.kind, w, R.arrays[w.aout]->esize, th);
+    b->tbox_cap = std::max(b->tbox_cap, nt);
+  }
+  b->d_tbox = (int32_t *)dalloc(sizeof(int32_t) * (b->tbox_cap + 1));
+  if (!b->tab || !b->hdr || !b->bar || !b->d_wb || !b->d_tbox) return fail(HD_ENOMEM);
   HIPCK(hipMemset(b->hdr, 0, sizeof(MsgHdr)));
   HIPCK(hipMemset(b->bar, 0, 256));
   if (batch_config(b, 16, 1) != HD_OK) return g_last_error;
@@ -2186,6 +2204,7 @@ static int batch_capture(Batch *b) {
   a.tab_cap = b->tab_cap;
   a.stg = (uint32_t *)R.staging;
   a.wb = b->d_wb;
+  a.tbox = b->d_tbox;
   a.nbox = (int)b->boxes.size();
   a.ntiles = b->ntiles;
   a.bar = b->bar;
