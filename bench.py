@@ -342,12 +342,16 @@ def bench_batched(hd, rt, steps, warmup):
             "config": {"workload": "batched: 64 arrays, sides log-uniform [512,4096], 2-32 irregular row "
                                    "partitions, 5-point or lower-triangular stencil, ping-pong",
                        "cells": cells, "plain_steps_per_s": 1.0 / t_plain, "batched_over_plain": t_plain / t_batch,
-                       "autotuned_rows": cfg >> 8, "autotuned_row_first": cfg & 255,
+                       "autotuned_rows": (cfg >> 8) & 255, "autotuned_row_first": cfg & 255,
+                       "autotuned_workgroups_per_cu": cfg >> 16,
+                       # phases of the persistent launch up to the message table (device-clock stamps
+                       # of its workgroup 0); the rest of the step (pack + unpack and GDEF update in the
+                       # same launch, then the user-kernel launch) is the step's launch time minus these
                        "batch_phases_us": dict(zip(("runs", "band_flags", "band_scan", "heads", "compact_scan",
-                                                    "compact_prefix", "compact_write", "pack_unpack_gdef",
-                                                    "kernels"), phases))},
+                                                    "compact_prefix", "compact_write"), phases)),
+                       "pack_gdef_and_kernels_us": kms / kc * 1e3 - sum(phases[:7])},
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch + k_batch_tiles (one graph)",
                          "bytes_per_launch": bytes_step, "avg_launch_us": kms / kc * 1e3}}
 
 

@@ -6,9 +6,12 @@
 //   runs -> band flags -> band scan (block 0) -> heads -> compaction (three
 //   phases: chunk scans, prefixes and padding in block 0, writes)
 //   [3-D arrays: level-1 compaction in block 0, then level-2 stacking]
-//   -> pack + unpack (one pass) with the GDEF update -> user kernels
-//   (Jacobi / triangular / copy tiles of every box, dealt round-robin over
-//   the waves).
+//   -> pack + unpack (one pass) with the GDEF update.
+// The user kernels (Jacobi / triangular / copy tiles of every box) follow
+// as a second launch in the same graph, one wave per tile as in the
+// per-call kernels: the persistent grid keeps only a few waves per CU
+// (its workgroups must all be resident for the barriers), too few loads in
+// flight for the stencils, while a one-wave launch fills every CU.
 // The barrier spins with a bounded wait on the device clock: if a barrier
 // does not complete within the limit (workgroups not co-resident), the
 // kernel records an error and every workgroup leaves, so the launch always
@@ -85,23 +88,6 @@ __device__ inline bool grid_sync(unsigned *bar, unsigned nblk, unsigned &target,
   return s_ok != 0;
 }
 
-// Wave-uniform reads of data the launch never writes, through the constant
-// (address space 4) path.
-__device__ inline int32_t load_int_const(const int32_t *p, int64_t i) {
-  typedef const __attribute__((address_space(4))) int32_t cint;
-  return ((cint *)p)[i];
-}
-__device__ inline WorkBox load_box_const(const WorkBox *wb, int i) {
-  typedef const __attribute__((address_space(4))) int32_t cint;
-  static_assert(sizeof(WorkBox) % 4 == 0, "box words");
-  cint *p = (cint *)(wb + i);
-  WorkBox b;
-  int32_t *q = reinterpret_cast<int32_t *>(&b);
-#pragma unroll
-  for (int k = 0; k < (int)(sizeof(WorkBox) / 4); ++k) q[k] = p[k];
-  return b;
-}
-
 // the three compaction phases (modes 0 and 2) with their barriers
 __device__ inline bool batch_compact(const BatchArgs &B, const Level &L, int mode, unsigned nblk, unsigned &target,
                                      int32_t *err, int &ph, int64_t *lds) {
@@ -117,7 +103,6 @@ __device__ inline bool batch_compact(const BatchArgs &B, const Level &L, int mod
   return true;
 }
 
-template <int TH, bool HF>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   __shared__ WaveLds s_lds[kBWaves];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -215,64 +200,73 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
       const int t = c * 64 + lane;
       if (t < B.P.ngfull) dev_gdef_full_lane(B.P, B.A, B.W, t);
     }
+    // the other rows 64 at a time: small rows one per lane (a row with no
+    // definition and no holder-adding run is left as it is), the larger
+    // ones by the whole wave, one after the other
     GdefLds S{my.g.iv, my.g.b, my.g.u, my.g.own, my.g.hold};
-    for (int t = B.P.ngfull + gw; t < B.P.ngrow; t += nw)
-      if (!dev_gdef_row_fast(B.P, B.A, B.W, t)) dev_gdef_row(B.P, B.A, B.W, t, S, kBatchMaxB);
-  }
-  if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
-  stamp();
-  // user kernels: the tiles are dealt round-robin over the waves (four
-  // consecutive tiles per workgroup), so the waves running together cover
-  // neighbouring tiles, as the waves of a per-call launch do.  The tile's
-  // box comes from the per-tile table and the box table, both read-only in
-  // this launch, with wave-uniform indices: loads through the constant
-  // cache, which do not wait for the previous tile's stores (a search over
-  // the boxes with vector loads cost about ten dependent round trips per
-  // tile).
-  {
-    const int ugw = __builtin_amdgcn_readfirstlane(gw);
-    for (int64_t t = ugw; t < B.ntiles; t += nw) {
-      const WorkBox bx = load_box_const(B.wb, load_int_const(B.tbox, t));
-      if (bx.kind == 1)
-        dev_jacobi_tile<TH, false, HF>(bx, t - bx.tile0, B.A);
-      else if (bx.kind == 5)
-        dev_jacobi_tile<TH, true, HF>(bx, t - bx.tile0, B.A);
-      else if (bx.kind == 2)
-        dev_copy_tile(bx, t - bx.tile0, B.A);
+    const int nrest = B.P.ngrow - B.P.ngfull;
+    for (int c = gw; c * 64 < nrest; c += nw) {
+      const int t0 = B.P.ngfull + c * 64;
+      const bool done = c * 64 + lane >= nrest || dev_gdef_small_lane(B.P, B.A, B.W, t0 + lane);
+      uint64_t m = __ballot(!done);
+      while (m) {
+        const int t = t0 + __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        if (!dev_gdef_row_fast(B.P, B.A, B.W, t)) dev_gdef_row(B.P, B.A, B.W, t, S, kBatchMaxB);
+      }
     }
   }
-  stamp();
+  // the user kernels follow in their own launch (stream order makes the
+  // unpacked halos visible to them)
 }
 
 __global__ void k_zero_bar(unsigned *bar) {
   if (threadIdx.x == 0) *bar = 0u;
 }
 
-typedef void (*batch_kernel_t)(BatchArgs);
-
-// th: rows per stencil tile; hf: tiles numbered along rows first
-static batch_kernel_t pick(int th, int hf) {
-  if (th == 4) return hf ? k_batch<4, true> : k_batch<4, false>;
-  if (th == 16) return hf ? k_batch<16, true> : k_batch<16, false>;
-  return hf ? k_batch<8, true> : k_batch<8, false>;
+// The user kernels of a batch: one wave per tile; the tile's box from the
+// per-tile table (both tables read-only, indices uniform per workgroup).
+template <int TH, bool HF>
+__global__ __launch_bounds__(64) void k_batch_tiles(const WorkBox *__restrict__ wb, const int32_t *__restrict__ tbox,
+                                                    const ArrDev *__restrict__ A, int64_t ntiles) {
+  const int64_t t = xcd_remap(blockIdx.x, ntiles);
+  const WorkBox bx = wb[tbox[t]];
+  if (bx.kind == 1)
+    dev_jacobi_tile<TH, false, HF>(bx, t - bx.tile0, A);
+  else if (bx.kind == 5)
+    dev_jacobi_tile<TH, true, HF>(bx, t - bx.tile0, A);
+  else if (bx.kind == 2)
+    dev_copy_tile(bx, t - bx.tile0, A);
 }
 
-int batch_max_blocks(int th, int hf) {
+typedef void (*tiles_kernel_t)(const WorkBox *, const int32_t *, const ArrDev *, int64_t);
+
+// th: rows per stencil tile; hf: tiles numbered along rows first
+static tiles_kernel_t pick_tiles(int th, int hf) {
+  if (th == 4) return hf ? k_batch_tiles<4, true> : k_batch_tiles<4, false>;
+  if (th == 16) return hf ? k_batch_tiles<16, true> : k_batch_tiles<16, false>;
+  return hf ? k_batch_tiles<8, true> : k_batch_tiles<8, false>;
+}
+
+int batch_max_blocks(int max_per_cu) {
   int dev = 0, ncu = 0, occ = 0;
   if (hipGetDevice(&dev) != hipSuccess) return -1;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)pick(th, hf), 256, 0) != hipSuccess)
-    return -1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void *)k_batch, 256, 0) != hipSuccess) return -1;
   if (occ < 1) occ = 1;
-  if (occ > 4) occ = 4;
+  if (occ > max_per_cu) occ = max_per_cu;
   // the compaction keeps one chunk per workgroup
   return ncu * occ < kCompactCarr ? ncu * occ : kCompactCarr;
 }
 
-// the step as two nodes on one stream: zero the barrier, run the batch
+// the step as three nodes on one stream: zero the barrier, run the
+// persistent metadata + communication kernel, then the user kernels
 hipError_t launch_batch(const BatchArgs &a, int th, int hf, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_bar, dim3(1), dim3(64), 0, s, a.bar);
-  hipLaunchKernelGGL(pick(th, hf), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(256), 0, s, a);
+  if (a.ntiles > 0)
+    hipLaunchKernelGGL(pick_tiles(th, hf), dim3((unsigned)a.ntiles), dim3(64), 0, s, a.wb, a.tbox,
+                       (const ArrDev *)a.A, a.ntiles);
   return hipGetLastError();
 }
 

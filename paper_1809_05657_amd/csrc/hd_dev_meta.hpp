@@ -871,6 +871,154 @@ __device__ inline void dev_gdef_full_lane(const PlanDev &P, ArrDev *__restrict__
   a.cnt[gr.grow] = nds;
 }
 
+// Lane-per-row update of a small row (at most kGL old intervals, kGR
+// holder-adding runs and kGD definitions): the boundaries and the state at
+// each (the old interval containing it, holders added by the runs covering
+// it, then the definitions covering it) as in the wave form, in registers.
+// Returns false, leaving the row alone, when the row is larger or the
+// definitions tile it (other paths take those rows).  A row with neither
+// runs nor definitions keeps its (already merged) list.
+constexpr int kGL = 4, kGR = 4, kGD = 2, kGB = kGL + 2 * (kGR + kGD);
+
+struct SmallRow {
+  int n, nrun, nds;
+  int st[kGL], ow[kGL];
+  uint64_t ho[kGL];
+  int ra0[kGR], ra1[kGR], rd[kGR];
+  int dc0[kGD], dc1[kGD], dd[kGD];
+  uint64_t dh[kGD];
+};
+
+__device__ inline void small_state(const SmallRow &R, int x, int &own, uint64_t &hol) {
+  own = R.ow[0];
+  hol = R.ho[0];
+#pragma unroll
+  for (int k = 1; k < kGL; ++k)
+    if (k < R.n && R.st[k] <= x) {
+      own = R.ow[k];
+      hol = R.ho[k];
+    }
+#pragma unroll
+  for (int e = 0; e < kGR; ++e)
+    if (e < R.nrun && R.ra0[e] <= x && x < R.ra1[e]) hol |= 1ull << R.rd[e];
+#pragma unroll
+  for (int e = 0; e < kGD; ++e)
+    if (e < R.nds && R.dc0[e] <= x && x < R.dc1[e]) {
+      own = R.dd[e];
+      hol = R.dh[e];
+    }
+}
+
+__device__ inline bool dev_gdef_small_lane(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t) {
+  const GRowRec gr = P.grec[t];
+  if (gr.full) return false;
+  const int sl = gr.slice;
+  SmallRow R;
+  R.nds = gr.ndseg;
+  R.nrun = sl >= 0 ? W.rcnt[sl] : 0;
+  if (R.nrun == 0 && R.nds == 0) return true;
+  ArrDev &a = A[gr.arr];
+  const int64_t grow = gr.grow;
+  R.n = a.cnt[grow];
+  if (R.n > kGL || R.nrun > kGR || R.nds > kGD) return false;
+  Ivl *row = a.ivl + grow * (int64_t)a.cap;
+  const int roff = sl >= 0 ? W.roff[sl] : 0;
+  const int W2 = (int)a.n[2];
+#pragma unroll
+  for (int k = 0; k < kGL; ++k) {
+    Ivl v{0x7fffffff, 0, 0ull};
+    if (k < R.n) v = row[k];
+    R.st[k] = v.start;
+    R.ow[k] = v.owner;
+    R.ho[k] = v.holders;
+  }
+#pragma unroll
+  for (int e = 0; e < kGR; ++e) {
+    R.ra0[e] = R.ra1[e] = R.rd[e] = 0;
+    if (e < R.nrun) {
+      const Item r = W.runs[roff + e];
+      R.ra0[e] = r.a0;
+      R.ra1[e] = r.a1;
+      R.rd[e] = r.dst;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kGD; ++e) {
+    R.dc0[e] = R.dc1[e] = R.dd[e] = 0;
+    R.dh[e] = 0ull;
+    if (e < R.nds) {
+      const Seg d = P.dseg[gr.dseg0 + e];
+      R.dc0[e] = d.c0;
+      R.dc1[e] = d.c1;
+      R.dd[e] = d.dst;
+      R.dh[e] = (1ull << d.dst) | ((d.flags & 1) ? (1ull << kHost) : 0ull);
+    }
+  }
+  // boundaries: old starts, run starts / ends, definition starts / ends (an
+  // end at the row's width is the wrap to 0, already a start)
+  int b[kGB];
+  bool ok[kGB];
+#pragma unroll
+  for (int k = 0; k < kGL; ++k) {
+    b[k] = R.st[k];
+    ok[k] = k < R.n;
+  }
+#pragma unroll
+  for (int e = 0; e < kGR; ++e) {
+    b[kGL + 2 * e] = R.ra0[e];
+    b[kGL + 2 * e + 1] = R.ra1[e] < W2 ? R.ra1[e] : 0;
+    ok[kGL + 2 * e] = ok[kGL + 2 * e + 1] = e < R.nrun;
+  }
+#pragma unroll
+  for (int e = 0; e < kGD; ++e) {
+    b[kGL + 2 * kGR + 2 * e] = R.dc0[e];
+    b[kGL + 2 * kGR + 2 * e + 1] = R.dc1[e] < W2 ? R.dc1[e] : 0;
+    ok[kGL + 2 * kGR + 2 * e] = ok[kGL + 2 * kGR + 2 * e + 1] = e < R.nds;
+  }
+  // a boundary stays if it is the first of its value and the state there
+  // differs from the state at the next smaller boundary value
+  bool keep[kGB];
+  int nn = 0;
+#pragma unroll
+  for (int j = 0; j < kGB; ++j) {
+    bool first = ok[j];
+    int pv = -1;
+#pragma unroll
+    for (int i = 0; i < kGB; ++i) {
+      if (!ok[i]) continue;
+      if (i < j && b[i] == b[j]) first = false;
+      if (b[i] < b[j] && b[i] > pv) pv = b[i];
+    }
+    bool k = first;
+    if (first && pv >= 0) {
+      int o0, o1;
+      uint64_t h0, h1;
+      small_state(R, b[j], o0, h0);
+      small_state(R, pv, o1, h1);
+      k = o0 != o1 || h0 != h1;
+    }
+    keep[j] = k;
+    nn += k ? 1 : 0;
+  }
+  if (nn > a.cap) {
+    set_err(W.err, -8);
+    return true;
+  }
+#pragma unroll
+  for (int j = 0; j < kGB; ++j) {
+    if (!keep[j]) continue;
+    int r = 0;
+#pragma unroll
+    for (int i = 0; i < kGB; ++i) r += (keep[i] && b[i] < b[j]) ? 1 : 0;
+    int o;
+    uint64_t h;
+    small_state(R, b[j], o, h);
+    row[r] = Ivl{b[j], o, h};
+  }
+  a.cnt[grow] = nn;
+  return true;
+}
+
 __device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t) {
   const int lane = threadIdx.x & 63;
   const GRowRec gr = P.grec[t];

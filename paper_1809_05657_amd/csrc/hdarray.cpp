@@ -45,7 +45,7 @@ hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const Ar
                          uint32_t *pi, void *res, hipStream_t s);
 hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipStream_t s);
 int reduce_blocks();
-int batch_max_blocks(int th, int hf);
+int batch_max_blocks(int max_per_cu);
 hipError_t launch_batch(const BatchArgs &a, int th, int hf, int grid, hipStream_t s);
 int64_t adj_tiles(const WorkBox &B, const int64_t *n);
 hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const float *coef, double *part,
@@ -2049,7 +2049,7 @@ struct Batch {
   int32_t *d_tbox = nullptr;  // box of every tile (sized for the smallest tile height)
   int64_t tbox_cap = 0;
   int64_t ntiles = 0;
-  int th = 16, hf = 1, grid = 0;
+  int th = 16, hf = 1, occ = 2, grid = 0;
   MsgRec *tab = nullptr;
   MsgHdr *hdr = nullptr;
   int64_t tab_cap = 0;
@@ -2057,7 +2057,7 @@ struct Batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int64_t epoch = -1;
-  int gth = 0, ghf = 0;
+  int gth = 0, ghf = 0, ggrid = 0;
 };
 
 static void drop_graph(Batch *b) {
@@ -2099,7 +2099,7 @@ static void last_table(MsgRec **tab, MsgHdr **hdr) {
   }
 }
 
-static int batch_config(Batch *b, int th, int hf) {
+static int batch_config(Batch *b, int th, int hf, int occ) {
   int64_t t0 = 0;
   for (WorkBox &w : b->boxes) {
     w.tile0 = t0;
@@ -2118,7 +2118,8 @@ static int batch_config(Batch *b, int th, int hf) {
   if (t0 > 0) HIPCK(hipMemcpy(b->d_tbox, tb.data(), sizeof(int32_t) * t0, hipMemcpyHostToDevice));
   b->th = th;
   b->hf = hf;
-  b->grid = batch_max_blocks(th, hf);
+  b->occ = occ;
+  b->grid = batch_max_blocks(occ);
   if (b->grid <= 0) return fail(HD_EHIP);
   return HD_OK;
 }
@@ -2180,7 +2181,7 @@ extern "C" int hdarray_batch_end(void) {
   if (!b->tab || !b->hdr || !b->bar || !b->d_wb || !b->d_tbox) return fail(HD_ENOMEM);
   HIPCK(hipMemset(b->hdr, 0, sizeof(MsgHdr)));
   HIPCK(hipMemset(b->bar, 0, 256));
-  if (batch_config(b, 16, 1) != HD_OK) return g_last_error;
+  if (batch_config(b, 16, 1, 2) != HD_OK) return g_last_error;
   R.batches.push_back(b);
   R.stats.plans_built++;
   return (int)R.batches.size() - 1;
@@ -2224,6 +2225,7 @@ static int batch_capture(Batch *b) {
   b->epoch = R.ws_epoch;
   b->gth = b->th;
   b->ghf = b->hf;
+  b->ggrid = b->grid;
   return HD_OK;
 }
 
@@ -2231,7 +2233,7 @@ extern "C" int hdarray_batch_run(int id) {
   if (!R.inited || R.recording) return fail(HD_ESTATE);
   if (id < 0 || id >= (int)R.batches.size() || !R.batches[id]) return fail(HD_EINVAL);
   Batch *b = R.batches[id];
-  if (!b->exec || b->epoch != R.ws_epoch || b->gth != b->th || b->ghf != b->hf)
+  if (!b->exec || b->epoch != R.ws_epoch || b->gth != b->th || b->ghf != b->hf || b->ggrid != b->grid)
     if (batch_capture(b) != HD_OK) return g_last_error;
   // ordered after the metadata work of earlier calls, and before later ones
   HIPCK(hipEventRecord(R.ev_meta, R.meta));
@@ -2261,7 +2263,7 @@ extern "C" int hdarray_batch_phase_us(int id, double *us, int max) {
   HIPCK(hipGetDevice(&dev));
   if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate_khz <= 0)
     rate_khz = 100000;
-  const int nst = b->pl.P.has3d ? 14 : 10;
+  const int nst = b->pl.P.has3d ? 12 : 8;
   int n = 0;
   for (int k = 1; k < nst && n < max; ++k) us[n++] = (double)(clk[k] - clk[k - 1]) * 1e3 / rate_khz;
   return n;
@@ -2271,16 +2273,20 @@ extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
   if (!R.inited || !ids || n <= 0 || reps <= 0) return fail(HD_EINVAL);
   for (int i = 0; i < n; ++i)
     if (ids[i] < 0 || ids[i] >= (int)R.batches.size()) return fail(HD_EINVAL);
-  const int ths[3] = {4, 8, 16}, hfs[2] = {0, 1};  // rows per tile x tile order (1: along rows)
+  // rows per tile x tile order (1: along rows) x workgroups per CU of the
+  // persistent kernel (fewer make cheaper grid barriers, more run the
+  // metadata phases wider)
+  const int ths[3] = {4, 8, 16}, hfs[2] = {0, 1}, occs[3] = {1, 2, 4};
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
   float best = 1e30f;
-  int bth = 8, bhf = 0;
+  int bth = 8, bhf = 0, bocc = 2;
+  for (int occ : occs)
   for (int th : ths)
     for (int hf : hfs) {
       for (int i = 0; i < n; ++i)
-        if (batch_config(R.batches[ids[i]], th, hf) != HD_OK) return g_last_error;
+        if (batch_config(R.batches[ids[i]], th, hf, occ) != HD_OK) return g_last_error;
       for (int i = 0; i < n; ++i)
         if (hdarray_batch_run(ids[i]) != HD_OK) return g_last_error;
       HIPCK(hipEventRecord(e0, R.data));
@@ -2295,15 +2301,16 @@ extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
         best = ms;
         bth = th;
         bhf = hf;
+        bocc = occ;
       }
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   for (int i = 0; i < n; ++i)
-    if (batch_config(R.batches[ids[i]], bth, bhf) != HD_OK) return g_last_error;
+    if (batch_config(R.batches[ids[i]], bth, bhf, bocc) != HD_OK) return g_last_error;
   int rc = hdarray_sync();
   if (rc != HD_OK) return rc;
-  return (bth << 8) | bhf;
+  return (bocc << 16) | (bth << 8) | bhf;
 }
 
 // ---------------------------------------------------------------- adjoint
