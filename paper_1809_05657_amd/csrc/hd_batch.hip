@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     }
   }
   {
-    // rows the definitions tile: one lane per row; the others one wave per row
+    // rows the definitions tile: one lane per row
     for (int c = gw; c * 64 < B.P.ngfull; c += nw) {
       const int t = c * 64 + lane;
       if (t < B.P.ngfull) dev_gdef_full_lane(B.P, B.A, B.W, t);

@@ -2106,7 +2106,8 @@ static int batch_config(Batch *b, int th, int hf, int occ) {
     t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, th);
   }
   b->ntiles = t0;
-  if (t0 > b->tbox_cap) return fail(HD_EINVAL);
+  // one workgroup per tile in the user-kernel launch
+  if (t0 > b->tbox_cap || t0 > INT32_MAX) return fail(HD_EINVAL);
   std::vector<int32_t> tb((size_t)t0);
   for (size_t i = 0; i < b->boxes.size(); ++i) {
     const int64_t e = i + 1 < b->boxes.size() ? b->boxes[i + 1].tile0 : t0;
