@@ -27,16 +27,19 @@ METRIC = "ApplyKernel steps/s + pack/unpack GB/s (% HBM peak), plain vs batched/
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1809_05657_amd/csrc/hd_jacobi.hip", "paper_1809_05657_amd/csrc/hd_dev_jacobi.hpp",
                   "paper_1809_05657_amd/csrc/hd_dev_common.hpp"]
+# sources of the 3-D stencil, its adjoint and the adjoint's reverse pack / add
+S3D_SOURCES = ["paper_1809_05657_amd/csrc/hd_adj.hip", "paper_1809_05657_amd/csrc/hd_data.hip",
+               "paper_1809_05657_amd/csrc/hd_dev_data.hpp", "paper_1809_05657_amd/csrc/hd_dev_common.hpp"]
 
 
-def kernel_hash():
+def kernel_hash(sources=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def committed_traffic(name, kernel):
+def committed_traffic(name, kernel, sources=KERNEL_SOURCES):
     """HBM traffic per launch from committed rocprofv3 PMC summaries, or None
     when absent, taken on another version of the kernel source, or on
     another tile shape of the kernel."""
@@ -44,7 +47,7 @@ def committed_traffic(name, kernel):
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_source_hash") != kernel_hash():
+    if d.get("kernel_source_hash") != kernel_hash(sources):
         return None
     return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
@@ -399,11 +402,13 @@ def bench_stencil3d(hd, rt, steps, warmup, n=512, T=64, ckpt=8):
                        "backward_ms": (t2 - t1) * 1e3},
             "phases_us": {k: (v[0] / max(v[1], 1)) * 1e3 for k, v in ph.items()},
             "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": adj_gbs / HBM_PEAK_GBS if adj_gbs else None, "traffic": None,
+                         "frac": adj_gbs / HBM_PEAK_GBS if adj_gbs else None,
+                         "traffic": committed_traffic("stencil3d_512", "adjoint_step", S3D_SOURCES),
                          "kernel": "adjoint step (k_rev_pack, k_s3d_adj, k_unpack_add)",
                          "bytes_per_launch": adj_bytes, "avg_launch_us": adj_us},
             "forward_kernel": {"kernel": "k_s3d", "bytes_per_launch": fwd_bytes, "avg_launch_us": fwd_us,
-                               "GBps": fwd_gbs, "frac": fwd_gbs / HBM_PEAK_GBS if fwd_gbs else None}}
+                               "GBps": fwd_gbs, "frac": fwd_gbs / HBM_PEAK_GBS if fwd_gbs else None,
+                               "traffic": committed_traffic("stencil3d_512", "k_s3d", S3D_SOURCES)}}
 
 
 def bench_copy_calib(hd, rt, steps, warmup):
