@@ -203,15 +203,18 @@ int hdarray_reduce(hd_array_t *a, void *res, hd_reduce_t op, int part);
  * built-ins jacobi2d, tri2d or copy, with at most 1024 array arguments in
  * total (HD_EINVAL otherwise).  hdarray_batch_end() returns a batch id;
  * hdarray_batch_run(id) enqueues one execution of every recorded call —
- * communication sets, packs, unpacks, kernels and GDEF updates — as one
- * persistent kernel (phases separated by grid-wide barriers with a bounded
- * wait) replayed from a HIP graph.  Results are bit-identical to running the
- * calls one by one.  Within a batch a use row may produce at most 64 runs
- * and a GDEF row update at most 256 interval boundaries (the per-workgroup
- * scratch is kept small so that four workgroups share a CU); beyond that the
- * next synchronising call returns HD_ECAPACITY.  A barrier that times out
+ * communication sets, packs, unpacks, GDEF updates and kernels — as one
+ * HIP graph replay: a persistent kernel for the communication sets, packs,
+ * unpacks and GDEF updates (phases separated by grid-wide barriers with a
+ * bounded wait), then one launch of the user kernels of every call (one
+ * wave per tile).  Results are bit-identical to running the calls one by
+ * one.  Within a batch a use row may produce at most 64 runs and a GDEF row
+ * update at most 256 interval boundaries (the per-workgroup scratch is kept
+ * small so that four workgroups share a CU); beyond that the next
+ * synchronising call returns HD_ECAPACITY.  A barrier that times out
  * (workgroups not co-resident) makes the launch exit early; the next
- * synchronising call then returns HD_EHIP. */
+ * synchronising call then returns HD_EHIP.  HD_EINVAL also when the user
+ * kernels of a batch have more than 2^31 - 1 tiles. */
 int hdarray_batch_begin(void);
 int hdarray_batch_end(void);
 int hdarray_batch_run(int batch);
@@ -226,12 +229,13 @@ int hdarray_batch_run(int batch);
 int hdarray_batch_autotune(const int *batches, int n, int reps);
 /* Device time of each phase of the last run of a batch, in microseconds, from
  * clock stamps taken by workgroup 0 at the phase boundaries (a measurement
- * aid; synchronises).  Phases for 2-D batches: runs, band flags, band scan,
- * heads, compaction (chunk scans, prefixes, writes: 3 phases), pack + unpack
- * + GDEF update, user kernels (9); 3-D batches insert the first level's
- * compaction and the second level's band flags, band scan and heads before
- * the three compaction phases (13).  Writes at most max values to us and
- * returns their number, or a negative error. */
+ * aid; synchronises).  Phases of the persistent kernel up to the message
+ * table, for 2-D batches: runs, band flags, band scan, heads, compaction
+ * (chunk scans, prefixes, writes: 3 phases) (7); 3-D batches insert the
+ * first level's compaction and the second level's band flags, band scan and
+ * heads before the three compaction phases (11).  The pack + unpack, GDEF
+ * update and user-kernel launch that follow are not stamped.  Writes at
+ * most max values to us and returns their number, or a negative error. */
 int hdarray_batch_phase_us(int batch, double *us, int max);
 
 /* Adjoint of one ApplyKernel of a "stencil3d7" kernel kname on partition
