@@ -97,3 +97,50 @@ def test_batched_matches_oracle(hd, scale, narr):
         og, hg = rt.gdef(gB)
         oo, ho = orc.gdef(oB)
         assert np.array_equal(og, oo) and np.array_equal(hg, ho)
+
+
+def _block_arrays(api, shapes, base):
+    """Jacobi arrays on block partitions: a row crosses several devices, so
+    its GDEF list and holder-adding runs outgrow the one-lane update and the
+    batch's wave form takes it."""
+    out = []
+    for i, (n0, n1, nd) in enumerate(shapes):
+        rng = np.random.default_rng(50 + i)
+        A0 = rng.random((n0, n1), dtype=np.float32)
+        B0 = rng.random((n0, n1), dtype=np.float32)
+        A, B = api.create(A0), api.create(B0)
+        p = api.partition(2, (n0, n1), ndev=nd)
+        for k in (f"b{base + i}AB", f"b{base + i}BA"):
+            api.kernel(k, prog.K_JACOBI2D)
+            api.set_offsets(k, 1, 0, prog.J2D_OFFSETS)
+            api.set_offsets(k, 0, 1, [(0, 0)])
+        api.write(A, A0, p)
+        api.write(B, B0, p)
+        out.append((A, B, p, 0))
+    return out
+
+
+def test_batched_wide_rows(hd):
+    """Block partitions (rows over 4-8 devices) beside row partitions in one
+    batch: every step's tables, packs, values and GDEF against the oracle."""
+    shapes = [(96, 700, 16), (130, 260, 6), (70, 2100, 8)]
+    say(f"case batched wide rows {shapes}")
+    rt, orc = hd.Runtime(), O.Oracle()
+    inst = batched_instance(seed=4, narrays=6, scale=0.05)
+    ga = prog.batched_arrays(rt, inst)
+    oa = prog.batched_arrays(orc, inst)
+    # kernels b<i>AB / b<i>BA, i = position in the batch
+    ga += _block_arrays(rt, shapes, len(ga))
+    oa += _block_arrays(orc, shapes, len(oa))
+    b0, b1 = _record(rt, ga, True), _record(rt, ga, False)
+    for step in range(5):
+        even = step % 2 == 0
+        assert rt.L.hdarray_batch_run(b0 if even else b1) == 0
+        tables, packs = _oracle_step(orc, oa, even)
+        _check_tables(rt.messages(), tables)
+        assert np.array_equal(rt.pack(), np.concatenate(packs))
+    for (gA, gB, gp, _), (oA, oB, op, _) in zip(ga, oa):
+        assert np.array_equal(rt.read(gA, gp), orc.read(oA, op))
+        og, hg = rt.gdef(gB)
+        oo, ho = orc.gdef(oB)
+        assert np.array_equal(og, oo) and np.array_equal(hg, ho)
