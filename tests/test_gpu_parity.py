@@ -118,6 +118,29 @@ def test_block_parity(hd, n0, n1, ndev, use_box):
     assert np.array_equal(rt.read(g[1], g[2]), orc.read(o[1], o[2]))
 
 
+@pytest.mark.parametrize("shape,ndev,kind", [((1, 300), 4, prog.ROW), ((5, 5), 16, prog.BLOCK),
+                                             ((3, 700), 1, prog.BLOCK), ((2, 2), 4, prog.BLOCK),
+                                             ((7, 1), 3, prog.ROW), ((6, 9), 8, prog.COL)])
+def test_degenerate_parity(hd, shape, ndev, kind):
+    """Degenerate partitions: devices with empty boxes (more devices than
+    rows), one-cell and one-column boxes, a single device (no messages),
+    arrays narrower than one lane's four columns."""
+    say(f"case degenerate {shape} ndev={ndev} kind={kind}")
+    rng = np.random.default_rng(shape[0] * 31 + shape[1])
+    A0 = rng.random(shape, dtype=np.float32)
+    B0 = rng.random(shape, dtype=np.float32)
+    rt, orc = hd.Runtime(), O.Oracle()
+    g = prog.jacobi_blocks(rt, A0, B0, ndev, False, kind)
+    o = prog.jacobi_blocks(orc, A0, B0, ndev, False, kind)
+    for it in range(3):
+        k, ag, ao = ("jacAB", [g[0], g[1]], [o[0], o[1]]) if it % 2 == 0 else ("jacBA", [g[1], g[0]], [o[1], o[0]])
+        rt.apply(k, g[2], ag)
+        orc.apply(k, o[2], ao)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"step {it}")
+    assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+    assert np.array_equal(rt.read(g[1], g[2]), orc.read(o[1], o[2]))
+
+
 @pytest.mark.parametrize("n0,n1,ndev,kind", [(64, 64, 16, prog.BLOCK), (70, 300, 16, prog.BLOCK),
                                              (37, 530, 4, prog.COL), (130, 45, 6, prog.ROW)])
 def test_conv2d_parity(hd, n0, n1, ndev, kind):
