@@ -97,31 +97,27 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
     f4 gjm = ld_rowv(row_ptr(g1, i0, j - 1, N0, N1, N2), c, N2, vec);
     f4 gjp = ld_rowv(row_ptr(g1, i0, j + 1, N0, N1, N2), c, N2, vec);
     RowQ gpp = ld_rowq(row_ptr(g1, i0 + 1, j, N0, N1, N2), c, N2, vec, lane);
-    f4 wpm = ld_rowv(row_ptr(u, i0 - 1, j, N0, N1, N2), c, N2, vec);
+    // u only at the cell itself: the coefficient gradients are summed over
+    // the cells y this wave visits, c_e-bar += u[y] * du1[y - off_e] for
+    // every y whose output y - off_e is an owned interior cell -- the same
+    // terms as du1[x] * u[x + off_e] over the owned interior outputs x, and
+    // du1 at the neighbours is already in registers
     RowQ wcu = ld_rowq(row_ptr(u, i0, j, N0, N1, N2), c, N2, vec, lane);
-    f4 wjm = ld_rowv(row_ptr(u, i0, j - 1, N0, N1, N2), c, N2, vec);
-    f4 wjp = ld_rowv(row_ptr(u, i0, j + 1, N0, N1, N2), c, N2, vec);
-    RowQ wpp = ld_rowq(row_ptr(u, i0 + 1, j, N0, N1, N2), c, N2, vec, lane);
     const bool rj = adj_in(j, B.lo[1], B.hi[1], N1), rjm = adj_in(j - 1, B.lo[1], B.hi[1], N1),
                rjp = adj_in(j + 1, B.lo[1], B.hi[1], N1);
     const bool jown = j >= B.lo[1] && j < B.hi[1], jint = j >= 1 && j <= N1 - 2;
     for (int i = i0; i < i1; ++i) {
       RowQ gnq{}, wnq{};
-      f4 gnjm{}, gnjp{}, wnjm{}, wnjp{};
+      f4 gnjm{}, gnjp{};
       if (i + 1 < i1) {
         gnq = ld_rowq(row_ptr(g1, i + 2, j, N0, N1, N2), c, N2, vec, lane);
         gnjm = ld_rowv(row_ptr(g1, i + 1, j - 1, N0, N1, N2), c, N2, vec);
         gnjp = ld_rowv(row_ptr(g1, i + 1, j + 1, N0, N1, N2), c, N2, vec);
-        wnq = ld_rowq(row_ptr(u, i + 2, j, N0, N1, N2), c, N2, vec, lane);
-        wnjm = ld_rowv(row_ptr(u, i + 1, j - 1, N0, N1, N2), c, N2, vec);
-        wnjp = ld_rowv(row_ptr(u, i + 1, j + 1, N0, N1, N2), c, N2, vec);
+        wnq = ld_rowq(row_ptr(u, i + 1, j, N0, N1, N2), c, N2, vec, lane);
       }
       const float glw = __shfl_up(gcu.v.w, 1), grx = __shfl_down(gcu.v.x, 1);
-      const float wlw = __shfl_up(wcu.v.w, 1), wrx = __shfl_down(wcu.v.x, 1);
       const float gkl[4] = {lane == 0 ? gcu.l : glw, gcu.v.x, gcu.v.y, gcu.v.z};
       const float gkr[4] = {gcu.v.y, gcu.v.z, gcu.v.w, lane == 63 ? gcu.r : grx};
-      const float wkl[4] = {lane == 0 ? wcu.l : wlw, wcu.v.x, wcu.v.y, wcu.v.z};
-      const float wkr[4] = {wcu.v.y, wcu.v.z, wcu.v.w, lane == 63 ? wcu.r : wrx};
       const bool pi = adj_in(i, B.lo[0], B.hi[0], N0), pim = adj_in(i - 1, B.lo[0], B.hi[0], N0),
                  pip = adj_in(i + 1, B.lo[0], B.hi[0], N0);
       const bool iown = i >= B.lo[0] && i < B.hi[0], iint = i >= 1 && i <= N0 - 2;
@@ -137,16 +133,15 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
         const bool xint = iint && jint && k >= 1 && k <= N2 - 2;
         q[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gx, f4at(gpp.v, e), f4at(gpm, e), f4at(gjp, e),
                         f4at(gjm, e), gkr[e], gkl[e], xown, xint);
-        if (xown && xint) {
-          const double gy = (double)gx;
-          cb[0] += gy * (double)f4at(wcu.v, e);
-          cb[1] += gy * (double)f4at(wpm, e);
-          cb[2] += gy * (double)f4at(wpp.v, e);
-          cb[3] += gy * (double)f4at(wjm, e);
-          cb[4] += gy * (double)f4at(wjp, e);
-          cb[5] += gy * (double)wkl[e];
-          cb[6] += gy * (double)wkr[e];
-        }
+        // the terms of adj_elem, each times u[y]
+        const double uy = (double)f4at(wcu.v, e);
+        if (pi && rj && kk) cb[0] += uy * (double)gx;
+        if (pip && rj && kk) cb[1] += uy * (double)f4at(gpp.v, e);
+        if (pim && rj && kk) cb[2] += uy * (double)f4at(gpm, e);
+        if (pi && rjp && kk) cb[3] += uy * (double)f4at(gjp, e);
+        if (pi && rjm && kk) cb[4] += uy * (double)f4at(gjm, e);
+        if (pi && rj && kkp) cb[5] += uy * (double)gkr[e];
+        if (pi && rj && kkm) cb[6] += uy * (double)gkl[e];
       }
       // the extended column next to the box: only the term of its neighbour
       // inside the box can be nonzero (every other term needs the cell itself
@@ -157,6 +152,7 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
                    kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
         q[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gcu.l, 0.f, 0.f, 0.f, 0.f, gcu.v.x, 0.f, false,
                         false);
+        if (pi && rj && kkp) cb[5] += (double)wcu.l * (double)gcu.v.x;
       }
       if (xr) {
         const int k = c + 4;
@@ -164,17 +160,14 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
                    kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
         q[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gcu.r, 0.f, 0.f, 0.f, 0.f, 0.f, gcu.v.w, false,
                         false);
+        if (pi && rj && kkm) cb[6] += (double)wcu.r * (double)gcu.v.w;
       }
       gpm = gcu.v;
       gcu = gpp;
       gpp = gnq;
       gjm = gnjm;
       gjp = gnjp;
-      wpm = wcu.v;
-      wcu = wpp;
-      wpp = wnq;
-      wjm = wnjm;
-      wjp = wnjp;
+      wcu = wnq;
     }
   }
   // fixed-order reduction of the FP64 coefficient partials of this workgroup
