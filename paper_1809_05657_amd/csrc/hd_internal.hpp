@@ -160,6 +160,7 @@ struct PlanDev {
   // GDEF update rows: the ngfull rows the definitions tile come first
   int32_t ngrow;
   int32_t ngfull;
+  int32_t gdef_lane;  // 1: update the other GDEF rows one per lane first (k_gdef), 0: one wave per row
   const GRowRec *grec;  // [ngrow]
   const Seg *dseg;
 };

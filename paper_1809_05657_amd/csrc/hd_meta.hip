@@ -76,27 +76,59 @@ __global__ __launch_bounds__(256) void k_compact_wg(PlanDev P, Level L, Work W, 
 }
 
 // The first nfw workgroups copy the rows the definitions tile, one lane
-// per row; in the others, rows with at most 64 boundaries are updated
-// register-only, one wave each, and larger rows are listed (count in *cnt)
-// for k_gdef_large.
+// per row; the others take 64 of the other rows each, one per lane where
+// the row is small (dev_gdef_small_lane), and list the rest (count in
+// *cnt, one atomic per wave) for k_gdef_large.
 __global__ __launch_bounds__(64) void k_gdef(PlanDev P, ArrDev *__restrict__ A, Work W, int32_t *cnt, int nfw) {
   if ((int)blockIdx.x < nfw) {
     const int t = blockIdx.x * 64 + threadIdx.x;
     if (t < P.ngfull) dev_gdef_full_lane(P, A, W, t);
     return;
   }
-  const int g = (int)gridDim.x - nfw;
-  for (int t = P.ngfull + (int)blockIdx.x - nfw; t < P.ngrow; t += g) {
-    if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list[atomicAdd(cnt, 1)] = t;
+  const int t = P.ngfull + ((int)blockIdx.x - nfw) * 64 + (int)threadIdx.x;
+  const bool done = t >= P.ngrow || dev_gdef_small_lane(P, A, W, t);
+  const uint64_t m = __ballot(!done);
+  if (m) {
+    int base = 0;
+    if (threadIdx.x == 0) base = atomicAdd(cnt, __popcll(m));
+    base = __shfl(base, 0);
+    if (!done) W.ovf_list[base + __popcll(m & lanemask_lt())] = t;
   }
 }
 
-// The listed large rows, one wave each with LDS scratch (such rows are
-// rare, so the grid is small).  Two list counters alternate between calls:
+// The other form: the first nfw workgroups as above, then one wave per row,
+// register-only up to 64 boundaries; larger rows are marked (-t-1) in the
+// list for k_gdef_large.
+__global__ __launch_bounds__(64) void k_gdef_wave(PlanDev P, ArrDev *__restrict__ A, Work W, int32_t *cnt, int nfw) {
+  if ((int)blockIdx.x < nfw) {
+    const int t = blockIdx.x * 64 + threadIdx.x;
+    if (t < P.ngfull) dev_gdef_full_lane(P, A, W, t);
+    return;
+  }
+  const int g = (int)gridDim.x - nfw;
+  for (int t = P.ngfull + (int)blockIdx.x - nfw; t < P.ngrow; t += g)
+    if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list[atomicAdd(cnt, 1)] = -t - 1;
+}
+
+// The listed rows, one wave each, register-only; a row with more than 64
+// boundaries is marked (entry -t-1) for k_gdef_large.
+constexpr int kGdefListGrid = 2048;
+__global__ __launch_bounds__(64) void k_gdef_list(PlanDev P, ArrDev *__restrict__ A, Work W, const int32_t *cnt) {
+  const int n = *cnt;
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int t = W.ovf_list[q];
+    if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list[q] = -t - 1;
+  }
+}
+
+// The marked rows, one wave each with LDS scratch (such rows are rare; the
+// grid only has to scan the list).  Two list counters alternate between calls:
 // this launch clears the other one, which the previous launch (finished,
 // same stream) read and the next k_gdef appends to, so no workgroup has to
 // wait for the others before a counter is reset.
-constexpr int kGdefLargeGrid = 32;
+// (the lane form's list holds every row too large for one lane, so its scan
+// takes a wider grid)
+constexpr int kGdefLargeGrid = 32, kGdefLargeGridLane = 512;
 __global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict__ A, Work W, const int32_t *cnt,
                                                    int32_t *other) {
   __shared__ Ivl s_iv[kMaxCap];
@@ -105,7 +137,10 @@ __global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict
   GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
   if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
   const int n = *cnt;
-  for (int q = blockIdx.x; q < n; q += gridDim.x) dev_gdef_row(P, A, W, W.ovf_list[q], S, kGdefMaxB);
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int t = W.ovf_list[q];
+    if (t < 0) dev_gdef_row(P, A, W, -t - 1, S, kGdefMaxB);
+  }
 }
 
 // Every row starts as one interval [0, n2) owned and held by the host.
@@ -209,9 +244,14 @@ hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s
   int32_t *cur = W.ovf_cnt + p, *other = W.ovf_cnt + (1 - p);
   const int nfw = cdiv(P.ngfull, 64);
   const int rest = P.ngrow - P.ngfull;
-  const int grid = nfw + (rest < (1 << 20) ? rest : (1 << 20));
-  hipLaunchKernelGGL(k_gdef, dim3(grid), dim3(64), 0, s, P, A, W, cur, nfw);
-  hipLaunchKernelGGL(k_gdef_large, dim3(kGdefLargeGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur, other);
+  if (P.gdef_lane) {
+    hipLaunchKernelGGL(k_gdef, dim3(nfw + cdiv(rest, 64)), dim3(64), 0, s, P, A, W, cur, nfw);
+    hipLaunchKernelGGL(k_gdef_list, dim3(kGdefListGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur);
+  } else {
+    const int grid = nfw + (rest < (1 << 20) ? rest : (1 << 20));
+    hipLaunchKernelGGL(k_gdef_wave, dim3(grid), dim3(64), 0, s, P, A, W, cur, nfw);
+  }
+  hipLaunchKernelGGL(k_gdef_large, dim3(P.gdef_lane ? kGdefLargeGridLane : kGdefLargeGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur, other);
   return hipGetLastError();
 }
 

@@ -1086,6 +1086,33 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   P.ngrow = (int32_t)grec.size();
   P.ngfull = 0;
   for (const GRowRec &g : grec) P.ngfull += g.full ? 1 : 0;
+  // GDEF update form of the other rows: when nearly all of them involve at
+  // most two devices (row partitions, 3-D blocks split once along the row)
+  // their lists stay short and one lane per row updates them; rows shared by
+  // more devices (2-D block partitions) are updated one wave per row
+  {
+    int64_t small = 0, rest = 0;
+    for (const GRowRec &g : grec) {
+      if (g.full) continue;
+      ++rest;
+      int d0 = -1, d1 = -1;
+      bool more = false;
+      auto see = [&](int d) {
+        if (d == d0 || d == d1) return;
+        if (d0 < 0)
+          d0 = d;
+        else if (d1 < 0)
+          d1 = d;
+        else
+          more = true;
+      };
+      if (g.slice >= 0)
+        for (int e = 0; e < nseg[g.slice]; ++e) see(useg[seg0[g.slice] + e].dst);
+      for (int e = 0; e < g.ndseg; ++e) see(dseg[g.dseg0 + e].dst);
+      if (!more) ++small;
+    }
+    P.gdef_lane = rest > 0 && small * 10 >= rest * 9 ? 1 : 0;
+  }
   pl->nsl1 = P.nsl1;
   pl->ngrp = P.ngrp;
   pl->ngrow = P.ngrow;
