@@ -173,6 +173,7 @@ struct Work {
   int64_t run_cap;
   int32_t *ovf_cnt;   // GDEF rows left to the large-row path ([1]: workgroups done)
   int32_t *ovf_list;
+  int32_t *ovf_list2;  // rows with more than 64 boundaries (LDS update)
   int32_t *goff;   // [ngrp] level-1 output offset per group
   int32_t *gcnt;   // [ngrp]
   Item *l1out;     // level-1 output (3-D)

@@ -97,8 +97,8 @@ __global__ __launch_bounds__(64) void k_gdef(PlanDev P, ArrDev *__restrict__ A, 
 }
 
 // The other form: the first nfw workgroups as above, then one wave per row,
-// register-only up to 64 boundaries; larger rows are marked (-t-1) in the
-// list for k_gdef_large.
+// register-only up to 64 boundaries; larger rows are listed (count in
+// *cnt) for k_gdef_large.
 __global__ __launch_bounds__(64) void k_gdef_wave(PlanDev P, ArrDev *__restrict__ A, Work W, int32_t *cnt, int nfw) {
   if ((int)blockIdx.x < nfw) {
     const int t = blockIdx.x * 64 + threadIdx.x;
@@ -107,40 +107,40 @@ __global__ __launch_bounds__(64) void k_gdef_wave(PlanDev P, ArrDev *__restrict_
   }
   const int g = (int)gridDim.x - nfw;
   for (int t = P.ngfull + (int)blockIdx.x - nfw; t < P.ngrow; t += g)
-    if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list[atomicAdd(cnt, 1)] = -t - 1;
+    if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list2[atomicAdd(cnt, 1)] = t;
 }
 
 // The listed rows, one wave each, register-only; a row with more than 64
-// boundaries is marked (entry -t-1) for k_gdef_large.
+// boundaries goes to the second list (count in *cnt2) for k_gdef_large.
 constexpr int kGdefListGrid = 2048;
-__global__ __launch_bounds__(64) void k_gdef_list(PlanDev P, ArrDev *__restrict__ A, Work W, const int32_t *cnt) {
+__global__ __launch_bounds__(64) void k_gdef_list(PlanDev P, ArrDev *__restrict__ A, Work W, const int32_t *cnt,
+                                                  int32_t *cnt2) {
   const int n = *cnt;
   for (int q = blockIdx.x; q < n; q += gridDim.x) {
     const int t = W.ovf_list[q];
-    if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list[q] = -t - 1;
+    if (!dev_gdef_row_fast(P, A, W, t) && threadIdx.x == 0) W.ovf_list2[atomicAdd(cnt2, 1)] = t;
   }
 }
 
-// The marked rows, one wave each with LDS scratch (such rows are rare; the
-// grid only has to scan the list).  Two list counters alternate between calls:
+// The rows of the second list, one wave each with LDS scratch (such rows
+// are rare, so the grid is small).  Each list has two counters that
+// alternate between calls:
 // this launch clears the other one, which the previous launch (finished,
 // same stream) read and the next k_gdef appends to, so no workgroup has to
 // wait for the others before a counter is reset.
-// (the lane form's list holds every row too large for one lane, so its scan
-// takes a wider grid)
-constexpr int kGdefLargeGrid = 32, kGdefLargeGridLane = 512;
-__global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict__ A, Work W, const int32_t *cnt,
-                                                   int32_t *other) {
+constexpr int kGdefLargeGrid = 32;
+__global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict__ A, Work W, const int32_t *cnt2,
+                                                   int32_t *other, int32_t *other2) {
   __shared__ Ivl s_iv[kMaxCap];
   __shared__ int32_t s_b[kGdefMaxB], s_u[kGdefMaxB], s_own[kGdefMaxB];
   __shared__ uint64_t s_hold[kGdefMaxB];
   GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
-  if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
-  const int n = *cnt;
-  for (int q = blockIdx.x; q < n; q += gridDim.x) {
-    const int t = W.ovf_list[q];
-    if (t < 0) dev_gdef_row(P, A, W, -t - 1, S, kGdefMaxB);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *other = 0;
+    *other2 = 0;
   }
+  const int n = *cnt2;
+  for (int q = blockIdx.x; q < n; q += gridDim.x) dev_gdef_row(P, A, W, W.ovf_list2[q], S, kGdefMaxB);
 }
 
 // Every row starts as one interval [0, n2) owned and held by the host.
@@ -242,16 +242,17 @@ hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s
   const int p = g_ovf_parity;
   g_ovf_parity ^= 1;
   int32_t *cur = W.ovf_cnt + p, *other = W.ovf_cnt + (1 - p);
+  int32_t *cur2 = W.ovf_cnt + 2 + p, *other2 = W.ovf_cnt + 2 + (1 - p);
   const int nfw = cdiv(P.ngfull, 64);
   const int rest = P.ngrow - P.ngfull;
   if (P.gdef_lane) {
     hipLaunchKernelGGL(k_gdef, dim3(nfw + cdiv(rest, 64)), dim3(64), 0, s, P, A, W, cur, nfw);
-    hipLaunchKernelGGL(k_gdef_list, dim3(kGdefListGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur);
+    hipLaunchKernelGGL(k_gdef_list, dim3(kGdefListGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur, cur2);
   } else {
     const int grid = nfw + (rest < (1 << 20) ? rest : (1 << 20));
-    hipLaunchKernelGGL(k_gdef_wave, dim3(grid), dim3(64), 0, s, P, A, W, cur, nfw);
+    hipLaunchKernelGGL(k_gdef_wave, dim3(grid), dim3(64), 0, s, P, A, W, cur2, nfw);
   }
-  hipLaunchKernelGGL(k_gdef_large, dim3(P.gdef_lane ? kGdefLargeGridLane : kGdefLargeGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur, other);
+  hipLaunchKernelGGL(k_gdef_large, dim3(kGdefLargeGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur2, other, other2);
   return hipGetLastError();
 }
 

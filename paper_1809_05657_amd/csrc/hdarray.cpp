@@ -361,7 +361,9 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   HIPCK(hipMemset(R.counters, 0, 64));
   R.W.run_top = R.counters + 0;
   R.W.err = R.counters + 3;
-  R.W.ovf_cnt = R.counters + 4;  // [4], [5]: rows listed for the large-row GDEF update, alternating
+  // [4], [5]: rows listed past the one-lane GDEF update; [6], [7]: rows for
+  // the LDS update; each pair alternates between calls
+  R.W.ovf_cnt = R.counters + 4;
   HIPCK(hipHostMalloc((void **)&R.red_res_host, 64, hipHostMallocDefault));
   R.red_res_dev = dalloc(64);
   R.red_pf = (double *)dalloc(sizeof(double) * kMaxDev * 64 * 4);
@@ -868,7 +870,8 @@ static void free_ws() {
   R.bcarr = R.nofs = nullptr;
   dfree(R.heads);
   dfree(R.W.ovf_list);
-  R.W.ovf_list = nullptr;
+  dfree(R.W.ovf_list2);
+  R.W.ovf_list = R.W.ovf_list2 = nullptr;
   for (int k = 0; k < 2; ++k) {
     dfree(R.tab[k]);
     dfree(R.hdr[k]);
@@ -922,13 +925,14 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
     R.nofs = (int32_t *)dalloc(4 * ns);
     R.heads = (Item *)dalloc(sizeof(Item) * it);
     R.W.ovf_list = (int32_t *)dalloc(4 * ns);
+    R.W.ovf_list2 = (int32_t *)dalloc(4 * ns);
     for (int k = 0; k < 2; ++k) {
       R.tab[k] = (MsgRec *)dalloc(sizeof(MsgRec) * it);
       R.hdr[k] = (MsgHdr *)dalloc(sizeof(MsgHdr));
       if (R.hdr[k]) HIPCK(hipMemset(R.hdr[k], 0, sizeof(MsgHdr)));
     }
     if (!R.W.roff || !R.W.rcnt || !R.W.runs || !R.W.goff || !R.W.gcnt || !R.W.l1out || !R.bmask || !R.bcnt ||
-        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hbytes || !R.bofs || !R.bcarr || !R.nofs || !R.heads || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
+        !R.bbase || !R.bandslice || !R.hoff || !R.hcnt || !R.hbytes || !R.bofs || !R.bcarr || !R.nofs || !R.heads || !R.W.ovf_list || !R.W.ovf_list2 || !R.tab[0] || !R.tab[1] || !R.hdr[0] ||
         !R.hdr[1])
       return fail(HD_ENOMEM);
     HIPCK(hipMemset(R.W.roff, 0, 4 * ns));
