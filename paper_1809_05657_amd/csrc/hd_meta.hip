@@ -175,8 +175,10 @@ static void launch_bands(const Level &L, hipStream_t s) {
   hipLaunchKernelGGL(k_bandflags, dim3(cdiv(L.nsl, 64)), dim3(64), 0, s, L);
   if (L.nsl <= 8192)
     hipLaunchKernelGGL(k_bandscan<64>, dim3(1), dim3(64), 0, s, L);
-  else
+  else if (L.nsl <= (1 << 18))
     hipLaunchKernelGGL(k_bandscan<256>, dim3(1), dim3(256), 0, s, L);
+  else  // levels of 3-D arrays (a slice per use row of every plane)
+    hipLaunchKernelGGL(k_bandscan<1024>, dim3(1), dim3(1024), 0, s, L);
   launch_heads(L, s);
 }
 

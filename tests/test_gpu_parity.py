@@ -335,11 +335,12 @@ def test_random_programs_parity(hd, seed):
         same_call(rt, orc, [(res[0][i], res[1][i])], f"read {i}")
 
 
-@pytest.mark.parametrize("case", ["rows2d", "rows3d"])
+@pytest.mark.parametrize("case", ["rows2d", "rows3d", "rows3d_large"])
 def test_many_rows_parity(hd, case):
     """Levels with more than 32768 use rows, where the runs are found one
     row per lane (with the wave taking the rows that do not fit): a tall
-    2-D array with column partitions, and a 3-D array of many rows."""
+    2-D array with column partitions, and 3-D arrays of many rows (the
+    larger one past 2^18 slices, where the band scan takes 1024 threads)."""
     rng = np.random.default_rng(91)
     rt, orc = hd.Runtime(), O.Oracle()
     if case == "rows2d":
@@ -351,8 +352,9 @@ def test_many_rows_parity(hd, case):
         names = ("jacAB", "jacBA")
         coef = None
     else:
-        say("case many rows 3-D (40, 1000, 12) ndev=8")
-        u0 = rng.random((40, 1000, 12), dtype=np.float32)
+        shape = (40, 1000, 12) if case == "rows3d" else (300, 1000, 8)
+        say(f"case many rows 3-D {shape} ndev=8")
+        u0 = rng.random(shape, dtype=np.float32)
         g = prog.stencil3d(rt, u0, 8)
         o = prog.stencil3d(orc, u0, 8)
         names = ("s3dUV", "s3dVU")
