@@ -12,8 +12,12 @@ Conventions (same reading as the product, written independently):
   * messages are ordered by array argument, then row-major lower corner,
     then destination; pack offsets are in bytes, aligned to the element size.
 
-Functions whose result is not pinned by a test against the paper or the
-mathematics are marked "parity unpinned" in their docstring.
+Every function is pinned by a CPU test against the paper or the mathematics
+(tests/test_oracle_pins.py, tests/test_oracle_pins_exact.py): hand-derived
+message lists and trapezoid rows, Table 3 volumes, closed forms, an exact
+rational evaluation of the FP32 operation chains, exact products for the
+reductions.  A function without such a pin would be marked "parity
+unpinned" in its docstring; none is.
 """
 import ctypes as C
 import os

@@ -263,6 +263,50 @@ def test_trapezoid_parity(hd, n, cuts):
     assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
 
 
+def _trapezoid_copy_program(api, A0, B0, traps, boxes):
+    """Copy kernels A <- B and B <- A on a manual partition whose work boxes
+    lie inside general trapezoids (Table 2 SetTrapezoidUse): each device uses
+    its trapezoid of the input (a use larger than what the copy reads) and
+    defines its own box of the output."""
+    A, B = api.create(A0), api.create(B0)
+    p = api.partition_manual([b[0] for b in boxes], [b[1] for b in boxes])
+    for k, out, inp in (("cpAB", A, B), ("cpBA", B, A)):
+        api.kernel(k, prog.K_COPY)
+        api.set_offsets(k, 0, 1, [(0, 0)])
+        for d, c in enumerate(traps):
+            api.set_trapezoid(k, p, inp, d, 0, c)
+    api.write(A, A0, p)
+    return A, B, p
+
+
+def test_general_trapezoid_parity(hd):
+    """Trapezoids with non-unit and negative edge slopes, clipped on both
+    sides, a one-row trapezoid and crossed edges (the hand-derived fixture
+    cases) as use sections of copy kernels: messages, pack buffers, GDEF and
+    values bit-exact over four alternating calls."""
+    import json
+    say("case general trapezoids 16x20 ndev=5")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "trapezoid_rows.json")))
+    traps = [c["corners"] for c in gold["cases"]]
+    # a work box inside each trapezoid, pairwise disjoint
+    boxes = [((2, 3), (8, 6)), ((0, 6), (2, 9)), ((10, 7), (14, 15)), ((15, 4), (16, 10)), ((8, 0), (9, 2))]
+    rng = np.random.default_rng(1616)
+    A0 = rng.random((16, 20), dtype=np.float32)
+    B0 = rng.random((16, 20), dtype=np.float32)
+    rt, orc = hd.Runtime(), O.Oracle()
+    g = _trapezoid_copy_program(rt, A0, B0, traps, boxes)
+    o = _trapezoid_copy_program(orc, A0, B0, traps, boxes)
+    for it in range(4):
+        k, gi = ("cpAB", (0, 1)) if it % 2 == 0 else ("cpBA", (1, 0))
+        rt.apply(k, g[2], [g[gi[0]], g[gi[1]]])
+        orc.apply(k, o[2], [o[gi[0]], o[gi[1]]])
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"step {it}")
+        assert len(rt.messages()) > 0
+    for i in range(2):
+        assert np.array_equal(rt.read(g[i], g[2]), orc.read(o[i], o[2]))
+    assert orc.bad_reads() == 0
+
+
 @pytest.mark.parametrize("shape,ndev", [((12, 12, 12), 8), ((20, 17, 300), 8), ((9, 33, 65), 12)])
 def test_stencil3d_parity(hd, shape, ndev):
     """7-point stencil on 3-D blocks: boxes stacked over rows and planes,
