@@ -290,7 +290,7 @@ def bench_batched(hd, rt, steps, warmup):
     row partitions, 5-point or lower-triangular), ping-pong; plain per-call
     steps vs one persistent graph-replayed launch per step."""
     sys.path.insert(0, ROOT)
-    from tests import programs as prog
+    from workloads import programs as prog
     from workloads import batched_instance
     inst = batched_instance(seed=4)
     arrs = prog.batched_arrays(rt, inst)

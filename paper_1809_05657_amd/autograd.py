@@ -19,6 +19,21 @@ from . import BLOCK, K_COPY, K_STENCIL3D7
 S3D_OFFSETS = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
 
 
+def check_field(t, shape, what):
+    """The library reads and writes fields through raw device pointers as
+    dense fp32 of the solver's shape: anything else (a host tensor, another
+    dtype or shape) is refused here, before any pointer reaches the GPU."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{what}: expected float32, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: expected a GPU tensor, got one on {t.device}")
+    return t.contiguous()
+
+
 class Stencil3D:
     def __init__(self, rt, shape, ndev=8, T=64, ckpt=8):
         assert T % ckpt == 0
@@ -46,8 +61,10 @@ class Stencil3D:
 
     def forward(self, u0, coef):
         rt, p = self.rt, self.part
+        u0 = check_field(u0, self.shape, "u0")
         self.coef = [float(c) for c in coef]
-        u0 = u0.contiguous()
+        if len(self.coef) != 7:
+            raise ValueError(f"coef: expected 7 weights, got {len(self.coef)}")
         rt.write_device(self.S[0], u0.data_ptr(), p)
         for s in range(self.T // self.ckpt):
             rt.apply("s3dcp", p, [self.Ck[s], self.S[0]])
@@ -62,7 +79,7 @@ class Stencil3D:
 
     def backward(self, gT):
         rt, p = self.rt, self.part
-        gT = gT.contiguous().to(torch.float32)
+        gT = check_field(gT, self.shape, "grad of u_T")
         cbar = torch.zeros(8, dtype=torch.float64, device=gT.device)
         rt.write_device(self.G[0], gT.data_ptr(), p)
         cur = 0

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests import programs as prog
+from workloads import programs as prog
 from tests.test_gpu_parity import same_call
 from workloads import matmul_inputs, ternary_matmul_inputs
 

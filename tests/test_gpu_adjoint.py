@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests import programs as prog
+from workloads import programs as prog
 from workloads import S3D_COEFFS, stencil3d_inputs
 
 pytestmark = pytest.mark.gpu

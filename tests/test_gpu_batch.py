@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests import programs as prog
+from workloads import programs as prog
 from workloads import batched_instance
 
 pytestmark = pytest.mark.gpu

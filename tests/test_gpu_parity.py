@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests import canon, programs as prog
+from tests import canon
+from workloads import programs as prog
 from workloads import CONV9_WEIGHTS, S3D_COEFFS, jacobi_inputs, stencil3d_inputs, matmul_inputs, ternary_matmul_inputs
 
 pytestmark = pytest.mark.gpu

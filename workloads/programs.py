@@ -1,5 +1,7 @@
-"""HDArray programs written once and run on both the oracle and the HIP
-runtime (both expose create / partition / kernel / set_offsets /
+"""HDArray programs of the workloads, written once and run on both the
+oracle and the HIP runtime (the sequences of Table 2 calls a workload makes:
+arrays, partitions, offsets and sections; no communication sets, no
+kernels).  Both sides expose create / partition / kernel / set_offsets /
 set_absolute / set_trapezoid / apply / write / read / reduce / messages /
 pack / gdef with the same meaning).  Builtin ids: 1 jacobi2d, 2 copy,
 3 matmul, 4 tri2d, 5 stencil3d7, 6 conv2d9; kinds: 0 ROW, 1 COL, 2 BLOCK."""
