@@ -697,6 +697,10 @@ static void rle_dst(const int8_t *srcmap, const int64_t *wlo, const int64_t *whi
  * owner: sGDEF only lists what a process wrote (Sec. 2.1). */
 static void derive_messages(orc_ctx *c, int argpos, int arrid, arr_t *a, region_t *use /*[64]*/,
                             boxes_t *out) {
+  /* every destination on its own (OpenMP over devices), joined in device order */
+  boxes_t per[64];
+  memset(per, 0, sizeof(per));
+#pragma omp parallel for schedule(dynamic, 1)
   for (int d = 0; d < 64; d++) {
     if (use[d].n == 0) continue;
     int64_t lo[3], hi[3];
@@ -714,12 +718,13 @@ static void derive_messages(orc_ctx *c, int argpos, int arrid, arr_t *a, region_
           srcmap[w] = -1;
           if (mask[w] && !(a->holders[x] & BIT(d))) srcmap[w] = a->owner[x];
         }
-    boxes_t bx = {0, 0, NULL};
-    rle_dst(srcmap, lo, hi, d, &bx);
-    for (int64_t i = 0; i < bx.n; i++) boxes_push(out, &bx.b[i]);
-    free(bx.b);
+    rle_dst(srcmap, lo, hi, d, &per[d]);
     free(mask);
     free(srcmap);
+  }
+  for (int d = 0; d < 64; d++) {
+    for (int64_t i = 0; i < per[d].n; i++) boxes_push(out, &per[d].b[i]);
+    free(per[d].b);
   }
   (void)c;
   (void)argpos;
@@ -807,13 +812,16 @@ static int64_t check_coherent(orc_ctx *c, arr_t *a, region_t *use) {
     if (use[d].n == 0) continue;
     unsigned char *m = region_mask_full(&use[d], a->n);
     unsigned char *buf = c->simulate ? devbuf(a, d) : NULL;
+    int64_t bd = 0;
+#pragma omp parallel for reduction(+ : bd) schedule(static)
     for (int64_t x = 0; x < a->N; x++) {
       if (!m[x]) continue;
-      if (!(a->holders[x] & BIT(d))) bad++;
+      if (!(a->holders[x] & BIT(d))) bd++;
       else if (buf && memcmp(buf + (size_t)x * (size_t)a->esize, a->truth + (size_t)x * (size_t)a->esize,
                              (size_t)a->esize))
-        bad++;
+        bd++;
     }
+    bad += bd;
     free(m);
   }
   return bad;
@@ -1006,35 +1014,45 @@ static void eval_mm_cell(keval_t *t, int64_t i, int64_t j) {
   }
 }
 
+/* Every cell of the box [lo, hi) is evaluated on its own (the inputs are not
+ * the output), so the rows are shared out over OpenMP threads; each thread
+ * counts its reads of non-coherent data and the counts are summed. */
 static void eval_region(keval_t *t, int builtin, const int64_t *lo, const int64_t *hi) {
+  int64_t bad = 0;
+#pragma omp parallel for collapse(2) reduction(+ : bad) schedule(static)
   for (int64_t p = lo[0]; p < hi[0]; p++)
-    for (int64_t r = lo[1]; r < hi[1]; r++)
+    for (int64_t r = lo[1]; r < hi[1]; r++) {
+      keval_t u = *t;
+      u.bad = 0;
       for (int64_t q = lo[2]; q < hi[2]; q++) {
         switch (builtin) {
           case ORC_K_JACOBI2D:
-            eval_jacobi_cell(t, r, q, 0);
+            eval_jacobi_cell(&u, r, q, 0);
             break;
           case ORC_K_TRI2D:
-            if (q <= r) eval_jacobi_cell(t, r, q, 1);
+            if (q <= r) eval_jacobi_cell(&u, r, q, 1);
             break;
           case ORC_K_STENCIL3D7:
-            eval_s3d_cell(t, p, r, q);
+            eval_s3d_cell(&u, p, r, q);
             break;
           case ORC_K_CONV2D9:
-            eval_conv_cell(t, r, q);
+            eval_conv_cell(&u, r, q);
             break;
           case ORC_K_MATMUL:
-            eval_mm_cell(t, r, q);
+            eval_mm_cell(&u, r, q);
             break;
           case ORC_K_COPY: {
-            int64_t x = (p * t->aout->n[1] + r) * t->aout->n[2] + q;
-            size_t es = (size_t)t->aout->esize;
-            RD(t, x);
-            if (t->out) memcpy(t->out + es * (size_t)x, t->in0 + es * (size_t)x, es);
-            if (t->outd) t->outd[x] = t->in0d[x];
+            int64_t x = (p * u.aout->n[1] + r) * u.aout->n[2] + q;
+            size_t es = (size_t)u.aout->esize;
+            RD(&u, x);
+            if (u.out) memcpy(u.out + es * (size_t)x, u.in0 + es * (size_t)x, es);
+            if (u.outd) u.outd[x] = u.in0d[x];
           } break;
         }
       }
+      bad += u.bad;
+    }
+  t->bad += bad;
 }
 
 /* --------------------------------------------------------- region builder */
@@ -1167,14 +1185,14 @@ int orc_apply(orc_ctx *c, int k, int part, int nargs, const int *arrs, int nscal
         memset(wr, -1, (size_t)a->N);
       }
       unsigned char *m = region_mask_full(&def[j][d], a->n);
+      int race = 0;
+#pragma omp parallel for reduction(| : race) schedule(static)
       for (int64_t x = 0; x < a->N; x++)
         if (m[x]) {
-          if (wr[x] >= 0 && wr[x] != d) {
-            rc = ORC_ERACE;
-            break;
-          }
+          if (wr[x] >= 0 && wr[x] != d) race = 1;
           wr[x] = (int8_t)d;
         }
+      if (race) rc = ORC_ERACE;
       free(m);
     }
     free(wr);
@@ -1256,6 +1274,7 @@ int orc_apply(orc_ctx *c, int k, int part, int nargs, const int *arrs, int nscal
       for (int d = 0; d < pt->ndev; d++) {
         if (def[j][d].n == 0) continue;
         unsigned char *m = region_mask_full(&def[j][d], a->n);
+#pragma omp parallel for schedule(static)
         for (int64_t x = 0; x < a->N; x++)
           if (m[x]) {
             a->owner[x] = (int8_t)d;
