@@ -16,7 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
 def sources():
-    return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise FileNotFoundError("missing HIP sources: " + ", ".join(missing))
+    return [os.path.join(CSRC, s) for s in SOURCES]
 
 
 def build(verbose=False, jobs=8):
@@ -44,7 +47,7 @@ def build(verbose=False, jobs=8):
     if failed:
         raise RuntimeError("build of libhdarray.so failed")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp] + objs
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
