@@ -59,6 +59,7 @@ extern "C" {
 #define HD_EHIP (-6)      /* a HIP runtime call failed */
 #define HD_ESTATE (-7)    /* runtime not initialised / already shut down */
 #define HD_ECAPACITY (-8) /* a per-row GDEF list or a work pool overflowed */
+#define HD_ENOPLAN (-9)   /* no-allocation call without the plan an earlier call built */
 
 typedef struct hd_array hd_array_t;
 
@@ -195,6 +196,22 @@ int hdarray_read(hd_array_t *a, void *uA, int part);
  * receives one element of the array's type.  Synchronises. */
 int hdarray_reduce(hd_array_t *a, void *res, hd_reduce_t op, int part);
 
+/* Reduce without allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, result and error behaviour as
+ * hdarray_reduce, with two differences: the partial results and the
+ * device-side result live in a static device array of the library (64 KiB
+ * per GPU, held until the process ends; a partition of n non-empty boxes
+ * needs 256 + 768 n bytes, always within it for the 63 devices a partition
+ * may have; more would give HD_ECAPACITY), and the communication plan of
+ * (a, part) must already exist: an earlier hdarray_reduce on the same array
+ * and partition builds it, otherwise HD_ENOPLAN and nothing runs.  No
+ * device or host memory is allocated.  Every call on one GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other host threads) race.
+ * Phase timing (hdarray_profile) is suspended during the call.
+ * Synchronises. */
+int hdarray_reduce_noalloc(hd_array_t *a, void *res, hd_reduce_t op, int part);
+
 /* ---------------------------------------------------------- extensions */
 
 /* Batched step.  Between hdarray_batch_begin() and hdarray_batch_end(),
@@ -296,6 +313,7 @@ typedef struct {
   int64_t cache_hits;      /* plan-cache calls that reused a message table */
   int64_t cache_misses;    /* plan-cache calls that derived one */
   int64_t stencil_order;   /* tile order of the last stencil launch (1 along rows, 0 down columns) */
+  int64_t allocs;          /* device and pinned host allocations the library has made */
 } hd_stats_t;
 int hdarray_get_stats(hd_stats_t *st);
 

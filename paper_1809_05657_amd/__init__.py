@@ -26,7 +26,7 @@ SUM, PROD, MAX, MIN = 0, 1, 2, 3
 K_JACOBI2D, K_COPY, K_MATMUL, K_TRI2D, K_STENCIL3D7, K_CONV2D9 = 1, 2, 3, 4, 5, 6
 BUILTIN_NAMES = {K_JACOBI2D: "jacobi2d", K_COPY: "copy", K_MATMUL: "matmul", K_TRI2D: "tri2d",
                  K_STENCIL3D7: "stencil3d7", K_CONV2D9: "conv2d9"}
-EINVAL, EBOUNDS, ERACE, EKERNEL, ENOMEM, EHIP, ESTATE, ECAPACITY = -1, -2, -3, -4, -5, -6, -7, -8
+EINVAL, EBOUNDS, ERACE, EKERNEL, ENOMEM, EHIP, ESTATE, ECAPACITY, ENOPLAN = -1, -2, -3, -4, -5, -6, -7, -8, -9
 MSG_FIELDS = ("arg", "array", "src", "dst", "lo0", "lo1", "lo2", "hi0", "hi1", "hi2", "off", "bytes")
 _TYPE_NAME = {F32: b"float", I32: b"int", F64: b"double"}
 _DT = {F32: np.float32, I32: np.int32, F64: np.float64}
@@ -49,7 +49,8 @@ class Stats(C.Structure):
     _fields_ = [("calls", C.c_int64), ("last_messages", C.c_int64), ("last_bytes", C.c_int64),
                 ("total_messages", C.c_int64), ("total_bytes", C.c_int64), ("plans_built", C.c_int64),
                 ("stencil_rows", C.c_int64), ("stencil_waves", C.c_int64),
-                ("cache_hits", C.c_int64), ("cache_misses", C.c_int64), ("stencil_order", C.c_int64)]
+                ("cache_hits", C.c_int64), ("cache_misses", C.c_int64), ("stencil_order", C.c_int64),
+                ("allocs", C.c_int64)]
 
 
 class Profile(C.Structure):
@@ -100,6 +101,7 @@ def load():
         "hdarray_write": (C.c_int, [P, P, C.c_int]),
         "hdarray_read": (C.c_int, [P, P, C.c_int]),
         "hdarray_reduce": (C.c_int, [P, P, C.c_int, C.c_int]),
+        "hdarray_reduce_noalloc": (C.c_int, [P, P, C.c_int, C.c_int]),
         "hdarray_set_stream": (C.c_int, [P]),
         "hdarray_set_allocator": (C.c_int, [_ALLOC_T, _FREE_T, P]),
         "hdarray_sync": (C.c_int, []),
@@ -281,6 +283,13 @@ class Runtime:
     def reduce(self, arr, op, part):
         res = np.zeros(1, dtype=arr.dtype)
         self._ck(self.L.hdarray_reduce(arr.h, res.ctypes.data, op, part), "reduce")
+        return res[0].item()
+
+    def reduce_noalloc(self, arr, op, part):
+        """hdarray_reduce_noalloc: as reduce, with no allocation (the plan of
+        (arr, part) must come from an earlier reduce)."""
+        res = np.zeros(1, dtype=arr.dtype)
+        self._ck(self.L.hdarray_reduce_noalloc(arr.h, res.ctypes.data, op, part), "reduce_noalloc")
         return res[0].item()
 
     def sync(self):

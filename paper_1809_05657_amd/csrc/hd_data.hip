@@ -258,4 +258,45 @@ hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const Ar
 
 int reduce_blocks() { return kRedBlocks; }
 
+// ------------------------------------------------- reduce without allocation
+// Scratch of the no-allocation reduce: the device-side result (first 256
+// bytes), then the FP64 partials and the 32-bit integer partials of every
+// (box, block) pair.  One copy per GPU, held until the process ends; calls on
+// one GPU share it, so overlapping calls race.  In host code `scratch` is only
+// a host-side stand-in: its device address comes from hipGetSymbolAddress.
+constexpr int64_t kScratchBytes = 64 * 1024;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static void *g_scratch_ptr[kScratchDevices] = {};
+
+// Looks up this GPU's copy of the scratch array; called once per device at
+// set-up, with that device current.
+hipError_t reduce_scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+// Bytes of scratch one reduce over nbox boxes needs, and the maximum.
+int64_t reduce_scratch_need(int nbox) { return 256 + (int64_t)nbox * kRedBlocks * (8 + 4); }
+int64_t reduce_scratch_max() { return kScratchBytes; }
+
+// The reduce kernels of launch_reduce with the partials and the result in
+// this device's scratch; *res_dev receives the result's device address.
+hipError_t launch_reduce_scratch(int device, int type, int op, const WorkBox *wb, int nbox, const ArrDev *A, int arr,
+                                 void **res_dev, hipStream_t s) {
+  if (device < 0 || device >= kScratchDevices || !g_scratch_ptr[device]) return hipErrorNotInitialized;
+  if (reduce_scratch_need(nbox) > kScratchBytes) return hipErrorInvalidValue;
+  char *base = static_cast<char *>(g_scratch_ptr[device]);
+  double *pf = reinterpret_cast<double *>(base + 256);
+  uint32_t *pi = reinterpret_cast<uint32_t *>(base + 256 + (int64_t)nbox * kRedBlocks * 8);
+  *res_dev = base;
+  return launch_reduce(type, op, wb, nbox, A, arr, pf, pi, base, s);
+}
+
 }  // namespace hd

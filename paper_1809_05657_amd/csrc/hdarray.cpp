@@ -45,6 +45,11 @@ hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const Ar
                          uint32_t *pi, void *res, hipStream_t s);
 hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipStream_t s);
 int reduce_blocks();
+hipError_t reduce_scratch_init(int device);
+int64_t reduce_scratch_need(int nbox);
+int64_t reduce_scratch_max();
+hipError_t launch_reduce_scratch(int device, int type, int op, const WorkBox *wb, int nbox, const ArrDev *A, int arr,
+                                 void **res_dev, hipStream_t s);
 int batch_max_blocks(int max_per_cu);
 hipError_t launch_batch(const BatchArgs &a, int th, int hf, int grid, hipStream_t s);
 int64_t adj_tiles(const WorkBox &B, const int64_t *n);
@@ -243,6 +248,7 @@ static int fail(int code) {
 
 static void *dalloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
+  R.stats.allocs++;
   if (R.ualloc) return R.ualloc(bytes, R.uctx);
   void *p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
@@ -364,7 +370,10 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   // [4], [5]: rows listed past the one-lane GDEF update; [6], [7]: rows for
   // the LDS update; each pair alternates between calls
   R.W.ovf_cnt = R.counters + 4;
+  R.stats.allocs++;
   HIPCK(hipHostMalloc((void **)&R.red_res_host, 64, hipHostMallocDefault));
+  // this GPU's copy of the no-allocation reduce's static scratch
+  HIPCK(reduce_scratch_init(dev));
   R.red_res_dev = dalloc(64);
   R.red_pf = (double *)dalloc(sizeof(double) * kMaxDev * 64 * 4);
   R.red_pi = (uint32_t *)dalloc(sizeof(uint32_t) * kMaxDev * 64 * 4);
@@ -474,6 +483,7 @@ extern "C" const char *hdarray_error_string(int code) {
     case HD_EHIP: return "HIP runtime error";
     case HD_ESTATE: return "runtime not initialised";
     case HD_ECAPACITY: return "GDEF row list or work pool capacity exceeded";
+    case HD_ENOPLAN: return "no-allocation call needs the plan an earlier call on the same array and partition built";
   }
   return "unknown error";
 }
@@ -519,6 +529,7 @@ extern "C" hd_array_t *hdarray_create(const char *sym, const char *type, const v
     }
   a->N = a->n[0] * a->n[1] * a->n[2];
   size_t bytes = (size_t)a->N * a->esize;
+  R.stats.allocs++;
   if (hipHostMalloc((void **)&a->host, bytes, hipHostMallocDefault) != hipSuccess) {
     delete a;
     fail(HD_ENOMEM);
@@ -1958,6 +1969,34 @@ extern "C" int hdarray_reduce(hd_array_t *ah, void *res, hd_reduce_t op, int par
   HIPCK(hipStreamSynchronize(R.meta));
   int rc = check_err();
   if (rc != HD_OK) return rc;
+  memcpy(res, R.red_res_host, a->esize);
+  return HD_OK;
+}
+
+// Reduce with no allocation: the plan of (array, partition) must exist (an
+// earlier hdarray_reduce built it, with its workspace and device buffers);
+// the partials and the device-side result go to the library's static scratch.
+extern "C" int hdarray_reduce_noalloc(hd_array_t *ah, void *res, hd_reduce_t op, int part) {
+  if (!R.inited) return fail(HD_ESTATE);
+  hd_array *a = get_arr(ah);
+  if (!a || !res || op < HD_SUM || op > HD_MIN) return fail(HD_EINVAL);
+  const auto it = R.plans.find(std::vector<int64_t>{2, 1, part, a->id});
+  if (it == R.plans.end()) return fail(HD_ENOPLAN);
+  Plan *pl = it->second;
+  if (reduce_scratch_need(pl->nbox) > reduce_scratch_max()) return fail(HD_ECAPACITY);
+  // phase timers may create events; they stay off for this call
+  const int prof = R.prof;
+  R.prof = 0;
+  const int rc = enqueue(pl, nullptr);
+  R.prof = prof;
+  if (rc != HD_OK) return g_last_error;
+  void *res_dev = nullptr;
+  HIPCK(launch_reduce_scratch(R.device, a->type, op, pl->wb, pl->nbox, R.d_arrs, a->id, &res_dev, R.data));
+  HIPCK(hipMemcpyAsync(R.red_res_host, res_dev, 8, hipMemcpyDeviceToHost, R.data));
+  HIPCK(hipStreamSynchronize(R.data));
+  HIPCK(hipStreamSynchronize(R.meta));
+  const int rc2 = check_err();
+  if (rc2 != HD_OK) return rc2;
   memcpy(res, R.red_res_host, a->esize);
   return HD_OK;
 }
