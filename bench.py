@@ -55,15 +55,15 @@ def committed_traffic(name, kernel, sources=KERNEL_SOURCES):
 KERNEL_SAMPLE = 4  # every 4th step of a timed loop times its stencil launch
 
 
-def stencil_kernel_name(st, one, four, strip, op):
+def stencil_kernel_name(st, one, strip, op):
     """Name (as the profiler prints it, without spaces) of the 2-D stencil
     kernel the last call launched, from the shape in the runtime's stats."""
     rows, waves, order = st["stencil_rows"], st["stencil_waves"], st["stencil_order"]
     if rows >= 32:
         return f"{strip}<{rows},{op}>"
-    tri = ",false" if op == 0 else ""
     if waves == 4:
-        return f"{four}<{rows}{tri}>"
+        return f"k_stack<{rows},{op},{'true' if st['stencil_vec'] else 'false'}>"
+    tri = ",false" if op == 0 else ""
     return f"{one}<{rows}{tri},{'true' if order else 'false'}>"
 
 
@@ -271,7 +271,7 @@ def bench_conv2d(hd, rt, steps, warmup):
     byts = 2 * 4 * n * n
     avg_ms = kms / max(kcnt, 1)
     ach = byts / (avg_ms * 1e-3) / 1e9
-    kname = stencil_kernel_name(st, "k_conv1", "k_conv", "k_strip", 2)
+    kname = stencil_kernel_name(st, "k_conv1", "k_strip", 2)
     return {"metric": "conv2d steps/s", "value": steps / dt, "unit": "steps/s", "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": dt * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -535,7 +535,7 @@ def main():
     # those of both: read + write for the pack and again for the unpack
     pk_ms = ph["pack"][0] / max(ph["pack"][1], 1)
     moved = st["last_bytes"]
-    kname = stencil_kernel_name(st, "k_jacobi1", "k_jacobi", "k_strip", 0)
+    kname = stencil_kernel_name(st, "k_jacobi1", "k_strip", 0)
     out = {
         "metric": METRIC,
         "value": args.steps / dt,

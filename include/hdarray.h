@@ -314,16 +314,19 @@ typedef struct {
   int64_t cache_misses;    /* plan-cache calls that derived one */
   int64_t stencil_order;   /* tile order of the last stencil launch (1 along rows, 0 down columns) */
   int64_t allocs;          /* device and pinned host allocations the library has made */
+  int64_t stencil_vec;     /* 1: the last stencil launch read every row as float4 */
 } hd_stats_t;
 int hdarray_get_stats(hd_stats_t *st);
 
 /* Tile shape of the 2-D stencil kernels (jacobi2d, tri2d, conv2d9) for
- * later calls: rows = 4, 8 or 16 rows per tile with waves = 1 (one wave per
- * workgroup) or 4 (four tiles of the same rows per workgroup); order = 1:
- * consecutive tiles of an XCD run along a row of tiles, 0: down a column of
- * tiles (one-wave shapes only; four waves always run along rows).  rows =
- * 32 or 64 selects tall strips of that many rows, one wave each, streaming
- * through an 8-row register window (waves and order ignored).  (0, 0, any)
+ * later calls: rows = 4, 8 or 16 rows per wave with waves = 1 (one wave per
+ * workgroup, a tile of rows x 256 columns) or 4 (four waves stacked down a
+ * tile of 4 x rows x 256 columns, the rows above and below each wave's rows
+ * shared through LDS); order = 1: consecutive tiles of an XCD run along a
+ * row of tiles, 0: down a column of tiles (one-wave shapes only; stacked
+ * tiles always run along rows).  rows = 32 or 64 selects tall strips of that
+ * many rows, one wave each, streaming through an 8-row register window
+ * (waves and order ignored).  (0, 0, any)
  * restores the default: the runtime times candidate shapes on the first
  * calls of each work-box geometry and keeps the fastest.  No shape changes
  * a result.  HD_EINVAL for other values, HD_ESTATE before init. */

@@ -12,9 +12,9 @@ namespace hd {
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 int64_t mm_tiles(const int32_t *lo, const int32_t *hi);
 hipError_t launch_mm(const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles, hipStream_t s);
-hipError_t launch_jacobi(bool tri, int th, int waves, int order, const WorkBox *wb, int nbox, const ArrDev *A,
+hipError_t launch_jacobi(bool tri, int th, int waves, int order, bool vec, const WorkBox *wb, int nbox, const ArrDev *A,
                          int64_t ntiles, hipStream_t s);
-hipError_t launch_conv(int th, int waves, int order, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
+hipError_t launch_conv(int th, int waves, int order, bool vec, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
                        const float *coef, hipStream_t s);
 
 // Pack / unpack (mode 0 / 1) or both in one pass (mode 2).  Every message is
@@ -209,15 +209,17 @@ int64_t tiles_for(int kind, const WorkBox &B, int esize, int th) {
   return 0;
 }
 
-hipError_t launch_user(int kind, int th, int waves, int order, const WorkBox *wb, int nbox, const ArrDev *A,
+// vec: every box's rows can be read as float4 (row length and box start
+// multiples of 4); only the stacked 2-D stencil shape uses it.
+hipError_t launch_user(int kind, int th, int waves, int order, bool vec, const WorkBox *wb, int nbox, const ArrDev *A,
                        int64_t ntiles, const float *coef, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   switch (kind) {
     case 1:
     case 5:
-      return launch_jacobi(kind == 5, th, waves, order, wb, nbox, A, ntiles, s);
+      return launch_jacobi(kind == 5, th, waves, order, vec, wb, nbox, A, ntiles, s);
     case 6:
-      return launch_conv(th, waves, order, wb, nbox, A, ntiles, coef, s);
+      return launch_conv(th, waves, order, vec, wb, nbox, A, ntiles, coef, s);
     case 2:
       hipLaunchKernelGGL(k_copy, dim3(ntiles), dim3(64), 0, s, wb, nbox, A, ntiles);
       break;

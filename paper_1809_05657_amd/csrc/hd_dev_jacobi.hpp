@@ -352,6 +352,94 @@ __device__ inline void dev_strip(const WorkBox &B, int64_t lt, const ArrDev *__r
   }
 }
 
+// ------------------------------------------------------- stacked waves
+// W waves stacked down one tile of W*TH rows x 256 columns: each wave loads
+// its own TH rows once; the row above its first and the row below its last
+// come from the neighbouring waves through LDS (the top and bottom waves
+// load the tile's two halo rows), so a tile reads W*TH + 2 rows instead of
+// W*(TH + 2).  Tiles run along rows of tiles.  VEC: every box of the launch
+// has rows that can be read as float4 (row length and box start multiples
+// of 4); otherwise each wave takes the coalesced per-wave path (no LDS).
+// OP: 0 Jacobi, 1 lower-triangular Jacobi, 2 3 x 3 convolution.
+template <int W, int TH, int OP, bool VEC>
+__device__ inline void dev_stack_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef9 &Wt) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int tx, ty;
+  tile_pos<W * TH, true>(B, lt, tx, ty);
+  const int t0 = B.lo[1] + ty * (W * TH);
+  const int t1 = min(t0 + W * TH, B.hi[1]);
+  // triangular kernel: a tile entirely above the diagonal writes nothing
+  // (the whole workgroup leaves together, before the barrier)
+  if (OP == 1 && B.lo[2] + tx * 256 > t1 - 1) return;
+  const int c = B.lo[2] + tx * 256 + 4 * lane;
+  const ArrDev &ai = A[B.ain];
+  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
+  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const int r0 = t0 + wv * TH;
+  if (!VEC) {
+    if (r0 >= t1) return;
+    const int r1 = min(r0 + TH, t1);
+    if (OP != 2) {
+      dev_jacobi_tile_i<TH, OP == 1, true>(B, tx, r0, r1, in, out, N1, N2);
+    } else {
+      f4 v[TH + 2];
+      float L[TH + 2], R[TH + 2];
+      load_rows<TH>(in, r0, r1, c, N1, N2, false, v, L, R);
+#pragma unroll
+      for (int k = 1; k <= TH; ++k) {
+        const int i = r0 + k - 1;
+        if (i >= r1) break;
+        strip_row<2>(i, c, N1, N2, B, v[k - 1], v[k], v[k + 1], L[k - 1], R[k - 1], L[k], R[k], L[k + 1], R[k + 1],
+                     Wt, out, false);
+      }
+    }
+    return;
+  }
+  // [0]: each wave's first row, [1]: its last row; the convolution also
+  // needs those rows' left / right neighbour columns
+  __shared__ f4 sv[2][W][64];
+  __shared__ float sl[OP == 2 ? 2 : 1][W][64], sr[OP == 2 ? 2 : 1][W][64];
+  f4 v[TH + 2];
+  float L[TH + 2], R[TH + 2];
+  // rows up to t1 are read (t1 itself is the halo below the tile's last row);
+  // rows outside the array or past t1 read as zero and are never used
+#pragma unroll
+  for (int k = 1; k <= TH; ++k) load_row(in, r0 - 1 + k, t1, c, N1, N2, true, v[k], L[k], R[k]);
+  if (wv == 0) load_row(in, r0 - 1, t1, c, N1, N2, true, v[0], L[0], R[0]);
+  if (wv == W - 1) load_row(in, r0 + TH, t1, c, N1, N2, true, v[TH + 1], L[TH + 1], R[TH + 1]);
+  sv[0][wv][lane] = v[1];
+  sv[1][wv][lane] = v[TH];
+  if (OP == 2) {
+    sl[0][wv][lane] = L[1];
+    sr[0][wv][lane] = R[1];
+    sl[OP == 2 ? 1 : 0][wv][lane] = L[TH];
+    sr[OP == 2 ? 1 : 0][wv][lane] = R[TH];
+  }
+  __syncthreads();
+  if (wv > 0) {
+    v[0] = sv[1][wv - 1][lane];
+    if (OP == 2) {
+      L[0] = sl[OP == 2 ? 1 : 0][wv - 1][lane];
+      R[0] = sr[OP == 2 ? 1 : 0][wv - 1][lane];
+    }
+  }
+  if (wv < W - 1) {
+    v[TH + 1] = sv[0][wv + 1][lane];
+    if (OP == 2) {
+      L[TH + 1] = sl[0][wv + 1][lane];
+      R[TH + 1] = sr[0][wv + 1][lane];
+    }
+  }
+#pragma unroll
+  for (int k = 1; k <= TH; ++k) {
+    const int i = r0 + k - 1;
+    if (i >= t1) break;
+    strip_row<OP>(i, c, N1, N2, B, v[k - 1], v[k], v[k + 1], L[k - 1], R[k - 1], L[k], R[k], L[k + 1], R[k + 1], Wt,
+                  out, true);
+  }
+}
+
 __host__ __device__ inline int64_t jacobi_tiles(const WorkBox &B, int th) {
   const int64_t h = B.hi[1] - B.lo[1], w = B.hi[2] - B.lo[2];
   if (h <= 0 || w <= 0 || B.hi[0] <= B.lo[0]) return 0;

@@ -1,24 +1,40 @@
 // hd_jacobi.hip — the per-call Jacobi / lower-triangular / 3 x 3
 // convolution kernels over every logical device's work box in one launch
 // (device code in hd_dev_jacobi.hpp).
-// Two workgroup shapes: four waves walking a row of tiles, or one wave per
-// workgroup with the tiles of an XCD walking down columns; the runtime picks
-// one by timing both on real calls.
+// Workgroup shapes: four waves stacked down a tile (halo rows shared through
+// LDS), one wave per tile (tiles of an XCD along rows or down columns), or
+// tall one-wave strips; the runtime picks one by timing them on real calls.
 #include <hip/hip_runtime.h>
 
 #include "hd_dev_jacobi.hpp"
 
 namespace hd {
 
-// Four waves per workgroup, one tile each (4 x 256 columns of the same rows).
-template <int TH, bool TRI>
-__global__ __launch_bounds__(256) void k_jacobi(const WorkBox *__restrict__ wb, int nbox,
-                                                const ArrDev *__restrict__ A, int64_t ntiles) {
-  const int64_t nwg = (ntiles + 3) >> 2;
-  const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
-  if (t >= ntiles) return;
+// Four waves stacked down a tile of 4*TH rows x 256 columns, halo rows
+// shared through LDS (OP: 0 Jacobi, 1 triangular, 2 convolution; VEC: all
+// boxes float4-aligned).
+template <int TH, int OP, bool VEC>
+__global__ __launch_bounds__(256) void k_stack(const WorkBox *__restrict__ wb, int nbox,
+                                               const ArrDev *__restrict__ A, int64_t ntiles, Coef9 w) {
+  const int64_t t = xcd_remap(blockIdx.x, ntiles);
   const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_jacobi_tile<TH, TRI, true>(B, t - B.tile0, A);
+  dev_stack_tile<4, TH, OP, VEC>(B, t - B.tile0, A, w);
+}
+
+template <int TH, bool VEC>
+static void *stack_kernel(int op) {
+  return op == 0 ? (void *)k_stack<TH, 0, VEC> : op == 1 ? (void *)k_stack<TH, 1, VEC> : (void *)k_stack<TH, 2, VEC>;
+}
+
+static hipError_t launch_stack(int op, int th, bool vec, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
+                               const Coef9 &w, hipStream_t s) {
+  typedef void (*sk_t)(const WorkBox *, int, const ArrDev *, int64_t, Coef9);
+  void *k;
+  if (th == 4) k = vec ? stack_kernel<4, true>(op) : stack_kernel<4, false>(op);
+  else if (th == 8) k = vec ? stack_kernel<8, true>(op) : stack_kernel<8, false>(op);
+  else k = vec ? stack_kernel<16, true>(op) : stack_kernel<16, false>(op);
+  hipLaunchKernelGGL((sk_t)k, dim3((unsigned)ntiles), dim3(256), 0, s, wb, nbox, A, ntiles, w);
+  return hipGetLastError();
 }
 
 // One wave per workgroup; the tiles of an XCD walk along rows of tiles (HF)
@@ -50,16 +66,12 @@ static hipError_t launch_strip(int op, int th, const WorkBox *wb, int nbox, cons
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi(bool tri, int th, int waves, int order, const WorkBox *wb, int nbox, const ArrDev *A,
-                         int64_t ntiles, hipStream_t s) {
+hipError_t launch_jacobi(bool tri, int th, int waves, int order, bool vec, const WorkBox *wb, int nbox,
+                         const ArrDev *A, int64_t ntiles, hipStream_t s) {
   typedef void (*jk_t)(const WorkBox *, int, const ArrDev *, int64_t);
   if (th >= 32) return launch_strip(tri ? 1 : 0, th, wb, nbox, A, ntiles, Coef9{}, s);
-  if (waves == 4) {
-    jk_t k = tri ? k_jacobi<8, true> : k_jacobi<8, false>;
-    if (th == 4) k = tri ? k_jacobi<4, true> : k_jacobi<4, false>;
-    if (th == 16) k = tri ? k_jacobi<16, true> : k_jacobi<16, false>;
-    hipLaunchKernelGGL(k, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles);
-  } else if (order) {
+  if (waves == 4) return launch_stack(tri ? 1 : 0, th, vec, wb, nbox, A, ntiles, Coef9{}, s);
+  if (order) {
     jk_t k = tri ? k_jacobi1<8, true, true> : k_jacobi1<8, false, true>;
     if (th == 4) k = tri ? k_jacobi1<4, true, true> : k_jacobi1<4, false, true>;
     if (th == 16) k = tri ? k_jacobi1<16, true, true> : k_jacobi1<16, false, true>;
@@ -73,17 +85,7 @@ hipError_t launch_jacobi(bool tri, int th, int waves, int order, const WorkBox *
   return hipGetLastError();
 }
 
-// The 3 x 3 convolution on the same two workgroup shapes.
-template <int TH>
-__global__ __launch_bounds__(256) void k_conv(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
-                                              int64_t ntiles, Coef9 w) {
-  const int64_t nwg = (ntiles + 3) >> 2;
-  const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
-  if (t >= ntiles) return;
-  const WorkBox B = wb[find_box(wb, nbox, t)];
-  dev_conv_tile<TH, true>(B, t - B.tile0, A, w);
-}
-
+// The 3 x 3 convolution on the same workgroup shapes.
 template <int TH, bool HF>
 __global__ __launch_bounds__(64) void k_conv1(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
                                               int64_t ntiles, Coef9 w) {
@@ -92,16 +94,14 @@ __global__ __launch_bounds__(64) void k_conv1(const WorkBox *__restrict__ wb, in
   dev_conv_tile<TH, HF>(B, t - B.tile0, A, w);
 }
 
-hipError_t launch_conv(int th, int waves, int order, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
-                       const float *coef, hipStream_t s) {
+hipError_t launch_conv(int th, int waves, int order, bool vec, const WorkBox *wb, int nbox, const ArrDev *A,
+                       int64_t ntiles, const float *coef, hipStream_t s) {
   typedef void (*ck_t)(const WorkBox *, int, const ArrDev *, int64_t, Coef9);
   Coef9 w;
   for (int e = 0; e < 9; ++e) w.w[e] = coef ? coef[e] : 0.f;
   if (th >= 32) return launch_strip(2, th, wb, nbox, A, ntiles, w, s);
-  if (waves == 4) {
-    ck_t k = th == 4 ? k_conv<4> : th == 16 ? k_conv<16> : k_conv<8>;
-    hipLaunchKernelGGL(k, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles, w);
-  } else if (order) {
+  if (waves == 4) return launch_stack(2, th, vec, wb, nbox, A, ntiles, w, s);
+  if (order) {
     ck_t k = th == 4 ? k_conv1<4, true> : th == 16 ? k_conv1<16, true> : k_conv1<8, true>;
     hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(64), 0, s, wb, nbox, A, ntiles, w);
   } else {

@@ -39,7 +39,7 @@ hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32
 int64_t tiles_for(int kind, const WorkBox &B, int esize, int th);
 hipError_t launch_ext_copy(const WorkBox *wb, int nbox, int64_t rows, const ArrDev *A, int arr, void *ext,
                            int to_ext, hipStream_t s);
-hipError_t launch_user(int kind, int th, int waves, int order, const WorkBox *wb, int nbox, const ArrDev *A,
+hipError_t launch_user(int kind, int th, int waves, int order, bool vec, const WorkBox *wb, int nbox, const ArrDev *A,
                        int64_t ntiles, const float *coef, hipStream_t s);
 hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const ArrDev *A, int arr, double *pf,
                          uint32_t *pi, void *res, hipStream_t s);
@@ -114,6 +114,7 @@ struct Plan {
   // stencil kinds: the work boxes for 4, 8 and 16 rows per tile, and the
   // key of the tile-shape tuning shared by plans with the same boxes
   WorkBox *wbj[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool vec = false;  // every work box's rows can be read as float4
   int64_t ntj[5] = {0, 0, 0, 0, 0};
   std::vector<int64_t> tkey;
   // device-pointer Write / Read plans: the partition's regions as boxes whose
@@ -146,13 +147,13 @@ struct CallArray;
 struct RecCall;
 struct Batch;
 
-// Stencil tile shapes tried on real calls (rows per tile, waves per
-// workgroup; one wave walks tiles down the box, four walk along rows), each
-// timed kTuneReps times in interleaved order; the fastest is kept.  The
-// shape never changes a result.
+// Stencil tile shapes tried on real calls, each timed kTuneReps times in
+// interleaved order; the fastest is kept.  The shape never changes a result.
 constexpr int kTuneN = 4, kTuneReps = 2;
-// (rows per tile, waves per workgroup, order: 1 along rows, 0 down columns)
-constexpr int kTuneCand[kTuneN][3] = {{4, 1, 1}, {8, 1, 1}, {4, 4, 1}, {4, 1, 0}};
+// (rows per wave, waves per workgroup, order): one wave per tile with the
+// tiles of an XCD along rows (order 1) or down columns (0), or four waves
+// stacked down a tile of 4 x rows (halo rows shared through LDS)
+constexpr int kTuneCand[kTuneN][3] = {{4, 4, 1}, {8, 4, 1}, {4, 1, 1}, {4, 1, 0}};
 struct TuneState {
   int next = 0;
   bool done = false;
@@ -1538,17 +1539,20 @@ static int enqueue_user(Plan *pl, const float *coef) {
     int th = 8, waves = 1, order = 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     stencil_shape(pl, th, waves, order, e0, e1);
-    const int q = th == 4 ? 0 : th == 8 ? 1 : th == 16 ? 2 : th == 32 ? 3 : 4;
+    // tile height: rows per wave, times four for the stacked shape
+    const int tr = waves == 4 && th < 32 ? 4 * th : th;
+    const int q = tr == 4 ? 0 : tr == 8 ? 1 : tr == 16 ? 2 : tr == 32 ? 3 : 4;
     R.stats.stencil_rows = th;
     R.stats.stencil_waves = waves;
     R.stats.stencil_order = order;
+    R.stats.stencil_vec = pl->vec ? 1 : 0;
     PhaseTimer tm(3, R.data);
     if (e0) HIPCK(hipEventRecord(e0, R.data));
-    HIPCK(launch_user(pl->ukind, th, waves, order, pl->wbj[q], pl->nbox, R.d_arrs, pl->ntj[q], coef, R.data));
+    HIPCK(launch_user(pl->ukind, th, waves, order, pl->vec, pl->wbj[q], pl->nbox, R.d_arrs, pl->ntj[q], coef, R.data));
     if (e1) HIPCK(hipEventRecord(e1, R.data));
   } else if (pl->ukind) {
     PhaseTimer tm(3, R.data);
-    HIPCK(launch_user(pl->ukind, pl->th, 1, 1, pl->wb, pl->nbox, R.d_arrs, pl->ntiles, coef, R.data));
+    HIPCK(launch_user(pl->ukind, pl->th, 1, 1, pl->vec, pl->wb, pl->nbox, R.d_arrs, pl->ntiles, coef, R.data));
   }
   return HD_OK;
 }
@@ -1782,6 +1786,9 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
         pl->ntj[q] = t0;
         if (!wb.empty()) HIPCK(hipMemcpy(pl->wbj[q], wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice));
       }
+      pl->vec = true;
+      for (const WorkBox &w : wb)
+        if ((w.lo[2] & 3) || (R.arrays[w.ain]->n[2] & 3)) pl->vec = false;
       pl->th = 8;
       pl->wb = pl->wbj[1];
       pl->ntiles = pl->ntj[1];

@@ -224,6 +224,44 @@ def test_stencil_shapes_parity(hd, rows, waves, order):
         orc.apply(k, o[2], [o[gi[0]], o[gi[1]]], w)
         same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"conv step {it}")
     assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+    # float4-aligned boxes (row lengths and box starts multiples of 4: the
+    # stacked shape's LDS path), heights not a multiple of the tile, widths
+    # past one 256-column tile
+    for n0, n1, nd, kind in ((150, 520, 8, prog.BLOCK), (77, 1040, 4, prog.COL)):
+        say(f"  aligned boxes {n0}x{n1} ndev={nd}")
+        A0 = rng.random((n0, n1), dtype=np.float32)
+        B0 = rng.random((n0, n1), dtype=np.float32)
+        rt, orc = hd.Runtime(), O.Oracle()
+        rt.set_stencil_shape(rows, waves, order)
+        g = prog.jacobi_blocks(rt, A0, B0, nd, False, kind)
+        o = prog.jacobi_blocks(orc, A0, B0, nd, False, kind)
+        for it in range(3):
+            k, ag, ao = ("jacAB", [g[0], g[1]], [o[0], o[1]]) if it % 2 == 0 else ("jacBA", [g[1], g[0]], [o[1], o[0]])
+            rt.apply(k, g[2], ag)
+            orc.apply(k, o[2], ao)
+            same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"aligned jacobi step {it}")
+            assert rows >= 32 or waves == 1 or rt.stats()["stencil_vec"] == 1
+        rt, orc = hd.Runtime(), O.Oracle()
+        rt.set_stencil_shape(rows, waves, order)
+        g = prog.conv2d(rt, A0, nd, kind)
+        o = prog.conv2d(orc, A0, nd, kind)
+        for it in range(3):
+            k, gi = ("convAB", (0, 1)) if it % 2 == 0 else ("convBA", (1, 0))
+            rt.apply(k, g[2], [g[gi[0]], g[gi[1]]], w)
+            orc.apply(k, o[2], [o[gi[0]], o[gi[1]]], w)
+            same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"aligned conv step {it}")
+        assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
+    T0, U0 = jacobi_inputs(152, 10)
+    rt, orc = hd.Runtime(), O.Oracle()
+    rt.set_stencil_shape(rows, waves, order)
+    g = prog.tri(rt, T0, U0, [0, 4, 40, 44, 100, 152])
+    o = prog.tri(orc, T0, U0, [0, 4, 40, 44, 100, 152])
+    for it in range(3):
+        k, ag, ao = ("triAB", [g[0], g[1]], [o[0], o[1]]) if it % 2 == 0 else ("triBA", [g[1], g[0]], [o[1], o[0]])
+        rt.apply(k, g[2], ag)
+        orc.apply(k, o[2], ao)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"aligned tri step {it}")
+    assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
 
 
 @pytest.mark.parametrize("n,P", [(64, 4), (96, 3)])
