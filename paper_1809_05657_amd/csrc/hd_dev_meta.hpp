@@ -47,6 +47,9 @@ __device__ inline void wave_lds_sync() {
 
 __device__ inline void set_err(int32_t *err, int code) { atomicCAS(err, 0, code); }
 
+// End (exclusive) of slice s's positions.
+__device__ inline int pend_of(const Level &L, int s) { return L.pend ? L.pend[s] : L.pos[s] + 1; }
+
 // Value of v in lane l (l the same in every lane).
 __device__ inline int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
@@ -283,11 +286,11 @@ __device__ inline void dev_bandflags(const Level &L, int s) {
     } else {
       // every index is read in one round; the item lists are compared four
       // pairs at a time (loads issued together)
-      const int g0 = L.grp[s], g1 = L.grp[s - 1], p0 = L.pos[s], p1 = L.pos[s - 1];
+      const int g0 = L.grp[s], g1 = L.grp[s - 1], p0 = L.pos[s];
       const int c = L.icnt[s], cp = L.icnt[s - 1];
       const Item *x = L.items + L.ioff[s];
       const Item *y = L.items + L.ioff[s - 1];
-      st = g0 != g1 || p0 != p1 + 1 || c != cp;
+      st = g0 != g1 || p0 != pend_of(L, s - 1) || c != cp;
       for (int k = 0; k < c && !st; k += 4) {
         Item xa[4], ya[4];
 #pragma unroll
@@ -407,7 +410,7 @@ __device__ inline void lds_items(Item *dst, const Item *src, int cnt, int hcap) 
 __device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *sw, int hcap = kHeadLds) {
   const int lane = threadIdx.x & 63;
   const int s0 = L.bandslice[b], s1 = L.bandslice[b + 1];
-  const bool adj = s0 > 0 && L.grp[s0 - 1] == L.grp[s0] && L.pos[s0 - 1] + 1 == L.pos[s0];
+  const bool adj = s0 > 0 && L.grp[s0 - 1] == L.grp[s0] && pend_of(L, s0 - 1) == L.pos[s0];
   const int off = L.ioff[s0];
   const Item *cur = L.items + off;
   const int cc = L.icnt[s0];
@@ -423,7 +426,7 @@ __device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *
     const int t0 = L.bandslice[bl];
     n_end = L.bandslice[bl + 1];
     if (t0 < L.nsl) {
-      n_cont = L.grp[t0] == L.grp[t0 - 1] && L.pos[t0] == L.pos[t0 - 1] + 1;
+      n_cont = L.grp[t0] == L.grp[t0 - 1] && L.pos[t0] == pend_of(L, t0 - 1);
       n_tc = L.icnt[t0];
       n_to = L.ioff[t0];
     }
@@ -453,7 +456,7 @@ __device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *
         tend = lane_read(n_end, q);
       } else {
         const int t0 = bb < nb ? L.bandslice[bb] : L.nsl;
-        cont = bb < nb && t0 < L.nsl && L.grp[t0] == L.grp[t0 - 1] && L.pos[t0] == L.pos[t0 - 1] + 1;
+        cont = bb < nb && t0 < L.nsl && L.grp[t0] == L.grp[t0 - 1] && L.pos[t0] == pend_of(L, t0 - 1);
         tc = cont ? L.icnt[t0] : 0;
         toff = cont ? L.ioff[t0] : 0;
         tend = cont ? L.bandslice[bb + 1] : L.nsl;
@@ -472,7 +475,7 @@ __device__ inline void dev_heads(const Level &L, int b, int nb, Item *sp, Item *
     }
     if (head) {
       it.pos0 = p0;
-      it.pos1 = L.pos[e - 1] + 1;
+      it.pos1 = pend_of(L, e - 1);
       L.heads[off + nh + __popcll(m & lanemask_lt())] = it;
       vol += (int64_t)(it.pos1 - it.pos0) * (it.a1 - it.a0) * max(1, it.b1 - it.b0);
     }

@@ -7,6 +7,14 @@
 // Each row holds a run-length list of intervals [start_i, start_{i+1}) with
 // one (owner, holders) state each; adjacent intervals always differ, so the
 // list of a row is unique.  The list of row g lives at ivl[g*cap .. g*cap+cnt[g]).
+//
+// Bands: the host keeps, per array, plane and row breakpoints between which
+// every row is known to hold the same list.  A call's derivation works on
+// cells (a band of planes x a band of rows on which the call's use and def
+// sections are uniform too): one slice per cell with use sections, read
+// from the cell's first row (its representative), and one GDEF update per
+// cell, written to the representative and then copied to the cell's other
+// rows.  So the work of a call is proportional to its sections, not to rows.
 #pragma once
 #include <stdint.h>
 
@@ -56,7 +64,8 @@ struct Run {
   int32_t src, dst, a0, a1;
 };
 
-// One level-1 slice (a use row) as dev_runs reads it: a single record.
+// One level-1 slice (a cell with use sections, read at its representative
+// row) as dev_runs reads it: a single record.
 struct SliceRec {
   int32_t arr;   // runtime array id
   int32_t seg0;  // first use segment of the row
@@ -65,7 +74,8 @@ struct SliceRec {
   int64_t grow;  // global row (plane * n1 + row)
 };
 
-// One row of a GDEF update as k_gdef reads it: a single record.
+// One cell of a GDEF update as k_gdef reads it (its representative row):
+// a single record.
 struct GRowRec {
   int32_t arr;    // runtime array id
   int32_t slice;  // level-1 slice whose runs add holders, or -1
@@ -98,11 +108,29 @@ struct MsgHdr {
   int64_t bytes;
 };
 
+// A GDEF cell of more than one row: planes [p0, p1) x rows [r0, r1) of an
+// array; grow is the representative (p0, r0) as a global row.
+struct RepRec {
+  int32_t arr;
+  int32_t p0, p1, r0, r1;
+  int32_t pad;
+  int64_t grow;
+};
+
+// 64 rows of a cell (k0: first row index within the cell, row-major).
+struct RepChunk {
+  int32_t cell;
+  int32_t k0;
+};
+
 // One stacking level: slices with a (group, position) key and an item list.
+// A slice covers positions [pos, pend) (rows of a band, or planes of a band
+// at level 2); pend null: one position each.
 struct Level {
   int32_t nsl;
   const int32_t *grp;  // [nsl]
   const int32_t *pos;  // [nsl]
+  const int32_t *pend; // [nsl] or null
   const int32_t *ioff; // [nsl]
   const int32_t *icnt; // [nsl]
   const Item *items;
@@ -146,6 +174,7 @@ struct PlanDev {
   int32_t nsl1;
   const int32_t *grp1;
   const int32_t *pos1;
+  const int32_t *pend1;  // end row (exclusive) of each slice's band
   const int64_t *grow1;  // global row of each slice
   const int32_t *seg0;
   const int32_t *nseg;
@@ -156,13 +185,19 @@ struct PlanDev {
   const int32_t *grp_plane;  // [ngrp]
   // level 2 (3-D arrays): slices = groups
   const int32_t *grp2;  // [ngrp] = aidx
-  const int32_t *pos2;  // [ngrp] = plane
+  const int32_t *pos2;  // [ngrp] = first plane of the group's band
+  const int32_t *pend2; // [ngrp] end plane (exclusive)
   // GDEF update rows: the ngfull rows the definitions tile come first
   int32_t ngrow;
   int32_t ngfull;
   int32_t gdef_lane;  // 1: update the other GDEF rows one per lane first (k_gdef), 0: one wave per row
   const GRowRec *grec;  // [ngrow]
   const Seg *dseg;
+  // cells of more than one row: their other rows take the representative's
+  // list after the update
+  int32_t nrep, nrepchunk;
+  const RepRec *rep;
+  const RepChunk *repchunk;
 };
 
 struct Work {

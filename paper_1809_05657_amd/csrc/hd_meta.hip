@@ -143,6 +143,29 @@ __global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict
   for (int q = blockIdx.x; q < n; q += gridDim.x) dev_gdef_row(P, A, W, W.ovf_list2[q], S, kGdefMaxB);
 }
 
+// The other rows of every GDEF cell take the list the update wrote to the
+// cell's representative (they held the same list before the call and get
+// the same update); one wave per 64 rows of a cell, one row per lane.
+__global__ __launch_bounds__(64) void k_gdef_rep(PlanDev P, ArrDev *__restrict__ A) {
+  const int lane = threadIdx.x & 63;
+  for (int q = blockIdx.x; q < P.nrepchunk; q += gridDim.x) {
+    const RepChunk ch = P.repchunk[q];
+    const RepRec c = P.rep[ch.cell];
+    const ArrDev &a = A[c.arr];
+    const int64_t cap = a.cap;
+    const int nr = c.r1 - c.r0;
+    const int64_t rows = (int64_t)(c.p1 - c.p0) * nr;
+    const int64_t k = (int64_t)ch.k0 + lane;
+    if (k < 1 || k >= rows) continue;  // k = 0 is the representative itself
+    const Ivl *src = a.ivl + c.grow * cap;
+    const int n = a.cnt[c.grow];
+    const int64_t g = (int64_t)(c.p0 + k / nr) * a.n[1] + c.r0 + k % nr;
+    Ivl *dst = a.ivl + g * cap;
+    for (int i = 0; i < n; ++i) dst[i] = src[i];
+    a.cnt[g] = n;
+  }
+}
+
 // Every row starts as one interval [0, n2) owned and held by the host.
 __global__ void k_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < rows; g += (int64_t)gridDim.x * blockDim.x) {
@@ -255,6 +278,10 @@ hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s
     hipLaunchKernelGGL(k_gdef_wave, dim3(grid), dim3(64), 0, s, P, A, W, cur2, nfw);
   }
   hipLaunchKernelGGL(k_gdef_large, dim3(kGdefLargeGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur2, other, other2);
+  if (P.nrepchunk > 0) {
+    const int grid = P.nrepchunk < 4096 ? P.nrepchunk : 4096;
+    hipLaunchKernelGGL(k_gdef_rep, dim3(grid), dim3(64), 0, s, P, A);
+  }
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <string>
 #include <tuple>
@@ -87,6 +88,9 @@ struct hd_array {
   // deterministic function of the state before and the plan).
   std::vector<uint64_t> hist;
   bool hist_ok = false;
+  // GDEF bands: sorted plane / row breakpoints (with 0 and n); all rows of
+  // planes [pbrk[i], pbrk[i+1]) x rows [rbrk[k], rbrk[k+1]) hold the same list
+  std::vector<int64_t> pbrk, rbrk;
 };
 
 struct Partition {
@@ -103,10 +107,36 @@ struct Kernel {
   int64_t version;
 };
 
-struct Plan {
+struct CallArray {
+  hd_array *a;
+  int argpos;
+  std::vector<Shape> use[64];
+  std::vector<Shape> def[64];
+  int def_flags = 0;
+  bool no_holders = false;  // receivers do not become holders (adjoint partial sums)
+};
+
+// The device data of a plan for one set of GDEF bands of its arrays.
+struct PlanInst {
   PlanDev P;
   void *mem = nullptr;
+};
+
+struct Plan {
+  PlanDev P;          // the instance selected for the current call
+  void *mem = nullptr;  // work boxes
   int nsl1 = 0, ngrp = 0, ngrow = 0, has3d = 0;
+  int64_t nsl_max = 0;  // slices of the finest instance (one per use row)
+  // the call's arrays with their shapes; per call-array the (endpoint,
+  // shape) lists and the plan's own plane / row breakpoints
+  std::vector<CallArray> cas;
+  std::vector<std::vector<std::pair<int, const Shape *>>> uses, defs;
+  std::vector<std::vector<int64_t>> pbp, rbp;
+  std::map<std::vector<int64_t>, PlanInst *> insts;
+  PlanInst *cur = nullptr;
+  std::vector<int64_t> cur_key;
+  bool rowwise = false;  // one cell per row whatever the bands (batched plans)
+  PlanInst *last_inst = nullptr;  // instance of the plan cache's last derivation
   int64_t stg_bound = 0;  // bytes
   // user kernel
   int ukind = 0, th = 8;
@@ -385,18 +415,14 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
 static void free_ws();
 static void free_batches();
 static void free_plan_buffers(Plan *pl);
+static void plan_free(Plan *pl);
 
 extern "C" void hdarray_exit(void) {
   if (!R.inited) return;
   (void)hipStreamSynchronize(R.meta);
   (void)hipStreamSynchronize(R.meta2);
   (void)hipStreamSynchronize(R.data);
-  for (auto &kv : R.plans) {
-    free_plan_buffers(kv.second);
-    dfree(kv.second->mem);
-    dfree(kv.second->part);
-    delete kv.second;
-  }
+  for (auto &kv : R.plans) plan_free(kv.second);
   R.plans.clear();
   free_batches();
   for (hd_array *a : R.arrays) {
@@ -529,6 +555,9 @@ extern "C" hd_array_t *hdarray_create(const char *sym, const char *type, const v
       return nullptr;
     }
   a->N = a->n[0] * a->n[1] * a->n[2];
+  // every row starts with the same list (the host owns and holds it all)
+  a->pbrk = {0, a->n[0]};
+  a->rbrk = {0, a->n[1]};
   size_t bytes = (size_t)a->N * a->esize;
   R.stats.allocs++;
   if (hipHostMalloc((void **)&a->host, bytes, hipHostMallocDefault) != hipSuccess) {
@@ -838,15 +867,6 @@ static void merge_spans(std::vector<Span> &v) {
   v.resize(o);
 }
 
-struct CallArray {
-  hd_array *a;
-  int argpos;
-  std::vector<Shape> use[64];
-  std::vector<Shape> def[64];
-  int def_flags = 0;
-  bool no_holders = false;  // receivers do not become holders (adjoint partial sums)
-};
-
 struct RecCall {
   std::vector<CallArray> cas;
   std::vector<WorkBox> boxes;
@@ -966,26 +986,120 @@ static int ensure_ws(int64_t nsl, int64_t ngrp, int64_t items, int64_t stg, int6
   return HD_OK;
 }
 
-// Builds the device plan for one communication + GDEF update.  cas: the
-// distinct arrays of the call in argument order with per-endpoint use and
-// def shapes.
-static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
-  std::vector<CallArr> carr(cas.size());
-  std::vector<int32_t> grp1, pos1, seg0, nseg, grp_aidx, grp_plane, grp2, pos2;
+// Columns [c0, c1) of shape s on row r of plane p, clipped to the array
+// (the same rows and columns as shape_rows).
+static bool shape_seg(const Shape &s, const int64_t *n, int64_t p, int64_t r, int32_t &c0, int32_t &c1) {
+  if (s.kind == 0) {
+    if (p < std::max<int64_t>(s.lo[0], 0) || p >= std::min<int64_t>(s.hi[0], n[0])) return false;
+    if (r < std::max<int64_t>(s.lo[1], 0) || r >= std::min<int64_t>(s.hi[1], n[1])) return false;
+    const int64_t a = std::max<int64_t>(s.lo[2], 0), b = std::min<int64_t>(s.hi[2], n[2]);
+    if (a >= b) return false;
+    c0 = (int32_t)a;
+    c1 = (int32_t)b;
+    return true;
+  }
+  const int64_t r0 = s.c[0], r1 = s.c[4];
+  if (p != 0 || r < std::max<int64_t>(r0, 0) || r > std::min<int64_t>(r1, n[1] - 1)) return false;
+  int64_t l, rt;
+  if (r1 == r0) {
+    l = s.c[1];
+    rt = s.c[3];
+  } else {
+    l = s.c[1] + floordiv((r - r0) * (s.c[5] - s.c[1]), r1 - r0);
+    rt = s.c[3] + floordiv((r - r0) * (s.c[7] - s.c[3]), r1 - r0);
+  }
+  l = std::max<int64_t>(l, 0);
+  rt = std::min<int64_t>(rt, n[2] - 1);
+  if (l > rt) return false;
+  c0 = (int32_t)l;
+  c1 = (int32_t)(rt + 1);
+  return true;
+}
+
+// Plane and row breakpoints of a shape: its segment is the same on every
+// row between two consecutive ones (a box: its faces; a trapezoid: every
+// row unless both edges are vertical).
+static void shape_breaks(const Shape &s, const int64_t *n, std::vector<int64_t> &pb, std::vector<int64_t> &rb) {
+  auto clip = [](int64_t v, int64_t hi) { return std::min<int64_t>(std::max<int64_t>(v, 0), hi); };
+  if (s.kind == 0) {
+    pb.push_back(clip(s.lo[0], n[0]));
+    pb.push_back(clip(s.hi[0], n[0]));
+    rb.push_back(clip(s.lo[1], n[1]));
+    rb.push_back(clip(s.hi[1], n[1]));
+    return;
+  }
+  const int64_t a = clip(s.c[0], n[1]), b = clip(s.c[4] + 1, n[1]);
+  if (s.c[1] == s.c[5] && s.c[3] == s.c[7]) {
+    rb.push_back(a);
+    rb.push_back(b);
+  } else {
+    for (int64_t r = a; r <= b; ++r) rb.push_back(r);
+  }
+}
+
+// Sorted, unique breakpoints including 0 and n.
+static void norm_breaks(std::vector<int64_t> &v, int64_t n) {
+  v.push_back(0);
+  v.push_back(n);
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+}
+
+static std::vector<int64_t> merge_breaks(const std::vector<int64_t> &x, const std::vector<int64_t> &y) {
+  std::vector<int64_t> v;
+  v.reserve(x.size() + y.size());
+  std::merge(x.begin(), x.end(), y.begin(), y.end(), std::back_inserter(v));
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  return v;
+}
+
+// The segments of (plane p, row r) for every endpoint of a shape list,
+// merged per endpoint (overlapping or touching segments joined) and ordered
+// by (endpoint, column).
+static void row_segs(const std::vector<std::pair<int, const Shape *>> &sh, const int64_t *n, int64_t p, int64_t r,
+                     int flags, std::vector<Seg> &out) {
+  out.clear();
+  for (const auto &es : sh) {
+    int32_t c0, c1;
+    if (shape_seg(*es.second, n, p, r, c0, c1)) out.push_back(Seg{es.first, c0, c1, flags});
+  }
+  std::sort(out.begin(), out.end(), [](const Seg &a, const Seg &b) { return std::tie(a.dst, a.c0) < std::tie(b.dst, b.c0); });
+  size_t o = 0;
+  for (size_t i = 0; i < out.size(); ++i) {
+    if (o && out[o - 1].dst == out[i].dst && out[i].c0 <= out[o - 1].c1)
+      out[o - 1].c1 = std::max(out[o - 1].c1, out[i].c1);
+    else
+      out[o++] = out[i];
+  }
+  out.resize(o);
+}
+
+static void free_inst(PlanInst *in) {
+  if (!in) return;
+  dfree(in->mem);
+  delete in;
+}
+
+// Device data of one plan instance: the call's slices and GDEF cells for the
+// given plane / row bands of every call-array (each band uniform in the
+// arrays' GDEF and in the call's sections).
+static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &PB,
+                            const std::vector<std::vector<int64_t>> &QB) {
+  std::vector<CallArr> carr(pl->cas.size());
+  std::vector<int32_t> grp1, pos1, pend1, seg0, nseg, grp_aidx, grp_plane, grp2, pos2, pend2;
   std::vector<int64_t> grow1;
-  std::vector<Seg> useg, dseg;
+  std::vector<Seg> useg, dseg, us, ds;
   std::vector<SliceRec> srec;
   std::vector<GRowRec> grec;
-  PlanDev &P = pl->P;
+  std::vector<RepRec> rep;
+  std::vector<RepChunk> chunks;
+  PlanInst *in = new PlanInst();
+  PlanDev &P = in->P;
   memset(&P, 0, sizeof(P));
-  pl->ca_arr.clear();
-  pl->ca_full.clear();
-  pl->uid = R.next_uid++;
-  P.ncarr = (int)cas.size();
-  int64_t stg = 0;
+  P.ncarr = (int)pl->cas.size();
   int has3d = 0;
-  for (size_t j = 0; j < cas.size(); ++j) {
-    CallArray &ca = cas[j];
+  for (size_t j = 0; j < pl->cas.size(); ++j) {
+    const CallArray &ca = pl->cas[j];
     hd_array *a = ca.a;
     CallArr &C = carr[j];
     C.arr = a->id;
@@ -994,118 +1108,83 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
     C.is3d = a->n[0] > 1;
     for (int k = 0; k < 3; ++k) C.n[k] = a->n[k];
     has3d |= C.is3d;
-    // use spans
-    std::vector<Span> us;
-    for (int e = 0; e < 64; ++e)
-      for (const Shape &s : ca.use[e])
-        shape_rows(s, a->n, [&](int64_t p, int64_t r, int64_t c0, int64_t c1) {
-          us.push_back(Span{p * a->n[1] + r, e, (int32_t)c0, (int32_t)c1, 0});
-        });
-    merge_spans(us);
-    // def spans, race check across devices
-    std::vector<Span> ds;
-    for (int e = 0; e < 64; ++e)
-      for (const Shape &s : ca.def[e])
-        shape_rows(s, a->n, [&](int64_t p, int64_t r, int64_t c0, int64_t c1) {
-          ds.push_back(Span{p * a->n[1] + r, e, (int32_t)c0, (int32_t)c1, ca.def_flags});
-        });
-    merge_spans(ds);
-    {
-      std::vector<Span> byc = ds;
-      std::sort(byc.begin(), byc.end(),
-                [](const Span &x, const Span &y) { return std::tie(x.row, x.c0) < std::tie(y.row, y.c0); });
-      for (size_t i = 1; i < byc.size(); ++i)
-        if (byc[i].row == byc[i - 1].row && byc[i].c0 < byc[i - 1].c1 && byc[i].e != byc[i - 1].e)
-          return fail(HD_ERACE);
-    }
     C.slice0 = (int32_t)grow1.size();
     C.grp0 = (int32_t)grp_aidx.size();
-    // slices: one per row with use spans, in row order; a group per plane
-    size_t i = 0;
-    std::vector<std::pair<int64_t, int32_t>> slice_of_row;  // (row, slice)
-    while (i < us.size()) {
-      const int64_t row = us[i].row;
-      const int32_t plane = (int32_t)(row / a->n[1]);
-      if (grp_aidx.size() == (size_t)C.grp0 || grp_plane.back() != plane) {
-        grp_aidx.push_back((int32_t)j);
-        grp_plane.push_back(plane);
-        grp2.push_back((int32_t)j);
-        pos2.push_back(plane);
+    const std::vector<int64_t> &pb = PB[j], &qb = QB[j];
+    for (size_t ip = 0; ip + 1 < pb.size(); ++ip) {
+      const int64_t pa = pb[ip], pe = pb[ip + 1];
+      bool open = false;
+      for (size_t ir = 0; ir + 1 < qb.size(); ++ir) {
+        const int64_t ra = qb[ir], re = qb[ir + 1];
+        const int64_t grow = pa * a->n[1] + ra;
+        row_segs(pl->uses[j], a->n, pa, ra, 0, us);
+        row_segs(pl->defs[j], a->n, pa, ra, ca.def_flags, ds);
+        int32_t slice = -1;
+        if (!us.empty()) {
+          if (!open) {
+            grp_aidx.push_back((int32_t)j);
+            grp_plane.push_back((int32_t)pa);
+            grp2.push_back((int32_t)j);
+            pos2.push_back((int32_t)pa);
+            pend2.push_back((int32_t)pe);
+            open = true;
+          }
+          slice = (int32_t)grow1.size();
+          grp1.push_back((int32_t)grp_aidx.size() - 1);
+          pos1.push_back((int32_t)ra);
+          pend1.push_back((int32_t)re);
+          grow1.push_back(grow);
+          seg0.push_back((int32_t)useg.size());
+          nseg.push_back((int32_t)us.size());
+          useg.insert(useg.end(), us.begin(), us.end());
+          srec.push_back(SliceRec{(int32_t)a->id, seg0.back(), (int32_t)us.size(), 0, grow});
+        }
+        if (us.empty() && ds.empty()) continue;
+        GRowRec g{};
+        g.arr = (int32_t)a->id;
+        g.grow = grow;
+        g.slice = slice >= 0 && !ca.no_holders ? slice : -1;
+        g.dseg0 = (int32_t)dseg.size();
+        g.ndseg = (int32_t)ds.size();
+        // definitions sorted by column that tile [0, n2), no holder additions
+        bool full = !ds.empty() && g.slice < 0;
+        if (full) {
+          std::vector<Seg> v = ds;
+          std::sort(v.begin(), v.end(), [](const Seg &x, const Seg &y) { return x.c0 < y.c0; });
+          int64_t at = 0;
+          for (const Seg &q : v) {
+            if (q.c0 != at) full = false;
+            at = q.c1;
+          }
+          if (at != a->n[2]) full = false;
+          if (full) ds = v;
+        }
+        dseg.insert(dseg.end(), ds.begin(), ds.end());
+        g.full = full ? 1 : 0;
+        grec.push_back(g);
+        const int64_t rows = (pe - pa) * (re - ra);
+        if (rows > 1) {
+          rep.push_back(RepRec{(int32_t)a->id, (int32_t)pa, (int32_t)pe, (int32_t)ra, (int32_t)re, 0, grow});
+          for (int64_t k0 = 0; k0 < rows; k0 += 64) chunks.push_back(RepChunk{(int32_t)rep.size() - 1, (int32_t)k0});
+        }
       }
-      const int32_t s = (int32_t)grow1.size();
-      grp1.push_back((int32_t)grp_aidx.size() - 1);
-      pos1.push_back((int32_t)(row % a->n[1]));
-      grow1.push_back(row);
-      seg0.push_back((int32_t)useg.size());
-      int cnt = 0;
-      for (; i < us.size() && us[i].row == row; ++i) {
-        useg.push_back(Seg{us[i].e, us[i].c0, us[i].c1, 0});
-        stg += (int64_t)(us[i].c1 - us[i].c0) * a->esize;
-        ++cnt;
-      }
-      nseg.push_back(cnt);
-      srec.push_back(SliceRec{(int32_t)a->id, seg0.back(), cnt, 0, row});
-      slice_of_row.push_back({row, s});
     }
     C.slice1 = (int32_t)grow1.size();
     C.grp1 = (int32_t)grp_aidx.size();
-    stg += 16;
-    // GDEF rows: rows with use or def spans
-    const size_t grec0 = grec.size();
-    size_t a_i = 0, b_i = 0;
-    while (a_i < slice_of_row.size() || b_i < ds.size()) {
-      const int64_t ra = a_i < slice_of_row.size() ? slice_of_row[a_i].first : INT64_MAX;
-      const int64_t rb = b_i < ds.size() ? ds[b_i].row : INT64_MAX;
-      const int64_t row = std::min(ra, rb);
-      GRowRec g{};
-      g.arr = (int32_t)a->id;
-      g.grow = row;
-      g.slice = ra == row && !ca.no_holders ? slice_of_row[a_i].second : -1;
-      if (ra == row) ++a_i;
-      g.dseg0 = (int32_t)dseg.size();
-      int cnt = 0;
-      while (b_i < ds.size() && ds[b_i].row == row) {
-        dseg.push_back(Seg{ds[b_i].e, ds[b_i].c0, ds[b_i].c1, ds[b_i].flags});
-        ++b_i;
-        ++cnt;
-      }
-      g.ndseg = cnt;
-      // definitions sorted by column that tile [0, n2), no holder additions
-      bool full = cnt > 0 && g.slice < 0;
-      if (full) {
-        std::vector<Seg> v(dseg.end() - cnt, dseg.end());
-        std::sort(v.begin(), v.end(), [](const Seg &x, const Seg &y) { return x.c0 < y.c0; });
-        int64_t at = 0;
-        for (const Seg &g : v) {
-          if (g.c0 != at) full = false;
-          at = g.c1;
-        }
-        if (at != a->n[2]) full = false;
-        if (full) std::copy(v.begin(), v.end(), dseg.end() - cnt);
-      }
-      g.full = full ? 1 : 0;
-      grec.push_back(g);
-    }
-    // a call that defines every row of the array whole and does not use it
-    // leaves a GDEF that does not depend on the one before (plan cache)
-    int64_t nfull = 0;
-    for (size_t q = grec0; q < grec.size(); ++q) nfull += grec[q].full;
-    pl->ca_arr.push_back(a->id);
-    pl->ca_full.push_back(C.slice1 == C.slice0 && nfull == a->n[0] * a->n[1] ? 1 : 0);
   }
   P.has3d = has3d;
   P.nsl1 = (int32_t)grow1.size();
   P.ngrp = (int32_t)grp_aidx.size();
-  // rows the definitions tile first (their update is a plain copy, one lane
-  // per row); the order of the other rows is kept
+  // cells the definitions tile first (their update is a plain copy, one lane
+  // per cell); the order of the other cells is kept
   std::stable_partition(grec.begin(), grec.end(), [](const GRowRec &g) { return g.full != 0; });
   P.ngrow = (int32_t)grec.size();
   P.ngfull = 0;
   for (const GRowRec &g : grec) P.ngfull += g.full ? 1 : 0;
-  // GDEF update form of the other rows: when nearly all of them involve at
+  // GDEF update form of the other cells: when nearly all of them involve at
   // most two devices (row partitions, 3-D blocks split once along the row)
-  // their lists stay short and one lane per row updates them; rows shared by
-  // more devices (2-D block partitions) are updated one wave per row
+  // their lists stay short and one lane per cell updates them; cells shared
+  // by more devices (2-D block partitions) are updated one wave per cell
   {
     int64_t small = 0, rest = 0;
     for (const GRowRec &g : grec) {
@@ -1129,28 +1208,30 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
     }
     P.gdef_lane = rest > 0 && small * 10 >= rest * 9 ? 1 : 0;
   }
-  pl->nsl1 = P.nsl1;
-  pl->ngrp = P.ngrp;
-  pl->ngrow = P.ngrow;
-  pl->has3d = has3d;
-  pl->stg_bound = stg;
-  // one device allocation for all plan arrays
+  P.nrep = (int32_t)rep.size();
+  P.nrepchunk = (int32_t)chunks.size();
+  // one device allocation for all instance arrays
   std::vector<char> blob;
   size_t o_carr = push_blob(blob, carr);
-  size_t o_grp1 = push_blob(blob, grp1), o_pos1 = push_blob(blob, pos1), o_grow1 = push_blob(blob, grow1);
+  size_t o_grp1 = push_blob(blob, grp1), o_pos1 = push_blob(blob, pos1), o_pend1 = push_blob(blob, pend1);
+  size_t o_grow1 = push_blob(blob, grow1);
   size_t o_seg0 = push_blob(blob, seg0), o_nseg = push_blob(blob, nseg), o_useg = push_blob(blob, useg);
   size_t o_srec = push_blob(blob, srec);
   size_t o_ga = push_blob(blob, grp_aidx), o_gp = push_blob(blob, grp_plane);
-  size_t o_g2 = push_blob(blob, grp2), o_p2 = push_blob(blob, pos2);
+  size_t o_g2 = push_blob(blob, grp2), o_p2 = push_blob(blob, pos2), o_pe2 = push_blob(blob, pend2);
   size_t o_grec = push_blob(blob, grec), o_ds = push_blob(blob, dseg);
-  size_t o_wb = (blob.size() + 255) / 256 * 256;
-  blob.resize(o_wb + sizeof(WorkBox) * 5 * kMaxDev + 16);
-  pl->mem = dalloc(blob.size());
-  if (!pl->mem) return fail(HD_ENOMEM);
-  char *b = (char *)pl->mem;
+  size_t o_rep = push_blob(blob, rep), o_rch = push_blob(blob, chunks);
+  in->mem = dalloc(blob.size());
+  if (!in->mem) {
+    delete in;
+    fail(HD_ENOMEM);
+    return nullptr;
+  }
+  char *b = (char *)in->mem;
   P.carr = (const CallArr *)(b + o_carr);
   P.grp1 = (const int32_t *)(b + o_grp1);
   P.pos1 = (const int32_t *)(b + o_pos1);
+  P.pend1 = (const int32_t *)(b + o_pend1);
   P.grow1 = (const int64_t *)(b + o_grow1);
   P.seg0 = (const int32_t *)(b + o_seg0);
   P.nseg = (const int32_t *)(b + o_nseg);
@@ -1160,16 +1241,203 @@ static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
   P.grp_plane = (const int32_t *)(b + o_gp);
   P.grp2 = (const int32_t *)(b + o_g2);
   P.pos2 = (const int32_t *)(b + o_p2);
+  P.pend2 = (const int32_t *)(b + o_pe2);
   P.grec = (const GRowRec *)(b + o_grec);
   P.dseg = (const Seg *)(b + o_ds);
-  pl->wb = (WorkBox *)(b + o_wb);
+  P.rep = (const RepRec *)(b + o_rep);
+  P.repchunk = (const RepChunk *)(b + o_rch);
+  if (hipMemcpy(in->mem, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    free_inst(in);
+    fail(HD_EHIP);
+    return nullptr;
+  }
+  return in;
+}
+
+// Instance of a plan for the arrays' current bands (built on first use;
+// may_build false: only an existing one, else HD_ENOPLAN).  A plan keeps at
+// most kMaxInst instances; past that the others are dropped (after the
+// streams are idle, so no queued work reads them).
+constexpr size_t kMaxInst = 32;
+static int select_inst(Plan *pl, bool may_build = true) {
+  if (pl->rowwise && pl->cur) return HD_OK;
+  const size_t nc = pl->cas.size();
+  std::vector<std::vector<int64_t>> pb(nc), qb(nc);
+  std::vector<int64_t> key;
+  for (size_t j = 0; j < nc; ++j) {
+    const hd_array *a = pl->cas[j].a;
+    if (pl->rowwise) {
+      for (int64_t p = 0; p <= a->n[0]; ++p) pb[j].push_back(p);
+      for (int64_t r = 0; r <= a->n[1]; ++r) qb[j].push_back(r);
+    } else {
+      pb[j] = merge_breaks(a->pbrk, pl->pbp[j]);
+      qb[j] = merge_breaks(a->rbrk, pl->rbp[j]);
+    }
+    key.push_back(-1);
+    key.insert(key.end(), pb[j].begin(), pb[j].end());
+    key.push_back(-2);
+    key.insert(key.end(), qb[j].begin(), qb[j].end());
+  }
+  if (pl->cur && key == pl->cur_key) return HD_OK;
+  PlanInst *in = nullptr;
+  auto it = pl->insts.find(key);
+  if (it != pl->insts.end()) {
+    in = it->second;
+  } else {
+    if (!may_build) return fail(HD_ENOPLAN);
+    if (pl->insts.size() >= kMaxInst) {
+      HIPCK(hipStreamSynchronize(R.meta));
+      HIPCK(hipStreamSynchronize(R.meta2));
+      HIPCK(hipStreamSynchronize(R.data));
+      for (auto &kv : pl->insts) free_inst(kv.second);
+      pl->insts.clear();
+      pl->cur = nullptr;
+    }
+    in = build_inst(pl, pb, qb);
+    if (!in) return g_last_error;
+    pl->insts[key] = in;
+  }
+  pl->cur = in;
+  pl->cur_key = key;
+  pl->P = in->P;
+  pl->nsl1 = in->P.nsl1;
+  pl->ngrp = in->P.ngrp;
+  pl->ngrow = in->P.ngrow;
+  return HD_OK;
+}
+
+// After a call's GDEF update: the bands every call-array now holds.  A call
+// that defines the whole array without using it leaves lists that depend
+// only on its definitions (bands: the plan's own); otherwise the old bands
+// are refined by the plan's.
+static void advance_bands(const Plan *pl) {
+  for (size_t j = 0; j < pl->cas.size(); ++j) {
+    hd_array *a = pl->cas[j].a;
+    if (pl->ca_full[j]) {
+      a->pbrk = pl->pbp[j];
+      a->rbrk = pl->rbp[j];
+    } else {
+      a->pbrk = merge_breaks(a->pbrk, pl->pbp[j]);
+      a->rbrk = merge_breaks(a->rbrk, pl->rbp[j]);
+    }
+  }
+}
+
+// Builds a plan for one communication + GDEF update.  cas: the distinct
+// arrays of the call in argument order with per-endpoint use and def
+// shapes.  Checks the definitions for races, sizes the workspace for the
+// finest instance (one cell per row), and selects the instance for the
+// arrays' current bands.
+static int build_plan(std::vector<CallArray> &cas, Plan *pl) {
+  pl->ca_arr.clear();
+  pl->ca_full.clear();
+  pl->uid = R.next_uid++;
+  int64_t stg = 0;
+  int has3d = 0;
+  int64_t nsl_max = 0, ngrp_max = 0, ngrow_max = 0, nseg_all = 0;
+  pl->pbp.assign(cas.size(), {});
+  pl->rbp.assign(cas.size(), {});
+  for (size_t j = 0; j < cas.size(); ++j) {
+    CallArray &ca = cas[j];
+    hd_array *a = ca.a;
+    has3d |= a->n[0] > 1;
+    // use spans
+    std::vector<Span> us;
+    for (int e = 0; e < 64; ++e)
+      for (const Shape &s : ca.use[e]) {
+        shape_breaks(s, a->n, pl->pbp[j], pl->rbp[j]);
+        shape_rows(s, a->n, [&](int64_t p, int64_t r, int64_t c0, int64_t c1) {
+          us.push_back(Span{p * a->n[1] + r, e, (int32_t)c0, (int32_t)c1, 0});
+        });
+      }
+    merge_spans(us);
+    // def spans, race check across devices
+    std::vector<Span> ds;
+    for (int e = 0; e < 64; ++e)
+      for (const Shape &s : ca.def[e]) {
+        shape_breaks(s, a->n, pl->pbp[j], pl->rbp[j]);
+        shape_rows(s, a->n, [&](int64_t p, int64_t r, int64_t c0, int64_t c1) {
+          ds.push_back(Span{p * a->n[1] + r, e, (int32_t)c0, (int32_t)c1, ca.def_flags});
+        });
+      }
+    merge_spans(ds);
+    norm_breaks(pl->pbp[j], a->n[0]);
+    norm_breaks(pl->rbp[j], a->n[1]);
+    {
+      std::vector<Span> byc = ds;
+      std::sort(byc.begin(), byc.end(),
+                [](const Span &x, const Span &y) { return std::tie(x.row, x.c0) < std::tie(y.row, y.c0); });
+      for (size_t i = 1; i < byc.size(); ++i)
+        if (byc[i].row == byc[i - 1].row && byc[i].c0 < byc[i - 1].c1 && byc[i].e != byc[i - 1].e)
+          return fail(HD_ERACE);
+    }
+    // sizes of the finest instance: one slice per use row, one group per
+    // plane with use rows, one cell per row with use or def spans
+    std::vector<int64_t> urows, drows;
+    for (const Span &s : us) {
+      stg += (int64_t)(s.c1 - s.c0) * a->esize;
+      if (urows.empty() || urows.back() != s.row) urows.push_back(s.row);
+    }
+    stg += 16;
+    nseg_all += (int64_t)us.size();
+    nsl_max += (int64_t)urows.size();
+    {
+      int64_t last = -1;
+      for (int64_t r : urows)
+        if (r / a->n[1] != last) {
+          last = r / a->n[1];
+          ++ngrp_max;
+        }
+    }
+    for (const Span &s : ds)
+      if (drows.empty() || drows.back() != s.row) drows.push_back(s.row);
+    std::vector<int64_t> rows;
+    std::set_union(urows.begin(), urows.end(), drows.begin(), drows.end(), std::back_inserter(rows));
+    ngrow_max += (int64_t)rows.size();
+    // a call that defines every row of the array whole and does not use it
+    // leaves a GDEF that does not depend on the one before (plan cache)
+    int64_t nfull = 0;
+    if (urows.empty()) {
+      size_t i = 0;
+      while (i < ds.size()) {
+        const int64_t row = ds[i].row;
+        std::vector<Span> v;
+        for (; i < ds.size() && ds[i].row == row; ++i) v.push_back(ds[i]);
+        std::sort(v.begin(), v.end(), [](const Span &x, const Span &y) { return x.c0 < y.c0; });
+        int64_t at = 0;
+        bool full = true;
+        for (const Span &q : v) {
+          if (q.c0 != at) full = false;
+          at = q.c1;
+        }
+        if (full && at == a->n[2]) ++nfull;
+      }
+    }
+    pl->ca_arr.push_back(a->id);
+    pl->ca_full.push_back(urows.empty() && nfull == a->n[0] * a->n[1] ? 1 : 0);
+  }
+  pl->has3d = has3d;
+  pl->stg_bound = stg;
+  pl->nsl_max = nsl_max;
+  pl->cas = std::move(cas);
+  pl->uses.assign(pl->cas.size(), {});
+  pl->defs.assign(pl->cas.size(), {});
+  for (size_t j = 0; j < pl->cas.size(); ++j)
+    for (int e = 0; e < 64; ++e) {
+      for (const Shape &s : pl->cas[j].use[e]) pl->uses[j].push_back({e, &s});
+      for (const Shape &s : pl->cas[j].def[e]) pl->defs[j].push_back({e, &s});
+    }
+  // work boxes (filled by the caller)
+  pl->mem = dalloc(sizeof(WorkBox) * 5 * kMaxDev + 256);
+  if (!pl->mem) return fail(HD_ENOMEM);
+  pl->wb = (WorkBox *)pl->mem;
   for (int k = 0; k < 5; ++k) pl->wbj[k] = pl->wb + k * kMaxDev;
-  // work boxes are filled by the caller into the host blob first
   pl->nbox = 0;
-  HIPCK(hipMemcpy(pl->mem, blob.data(), blob.size(), hipMemcpyHostToDevice));
-  // workspace sizing: a slot of kRunSlot runs per use row plus a spill pool
-  const int64_t items = (int64_t)P.nsl1 * kRunSlot + std::max<int64_t>(int64_t(1) << 20, 4 * (int64_t)useg.size());
-  return ensure_ws(P.nsl1, P.ngrp, items, stg, P.ngrow);
+  // workspace sizing for the finest instance: a slot of kRunSlot runs per
+  // slice plus a spill pool
+  const int64_t items = nsl_max * kRunSlot + std::max<int64_t>(int64_t(1) << 20, 4 * nseg_all);
+  if (ensure_ws(nsl_max, ngrp_max, items, stg, ngrow_max) != HD_OK) return g_last_error;
+  return select_inst(pl);
 }
 
 static Level make_level(int which, const PlanDev &P) {
@@ -1178,6 +1446,7 @@ static Level make_level(int which, const PlanDev &P) {
     L.nsl = P.nsl1;
     L.grp = P.grp1;
     L.pos = P.pos1;
+    L.pend = P.pend1;
     L.ioff = R.W.roff;
     L.icnt = R.W.rcnt;
     L.items = R.W.runs;
@@ -1185,6 +1454,7 @@ static Level make_level(int which, const PlanDev &P) {
     L.nsl = P.ngrp;
     L.grp = P.grp2;
     L.pos = P.pos2;
+    L.pend = P.pend2;
     L.ioff = R.W.goff;
     L.icnt = R.W.gcnt;
     L.items = R.W.l1out;
@@ -1376,8 +1646,8 @@ static int plan_buffers(Plan *pl) {
   pl->ptab = (MsgRec *)dalloc(sizeof(MsgRec) * pl->pcap);
   pl->phdr = (MsgHdr *)dalloc(sizeof(MsgHdr));
   pl->pruns = (Item *)dalloc(sizeof(Item) * pl->pcap);
-  pl->proff = (int32_t *)dalloc(4 * ((int64_t)pl->nsl1 + 1));
-  pl->prcnt = (int32_t *)dalloc(4 * ((int64_t)pl->nsl1 + 1));
+  pl->proff = (int32_t *)dalloc(4 * (pl->nsl_max + 1));
+  pl->prcnt = (int32_t *)dalloc(4 * (pl->nsl_max + 1));
   if (!pl->ptab || !pl->phdr || !pl->pruns || !pl->proff || !pl->prcnt) return fail(HD_ENOMEM);
   HIPCK(hipMemset(pl->phdr, 0, sizeof(MsgHdr)));
   HIPCK(hipEventCreateWithFlags(&pl->ev_ready, R.sync_ev));
@@ -1398,6 +1668,17 @@ static void free_plan_buffers(Plan *pl) {
   pl->pruns = nullptr;
   pl->proff = pl->prcnt = nullptr;
   pl->ev_ready = pl->ev_used = nullptr;
+}
+
+static void free_inst(PlanInst *in);
+static void plan_free(Plan *pl) {
+  if (!pl) return;
+  free_plan_buffers(pl);
+  for (auto &kv : pl->insts) free_inst(kv.second);
+  pl->insts.clear();
+  dfree(pl->mem);
+  dfree(pl->part);
+  delete pl;
 }
 
 static int enqueue_user(Plan *pl, const float *coef);
@@ -1434,8 +1715,10 @@ static hipError_t derive_and_update(const PlanDev &P, const Work &W, const Level
 static int enqueue_cached(Plan *pl, const float *coef) {
   const hipStream_t meta = R.serial ? R.data : R.meta;
   if (plan_buffers(pl) != HD_OK) return g_last_error;
+  if (select_inst(pl) != HD_OK) return g_last_error;
   const std::vector<uint64_t> key = plan_key(pl);
-  const bool hit = pl->have && !key.empty() && key == pl->last_key;
+  // equal histories give equal GDEF and so equal bands: the same instance
+  const bool hit = pl->have && !key.empty() && key == pl->last_key && pl->cur == pl->last_inst;
   const PlanDev &P = pl->P;
   Work W = R.W;
   W.runs = pl->pruns;
@@ -1459,8 +1742,10 @@ static int enqueue_cached(Plan *pl, const float *coef) {
     }
   }
   pl->last_key = key;
+  pl->last_inst = pl->cur;
   pl->have = !key.empty();
   advance_hist(pl);
+  advance_bands(pl);
   HIPCK(hipStreamWaitEvent(R.data, pl->ev_ready, 0));
   {
     PhaseTimer tm(1, R.data);
@@ -1477,8 +1762,10 @@ static int enqueue_cached(Plan *pl, const float *coef) {
 
 static int enqueue(Plan *pl, const float *coef) {
   if (pl->apply && !pl->adjoint && R.plan_cache) return enqueue_cached(pl, coef);
+  if (select_inst(pl) != HD_OK) return g_last_error;
   // every plan's GDEF update is a function of the plan and the GDEF before it
   advance_hist(pl);
+  advance_bands(pl);
   R.last_ptab = nullptr;
   R.last_phdr = nullptr;
   const hipStream_t meta = R.serial ? R.data : R.meta;
@@ -1767,8 +2054,7 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
     if (prepare_call(*k, part, A, cas, wb) != HD_OK) return g_last_error;
     pl = new Plan();
     if (build_plan(cas, pl) != HD_OK) {
-      dfree(pl->mem);
-      delete pl;
+      plan_free(pl);
       return g_last_error;
     }
     pl->ukind = user_kind(k->builtin);
@@ -1867,8 +2153,7 @@ static Plan *io_plan(int op, int part, hd_array *a) {
     if (ensure_buf(a, d) != HD_OK) return nullptr;
   Plan *pl = new Plan();
   if (build_plan(cas, pl) != HD_OK) {
-    dfree(pl->mem);
-    delete pl;
+    plan_free(pl);
     return nullptr;
   }
   std::vector<WorkBox> wb;
@@ -1933,8 +2218,10 @@ extern "C" int hdarray_write(hd_array_t *ah, const void *uA, int part) {
   // GDEF: definitions by each device with the host as a second holder; no
   // communication (the plan has no use rows)
   pl->ukind = 0;
+  if (select_inst(pl) != HD_OK) return g_last_error;
   HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, R.meta));
   advance_hist(pl);
+  advance_bands(pl);
   return HD_OK;
 }
 
@@ -1991,6 +2278,8 @@ extern "C" int hdarray_reduce_noalloc(hd_array_t *ah, void *res, hd_reduce_t op,
   if (it == R.plans.end()) return fail(HD_ENOPLAN);
   Plan *pl = it->second;
   if (reduce_scratch_need(pl->nbox) > reduce_scratch_max()) return fail(HD_ECAPACITY);
+  // the instance for the arrays' current bands must exist too
+  if (select_inst(pl, false) != HD_OK) return g_last_error;
   // phase timers may create events; they stay off for this call
   const int prof = R.prof;
   R.prof = 0;
@@ -2148,6 +2437,7 @@ static void free_batches() {
   for (Batch *b : R.batches) {
     if (!b) continue;
     drop_graph(b);
+    for (auto &kv : b->pl.insts) free_inst(kv.second);
     dfree(b->pl.mem);
     dfree(b->d_wb);
     dfree(b->d_tbox);
@@ -2237,7 +2527,10 @@ extern "C" int hdarray_batch_end(void) {
   }
   R.rec.clear();
   Batch *b = new Batch();
+  // the batch's graph keeps one plan instance, valid for any bands
+  b->pl.rowwise = true;
   if (build_plan(all, &b->pl) != HD_OK) {
+    for (auto &kv : b->pl.insts) free_inst(kv.second);
     dfree(b->pl.mem);
     delete b;
     return g_last_error;
@@ -2323,6 +2616,7 @@ extern "C" int hdarray_batch_run(int id) {
   HIPCK(hipEventRecord(R.ev_data, R.data));
   HIPCK(hipStreamWaitEvent(R.meta, R.ev_data, 0));
   advance_hist(&b->pl);
+  advance_bands(&b->pl);
   R.last_ptab = nullptr;
   R.last_phdr = nullptr;
   R.last_batch = id;
@@ -2440,8 +2734,7 @@ extern "C" int hdarray_apply_adjoint(const char *kname, int part, hd_array_t *di
     }
     pl = new Plan();
     if (build_plan(cas, pl) != HD_OK) {
-      dfree(pl->mem);
-      delete pl;
+      plan_free(pl);
       return g_last_error;
     }
     int64_t t0 = 0;
@@ -2499,8 +2792,10 @@ extern "C" int hdarray_write_device(hd_array_t *ah, const void *dptr, int part) 
   if (ext_boxes(pl, part, a) != HD_OK) return g_last_error;
   // every device's region in one launch (rows of the regions, in device order)
   HIPCK(launch_ext_copy(pl->wbj[2], pl->xn, pl->xrows, R.d_arrs, a->id, const_cast<void *>(dptr), 0, R.data));
+  if (select_inst(pl) != HD_OK) return g_last_error;
   HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, R.meta));
   advance_hist(pl);
+  advance_bands(pl);
   return HD_OK;
 }
 
