@@ -62,6 +62,8 @@ def stencil_kernel_name(st, one, strip, op):
     if rows >= 32:
         return f"{strip}<{rows},{op}>"
     if waves == 4:
+        if st["stencil_vec"] == 2:
+            return f"k_stack_a<{rows},{op}>"
         return f"k_stack<{rows},{op},{'true' if st['stencil_vec'] else 'false'}>"
     tri = ",false" if op == 0 else ""
     return f"{one}<{rows}{tri},{'true' if order else 'false'}>"
@@ -81,6 +83,111 @@ def setup_jacobi_large(rt, hd, n):
     rt.write(B, B0, p)
     del A0, B0
     return A, B, p
+
+
+def jacobi64_window(b0, r0, r1, iters):
+    """FP64 Jacobi (Sec. 5.1 update on interior cells, boundary copied) of
+    the global array b0 after `iters` steps, exact on rows [r0, r1): the
+    window carries `iters` extra rows on each side (each step invalidates one
+    row at a window edge that is not the array's)."""
+    n0, n1 = b0.shape
+    w0, w1 = max(0, r0 - iters), min(n0, r1 + iters)
+    W = b0[w0:w1].astype(np.float64)
+    for _ in range(iters):
+        new = W.copy()
+        lo = max(1, w0 + 1) - w0          # first window row with both neighbours in the window
+        hi = min(n0 - 2, w1 - 2) - w0     # last such row (inclusive)
+        if hi >= lo:
+            new[lo:hi + 1, 1:n1 - 1] = (((W[lo:hi + 1, 0:n1 - 2] + W[lo:hi + 1, 2:n1]) + W[lo - 1:hi, 1:n1 - 1])
+                                        + W[lo + 1:hi + 2, 1:n1 - 1]) * 0.25
+        W = new
+    return W[r0 - w0:r1 - w0]
+
+
+def err_stats(x, ref):
+    d = np.asarray(x, np.float64) - ref
+    return {"max_abs": float(np.max(np.abs(d))), "rms": float(np.sqrt(np.mean(d * d)))}
+
+
+def fp64_error_jacobi(hd, stream, n, iters=(10, 100), band=(2016, 2080)):
+    """The GPU's FP32 Jacobi (jacobi_large layout: 16 devices, 4 x 4 blocks)
+    after 10 and 100 steps against FP64 on a band of rows across a block
+    boundary (the band's dependence cone computed in FP64 with numpy)."""
+    from workloads import jacobi_inputs
+    rt = hd.Runtime(stream=stream)
+    A, B, p = setup_jacobi_large(rt, hd, n)
+    _, B0 = jacobi_inputs(n, 2)
+    r0, r1 = band
+    res = {"rows": [r0, r1], "iterations": list(iters)}
+    done = 0
+    for k in iters:
+        while done < k:
+            if done % 2 == 0:
+                rt.apply("jacAB", p, [A, B])
+            else:
+                rt.apply("jacBA", p, [B, A])
+            done += 1
+        got = rt.read(A if k % 2 == 1 else B, p)[r0:r1]
+        res[str(k)] = err_stats(got, jacobi64_window(B0, r0, r1, k))
+    rt.close()
+    return res
+
+
+def s3d64_adjoint(u0, c, T, w):
+    """FP64 reverse mode of L = sum(w * u_T) for T 7-point steps (interior
+    cells updated, boundary copied): dL/du0 and dL/dc (numpy, whole array)."""
+    offs = [(0, 0, 0), (-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)]
+    n = u0.shape[0]
+    I = (slice(1, n - 1),) * 3
+
+    def sh(a, o):
+        return a[tuple(slice(1 + d, n - 1 + d) for d in o)]
+
+    us = [u0.astype(np.float64)]
+    for _ in range(T):
+        u = us[-1]
+        v = u.copy()
+        acc = c[0] * u[I]
+        for e in range(1, 7):
+            acc = acc + c[e] * sh(u, offs[e])
+        v[I] = acc
+        us.append(v)
+    g = w.astype(np.float64)
+    gc = np.zeros(7)
+    for t in reversed(range(T)):
+        u = us[t]
+        gi = g[I]
+        for e in range(7):
+            gc[e] += np.sum(gi * sh(u, offs[e]))
+        gn = g.copy()
+        gn[I] = 0.0
+        for e in range(7):
+            gn[tuple(slice(1 + d, n - 1 + d) for d in offs[e])] += c[e] * gi
+        g = gn
+    return g, gc
+
+
+def adjoint_error_32(hd, stream):
+    """Gradient of the 32^3 copy (T = 64, checkpoint every 8) through the
+    differentiable stencil against the FP64 adjoint above."""
+    import torch
+    from paper_1809_05657_amd import autograd as ag
+    from workloads import S3D_COEFFS, stencil3d_inputs
+    n, T = 32, 64
+    u0, w = stencil3d_inputs(n)
+    coef = [float(x) for x in S3D_COEFFS]
+    rt = hd.Runtime(stream=stream)
+    solver = ag.Stencil3D(rt, (n, n, n), ndev=8, T=T, ckpt=8)
+    dev = torch.device("cuda:0")
+    solver.forward(torch.from_numpy(u0).to(dev), coef)
+    g0, cb = solver.backward(torch.from_numpy(w).to(dev))
+    g0 = g0.cpu().numpy().astype(np.float64)
+    cb = cb.cpu().numpy()
+    rt.close()
+    g64, gc64 = s3d64_adjoint(u0, np.array(S3D_COEFFS, np.float64), T, w)
+    return {"size": f"{n}^3, T={T}, checkpoint every 8",
+            "grad_u0_rel_l2": float(np.linalg.norm(g0 - g64) / np.linalg.norm(g64)),
+            "grad_coef_max_rel": float(np.max(np.abs(cb - gc64) / np.abs(gc64)))}
 
 
 def cpu_baseline_jacobi(n, steps):
@@ -143,6 +250,14 @@ def bench_matmul(hd, rt, steps, warmup):
     dt = time.perf_counter() - t0
     kms, kc = rt.profile_read()["kernel"]
     rt.profile(0)
+    # FP64 error of C on 64 evenly spaced rows (bound: K 2^-24 (|A||B|)_ij)
+    rows = np.linspace(0, n - 1, 64).astype(np.int64)
+    cg = rt.read(Cc, p)[rows].astype(np.float64)
+    ref = a0[rows].astype(np.float64) @ b0.astype(np.float64)
+    bound = n * 2.0 ** -24 * (np.abs(a0[rows]).astype(np.float64) @ np.abs(b0).astype(np.float64))
+    fp64 = err_stats(cg, ref)
+    fp64["max_over_bound"] = float(np.max(np.abs(cg - ref) / bound))
+    fp64["rows_sampled"] = 64
     flops = 2.0 * n ** 3
     tf = flops / (kms / kc * 1e-3) / 1e12
     moved = st["last_bytes"]
@@ -157,7 +272,8 @@ def bench_matmul(hd, rt, steps, warmup):
                          "traffic": None, "kernel": "k_mm_mfma", "avg_launch_us": kms / kc * 1e3},
             "pack_unpack": {"bytes": moved, "fused_pass_us": pk * 1e3,
                             "GBps": 4 * moved / (pk * 1e-3) / 1e9 if pk else None,
-                            "frac_hbm": (4 * moved / (pk * 1e-3) / 1e9) / HBM_PEAK_GBS if pk else None}}
+                            "frac_hbm": (4 * moved / (pk * 1e-3) / 1e9) / HBM_PEAK_GBS if pk else None},
+            "fp64_error": fp64}
 
 
 def bench_2mm(hd, rt, steps, warmup):
@@ -446,6 +562,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the jacobi_large line (no FP64-error, matmul, batched and adjoint legs)")
     ap.add_argument("--workload", default="jacobi_large",
                     choices=["jacobi_large", "matmul", "2mm", "conv2d", "batched", "stencil3d", "copy_calib"])
     args = ap.parse_args()
@@ -567,11 +685,36 @@ def main():
                        "phases_us": {k: (v[0] / max(v[1], 1)) * 1e3 for k, v in phc.items()}},
     }
     rt.close()
+    if not args.headline_only:
+        sp = stream.cuda_stream
+        # the metric's other legs: FP64 errors, matmul, batched vs plain, adjoint
+        out["fp64_error"] = {"jacobi_8192": fp64_error_jacobi(hd, sp, n)}
+        rt = hd.Runtime(stream=sp)
+        m = bench_matmul(hd, rt, 10, 2)
+        rt.close()
+        out["fp64_error"]["matmul_4096"] = m.pop("fp64_error")
+        out["matmul"] = {"steps_per_s": m["value"], "ms_per_step": m["ms_per_step"], "config": m["config"],
+                         "roofline": m["roofline"], "pack_unpack_first_step": m["pack_unpack"]}
+        rt = hd.Runtime(stream=sp)
+        b = bench_batched(hd, rt, 20, 5)
+        rt.close()
+        out["batched"] = {"steps_per_s": b["value"], "ms_per_step": b["ms_per_step"],
+                          "plain_steps_per_s": b["config"]["plain_steps_per_s"],
+                          "batched_over_plain": b["config"]["batched_over_plain"], "roofline": b["roofline"],
+                          "config": {k: v for k, v in b["config"].items() if k not in ("plain_steps_per_s",
+                                                                                  "batched_over_plain")}}
+        rt = hd.Runtime(stream=sp)
+        a = bench_stencil3d(hd, rt, 1, 1)
+        rt.close()
+        out["adjoint"] = {"passes_per_s": a["value"], "ms_per_pass": a["ms_per_step"], "config": a["config"],
+                          "phases_us": a["phases_us"], "roofline": a["roofline"],
+                          "forward_kernel": a["forward_kernel"], "fp64_check": adjoint_error_32(hd, sp)}
     if not args.no_cpu_baseline:
+        import oracle as O
         sps, secs = cpu_baseline_jacobi(n, args.cpu_steps)
-        out["cpu_baseline"] = {"value": sps, "unit": "steps/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": sps, "unit": "steps/s", "cores": O.threads(), "kind": "oracle",
                                "sample": f"{args.cpu_steps} ApplyKernel step(s) of jacobi_large ({n}x{n}, 16 "
-                                         f"devices) after setup, single-threaded C oracle, {secs:.1f} s"}
+                                         f"devices) after setup, C oracle with OpenMP, {secs:.1f} s"}
     print(json.dumps(out), flush=True)
 
 

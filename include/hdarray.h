@@ -314,7 +314,7 @@ typedef struct {
   int64_t cache_misses;    /* plan-cache calls that derived one */
   int64_t stencil_order;   /* tile order of the last stencil launch (1 along rows, 0 down columns) */
   int64_t allocs;          /* device and pinned host allocations the library has made */
-  int64_t stencil_vec;     /* 1: the last stencil launch read every row as float4 */
+  int64_t stencil_vec;     /* 1: the last stencil launch read every row as float4; 2: also with its boxes passed by value */
 } hd_stats_t;
 int hdarray_get_stats(hd_stats_t *st);
 

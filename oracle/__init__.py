@@ -75,6 +75,7 @@ def _load():
         "orc_bad_reads": (C.c_int64, [P]),
         "orc_inject_drop": (None, [P, C.c_int64]),
         "orc_s3d_forward64": (None, [I64P, P, P, C.c_int, P]),
+        "orc_threads": (C.c_int, []),
         "orc_s3d_adjoint64": (None, [I64P, P, P, C.c_int, P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -286,3 +287,8 @@ def s3d_adjoint64(u0, coeffs, T, w):
 
 def messages_as_dicts(msgs):
     return [dict(zip(MSG_FIELDS, map(int, m))) for m in msgs]
+
+
+def threads():
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().orc_threads())

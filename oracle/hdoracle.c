@@ -19,6 +19,7 @@
  *   Sec. 5.1            Jacobi update A = (B[i][j-1]+B[i][j+1]+B[i-1][j]+B[i+1][j])/4
  *   Sec. 4.2            merging adjacent sections (canonical rectangles here)
  */
+#include <omp.h>
 #include "hdoracle.h"
 
 #include <math.h>
@@ -1572,3 +1573,6 @@ void orc_s3d_adjoint64(const int64_t *n, const double *u0, const double *cf, int
   free(g);
   free(h);
 }
+
+/* Threads the OpenMP loops of the oracle use (timing reports only). */
+int orc_threads(void) { return omp_get_max_threads(); }

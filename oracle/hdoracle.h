@@ -86,6 +86,7 @@ int64_t orc_bad_reads(orc_ctx *c);
 void orc_inject_drop(orc_ctx *c, int64_t idx);
 
 /* global FP64 reference computations (no partitioning) */
+int orc_threads(void);
 void orc_s3d_forward64(const int64_t *n, const double *u0, const double *cf, int T, double *uT);
 void orc_s3d_adjoint64(const int64_t *n, const double *u0, const double *cf, int T, const double *w,
                        double *gu0, double *gcf);

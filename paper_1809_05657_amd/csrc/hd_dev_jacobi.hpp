@@ -362,7 +362,8 @@ __device__ inline void dev_strip(const WorkBox &B, int64_t lt, const ArrDev *__r
 // of 4); otherwise each wave takes the coalesced per-wave path (no LDS).
 // OP: 0 Jacobi, 1 lower-triangular Jacobi, 2 3 x 3 convolution.
 template <int W, int TH, int OP, bool VEC>
-__device__ inline void dev_stack_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef9 &Wt) {
+__device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const float *__restrict__ in,
+                                        float *__restrict__ out, int N1, int N2, const Coef9 &Wt) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int tx, ty;
   tile_pos<W * TH, true>(B, lt, tx, ty);
@@ -372,10 +373,6 @@ __device__ inline void dev_stack_tile(const WorkBox &B, int64_t lt, const ArrDev
   // (the whole workgroup leaves together, before the barrier)
   if (OP == 1 && B.lo[2] + tx * 256 > t1 - 1) return;
   const int c = B.lo[2] + tx * 256 + 4 * lane;
-  const ArrDev &ai = A[B.ain];
-  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
-  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
-  const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
   const int r0 = t0 + wv * TH;
   if (!VEC) {
     if (r0 >= t1) return;
@@ -402,6 +399,98 @@ __device__ inline void dev_stack_tile(const WorkBox &B, int64_t lt, const ArrDev
   __shared__ float sl[OP == 2 ? 2 : 1][W][64], sr[OP == 2 ? 2 : 1][W][64];
   f4 v[TH + 2];
   float L[TH + 2], R[TH + 2];
+  // A full tile away from the array boundary (the common case, uniform over
+  // the workgroup): every row and halo column exists, every cell is interior
+  // and written, so no per-lane guard is needed.
+  const int tc = B.lo[2] + tx * 256;
+  if (OP != 1 && t0 >= 1 && t0 + W * TH <= min(B.hi[1], N1 - 1) && tc >= 1 && tc + 256 <= min(B.hi[2], N2 - 1)) {
+    const float *p = in + (int64_t)(r0 - 1) * N2 + c;
+#pragma unroll
+    for (int k = 1; k <= TH; ++k) v[k] = *reinterpret_cast<const f4 *>(p + (int64_t)k * N2);
+    if (wv == 0) v[0] = *reinterpret_cast<const f4 *>(p);
+    if (wv == W - 1) v[TH + 1] = *reinterpret_cast<const f4 *>(p + (int64_t)(TH + 1) * N2);
+    const int k0 = OP == 2 ? 0 : 1, k1 = OP == 2 ? TH + 1 : TH;
+    float le[TH + 2], ri[TH + 2];
+#pragma unroll
+    for (int k = 0; k < TH + 2; ++k) le[k] = ri[k] = 0.f;
+    if (lane == 0) {
+#pragma unroll
+      for (int k = k0; k <= k1; ++k)
+        if ((k > 0 && k <= TH) || (k == 0 && wv == 0) || (k == TH + 1 && wv == W - 1)) le[k] = p[(int64_t)k * N2 - 1];
+    }
+    if (lane == 63) {
+#pragma unroll
+      for (int k = k0; k <= k1; ++k)
+        if ((k > 0 && k <= TH) || (k == 0 && wv == 0) || (k == TH + 1 && wv == W - 1)) ri[k] = p[(int64_t)k * N2 + 4];
+    }
+#pragma unroll
+    for (int k = k0; k <= k1; ++k) {
+      if ((k == 0 && wv != 0) || (k == TH + 1 && wv != W - 1)) continue;
+      const float lw = __shfl_up(v[k].w, 1), rx = __shfl_down(v[k].x, 1);
+      L[k] = lane == 0 ? le[k] : lw;
+      R[k] = lane == 63 ? ri[k] : rx;
+    }
+    sv[0][wv][lane] = v[1];
+    sv[1][wv][lane] = v[TH];
+    if (OP == 2) {
+      sl[0][wv][lane] = L[1];
+      sr[0][wv][lane] = R[1];
+      sl[OP == 2 ? 1 : 0][wv][lane] = L[TH];
+      sr[OP == 2 ? 1 : 0][wv][lane] = R[TH];
+    }
+    __syncthreads();
+    if (wv > 0) {
+      v[0] = sv[1][wv - 1][lane];
+      if (OP == 2) {
+        L[0] = sl[OP == 2 ? 1 : 0][wv - 1][lane];
+        R[0] = sr[OP == 2 ? 1 : 0][wv - 1][lane];
+      }
+    }
+    if (wv < W - 1) {
+      v[TH + 1] = sv[0][wv + 1][lane];
+      if (OP == 2) {
+        L[TH + 1] = sl[0][wv + 1][lane];
+        R[TH + 1] = sr[0][wv + 1][lane];
+      }
+    }
+    float *q = out + (int64_t)r0 * N2 + c;
+#pragma unroll
+    for (int k = 1; k <= TH; ++k) {
+      const f4 up = v[k - 1], cu = v[k], dn = v[k + 1];
+      const float cv[6] = {L[k], cu.x, cu.y, cu.z, cu.w, R[k]};
+      float o[4];
+      if (OP == 2) {
+        const float uv[6] = {L[k - 1], up.x, up.y, up.z, up.w, R[k - 1]};
+        const float dv[6] = {L[k + 1], dn.x, dn.y, dn.z, dn.w, R[k + 1]};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float acc = Wt.w[0] * uv[e];
+          acc = __builtin_fmaf(Wt.w[1], uv[e + 1], acc);
+          acc = __builtin_fmaf(Wt.w[2], uv[e + 2], acc);
+          acc = __builtin_fmaf(Wt.w[3], cv[e], acc);
+          acc = __builtin_fmaf(Wt.w[4], cv[e + 1], acc);
+          acc = __builtin_fmaf(Wt.w[5], cv[e + 2], acc);
+          acc = __builtin_fmaf(Wt.w[6], dv[e], acc);
+          acc = __builtin_fmaf(Wt.w[7], dv[e + 1], acc);
+          acc = __builtin_fmaf(Wt.w[8], dv[e + 2], acc);
+          o[e] = acc;
+        }
+      } else {
+        const float uv[4] = {up.x, up.y, up.z, up.w};
+        const float dv[4] = {dn.x, dn.y, dn.z, dn.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          float t = cv[e] + cv[e + 2];
+          t = t + uv[e];
+          t = t + dv[e];
+          o[e] = t * 0.25f;
+        }
+      }
+      const f4 ov = {o[0], o[1], o[2], o[3]};
+      __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q + (int64_t)(k - 1) * N2));
+    }
+    return;
+  }
   // rows up to t1 are read (t1 itself is the halo below the tile's last row);
   // rows outside the array or past t1 read as zero and are never used
 #pragma unroll
@@ -439,6 +528,14 @@ __device__ inline void dev_stack_tile(const WorkBox &B, int64_t lt, const ArrDev
                   out, true);
   }
 }
+
+template <int W, int TH, int OP, bool VEC>
+__device__ inline void dev_stack_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef9 &Wt) {
+  const ArrDev &ai = A[B.ain];
+  dev_stack_tile_p<W, TH, OP, VEC>(B, lt, reinterpret_cast<const float *>(ai.buf[B.dev]),
+                                   reinterpret_cast<float *>(A[B.aout].buf[B.dev]), (int)ai.n[1], (int)ai.n[2], Wt);
+}
+
 
 __host__ __device__ inline int64_t jacobi_tiles(const WorkBox &B, int th) {
   const int64_t h = B.hi[1] - B.lo[1], w = B.hi[2] - B.lo[2];

@@ -83,7 +83,7 @@ struct GRowRec {
   int32_t ndseg;
   int64_t grow;   // global row (plane * n1 + row)
   int32_t full;   // 1: the definitions tile the row and no holders are added
-  int32_t pad;
+  int32_t rep;    // the cell's RepRec when it has more than one row, else -1
 };
 
 struct MsgRec {
@@ -117,9 +117,11 @@ struct RepRec {
   int64_t grow;
 };
 
-// 64 rows of a cell (k0: first row index within the cell, row-major).
-struct RepChunk {
-  int32_t cell;
+// One task of the GDEF update: rows [k0, k0 + kCellChunk) (clipped) of the
+// cell of record t, rows numbered row-major over the cell's planes x rows.
+constexpr int kCellChunk = 32;
+struct GTask {
+  int32_t t;
   int32_t k0;
 };
 
@@ -165,6 +167,18 @@ struct WorkBox {
   int32_t pad;
 };
 
+// Up to kArgBoxes work boxes of one 2-D stencil launch passed by value
+// (kernel arguments sit in the scalar cache): a workgroup finds its box and
+// buffers without a dependent global load before its first data load.
+constexpr int kArgBoxes = 16;
+struct StackArgs {
+  int32_t nbox, N1, N2, pad;
+  int32_t lo1[kArgBoxes], lo2[kArgBoxes], hi1[kArgBoxes], hi2[kArgBoxes];
+  int64_t tile0[kArgBoxes];
+  const float *in[kArgBoxes];
+  float *out[kArgBoxes];
+};
+
 // Per-call constant data uploaded once per plan.
 struct PlanDev {
   int32_t ncarr;
@@ -195,9 +209,11 @@ struct PlanDev {
   const Seg *dseg;
   // cells of more than one row: their other rows take the representative's
   // list after the update
-  int32_t nrep, nrepchunk;
+  int32_t nrep;
   const RepRec *rep;
-  const RepChunk *repchunk;
+  // the update as tasks of at most kCellChunk rows of one cell
+  int32_t ntask;
+  const GTask *task;
 };
 
 struct Work {

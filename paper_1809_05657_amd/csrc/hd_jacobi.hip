@@ -21,6 +21,35 @@ __global__ __launch_bounds__(256) void k_stack(const WorkBox *__restrict__ wb, i
   dev_stack_tile<4, TH, OP, VEC>(B, t - B.tile0, A, w);
 }
 
+// The same tiles with the boxes and buffers in the kernel arguments (float4
+// rows, at most kArgBoxes boxes).
+template <int TH, int OP>
+__global__ __launch_bounds__(256) void k_stack_a(StackArgs a, int64_t ntiles, Coef9 w) {
+  const int64_t t = xcd_remap(blockIdx.x, ntiles);
+  int b = 0;
+#pragma unroll
+  for (int k = 1; k < kArgBoxes; ++k)
+    if (k < a.nbox && a.tile0[k] <= t) b = k;
+  WorkBox B;
+  B.lo[1] = a.lo1[b];
+  B.lo[2] = a.lo2[b];
+  B.hi[1] = a.hi1[b];
+  B.hi[2] = a.hi2[b];
+  dev_stack_tile_p<4, TH, OP, true>(B, t - a.tile0[b], a.in[b], a.out[b], a.N1, a.N2, w);
+}
+
+hipError_t launch_stack_args(int op, int th, const StackArgs &a, int64_t ntiles, const float *coef, hipStream_t s) {
+  typedef void (*ak_t)(StackArgs, int64_t, Coef9);
+  Coef9 w;
+  for (int e = 0; e < 9; ++e) w.w[e] = coef ? coef[e] : 0.f;
+  ak_t k;
+  if (th == 4) k = op == 0 ? k_stack_a<4, 0> : op == 1 ? k_stack_a<4, 1> : k_stack_a<4, 2>;
+  else if (th == 8) k = op == 0 ? k_stack_a<8, 0> : op == 1 ? k_stack_a<8, 1> : k_stack_a<8, 2>;
+  else k = op == 0 ? k_stack_a<16, 0> : op == 1 ? k_stack_a<16, 1> : k_stack_a<16, 2>;
+  if (ntiles > 0) hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(256), 0, s, a, ntiles, w);
+  return hipGetLastError();
+}
+
 template <int TH, bool VEC>
 static void *stack_kernel(int op) {
   return op == 0 ? (void *)k_stack<TH, 0, VEC> : op == 1 ? (void *)k_stack<TH, 1, VEC> : (void *)k_stack<TH, 2, VEC>;

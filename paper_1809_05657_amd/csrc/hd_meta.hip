@@ -14,6 +14,8 @@ namespace hd {
 
 constexpr int kGdefMaxB = 1024;
 
+
+
 // One wave per use row (a measurement alternative; see launch_runs).
 template <int CAP>
 __global__ __launch_bounds__(64) void k_runs_wave(PlanDev P, const ArrDev *__restrict__ A, Work W) {
@@ -143,26 +145,72 @@ __global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict
   for (int q = blockIdx.x; q < n; q += gridDim.x) dev_gdef_row(P, A, W, W.ovf_list2[q], S, kGdefMaxB);
 }
 
-// The other rows of every GDEF cell take the list the update wrote to the
-// cell's representative (they held the same list before the call and get
-// the same update); one wave per 64 rows of a cell, one row per lane.
-__global__ __launch_bounds__(64) void k_gdef_rep(PlanDev P, ArrDev *__restrict__ A) {
-  const int lane = threadIdx.x & 63;
-  for (int q = blockIdx.x; q < P.nrepchunk; q += gridDim.x) {
-    const RepChunk ch = P.repchunk[q];
-    const RepRec c = P.rep[ch.cell];
-    const ArrDev &a = A[c.arr];
-    const int64_t cap = a.cap;
-    const int nr = c.r1 - c.r0;
-    const int64_t rows = (int64_t)(c.p1 - c.p0) * nr;
-    const int64_t k = (int64_t)ch.k0 + lane;
-    if (k < 1 || k >= rows) continue;  // k = 0 is the representative itself
-    const Ivl *src = a.ivl + c.grow * cap;
-    const int n = a.cnt[c.grow];
-    const int64_t g = (int64_t)(c.p0 + k / nr) * a.n[1] + c.r0 + k % nr;
-    Ivl *dst = a.ivl + g * cap;
-    for (int i = 0; i < n; ++i) dst[i] = src[i];
-    a.cnt[g] = n;
+
+// ------------------------------------------------------ small instances
+// Bands leave most calls with few slices and cells.  One workgroup then
+// derives the whole communication set (runs, band flags, band scan, heads,
+// compaction: one launch instead of five, each phase a few dependent loads
+// long), and each GDEF cell is updated by one wave.
+constexpr int kDerive1Max = 64;  // slices (and level-2 groups) of the small form
+
+// Eight waves: wave 0 finds the runs (one lane per slice) and the band
+// flags, the heads are shared out band by band over the waves (item lists
+// of up to kHead1 items staged in LDS, longer ones searched in memory).
+constexpr int kDerive1Waves = 8, kHead1 = 32;
+template <int CAP>
+__global__ __launch_bounds__(64 * kDerive1Waves) void k_derive1(PlanDev P, const ArrDev *__restrict__ A, Work W,
+                                                              Level L1, Level L2, MsgRec *out, MsgHdr *hdr,
+                                                              int64_t cap, int has3d) {
+  // wave 0's runs staging, then the wave path's scratch; then the heads'
+  // scratch (2 * kHead1 items per wave); then the compaction's scratch
+  __shared__ __align__(16) char s_buf[16384];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (wv == 0) {
+    const int s = lane;
+    const bool done = s >= P.nsl1 || dev_runs_lane<kRunSlot>(P, A, W, s, reinterpret_cast<int32_t *>(s_buf));
+    uint64_t left = __ballot(!done);
+    wave_lds_sync();
+    Ivl *iv = reinterpret_cast<Ivl *>(s_buf);
+    Run *rr = reinterpret_cast<Run *>(s_buf + sizeof(Ivl) * CAP);
+    while (left) {
+      const int l = __ffsll((unsigned long long)left) - 1;
+      left &= left - 1;
+      const int nr = dev_runs_find(P, A, W, l, iv, rr);
+      dev_runs_store(P, W, l, rr, nr);
+      wave_lds_sync();
+    }
+  }
+  __syncthreads();
+  for (int lv = 1; lv <= (has3d ? 2 : 1); ++lv) {
+    const Level &L = lv == 1 ? L1 : L2;
+    if (L.nsl > 0) {
+      if (wv == 0) dev_bandflags(L, lane);
+      __syncthreads();
+      dev_bandscan(L);
+      const int nb = *L.nb;
+      Item *sp = reinterpret_cast<Item *>(s_buf + wv * 2 * kHead1 * sizeof(Item));
+      for (int b = wv; b < nb; b += kDerive1Waves) dev_heads(L, b, nb, sp, sp + kHead1, kHead1);
+      __syncthreads();
+    }
+    dev_compact(P, L, W, out, hdr, cap, lv == 1 ? (has3d ? 1 : 0) : 2, reinterpret_cast<int64_t *>(s_buf));
+  }
+}
+
+// The GDEF update as tasks of at most kCellChunk rows of one cell, one wave
+// each: the task reads its first row (every row of a cell holds the same
+// list before the update), applies the cell's edits and writes the new list
+// to all its rows, so no task waits for another; rows with more than 64
+// boundaries take the LDS form in the same wave.
+__global__ __launch_bounds__(64) void k_gdef_tasks(PlanDev P, ArrDev *__restrict__ A, Work W) {
+  __shared__ Ivl s_iv[kMaxCap];
+  __shared__ int32_t s_b[kGdefMaxB], s_u[kGdefMaxB], s_own[kGdefMaxB];
+  __shared__ uint64_t s_hold[kGdefMaxB];
+  for (int q = blockIdx.x; q < P.ntask; q += gridDim.x) {
+    const GTask tk = P.task[q];
+    if (!dev_gdef_row_fast(P, A, W, tk.t, tk.k0)) {
+      GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
+      dev_gdef_row(P, A, W, tk.t, S, kGdefMaxB, tk.k0);
+    }
   }
 }
 
@@ -258,6 +306,19 @@ hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipSt
   return hipGetLastError();
 }
 
+// The one-wave derivation, when the instance is small enough; returns
+// hipErrorNotSupported otherwise (the caller then takes the per-phase form).
+hipError_t launch_derive1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L1, const Level &L2,
+                          MsgRec *out, MsgHdr *hdr, int64_t cap, int row_cap, hipStream_t s) {
+  if (P.nsl1 > kDerive1Max || P.ngrp > kDerive1Max) return hipErrorNotSupported;
+  const int h3 = P.has3d ? 1 : 0;
+  if (row_cap <= 64)
+    hipLaunchKernelGGL(k_derive1<64>, dim3(1), dim3(64 * kDerive1Waves), 0, s, P, A, W, L1, L2, out, hdr, cap, h3);
+  else
+    hipLaunchKernelGGL(k_derive1<kMaxCap>, dim3(1), dim3(64 * kDerive1Waves), 0, s, P, A, W, L1, L2, out, hdr, cap, h3);
+  return hipGetLastError();
+}
+
 // Every GDEF update of the runtime goes through here, in stream order (the
 // meta stream waits for the second internal stream before it launches
 // another), so the counter parity alternates launch by launch.
@@ -270,6 +331,14 @@ hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s
   int32_t *cur2 = W.ovf_cnt + 2 + p, *other2 = W.ovf_cnt + 2 + (1 - p);
   const int nfw = cdiv(P.ngfull, 64);
   const int rest = P.ngrow - P.ngfull;
+  if (P.nrep > 0 || P.ngrow <= 4096) {
+    // cells of several rows, or few cells: one launch of row-chunk tasks
+    if (P.ntask > 0) {
+      const int grid = P.ntask < (1 << 20) ? P.ntask : (1 << 20);
+      hipLaunchKernelGGL(k_gdef_tasks, dim3(grid), dim3(64), 0, s, P, A, W);
+    }
+    return hipGetLastError();
+  }
   if (P.gdef_lane) {
     hipLaunchKernelGGL(k_gdef, dim3(nfw + cdiv(rest, 64)), dim3(64), 0, s, P, A, W, cur, nfw);
     hipLaunchKernelGGL(k_gdef_list, dim3(kGdefListGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur, cur2);
@@ -278,10 +347,6 @@ hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s
     hipLaunchKernelGGL(k_gdef_wave, dim3(grid), dim3(64), 0, s, P, A, W, cur2, nfw);
   }
   hipLaunchKernelGGL(k_gdef_large, dim3(kGdefLargeGrid), dim3(64), 0, s, P, A, W, (const int32_t *)cur2, other, other2);
-  if (P.nrepchunk > 0) {
-    const int grid = P.nrepchunk < 4096 ? P.nrepchunk : 4096;
-    hipLaunchKernelGGL(k_gdef_rep, dim3(grid), dim3(64), 0, s, P, A);
-  }
   return hipGetLastError();
 }
 

@@ -27,6 +27,8 @@ namespace hd {
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr, int64_t cap,
                           int mode, hipStream_t s);
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
+hipError_t launch_derive1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L1, const Level &L2,
+                          MsgRec *out, MsgHdr *hdr, int64_t cap, int row_cap, hipStream_t s);
 extern int g_runs_wave_max;
 hipError_t launch_runs(const PlanDev &P, const ArrDev *A, const Work &W, int row_cap, hipStream_t s);
 hipError_t launch_level1_tail(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
@@ -40,6 +42,7 @@ hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32
 int64_t tiles_for(int kind, const WorkBox &B, int esize, int th);
 hipError_t launch_ext_copy(const WorkBox *wb, int nbox, int64_t rows, const ArrDev *A, int arr, void *ext,
                            int to_ext, hipStream_t s);
+hipError_t launch_stack_args(int op, int th, const StackArgs &a, int64_t ntiles, const float *coef, hipStream_t s);
 hipError_t launch_user(int kind, int th, int waves, int order, bool vec, const WorkBox *wb, int nbox, const ArrDev *A,
                        int64_t ntiles, const float *coef, hipStream_t s);
 hipError_t launch_reduce(int type, int op, const WorkBox *wb, int nbox, const ArrDev *A, int arr, double *pf,
@@ -144,6 +147,7 @@ struct Plan {
   // stencil kinds: the work boxes for 4, 8 and 16 rows per tile, and the
   // key of the tile-shape tuning shared by plans with the same boxes
   WorkBox *wbj[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<WorkBox> hwbj[5];  // host copies (for launches that pass the boxes by value)
   bool vec = false;  // every work box's rows can be read as float4
   int64_t ntj[5] = {0, 0, 0, 0, 0};
   std::vector<int64_t> tkey;
@@ -200,6 +204,7 @@ struct Runtime {
   void *uctx = nullptr;
   int row_cap = 64;
   bool serial = false;  // metadata work on the data stream (measurement aid)
+  bool fused = true;    // small plan instances: the derivation in one wave
   int jacobi_order = 1;  // with a fixed shape: 1 tiles along rows, 0 down columns
   int jacobi_rows = 0;   // HD_JACOBI_ROWS / HD_JACOBI_WAVES fix the stencil tile shape;
   int jacobi_waves = 0;  // otherwise it is tuned per work-box geometry
@@ -353,6 +358,7 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
     }
   }
   if (const char *e = getenv("HD_SERIAL")) R.serial = atoi(e) != 0;
+  if (const char *e = getenv("HD_FUSED_META")) R.fused = atoi(e) != 0;
   if (const char *e = getenv("HD_JACOBI_ROWS")) {
     const int v = atoi(e);
     if (v == 4 || v == 8 || v == 16 || v == 32 || v == 64) R.jacobi_rows = v;
@@ -1092,7 +1098,7 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
   std::vector<SliceRec> srec;
   std::vector<GRowRec> grec;
   std::vector<RepRec> rep;
-  std::vector<RepChunk> chunks;
+  std::vector<GTask> tasks;
   PlanInst *in = new PlanInst();
   PlanDev &P = in->P;
   memset(&P, 0, sizeof(P));
@@ -1161,12 +1167,12 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
         }
         dseg.insert(dseg.end(), ds.begin(), ds.end());
         g.full = full ? 1 : 0;
-        grec.push_back(g);
-        const int64_t rows = (pe - pa) * (re - ra);
-        if (rows > 1) {
+        g.rep = -1;
+        if ((pe - pa) * (re - ra) > 1) {
+          g.rep = (int32_t)rep.size();
           rep.push_back(RepRec{(int32_t)a->id, (int32_t)pa, (int32_t)pe, (int32_t)ra, (int32_t)re, 0, grow});
-          for (int64_t k0 = 0; k0 < rows; k0 += 64) chunks.push_back(RepChunk{(int32_t)rep.size() - 1, (int32_t)k0});
         }
+        grec.push_back(g);
       }
     }
     C.slice1 = (int32_t)grow1.size();
@@ -1209,7 +1215,16 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
     P.gdef_lane = rest > 0 && small * 10 >= rest * 9 ? 1 : 0;
   }
   P.nrep = (int32_t)rep.size();
-  P.nrepchunk = (int32_t)chunks.size();
+  // update tasks: kCellChunk rows of one cell each (after the reordering)
+  for (size_t t = 0; t < grec.size(); ++t) {
+    int64_t rows = 1;
+    if (grec[t].rep >= 0) {
+      const RepRec &r = rep[grec[t].rep];
+      rows = (int64_t)(r.p1 - r.p0) * (r.r1 - r.r0);
+    }
+    for (int64_t k0 = 0; k0 < rows; k0 += kCellChunk) tasks.push_back(GTask{(int32_t)t, (int32_t)k0});
+  }
+  P.ntask = (int32_t)tasks.size();
   // one device allocation for all instance arrays
   std::vector<char> blob;
   size_t o_carr = push_blob(blob, carr);
@@ -1220,7 +1235,7 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
   size_t o_ga = push_blob(blob, grp_aidx), o_gp = push_blob(blob, grp_plane);
   size_t o_g2 = push_blob(blob, grp2), o_p2 = push_blob(blob, pos2), o_pe2 = push_blob(blob, pend2);
   size_t o_grec = push_blob(blob, grec), o_ds = push_blob(blob, dseg);
-  size_t o_rep = push_blob(blob, rep), o_rch = push_blob(blob, chunks);
+  size_t o_rep = push_blob(blob, rep), o_task = push_blob(blob, tasks);
   in->mem = dalloc(blob.size());
   if (!in->mem) {
     delete in;
@@ -1245,7 +1260,7 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
   P.grec = (const GRowRec *)(b + o_grec);
   P.dseg = (const Seg *)(b + o_ds);
   P.rep = (const RepRec *)(b + o_rep);
-  P.repchunk = (const RepChunk *)(b + o_rch);
+  P.task = (const GTask *)(b + o_task);
   if (hipMemcpy(in->mem, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
     free_inst(in);
     fail(HD_EHIP);
@@ -1690,7 +1705,19 @@ static int enqueue_user(Plan *pl, const float *coef);
 // see the updated GDEF.  ev_table (optional) marks the message table done.
 static hipError_t derive_and_update(const PlanDev &P, const Work &W, const Level &L1, MsgRec *tab, MsgHdr *hdr,
                                     int64_t cap, int has3d, hipStream_t meta, hipEvent_t ev_table = nullptr) {
-  hipError_t e = launch_runs(P, R.d_arrs, W, R.row_cap, meta);
+  hipError_t e;
+  if (R.fused) {
+    // small instances: one wave derives the table, then the GDEF update
+    // follows on the same stream (no fork, no events)
+    e = launch_derive1(P, R.d_arrs, W, L1, make_level(2, P), tab, hdr, cap, R.row_cap, meta);
+    if (e == hipSuccess) {
+      if (ev_table && (e = hipEventRecord(ev_table, meta)) != hipSuccess) return e;
+      return launch_gdef(P, R.d_arrs, W, meta);
+    }
+    if (e != hipErrorNotSupported) return e;
+    (void)hipGetLastError();
+  }
+  e = launch_runs(P, R.d_arrs, W, R.row_cap, meta);
   if (e != hipSuccess) return e;
   const bool fork = meta != R.data;
   if (fork) {
@@ -1781,11 +1808,23 @@ static int enqueue(Plan *pl, const float *coef) {
   Level L1 = make_level(1, P);
   if (pl->adjoint) {
     HIPCK(launch_gdef(P, R.d_arrs, W, meta));
-    HIPCK(launch_level1(P, R.d_arrs, W, L1, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0, R.row_cap,
-                        meta));
-    if (pl->has3d) {
-      Level L2 = make_level(2, P);
-      HIPCK(launch_level2(P, W, L2, R.tab[slot], R.hdr[slot], R.ws_items, meta));
+    bool done = false;
+    if (R.fused) {
+      const hipError_t e = launch_derive1(P, R.d_arrs, W, L1, make_level(2, P), R.tab[slot], R.hdr[slot], R.ws_items,
+                                          R.row_cap, meta);
+      if (e == hipSuccess)
+        done = true;
+      else if (e != hipErrorNotSupported)
+        return fail(HD_EHIP);
+      (void)hipGetLastError();
+    }
+    if (!done) {
+      HIPCK(launch_level1(P, R.d_arrs, W, L1, R.tab[slot], R.hdr[slot], R.ws_items, pl->has3d ? 1 : 0, R.row_cap,
+                          meta));
+      if (pl->has3d) {
+        Level L2 = make_level(2, P);
+        HIPCK(launch_level2(P, W, L2, R.tab[slot], R.hdr[slot], R.ws_items, meta));
+      }
     }
     HIPCK(hipEventRecord(R.ev_cs[slot], meta));
   } else {
@@ -1835,7 +1874,30 @@ static int enqueue_user(Plan *pl, const float *coef) {
     R.stats.stencil_vec = pl->vec ? 1 : 0;
     PhaseTimer tm(3, R.data);
     if (e0) HIPCK(hipEventRecord(e0, R.data));
-    HIPCK(launch_user(pl->ukind, th, waves, order, pl->vec, pl->wbj[q], pl->nbox, R.d_arrs, pl->ntj[q], coef, R.data));
+    if (waves == 4 && th < 32 && pl->vec && pl->nbox <= kArgBoxes && !pl->hwbj[q].empty()) {
+      // the stacked shape with the boxes and buffers passed by value
+      const std::vector<WorkBox> &hb = pl->hwbj[q];
+      StackArgs a{};
+      a.nbox = (int32_t)hb.size();
+      const hd_array *ai = R.arrays[hb[0].ain];
+      a.N1 = (int32_t)ai->n[1];
+      a.N2 = (int32_t)ai->n[2];
+      for (size_t i = 0; i < hb.size(); ++i) {
+        a.lo1[i] = hb[i].lo[1];
+        a.lo2[i] = hb[i].lo[2];
+        a.hi1[i] = hb[i].hi[1];
+        a.hi2[i] = hb[i].hi[2];
+        a.tile0[i] = hb[i].tile0;
+        a.in[i] = reinterpret_cast<const float *>(R.arrays[hb[i].ain]->buf[hb[i].dev]);
+        a.out[i] = reinterpret_cast<float *>(R.arrays[hb[i].aout]->buf[hb[i].dev]);
+      }
+      const int op = pl->ukind == 1 ? 0 : pl->ukind == 5 ? 1 : 2;
+      HIPCK(launch_stack_args(op, th, a, pl->ntj[q], coef, R.data));
+      R.stats.stencil_vec = 2;
+    } else {
+      HIPCK(launch_user(pl->ukind, th, waves, order, pl->vec, pl->wbj[q], pl->nbox, R.d_arrs, pl->ntj[q], coef,
+                        R.data));
+    }
     if (e1) HIPCK(hipEventRecord(e1, R.data));
   } else if (pl->ukind) {
     PhaseTimer tm(3, R.data);
@@ -2070,6 +2132,7 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
           t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, ths[q]);
         }
         pl->ntj[q] = t0;
+        pl->hwbj[q] = wb;
         if (!wb.empty()) HIPCK(hipMemcpy(pl->wbj[q], wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice));
       }
       pl->vec = true;
