@@ -153,34 +153,49 @@ __global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict
 // long), and each GDEF cell is updated by one wave.
 constexpr int kDerive1Max = 64;  // slices (and level-2 groups) of the small form
 
-// Eight waves: wave 0 finds the runs (one lane per slice) and the band
-// flags, the heads are shared out band by band over the waves (item lists
-// of up to kHead1 items staged in LDS, longer ones searched in memory).
+// Two launches per call.  k_runs1 (one workgroup of eight waves): the runs,
+// one wave per slice (the intervals in lanes, runs by ballot).  k_tail1:
+// workgroup 0 turns the runs into the message table (band flags, band scan,
+// heads shared out band by band over its waves with item lists of up to
+// kHead1 items staged in LDS, compaction) while the other workgroups update
+// GDEF (both only read the runs), so the table and the update finish
+// together.
 constexpr int kDerive1Waves = 8, kHead1 = 32;
+
 template <int CAP>
-__global__ __launch_bounds__(64 * kDerive1Waves) void k_derive1(PlanDev P, const ArrDev *__restrict__ A, Work W,
-                                                              Level L1, Level L2, MsgRec *out, MsgHdr *hdr,
-                                                              int64_t cap, int has3d) {
-  // wave 0's runs staging, then the wave path's scratch; then the heads'
-  // scratch (2 * kHead1 items per wave); then the compaction's scratch
-  __shared__ __align__(16) char s_buf[16384];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (wv == 0) {
-    const int s = lane;
-    const bool done = s >= P.nsl1 || dev_runs_lane<kRunSlot>(P, A, W, s, reinterpret_cast<int32_t *>(s_buf));
-    uint64_t left = __ballot(!done);
-    wave_lds_sync();
-    Ivl *iv = reinterpret_cast<Ivl *>(s_buf);
-    Run *rr = reinterpret_cast<Run *>(s_buf + sizeof(Ivl) * CAP);
-    while (left) {
-      const int l = __ffsll((unsigned long long)left) - 1;
-      left &= left - 1;
-      const int nr = dev_runs_find(P, A, W, l, iv, rr);
-      dev_runs_store(P, W, l, rr, nr);
-      wave_lds_sync();
-    }
-  }
+__global__ __launch_bounds__(64 * kDerive1Waves) void k_runs1(PlanDev P, const ArrDev *__restrict__ A, Work W) {
+  constexpr int kWaveLds = CAP * sizeof(Ivl) + kMaxRunsRow * sizeof(Run);
+  __shared__ __align__(16) char s_buf[kDerive1Waves * kWaveLds];
+  const int wv = threadIdx.x >> 6;
+  // one workgroup: the spill pool can start over here
+  if (threadIdx.x == 0) *W.run_top = 0;
   __syncthreads();
+  Ivl *iv = reinterpret_cast<Ivl *>(s_buf + wv * kWaveLds);
+  Run *rr = reinterpret_cast<Run *>(s_buf + wv * kWaveLds + CAP * sizeof(Ivl));
+  for (int sl = wv; sl < P.nsl1; sl += kDerive1Waves) {
+    const int nr = dev_runs_find(P, A, W, sl, iv, rr);
+    dev_runs_store(P, W, sl, rr, nr);
+    wave_lds_sync();
+  }
+}
+
+__device__ inline void gdef_task(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int q, GdefLds S);
+
+__global__ __launch_bounds__(64 * kDerive1Waves) void k_tail1(PlanDev P, ArrDev *__restrict__ A, Work W, Level L1,
+                                                            Level L2, MsgRec *out, MsgHdr *hdr, int64_t cap,
+                                                            int has3d) {
+  // workgroup 0: the heads' scratch (2 * kHead1 items per wave), then the
+  // compaction's; the others: one wave's LDS form of the GDEF update
+  __shared__ __align__(16) char s_buf[sizeof(Ivl) * kMaxCap + (3 * 4 + 8) * kGdefMaxB];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (blockIdx.x > 0) {
+    Ivl *iv = reinterpret_cast<Ivl *>(s_buf);
+    int32_t *b = reinterpret_cast<int32_t *>(s_buf + sizeof(Ivl) * kMaxCap);
+    GdefLds S{iv, b, b + kGdefMaxB, b + 2 * kGdefMaxB, reinterpret_cast<uint64_t *>(b + 3 * kGdefMaxB)};
+    const int nw = (gridDim.x - 1) * kDerive1Waves;
+    for (int q = (blockIdx.x - 1) * kDerive1Waves + wv; q < P.ntask; q += nw) gdef_task(P, A, W, q, S);
+    return;
+  }
   for (int lv = 1; lv <= (has3d ? 2 : 1); ++lv) {
     const Level &L = lv == 1 ? L1 : L2;
     if (L.nsl > 0) {
@@ -201,17 +216,17 @@ __global__ __launch_bounds__(64 * kDerive1Waves) void k_derive1(PlanDev P, const
 // list before the update), applies the cell's edits and writes the new list
 // to all its rows, so no task waits for another; rows with more than 64
 // boundaries take the LDS form in the same wave.
+__device__ inline void gdef_task(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int q, GdefLds S) {
+  const GTask tk = P.task[q];
+  if (!dev_gdef_row_fast(P, A, W, tk.t, tk.k0)) dev_gdef_row(P, A, W, tk.t, S, kGdefMaxB, tk.k0);
+}
+
 __global__ __launch_bounds__(64) void k_gdef_tasks(PlanDev P, ArrDev *__restrict__ A, Work W) {
   __shared__ Ivl s_iv[kMaxCap];
   __shared__ int32_t s_b[kGdefMaxB], s_u[kGdefMaxB], s_own[kGdefMaxB];
   __shared__ uint64_t s_hold[kGdefMaxB];
-  for (int q = blockIdx.x; q < P.ntask; q += gridDim.x) {
-    const GTask tk = P.task[q];
-    if (!dev_gdef_row_fast(P, A, W, tk.t, tk.k0)) {
-      GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
-      dev_gdef_row(P, A, W, tk.t, S, kGdefMaxB, tk.k0);
-    }
-  }
+  GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
+  for (int q = blockIdx.x; q < P.ntask; q += gridDim.x) gdef_task(P, A, W, q, S);
 }
 
 // Every row starts as one interval [0, n2) owned and held by the host.
@@ -306,16 +321,21 @@ hipError_t launch_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap, hipSt
   return hipGetLastError();
 }
 
-// The one-wave derivation, when the instance is small enough; returns
-// hipErrorNotSupported otherwise (the caller then takes the per-phase form).
-hipError_t launch_derive1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L1, const Level &L2,
-                          MsgRec *out, MsgHdr *hdr, int64_t cap, int row_cap, hipStream_t s) {
+// The two-launch derivation of small instances (with the GDEF update unless
+// gdef is false); returns hipErrorNotSupported for larger ones (the caller
+// then takes the per-phase form).
+hipError_t launch_derive1(const PlanDev &P, ArrDev *A, const Work &W, const Level &L1, const Level &L2,
+                          MsgRec *out, MsgHdr *hdr, int64_t cap, int row_cap, bool gdef, hipStream_t s) {
   if (P.nsl1 > kDerive1Max || P.ngrp > kDerive1Max) return hipErrorNotSupported;
-  const int h3 = P.has3d ? 1 : 0;
-  if (row_cap <= 64)
-    hipLaunchKernelGGL(k_derive1<64>, dim3(1), dim3(64 * kDerive1Waves), 0, s, P, A, W, L1, L2, out, hdr, cap, h3);
-  else
-    hipLaunchKernelGGL(k_derive1<kMaxCap>, dim3(1), dim3(64 * kDerive1Waves), 0, s, P, A, W, L1, L2, out, hdr, cap, h3);
+  if (P.nsl1 > 0) {
+    if (row_cap <= 64)
+      hipLaunchKernelGGL(k_runs1<64>, dim3(1), dim3(64 * kDerive1Waves), 0, s, P, A, W);
+    else
+      hipLaunchKernelGGL(k_runs1<kMaxCap>, dim3(1), dim3(64 * kDerive1Waves), 0, s, P, A, W);
+  }
+  const int gw = gdef && P.ntask > 0 ? (P.ntask + kDerive1Waves - 1) / kDerive1Waves : 0;
+  hipLaunchKernelGGL(k_tail1, dim3(1 + (gw < 1024 ? gw : 1024)), dim3(64 * kDerive1Waves), 0, s, P, A, W, L1, L2,
+                     out, hdr, cap, P.has3d ? 1 : 0);
   return hipGetLastError();
 }
 

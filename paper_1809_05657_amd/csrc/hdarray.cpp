@@ -27,8 +27,8 @@ namespace hd {
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr, int64_t cap,
                           int mode, hipStream_t s);
 hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s);
-hipError_t launch_derive1(const PlanDev &P, const ArrDev *A, const Work &W, const Level &L1, const Level &L2,
-                          MsgRec *out, MsgHdr *hdr, int64_t cap, int row_cap, hipStream_t s);
+hipError_t launch_derive1(const PlanDev &P, ArrDev *A, const Work &W, const Level &L1, const Level &L2,
+                          MsgRec *out, MsgHdr *hdr, int64_t cap, int row_cap, bool gdef, hipStream_t s);
 extern int g_runs_wave_max;
 hipError_t launch_runs(const PlanDev &P, const ArrDev *A, const Work &W, int row_cap, hipStream_t s);
 hipError_t launch_level1_tail(const PlanDev &P, const Work &W, const Level &L, MsgRec *out, MsgHdr *hdr, int64_t cap,
@@ -1707,13 +1707,10 @@ static hipError_t derive_and_update(const PlanDev &P, const Work &W, const Level
                                     int64_t cap, int has3d, hipStream_t meta, hipEvent_t ev_table = nullptr) {
   hipError_t e;
   if (R.fused) {
-    // small instances: one wave derives the table, then the GDEF update
-    // follows on the same stream (no fork, no events)
-    e = launch_derive1(P, R.d_arrs, W, L1, make_level(2, P), tab, hdr, cap, R.row_cap, meta);
-    if (e == hipSuccess) {
-      if (ev_table && (e = hipEventRecord(ev_table, meta)) != hipSuccess) return e;
-      return launch_gdef(P, R.d_arrs, W, meta);
-    }
+    // small instances: two launches (runs; then the table and the GDEF
+    // update side by side), no fork and no events
+    e = launch_derive1(P, R.d_arrs, W, L1, make_level(2, P), tab, hdr, cap, R.row_cap, true, meta);
+    if (e == hipSuccess) return ev_table ? hipEventRecord(ev_table, meta) : hipSuccess;
     if (e != hipErrorNotSupported) return e;
     (void)hipGetLastError();
   }
@@ -1811,7 +1808,7 @@ static int enqueue(Plan *pl, const float *coef) {
     bool done = false;
     if (R.fused) {
       const hipError_t e = launch_derive1(P, R.d_arrs, W, L1, make_level(2, P), R.tab[slot], R.hdr[slot], R.ws_items,
-                                          R.row_cap, meta);
+                                          R.row_cap, false, meta);
       if (e == hipSuccess)
         done = true;
       else if (e != hipErrorNotSupported)
