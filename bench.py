@@ -55,6 +55,85 @@ def committed_traffic(name, kernel, sources=KERNEL_SOURCES):
 KERNEL_SAMPLE = 4  # every 4th step of a timed loop times its stencil launch
 
 
+def short_kernel_name(n):
+    """A profiler kernel name without namespace, return type, arguments or
+    spaces (k_stack_a<4,0>)."""
+    n = n.strip('"').replace("void ", "").replace("hd::", "")
+    return n.split("(")[0].replace(" ", "")
+
+
+def pmc_means(folder, counter):
+    """Mean value per dispatch of one counter for every kernel of a
+    rocprofv3 --pmc CSV output folder: {kernel: (mean, dispatches)}."""
+    import csv
+    import glob
+    acc = {}
+    for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] != counter:
+                    continue
+                s = acc.setdefault(short_kernel_name(row["Kernel_Name"]), [0.0, 0])
+                s[0] += float(row["Counter_Value"])
+                s[1] += 1
+    return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
+
+
+# algorithmic bytes per launch of the kernels whose traffic is summarised
+TRAFFIC_WORKLOADS = {
+    "jacobi2d_8192": {"workload": "jacobi_large (8192x8192 fp32, 16 devices 4x4, ping-pong); every tile shape the "
+                                  "runtime tries", "sources": KERNEL_SOURCES, "bytes": 8 * 8192 * 8192,
+                      "bench": "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --headline-only"},
+    "stencil3d_512": {"workload": "stencil3d 512^3 fp32, 8 devices (2x2x2), T=64, checkpoint every 8: forward and "
+                                  "adjoint steps", "sources": S3D_SOURCES,
+                      "bytes": {"k_s3d": 8 * 512 ** 3, "adjoint_step": 12 * 512 ** 3},
+                      "adjoint_step": ["k_rev_pack", "k_s3d_adj", "k_unpack_add"],
+                      "bench": "python3 bench.py --workload stencil3d"},
+}
+
+
+def traffic_summary(name, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE runs
+    (KiB per dispatch), each scaled by what the same counter reads for the
+    built-in copy of known size (--workload copy_calib: 256 MiB read and 256
+    MiB written per launch)."""
+    w = TRAFFIC_WORKLOADS[name]
+    n = 8192
+    cf = pmc_means(cal_fetch_dir, "FETCH_SIZE")["k_copy"][0] * 1024.0
+    cw = pmc_means(cal_write_dir, "WRITE_SIZE")["k_copy"][0] * 1024.0
+    ff, fw = 4.0 * n * n / cf, 4.0 * n * n / cw
+    fet, wri = pmc_means(fetch_dir, "FETCH_SIZE"), pmc_means(write_dir, "WRITE_SIZE")
+    out = {"workload": w["workload"], "kernel_source_hash": kernel_hash(w["sources"]),
+           "algorithmic_bytes_per_launch": w["bytes"], "kernels": {},
+           "copy_calibration": {"fetch_factor": ff, "write_factor": fw,
+                                "fetch_kib_per_dispatch": cf / 1024.0, "write_kib_per_dispatch": cw / 1024.0}}
+    for k in sorted(set(fet) & set(wri)):
+        if not k.startswith("k_") or k.startswith(("k_runs", "k_tail", "k_gdef", "k_band", "k_heads", "k_compact")):
+            continue
+        hb = fet[k][0] * 1024.0 * ff + wri[k][0] * 1024.0 * fw
+        rec = {"fetch_kib_per_dispatch": fet[k][0], "write_kib_per_dispatch": wri[k][0],
+               "dispatches": [fet[k][1], wri[k][1]], "hbm_bytes_per_launch": hb}
+        alg = w["bytes"] if isinstance(w["bytes"], int) else w["bytes"].get(k.split("<")[0])
+        if alg:
+            rec["traffic_over_algorithmic"] = hb / alg
+        out["kernels"][k.split("<")[0] if not isinstance(w["bytes"], int) else k] = rec
+    if "adjoint_step" in w:
+        parts = [k for k in out["kernels"] if k in w["adjoint_step"]]
+        if len(parts) == len(w["adjoint_step"]):
+            hb = sum(out["kernels"][k]["hbm_bytes_per_launch"] for k in parts)
+            out["kernels"]["adjoint_step"] = {"hbm_bytes_per_launch": hb, "of": parts,
+                                              "traffic_over_algorithmic": hb / w["bytes"]["adjoint_step"]}
+    cmd = w["bench"]
+    out["commands"] = [f"rocprofv3 --pmc FETCH_SIZE -f csv -d OUT/fetch -o t -- {cmd}",
+                       f"rocprofv3 --pmc WRITE_SIZE -f csv -d OUT/write -o t -- {cmd}",
+                       "rocprofv3 --pmc FETCH_SIZE -f csv -d OUT/cal_fetch -o t -- python3 bench.py --workload "
+                       "copy_calib --steps 20 --warmup 3",
+                       "rocprofv3 --pmc WRITE_SIZE -f csv -d OUT/cal_write -o t -- python3 bench.py --workload "
+                       "copy_calib --steps 20 --warmup 3",
+                       f"python3 bench.py --traffic {name} OUT/fetch OUT/write OUT/cal_fetch OUT/cal_write"]
+    return out
+
+
 def stencil_kernel_name(st, one, strip, op):
     """Name (as the profiler prints it, without spaces) of the 2-D stencil
     kernel the last call launched, from the shape in the runtime's stats."""
@@ -557,6 +636,9 @@ def bench_copy_calib(hd, rt, steps, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--traffic", nargs=5, metavar=("NAME", "FETCH", "WRITE", "CAL_FETCH", "CAL_WRITE"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE folders into profiles/NAME_traffic.json "
+                         "(no GPU needed)")
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=8192)
@@ -567,6 +649,13 @@ def main():
     ap.add_argument("--workload", default="jacobi_large",
                     choices=["jacobi_large", "matmul", "2mm", "conv2d", "batched", "stencil3d", "copy_calib"])
     args = ap.parse_args()
+    if args.traffic:
+        name = args.traffic[0]
+        out = traffic_summary(*args.traffic)
+        with open(os.path.join(ROOT, "profiles", f"{name}_traffic.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(json.dumps({k: v.get("traffic_over_algorithmic") for k, v in out["kernels"].items()}))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs the ApplyKernel path on one GPU only (the logical devices are "
               "partitions of one MI355X); multi-GPU runs are not supported.", file=sys.stderr)

@@ -87,7 +87,11 @@ typedef struct {
  * the paper; here kernels are built in (see hdarray_register_kernel), so kpath
  * may be NULL.  dpath (device info file) is unused on one GPU and may be NULL.
  * argv may carry "--hd-row-cap=N" (capacity of a per-row GDEF list,
- * 4..256, default 64; a row needing more intervals raises HD_ECAPACITY).
+ * 4..256, default 64; a row needing more intervals raises HD_ECAPACITY) and
+ * "--hd-windows=compact" (each device keeps, per 2-D array, only a box of
+ * the array around every section it holds or its kernels read, instead of
+ * a whole-array buffer; less memory, slower 2-D stencils) or
+ * "--hd-windows=full" (the default).
  * Environment, read here: HD_SERIAL=1 runs the communication-set
  * derivation and GDEF update on the data stream instead of overlapping
  * them (a measurement aid); HD_JACOBI_ROWS=4|8|16|32|64, HD_JACOBI_WAVES=1|4
@@ -97,8 +101,10 @@ typedef struct {
  * HD_EVENT_SCOPE=system makes the runtime's inter-stream events use HIP's
  * default system-scope release instead of a device-scope one, and
  * HD_RUNS_WAVE_MAX=N finds the runs of levels with fewer than N use rows
- * with one wave per row instead of one lane per row (measurement aids).  Returns the HIP device id (>= 0) or a negative
- * error. */
+ * with one wave per row instead of one lane per row, and HD_FUSED_META=0
+ * derives small plan instances (at most 64 slices and groups) with the
+ * general kernel sequence instead of the two-launch form (measurement
+ * aids).  Returns the HIP device id (>= 0) or a negative error. */
 int hdarray_init(int argc, char **argv, const char *kpath, const char *dpath);
 
 /* HDArrayExit: waits for the GPU, frees every array, plan and buffer. */
@@ -367,9 +373,14 @@ int64_t hdarray_debug_messages(int64_t *out, int64_t cap);
 int64_t hdarray_debug_pack(void *out, int64_t cap);
 /* GDEF expanded per element: owner (0..62, 63 = host) and holder bits. */
 int hdarray_debug_gdef(hd_array_t *a, int8_t *owner, uint64_t *holders);
-/* Device dev's full-extent buffer (dev = HD_HOST: the host buffer). */
+/* Device dev's buffer at the array's full extent, n0*n1*n2 elements row-major
+ * (dev = HD_HOST: the host buffer).  A device keeps only a window of the
+ * array (a box around every section it holds or reads); elements outside it
+ * read as zero. */
 int hdarray_debug_device_buffer(hd_array_t *a, int dev, void *out);
-/* Device pointer of (array, device) buffer, allocating it if needed. */
+/* Device pointer of (array, device)'s buffer laid out as the whole array,
+ * row-major with dense strides: allocates it, or widens the device's window
+ * to the whole array, if needed (a widened window stays whole). */
 void *hdarray_device_ptr(hd_array_t *a, int dev);
 
 #ifdef __cplusplus

@@ -151,7 +151,7 @@ class Runtime:
     """The process-wide runtime (one per process; creating a new one calls
     HDArrayExit on the previous state)."""
 
-    def __init__(self, use_torch_allocator=True, row_cap=None, stream=None):
+    def __init__(self, use_torch_allocator=True, row_cap=None, stream=None, windows=None):
         self.L = load()
         self.L.hdarray_exit()
         if use_torch_allocator:
@@ -159,6 +159,10 @@ class Runtime:
         argv = []
         if row_cap:
             argv.append(f"--hd-row-cap={int(row_cap)}".encode())
+        if windows is not None:
+            if windows not in ("full", "compact"):
+                raise ValueError("windows must be 'full' or 'compact'")
+            argv.append(f"--hd-windows={windows}".encode())
         arr = (C.c_char_p * max(len(argv), 1))(*argv)
         self._ck(self.L.hdarray_init(len(argv), C.cast(arr, C.c_void_p), None, None), "init")
         if stream is not None:

@@ -79,13 +79,14 @@ __global__ __launch_bounds__(256) void k_ext_copy(const WorkBox *__restrict__ wb
   const int h = B.hi[1] - B.lo[1];
   const int64_t p = B.lo[0] + lr / h, q = B.lo[1] + lr % h;
   const int k = a.esize >> 2;
-  const int64_t base = ((p * a.n[1] + q) * a.n[2] + B.lo[2]) * k;
+  const int64_t base = ((p * a.n[1] + q) * a.n[2] + B.lo[2]) * k;  // dense external array
+  const int64_t bb = HD_EOFF(a, B.dev, p, q, B.lo[2]) * k;          // the device's window
   const int64_t words = (int64_t)(B.hi[2] - B.lo[2]) * k;
   uint32_t *buf = reinterpret_cast<uint32_t *>(a.buf[B.dev]);
   if (to_ext) {
-    for (int64_t w = lane; w < words; w += 64) ext[base + w] = buf[base + w];
+    for (int64_t w = lane; w < words; w += 64) ext[base + w] = buf[bb + w];
   } else {
-    for (int64_t w = lane; w < words; w += 64) buf[base + w] = ext[base + w];
+    for (int64_t w = lane; w < words; w += 64) buf[bb + w] = ext[base + w];
   }
 }
 
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(256) void k_reduce_part(const WorkBox *__restrict__
   uint32_t iv = OP == 0 ? 0u : OP == 1 ? 1u : OP == 2 ? 0x80000000u : 0x7fffffffu;
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < tot; q += (int64_t)gridDim.x * 256) {
     const int64_t cc = q % w, rr = (q / w) % h, pp = q / (w * h);
-    const int64_t x = ((B.lo[0] + pp) * a.n[1] + B.lo[1] + rr) * a.n[2] + B.lo[2] + cc;
+    const int64_t x = HD_EOFF(a, B.dev, B.lo[0] + pp, B.lo[1] + rr, B.lo[2] + cc);
     if (TYPE == 1) {
       const int32_t v = reinterpret_cast<const int32_t *>(a.buf[B.dev])[x];
       if (OP == 0) iv += (uint32_t)v;

@@ -54,15 +54,16 @@ __device__ inline void dev_pack_word(const MsgRec *__restrict__ M, int64_t n, co
   const int64_t c = lw % wid, t = lw / wid;
   const int64_t rr = t % rows, p = t / rows;
   const ArrDev &a = A[r.arr];
-  const int64_t g = (((int64_t)r.lo[0] + p) * a.n[1] + r.lo[1] + rr) * a.n[2] * k + (int64_t)r.lo[2] * k + c;
+  const int64_t gs = HD_EOFF(a, r.src, r.lo[0] + p, r.lo[1] + rr, r.lo[2]) * k + c;
+  const int64_t gd = HD_EOFF(a, r.dst, r.lo[0] + p, r.lo[1] + rr, r.lo[2]) * k + c;
   if (unpack == 0) {
-    stg[w] = reinterpret_cast<const uint32_t *>(a.buf[r.src])[g];
+    stg[w] = reinterpret_cast<const uint32_t *>(a.buf[r.src])[gs];
   } else if (unpack == 1) {
-    reinterpret_cast<uint32_t *>(a.buf[r.dst])[g] = stg[w];
+    reinterpret_cast<uint32_t *>(a.buf[r.dst])[gd] = stg[w];
   } else {
-    const uint32_t v = reinterpret_cast<const uint32_t *>(a.buf[r.src])[g];
+    const uint32_t v = reinterpret_cast<const uint32_t *>(a.buf[r.src])[gs];
     stg[w] = v;
-    reinterpret_cast<uint32_t *>(a.buf[r.dst])[g] = v;
+    reinterpret_cast<uint32_t *>(a.buf[r.dst])[gd] = v;
   }
 }
 
@@ -75,14 +76,16 @@ __device__ inline void dev_pack_span(const MsgRec &r, const ArrDev *__restrict__
   const ArrDev &a = A[r.arr];
   const IT k = (IT)(r.esize >> 2);
   const IT wid = (IT)(r.hi[2] - r.lo[2]) * k, rows = (IT)(r.hi[1] - r.lo[1]);
-  const int64_t rowpitch = a.n[2] * (int64_t)k;
-  const int64_t base = ((int64_t)r.lo[0] * a.n[1] + r.lo[1]) * rowpitch + (int64_t)r.lo[2] * k;
-  const int64_t planepitch = a.n[1] * rowpitch;
+  // source and destination windows have their own strides
+  const int64_t rps = a.rs[r.src] * k, pps = a.ps[r.src] * k;
+  const int64_t rpd = a.rs[r.dst] * k, ppd = a.ps[r.dst] * k;
+  const int64_t bs = HD_EOFF(a, r.src, r.lo[0], r.lo[1], r.lo[2]) * k;
+  const int64_t bd = HD_EOFF(a, r.dst, r.lo[0], r.lo[1], r.lo[2]) * k;
   const uint32_t *__restrict__ src = reinterpret_cast<const uint32_t *>(a.buf[r.src]);
   uint32_t *__restrict__ dst = reinterpret_cast<uint32_t *>(a.buf[r.dst]);
   uint32_t *__restrict__ sp = stg + (r.off >> 2);
   for (IT q = b0 + (IT)threadIdx.x; q < b1; q += 4 * 256) {
-    int64_t g[4];
+    int64_t gs[4], gd[4];
     bool ok[4];
     uint32_t v[4];
 #pragma unroll
@@ -91,15 +94,16 @@ __device__ inline void dev_pack_span(const MsgRec &r, const ArrDev *__restrict__
       ok[e] = lw < b1;
       const IT c = lw % wid, t = lw / wid;
       const IT rr = t % rows, p = t / rows;
-      g[e] = base + (int64_t)p * planepitch + (int64_t)rr * rowpitch + (int64_t)c;
-      if (ok[e]) v[e] = mode == 1 ? sp[lw] : src[g[e]];
+      gs[e] = bs + (int64_t)p * pps + (int64_t)rr * rps + (int64_t)c;
+      gd[e] = bd + (int64_t)p * ppd + (int64_t)rr * rpd + (int64_t)c;
+      if (ok[e]) v[e] = mode == 1 ? sp[lw] : src[gs[e]];
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       if (!ok[e]) continue;
       const IT lw = q + (IT)(e * 256);
       if (mode != 1) sp[lw] = v[e];
-      if (mode != 0) dst[g[e]] = v[e];
+      if (mode != 0) dst[gd[e]] = v[e];
     }
   }
 }
@@ -128,19 +132,21 @@ __device__ inline void dev_copy_tile(const WorkBox &B, int64_t lt, const ArrDev 
   const int64_t rest = lt / nty;
   const int tx = (int)(rest % ntx);
   const int p = B.lo[0] + (int)(rest / ntx);
+  const ArrDev &ao = A[B.aout];
   const uint32_t *__restrict__ in = reinterpret_cast<const uint32_t *>(ai.buf[B.dev]);
-  uint32_t *__restrict__ out = reinterpret_cast<uint32_t *>(A[B.aout].buf[B.dev]);
-  const int64_t rowwords = ai.n[2] * k;
+  uint32_t *__restrict__ out = reinterpret_cast<uint32_t *>(ao.buf[B.dev]);
   const int64_t c0 = (int64_t)B.lo[2] * k + (int64_t)tx * 256 + 4 * lane;
   const int64_t cend = (int64_t)B.hi[2] * k;
-  const bool vec = (rowwords & 3) == 0 && (c0 & 3) == 0;
+  // window columns start at multiples of 4, so with row strides of a
+  // multiple of 4 words an aligned column gives aligned words
+  const bool vec = (c0 & 3) == 0 && ((ai.rs[B.dev] * k) & 3) == 0 && ((ao.rs[B.dev] * k) & 3) == 0;
   for (int r = B.lo[1] + ty * 16; r < min(B.lo[1] + ty * 16 + 16, B.hi[1]); ++r) {
-    const int64_t base = ((int64_t)p * ai.n[1] + r) * rowwords;
+    const int64_t bi = HD_EOFF(ai, B.dev, p, r, 0) * k, bo = HD_EOFF(ao, B.dev, p, r, 0) * k;
     if (vec && c0 + 4 <= cend) {
-      *reinterpret_cast<uint4 *>(out + base + c0) = *reinterpret_cast<const uint4 *>(in + base + c0);
+      *reinterpret_cast<uint4 *>(out + bo + c0) = *reinterpret_cast<const uint4 *>(in + bi + c0);
     } else {
       for (int e = 0; e < 4; ++e)
-        if (c0 + e < cend) out[base + c0 + e] = in[base + c0 + e];
+        if (c0 + e < cend) out[bo + c0 + e] = in[bi + c0 + e];
     }
   }
 }

@@ -33,13 +33,13 @@ __device__ inline void tile_pos(const WorkBox &B, int64_t lt, int &tx, int &ty) 
 // One row of the lane's 4 columns with its left / right neighbour column
 // (zero when the row is outside the array or past rlim; such rows are never
 // used).  Called by whole waves (the neighbours come from adjacent lanes).
-__device__ inline void load_row(const float *__restrict__ in, int r, int rlim, int c, int N1, int N2, bool vec,
+__device__ inline void load_row(const float *__restrict__ in, int64_t rs, int r, int rlim, int c, int N1, int N2, bool vec,
                                 f4 &v, float &Lh, float &Rh) {
   const int lane = threadIdx.x & 63;
   f4 x = {0.f, 0.f, 0.f, 0.f};
   float l = 0.f, rr = 0.f;
   if (r >= 0 && r < N1 && r <= rlim) {
-    const float *p = in + (int64_t)r * N2;
+    const float *p = in + (int64_t)r * rs;
     if (vec && c + 4 <= N2) {
       x = *reinterpret_cast<const f4 *>(p + c);
     } else {
@@ -61,10 +61,10 @@ __device__ inline void load_row(const float *__restrict__ in, int r, int rlim, i
 // Rows r0-1 .. r0+TH of the lane's 4 columns (rows past r1 or outside the
 // array read as zero and are never used).
 template <int TH>
-__device__ inline void load_rows(const float *__restrict__ in, int r0, int r1, int c, int N1, int N2, bool vec,
+__device__ inline void load_rows(const float *__restrict__ in, int64_t rs, int r0, int r1, int c, int N1, int N2, bool vec,
                                  f4 *v, float *Lh, float *Rh) {
 #pragma unroll
-  for (int k = 0; k < TH + 2; ++k) load_row(in, r0 - 1 + k, r1, c, N1, N2, vec, v[k], Lh[k], Rh[k]);
+  for (int k = 0; k < TH + 2; ++k) load_row(in, rs, r0 - 1 + k, r1, c, N1, N2, vec, v[k], Lh[k], Rh[k]);
 }
 
 __device__ inline void store4(float *q, const float *o, const bool *wr, bool vec) {
@@ -88,12 +88,12 @@ struct RowI {
   float x[4], l[4], r[4];
 };
 
-__device__ inline RowI load_row_i(const float *__restrict__ in, int r, int rlim, int tc, int N1, int N2) {
+__device__ inline RowI load_row_i(const float *__restrict__ in, int64_t rs, int r, int rlim, int tc, int N1, int N2) {
   const int lane = threadIdx.x & 63;
   RowI q;
   float el = 0.f, er = 0.f;
   const bool ok = r >= 0 && r < N1 && r <= rlim;
-  const float *p = in + (int64_t)r * N2;
+  const float *p = in + (int64_t)r * rs;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int col = tc + 64 * e + lane;
@@ -115,12 +115,12 @@ __device__ inline RowI load_row_i(const float *__restrict__ in, int r, int rlim,
 
 template <int TH, bool TRI, bool HF>
 __device__ inline void dev_jacobi_tile_i(const WorkBox &B, int tx, int r0, int r1, const float *__restrict__ in,
-                                         float *__restrict__ out, int N1, int N2) {
+                                         float *__restrict__ out, int64_t rsi, int64_t rso, int N1, int N2) {
   const int lane = threadIdx.x & 63;
   const int tc = B.lo[2] + tx * 256;
   RowI v[TH + 2];
 #pragma unroll
-  for (int k = 0; k < TH + 2; ++k) v[k] = load_row_i(in, r0 - 1 + k, r1, tc, N1, N2);
+  for (int k = 0; k < TH + 2; ++k) v[k] = load_row_i(in, rsi, r0 - 1 + k, r1, tc, N1, N2);
 #pragma unroll
   for (int k = 1; k <= TH; ++k) {
     const int i = r0 + k - 1;
@@ -138,7 +138,7 @@ __device__ inline void dev_jacobi_tile_i(const WorkBox &B, int tx, int r0, int r
       float s = v[k].l[e] + v[k].r[e];
       s = s + v[k - 1].x[e];
       s = s + v[k + 1].x[e];
-      if (write) out[(int64_t)i * N2 + j] = interior ? s * 0.25f : v[k].x[e];
+      if (write) out[(int64_t)i * rso + j] = interior ? s * 0.25f : v[k].x[e];
     }
   }
 }
@@ -157,14 +157,15 @@ __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDe
   const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
   float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
   const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const int64_t rsi = ai.rs[B.dev], rso = A[B.aout].rs[B.dev];
   const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
   if (!vec) {
-    dev_jacobi_tile_i<TH, TRI, HF>(B, tx, r0, r1, in, out, N1, N2);
+    dev_jacobi_tile_i<TH, TRI, HF>(B, tx, r0, r1, in, out, rsi, rso, N1, N2);
     return;
   }
   f4 v[TH + 2];
   float Lh[TH + 2], Rh[TH + 2];
-  load_rows<TH>(in, r0, r1, c, N1, N2, vec, v, Lh, Rh);
+  load_rows<TH>(in, rsi, r0, r1, c, N1, N2, vec, v, Lh, Rh);
 #pragma unroll
   for (int k = 1; k <= TH; ++k) {
     const int i = r0 + k - 1;
@@ -191,7 +192,7 @@ __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDe
       o[e] = interior ? s * 0.25f : cv[e + 1];
       wr[e] = write;
     }
-    store4(out + (int64_t)i * N2 + c, o, wr, vec);
+    store4(out + (int64_t)i * rso + c, o, wr, vec);
   }
 }
 
@@ -216,10 +217,11 @@ __device__ inline void dev_conv_tile(const WorkBox &B, int64_t lt, const ArrDev 
   const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
   float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
   const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const int64_t rsi = ai.rs[B.dev], rso = A[B.aout].rs[B.dev];
   const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
   f4 v[TH + 2];
   float Lh[TH + 2], Rh[TH + 2];
-  load_rows<TH>(in, r0, r1, c, N1, N2, vec, v, Lh, Rh);
+  load_rows<TH>(in, rsi, r0, r1, c, N1, N2, vec, v, Lh, Rh);
 #pragma unroll
   for (int k = 1; k <= TH; ++k) {
     const int i = r0 + k - 1;
@@ -246,7 +248,7 @@ __device__ inline void dev_conv_tile(const WorkBox &B, int64_t lt, const ArrDev 
       o[e] = interior ? acc : row[1][e + 1];
       wr[e] = j < B.hi[2];
     }
-    store4(out + (int64_t)i * N2 + c, o, wr, vec);
+    store4(out + (int64_t)i * rso + c, o, wr, vec);
   }
 }
 
@@ -257,7 +259,7 @@ __device__ inline void dev_conv_tile(const WorkBox &B, int64_t lt, const ArrDev 
 // (plus two halo rows per strip) with a small register footprint.
 // OP: 0 Jacobi, 1 lower-triangular Jacobi, 2 3 x 3 convolution (weights W).
 template <int OP>
-__device__ inline void strip_row(int i, int c, int N1, int N2, const WorkBox &B, const f4 &up, const f4 &cu,
+__device__ inline void strip_row(int i, int c, int N1, int N2, int64_t rso, const WorkBox &B, const f4 &up, const f4 &cu,
                                  const f4 &dn, float Lu, float Ru, float Lc, float Rc, float Ld, float Rd,
                                  const Coef9 &W, float *__restrict__ out, bool vec) {
   float o[4];
@@ -302,7 +304,7 @@ __device__ inline void strip_row(int i, int c, int N1, int N2, const WorkBox &B,
       wr[e] = write;
     }
   }
-  store4(out + (int64_t)i * N2 + c, o, wr, vec);
+  store4(out + (int64_t)i * rso + c, o, wr, vec);
 }
 
 template <int TS, int C, int OP, bool HF>
@@ -318,23 +320,24 @@ __device__ inline void dev_strip(const WorkBox &B, int64_t lt, const ArrDev *__r
   const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
   float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
   const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
+  const int64_t rsi = ai.rs[B.dev], rso = A[B.aout].rs[B.dev];
   const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
   // window: rows base-1 .. base+C
   f4 v[C + 2];
   float L[C + 2], R[C + 2];
-  load_rows<C>(in, r0, r1, c, N1, N2, vec, v, L, R);
+  load_rows<C>(in, rsi, r0, r1, c, N1, N2, vec, v, L, R);
   for (int base = r0; base < r1; base += C) {
     f4 nv[C];
     float nL[C], nR[C];
     if (base + C < r1) {
 #pragma unroll
-      for (int k = 0; k < C; ++k) load_row(in, base + C + 1 + k, r1, c, N1, N2, vec, nv[k], nL[k], nR[k]);
+      for (int k = 0; k < C; ++k) load_row(in, rsi, base + C + 1 + k, r1, c, N1, N2, vec, nv[k], nL[k], nR[k]);
     }
 #pragma unroll
     for (int k = 1; k <= C; ++k) {
       const int i = base + k - 1;
       if (i >= r1) break;
-      strip_row<OP>(i, c, N1, N2, B, v[k - 1], v[k], v[k + 1], L[k - 1], R[k - 1], L[k], R[k], L[k + 1], R[k + 1], W,
+      strip_row<OP>(i, c, N1, N2, rso, B, v[k - 1], v[k], v[k + 1], L[k - 1], R[k - 1], L[k], R[k], L[k + 1], R[k + 1], W,
                     out, vec);
     }
     v[0] = v[C];
@@ -362,8 +365,8 @@ __device__ inline void dev_strip(const WorkBox &B, int64_t lt, const ArrDev *__r
 // of 4); otherwise each wave takes the coalesced per-wave path (no LDS).
 // OP: 0 Jacobi, 1 lower-triangular Jacobi, 2 3 x 3 convolution.
 template <int W, int TH, int OP, bool VEC>
-__device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const float *__restrict__ in,
-                                        float *__restrict__ out, int N1, int N2, const Coef9 &Wt) {
+__device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const float *__restrict__ in, int64_t rsi,
+                                        float *__restrict__ out, int64_t rso, int N1, int N2, const Coef9 &Wt) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int tx, ty;
   tile_pos<W * TH, true>(B, lt, tx, ty);
@@ -378,16 +381,16 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
     if (r0 >= t1) return;
     const int r1 = min(r0 + TH, t1);
     if (OP != 2) {
-      dev_jacobi_tile_i<TH, OP == 1, true>(B, tx, r0, r1, in, out, N1, N2);
+      dev_jacobi_tile_i<TH, OP == 1, true>(B, tx, r0, r1, in, out, rsi, rso, N1, N2);
     } else {
       f4 v[TH + 2];
       float L[TH + 2], R[TH + 2];
-      load_rows<TH>(in, r0, r1, c, N1, N2, false, v, L, R);
+      load_rows<TH>(in, rsi, r0, r1, c, N1, N2, false, v, L, R);
 #pragma unroll
       for (int k = 1; k <= TH; ++k) {
         const int i = r0 + k - 1;
         if (i >= r1) break;
-        strip_row<2>(i, c, N1, N2, B, v[k - 1], v[k], v[k + 1], L[k - 1], R[k - 1], L[k], R[k], L[k + 1], R[k + 1],
+        strip_row<2>(i, c, N1, N2, rso, B, v[k - 1], v[k], v[k + 1], L[k - 1], R[k - 1], L[k], R[k], L[k + 1], R[k + 1],
                      Wt, out, false);
       }
     }
@@ -404,11 +407,11 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
   // and written, so no per-lane guard is needed.
   const int tc = B.lo[2] + tx * 256;
   if (OP != 1 && t0 >= 1 && t0 + W * TH <= min(B.hi[1], N1 - 1) && tc >= 1 && tc + 256 <= min(B.hi[2], N2 - 1)) {
-    const float *p = in + (int64_t)(r0 - 1) * N2 + c;
+    const float *p = in + (int64_t)(r0 - 1) * rsi + c;
 #pragma unroll
-    for (int k = 1; k <= TH; ++k) v[k] = *reinterpret_cast<const f4 *>(p + (int64_t)k * N2);
+    for (int k = 1; k <= TH; ++k) v[k] = *reinterpret_cast<const f4 *>(p + (int64_t)k * rsi);
     if (wv == 0) v[0] = *reinterpret_cast<const f4 *>(p);
-    if (wv == W - 1) v[TH + 1] = *reinterpret_cast<const f4 *>(p + (int64_t)(TH + 1) * N2);
+    if (wv == W - 1) v[TH + 1] = *reinterpret_cast<const f4 *>(p + (int64_t)(TH + 1) * rsi);
     const int k0 = OP == 2 ? 0 : 1, k1 = OP == 2 ? TH + 1 : TH;
     float le[TH + 2], ri[TH + 2];
 #pragma unroll
@@ -416,12 +419,12 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
     if (lane == 0) {
 #pragma unroll
       for (int k = k0; k <= k1; ++k)
-        if ((k > 0 && k <= TH) || (k == 0 && wv == 0) || (k == TH + 1 && wv == W - 1)) le[k] = p[(int64_t)k * N2 - 1];
+        if ((k > 0 && k <= TH) || (k == 0 && wv == 0) || (k == TH + 1 && wv == W - 1)) le[k] = p[(int64_t)k * rsi - 1];
     }
     if (lane == 63) {
 #pragma unroll
       for (int k = k0; k <= k1; ++k)
-        if ((k > 0 && k <= TH) || (k == 0 && wv == 0) || (k == TH + 1 && wv == W - 1)) ri[k] = p[(int64_t)k * N2 + 4];
+        if ((k > 0 && k <= TH) || (k == 0 && wv == 0) || (k == TH + 1 && wv == W - 1)) ri[k] = p[(int64_t)k * rsi + 4];
     }
 #pragma unroll
     for (int k = k0; k <= k1; ++k) {
@@ -453,7 +456,7 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
         R[TH + 1] = sr[0][wv + 1][lane];
       }
     }
-    float *q = out + (int64_t)r0 * N2 + c;
+    float *q = out + (int64_t)r0 * rso + c;
 #pragma unroll
     for (int k = 1; k <= TH; ++k) {
       const f4 up = v[k - 1], cu = v[k], dn = v[k + 1];
@@ -487,16 +490,16 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
         }
       }
       const f4 ov = {o[0], o[1], o[2], o[3]};
-      __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q + (int64_t)(k - 1) * N2));
+      __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q + (int64_t)(k - 1) * rso));
     }
     return;
   }
   // rows up to t1 are read (t1 itself is the halo below the tile's last row);
   // rows outside the array or past t1 read as zero and are never used
 #pragma unroll
-  for (int k = 1; k <= TH; ++k) load_row(in, r0 - 1 + k, t1, c, N1, N2, true, v[k], L[k], R[k]);
-  if (wv == 0) load_row(in, r0 - 1, t1, c, N1, N2, true, v[0], L[0], R[0]);
-  if (wv == W - 1) load_row(in, r0 + TH, t1, c, N1, N2, true, v[TH + 1], L[TH + 1], R[TH + 1]);
+  for (int k = 1; k <= TH; ++k) load_row(in, rsi, r0 - 1 + k, t1, c, N1, N2, true, v[k], L[k], R[k]);
+  if (wv == 0) load_row(in, rsi, r0 - 1, t1, c, N1, N2, true, v[0], L[0], R[0]);
+  if (wv == W - 1) load_row(in, rsi, r0 + TH, t1, c, N1, N2, true, v[TH + 1], L[TH + 1], R[TH + 1]);
   sv[0][wv][lane] = v[1];
   sv[1][wv][lane] = v[TH];
   if (OP == 2) {
@@ -524,16 +527,17 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
   for (int k = 1; k <= TH; ++k) {
     const int i = r0 + k - 1;
     if (i >= t1) break;
-    strip_row<OP>(i, c, N1, N2, B, v[k - 1], v[k], v[k + 1], L[k - 1], R[k - 1], L[k], R[k], L[k + 1], R[k + 1], Wt,
+    strip_row<OP>(i, c, N1, N2, rso, B, v[k - 1], v[k], v[k + 1], L[k - 1], R[k - 1], L[k], R[k], L[k + 1], R[k + 1], Wt,
                   out, true);
   }
 }
 
 template <int W, int TH, int OP, bool VEC>
 __device__ inline void dev_stack_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef9 &Wt) {
-  const ArrDev &ai = A[B.ain];
-  dev_stack_tile_p<W, TH, OP, VEC>(B, lt, reinterpret_cast<const float *>(ai.buf[B.dev]),
-                                   reinterpret_cast<float *>(A[B.aout].buf[B.dev]), (int)ai.n[1], (int)ai.n[2], Wt);
+  const ArrDev &ai = A[B.ain], &ao = A[B.aout];
+  dev_stack_tile_p<W, TH, OP, VEC>(B, lt, reinterpret_cast<const float *>(ai.buf[B.dev]), ai.rs[B.dev],
+                                   reinterpret_cast<float *>(ao.buf[B.dev]), ao.rs[B.dev], (int)ai.n[1], (int)ai.n[2],
+                                   Wt);
 }
 
 

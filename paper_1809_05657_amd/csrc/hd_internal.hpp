@@ -35,14 +35,28 @@ struct Ivl {
   uint64_t holders;
 };
 
+// Endpoint e's buffer holds a window of the array (every element e ever
+// holds or its kernels read lies inside it): element (p, r, c) sits at
+// buf[e] + (p * ps[e] + r * rs[e] + c) * esize, buf[e] being the window's
+// origin shifted back to global (0, 0, 0).  A window is either the whole
+// array with the dense strides (rs = n2, ps = n1 * n2; the default, and
+// always for 3-D arrays) or a box whose first column and row stride are
+// multiples of 4 elements; either way a float4 at a column that is a
+// multiple of 4 is aligned when rs is a multiple of 4.  [63] = the host
+// buffer (pinned, device-mapped, full extent).
 struct ArrDev {
   int64_t n[3];
   int32_t esize;
   int32_t cap;
   Ivl *ivl;
   int32_t *cnt;
-  char *buf[64];  // endpoint buffers; [63] = host buffer (pinned, device-mapped)
+  char *buf[64];
+  int64_t rs[64];  // row stride (elements)
+  int64_t ps[64];  // plane stride (elements)
 };
+
+// Element offset of (p, r, c) in endpoint e's buffer.
+#define HD_EOFF(a, e, p, r, c) ((int64_t)(p) * (a).ps[e] + (int64_t)(r) * (a).rs[e] + (int64_t)(c))
 
 // A use segment of one row for destination dst, or a def segment of device
 // dst (flags bit 0: the host also holds the value afterwards, for Write).
@@ -177,6 +191,7 @@ struct StackArgs {
   int64_t tile0[kArgBoxes];
   const float *in[kArgBoxes];
   float *out[kArgBoxes];
+  int64_t rsi[kArgBoxes], rso[kArgBoxes];  // row strides of the input and output buffers
 };
 
 // Per-call constant data uploaded once per plan.

@@ -81,7 +81,17 @@ struct hd_array {
   std::string sym;
   char *host;
   char *host_dev;
-  char *buf[kMaxDev];
+  // per device: a window of the array (a box covering every element the
+  // device ever holds or its kernels read).  mem: the allocation; buf: the
+  // window's origin shifted back to element (0, 0, 0), the address kernels
+  // index with p * ps + r * rs + c.  A full window (wfull) is the whole array
+  // with the dense strides n2 / n1 * n2; other windows start at a column that
+  // is a multiple of 4 and have a row stride that is a multiple of 4.
+  char *buf[kMaxDev] = {};
+  char *mem[kMaxDev] = {};
+  int64_t wlo[kMaxDev][3] = {}, whi[kMaxDev][3] = {};
+  int64_t rs[kMaxDev] = {}, ps[kMaxDev] = {};
+  bool wfull[kMaxDev] = {};
   Ivl *ivl;
   int32_t *cnt;
   int cap;
@@ -209,6 +219,11 @@ struct Runtime {
   int jacobi_rows = 0;   // HD_JACOBI_ROWS / HD_JACOBI_WAVES fix the stencil tile shape;
   int jacobi_waves = 0;  // otherwise it is tuned per work-box geometry
   int s3d_seg = 0;       // planes per wave of the 3-D stencil kernels (0: default)
+  // buffer windows: whole arrays by default (measured faster for the 2-D
+  // stencils); --hd-windows=compact keeps per device only a box around what
+  // it holds or reads (column origin and row stride multiples of win_align)
+  bool win_full = true;
+  int win_align = 4;
   std::map<std::vector<int64_t>, struct TuneState> tunes;
   std::vector<hd_array *> arrays;
   std::vector<Partition> parts;
@@ -327,23 +342,86 @@ static int push_arrdev(hd_array *a) {
   d.cap = a->cap;
   d.ivl = a->ivl;
   d.cnt = a->cnt;
-  for (int e = 0; e < kMaxDev; ++e) d.buf[e] = a->buf[e];
+  for (int e = 0; e < kMaxDev; ++e) {
+    d.buf[e] = a->buf[e];
+    d.rs[e] = a->buf[e] ? a->rs[e] : a->n[2];
+    d.ps[e] = a->buf[e] ? a->ps[e] : a->n[1] * a->n[2];
+  }
   d.buf[kHost] = a->host_dev;
+  d.rs[kHost] = a->n[2];
+  d.ps[kHost] = a->n[1] * a->n[2];
   HIPCK(hipMemcpyAsync(R.d_arrs + a->id, &d, sizeof(ArrDev), hipMemcpyHostToDevice, R.meta));
   HIPCK(hipStreamSynchronize(R.meta));
   return HD_OK;
 }
 
-static int ensure_buf(hd_array *a, int dev) {
-  if (dev == kHost || a->buf[dev]) return HD_OK;
-  // the meta stream may be reading the table entry; order the update after it
-  HIPCK(hipStreamSynchronize(R.meta));
-  HIPCK(hipStreamSynchronize(R.data));
-  void *p = dalloc((size_t)a->N * a->esize);
+// Make device dev's window of a cover [lo, hi) (clipped to the array), or
+// the whole array with dense strides when full (3-D arrays always: the 3-D
+// stencil, its adjoint and the matmul index with the array's extents).  A
+// window only grows: the new one is the union of the old and the request,
+// the old contents are copied over and the old allocation freed.  Kernels
+// in flight may use the old buffer, so the device is drained first.
+static int ensure_window(hd_array *a, int dev, const int64_t *lo, const int64_t *hi, bool full) {
+  if (dev < 0 || dev >= kMaxDev) return HD_OK;
+  if (a->n[0] > 1 || R.win_full) full = true;
+  if (a->wfull[dev]) return HD_OK;
+  int64_t nlo[3], nhi[3];
+  for (int q = 0; q < 3; ++q) {
+    nlo[q] = full ? 0 : std::max<int64_t>(lo[q], 0);
+    nhi[q] = full ? a->n[q] : std::min<int64_t>(hi[q], a->n[q]);
+    if (nlo[q] >= nhi[q]) return HD_OK;  // nothing to hold
+  }
+  if (a->mem[dev]) {
+    bool inside = !full;
+    for (int q = 0; q < 3; ++q) {
+      if (nlo[q] < a->wlo[dev][q] || nhi[q] > a->whi[dev][q]) inside = false;
+      nlo[q] = std::min(nlo[q], a->wlo[dev][q]);
+      nhi[q] = std::max(nhi[q], a->whi[dev][q]);
+    }
+    if (inside) return HD_OK;
+  }
+  int64_t rs, ps;
+  if (full) {
+    rs = a->n[2];
+    ps = a->n[1] * a->n[2];
+  } else {
+    const int64_t g = R.win_align;
+    nlo[2] = nlo[2] / g * g;
+    rs = (nhi[2] - nlo[2] + g - 1) / g * g;
+    ps = rs * (nhi[1] - nlo[1]);
+  }
+  const size_t es = a->esize;
+  const size_t bytes = (size_t)((nhi[0] - nlo[0]) * ps) * es;
+  HIPCK(hipDeviceSynchronize());
+  char *p = (char *)dalloc(bytes);
   if (!p) return fail(HD_ENOMEM);
-  HIPCK(hipMemset(p, 0, (size_t)a->N * a->esize));
-  a->buf[dev] = (char *)p;
+  HIPCK(hipMemset(p, 0, bytes));
+  char *org = (char *)((uintptr_t)p - (uintptr_t)((nlo[0] * ps + nlo[1] * rs + nlo[2]) * (int64_t)es));
+  if (a->mem[dev]) {
+    const int64_t *ol = a->wlo[dev], *oh = a->whi[dev];
+    const int64_t ors = a->rs[dev], ops = a->ps[dev];
+    for (int64_t q = ol[0]; q < oh[0]; ++q)
+      HIPCK(hipMemcpy2D(org + (q * ps + ol[1] * rs + ol[2]) * es, rs * es,
+                        a->buf[dev] + (q * ops + ol[1] * ors + ol[2]) * es, ors * es, (oh[2] - ol[2]) * es,
+                        oh[1] - ol[1], hipMemcpyDeviceToDevice));
+    HIPCK(hipDeviceSynchronize());
+    dfree(a->mem[dev]);
+  }
+  a->mem[dev] = p;
+  a->buf[dev] = org;
+  for (int q = 0; q < 3; ++q) {
+    a->wlo[dev][q] = nlo[q];
+    a->whi[dev][q] = nhi[q];
+  }
+  a->rs[dev] = rs;
+  a->ps[dev] = ps;
+  a->wfull[dev] = full;
   return push_arrdev(a);
+}
+
+static int ensure_full(hd_array *a, int dev) {
+  const int64_t z[3] = {0, 0, 0};
+  return ensure_window(a, dev, z, a->n, true);
 }
 
 // ------------------------------------------------------------- init/exit
@@ -356,6 +434,8 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
       int c = atoi(argv[i] + 13);
       if (c >= 4 && c <= kMaxCap) R.row_cap = c;
     }
+    if (argv[i] && !strcmp(argv[i], "--hd-windows=compact")) R.win_full = false;
+    if (argv[i] && !strcmp(argv[i], "--hd-windows=full")) R.win_full = true;
   }
   if (const char *e = getenv("HD_SERIAL")) R.serial = atoi(e) != 0;
   if (const char *e = getenv("HD_FUSED_META")) R.fused = atoi(e) != 0;
@@ -433,7 +513,7 @@ extern "C" void hdarray_exit(void) {
   free_batches();
   for (hd_array *a : R.arrays) {
     if (!a) continue;
-    for (int e = 0; e < kMaxDev; ++e) dfree(a->buf[e]);
+    for (int e = 0; e < kMaxDev; ++e) dfree(a->mem[e]);
     dfree(a->ivl);
     dfree(a->cnt);
     (void)hipHostFree(a->host);
@@ -1885,8 +1965,11 @@ static int enqueue_user(Plan *pl, const float *coef) {
         a.hi1[i] = hb[i].hi[1];
         a.hi2[i] = hb[i].hi[2];
         a.tile0[i] = hb[i].tile0;
-        a.in[i] = reinterpret_cast<const float *>(R.arrays[hb[i].ain]->buf[hb[i].dev]);
-        a.out[i] = reinterpret_cast<float *>(R.arrays[hb[i].aout]->buf[hb[i].dev]);
+        const hd_array *xi = R.arrays[hb[i].ain], *xo = R.arrays[hb[i].aout];
+        a.in[i] = reinterpret_cast<const float *>(xi->buf[hb[i].dev]);
+        a.out[i] = reinterpret_cast<float *>(xo->buf[hb[i].dev]);
+        a.rsi[i] = xi->rs[hb[i].dev];
+        a.rso[i] = xo->rs[hb[i].dev];
       }
       const int op = pl->ukind == 1 ? 0 : pl->ukind == 5 ? 1 : 2;
       HIPCK(launch_stack_args(op, th, a, pl->ntj[q], coef, R.data));
@@ -2006,16 +2089,44 @@ static int prepare_call(const Kernel &k, int part, const std::vector<hd_array *>
         arg_region(k, part, i, c.a, 1, d, pt.lo[d], pt.hi[d], c.def[d]);
       }
     }
-  // every device touching an array gets its buffer
+  // every device touching an array gets a window covering its use and def
+  // sections; the 2-D stencils also read, unused, the columns of their last
+  // 256-column tile past the box, and the matmul and 3-D stencil index whole
+  // arrays
+  const bool stencil2d = k.builtin == 1 || k.builtin == 5 || k.builtin == 6;
+  const bool whole = k.builtin == 3 || k.builtin == 4;
   for (auto &c : cas)
-    for (int d = 0; d < kMaxDev; ++d)
-      if (!c.use[d].empty() || !c.def[d].empty())
-        if (ensure_buf(c.a, d) != HD_OK) return g_last_error;
-  for (int d = 0; d < pt.ndev; ++d) {
-    if (part_dev_empty(pt, d)) continue;
-    for (hd_array *a : A)
-      if (ensure_buf(a, d) != HD_OK) return g_last_error;
-  }
+    for (int d = 0; d < kMaxDev; ++d) {
+      int64_t lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, hi[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
+      auto add = [&](const int64_t *l, const int64_t *h) {
+        for (int q = 0; q < 3; ++q) {
+          lo[q] = std::min(lo[q], l[q]);
+          hi[q] = std::max(hi[q], h[q]);
+        }
+      };
+      for (const auto *v : {&c.use[d], &c.def[d]})
+        for (const Shape &sh : *v) {
+          if (sh.kind == 0) {
+            add(sh.lo, sh.hi);
+          } else {
+            const int64_t l[3] = {0, sh.c[0], std::min(sh.c[1], sh.c[5])};
+            const int64_t h[3] = {1, sh.c[4] + 1, std::max(sh.c[3], sh.c[7]) + 1};
+            add(l, h);
+          }
+        }
+      const bool box = d < pt.ndev && !part_dev_empty(pt, d);
+      if (box) {
+        add(pt.lo[d], pt.hi[d]);
+        if (stencil2d) {
+          const int64_t w = pt.hi[d][2] - pt.lo[d][2];
+          const int64_t l[3] = {pt.lo[d][0], pt.lo[d][1] - 1, pt.lo[d][2] - 1};
+          const int64_t h[3] = {pt.hi[d][0], pt.hi[d][1] + 1, pt.lo[d][2] + (w + 255) / 256 * 256 + 4};
+          add(l, h);
+        }
+      }
+      if (lo[0] == INT64_MAX) continue;
+      if (ensure_window(c.a, d, lo, hi, whole) != HD_OK) return g_last_error;
+    }
   const int kind = user_kind(k.builtin);
   for (int d = 0; d < pt.ndev; ++d) {
     if (part_dev_empty(pt, d)) continue;
@@ -2210,7 +2321,7 @@ static Plan *io_plan(int op, int part, hd_array *a) {
   }
   cas[0].def_flags = op == 2 ? 1 : 0;
   for (int d : devs)
-    if (ensure_buf(a, d) != HD_OK) return nullptr;
+    if (ensure_window(a, d, pt.lo[d], pt.hi[d], false) != HD_OK) return nullptr;
   Plan *pl = new Plan();
   if (build_plan(cas, pl) != HD_OK) {
     plan_free(pl);
@@ -2271,8 +2382,9 @@ extern "C" int hdarray_write(hd_array_t *ah, const void *uA, int part) {
       const size_t pitch = a->n[2] * es, w = (hi[2] - lo[2]) * es, rows = hi[1] - lo[1];
       for (size_t r = 0; r < rows; ++r)
         memcpy(a->host + (base + r * a->n[2]) * es, (const char *)uA + (base + r * a->n[2]) * es, w);
-      HIPCK(hipMemcpy2DAsync(a->buf[d] + base * es, pitch, a->host + base * es, pitch, w, rows,
-                             hipMemcpyHostToDevice, R.data));
+      char *dst = a->buf[d] + (p * a->ps[d] + lo[1] * a->rs[d] + lo[2]) * (int64_t)es;
+      HIPCK(hipMemcpy2DAsync(dst, a->rs[d] * es, a->host + base * es, pitch, w, rows, hipMemcpyHostToDevice,
+                             R.data));
     }
   }
   // GDEF: definitions by each device with the host as a second holder; no
@@ -2448,11 +2560,14 @@ extern "C" int hdarray_debug_device_buffer(hd_array_t *ah, int dev, void *out) {
     memcpy(out, a->host, (size_t)a->N * a->esize);
     return HD_OK;
   }
-  if (!a->buf[dev]) {
-    memset(out, 0, (size_t)a->N * a->esize);
-    return HD_OK;
-  }
-  HIPCK(hipMemcpy(out, a->buf[dev], (size_t)a->N * a->esize, hipMemcpyDeviceToHost));
+  const size_t es = a->esize;
+  memset(out, 0, (size_t)a->N * es);
+  if (!a->buf[dev]) return HD_OK;
+  const int64_t *lo = a->wlo[dev], *hi = a->whi[dev];
+  for (int64_t p = lo[0]; p < hi[0]; ++p)
+    HIPCK(hipMemcpy2D((char *)out + ((p * a->n[1] + lo[1]) * a->n[2] + lo[2]) * es, a->n[2] * es,
+                      a->buf[dev] + (p * a->ps[dev] + lo[1] * a->rs[dev] + lo[2]) * es, a->rs[dev] * es,
+                      (hi[2] - lo[2]) * es, hi[1] - lo[1], hipMemcpyDeviceToHost));
   return HD_OK;
 }
 
@@ -2462,7 +2577,7 @@ extern "C" void *hdarray_device_ptr(hd_array_t *ah, int dev) {
     fail(HD_EINVAL);
     return nullptr;
   }
-  if (ensure_buf(a, dev) != HD_OK) return nullptr;
+  if (ensure_full(a, dev) != HD_OK) return nullptr;
   return a->buf[dev];
 }
 
@@ -2779,7 +2894,7 @@ extern "C" int hdarray_apply_adjoint(const char *kname, int part, hd_array_t *di
       arg_region(*k, part, 1, u, 0, d, pt.lo[d], pt.hi[d], cas[0].use[d]);
       cas[0].def[d].push_back(part_shape(pt, d));
       for (hd_array *a : {din, dout, u})
-        if (ensure_buf(a, d) != HD_OK) return g_last_error;
+        if (ensure_full(a, d) != HD_OK) return g_last_error;
       WorkBox w{};
       w.dev = d;
       w.kind = 3;
