@@ -82,11 +82,12 @@ def pmc_means(folder, counter):
 # algorithmic bytes per launch of the kernels whose traffic is summarised
 TRAFFIC_WORKLOADS = {
     "jacobi2d_8192": {"workload": "jacobi_large (8192x8192 fp32, 16 devices 4x4, ping-pong); every tile shape the "
-                                  "runtime tries", "sources": KERNEL_SOURCES, "bytes": 8 * 8192 * 8192,
+                                  "runtime tries", "sources": KERNEL_SOURCES,
+                      "bytes": {k: 8 * 8192 * 8192 for k in ("k_stack_a", "k_stack", "k_jacobi1", "k_strip")},
                       "bench": "python3 bench.py --steps 20 --warmup 3 --no-cpu-baseline --headline-only"},
     "stencil3d_512": {"workload": "stencil3d 512^3 fp32, 8 devices (2x2x2), T=64, checkpoint every 8: forward and "
                                   "adjoint steps", "sources": S3D_SOURCES,
-                      "bytes": {"k_s3d": 8 * 512 ** 3, "adjoint_step": 12 * 512 ** 3},
+                      "bytes": {"k_s3d": 8 * 512 ** 3, "k_s3d_adj": 12 * 512 ** 3, "adjoint_step": 12 * 512 ** 3},
                       "adjoint_step": ["k_rev_pack", "k_s3d_adj", "k_unpack_add"],
                       "bench": "python3 bench.py --workload stencil3d"},
 }
@@ -108,17 +109,18 @@ def traffic_summary(name, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir):
            "copy_calibration": {"fetch_factor": ff, "write_factor": fw,
                                 "fetch_kib_per_dispatch": cf / 1024.0, "write_kib_per_dispatch": cw / 1024.0}}
     for k in sorted(set(fet) & set(wri)):
-        if not k.startswith("k_") or k.startswith(("k_runs", "k_tail", "k_gdef", "k_band", "k_heads", "k_compact")):
+        if not k.startswith("k_") or k.startswith(("k_runs", "k_tail", "k_gdef", "k_band", "k_heads", "k_compact", "k_init",
+                                                        "k_mat", "k_bcast")):
             continue
         hb = fet[k][0] * 1024.0 * ff + wri[k][0] * 1024.0 * fw
         rec = {"fetch_kib_per_dispatch": fet[k][0], "write_kib_per_dispatch": wri[k][0],
                "dispatches": [fet[k][1], wri[k][1]], "hbm_bytes_per_launch": hb}
-        alg = w["bytes"] if isinstance(w["bytes"], int) else w["bytes"].get(k.split("<")[0])
+        alg = w["bytes"].get(k.split("<")[0])
         if alg:
             rec["traffic_over_algorithmic"] = hb / alg
-        out["kernels"][k.split("<")[0] if not isinstance(w["bytes"], int) else k] = rec
+        out["kernels"][k] = rec
     if "adjoint_step" in w:
-        parts = [k for k in out["kernels"] if k in w["adjoint_step"]]
+        parts = [k for k in out["kernels"] if k.split("<")[0] in w["adjoint_step"]]
         if len(parts) == len(w["adjoint_step"]):
             hb = sum(out["kernels"][k]["hbm_bytes_per_launch"] for k in parts)
             out["kernels"]["adjoint_step"] = {"hbm_bytes_per_launch": hb, "of": parts,

@@ -8,13 +8,16 @@
 // one (owner, holders) state each; adjacent intervals always differ, so the
 // list of a row is unique.  The list of row g lives at ivl[g*cap .. g*cap+cnt[g]).
 //
-// Bands: the host keeps, per array, plane and row breakpoints between which
-// every row is known to hold the same list.  A call's derivation works on
-// cells (a band of planes x a band of rows on which the call's use and def
-// sections are uniform too): one slice per cell with use sections, read
-// from the cell's first row (its representative), and one GDEF update per
-// cell, written to the representative and then copied to the cell's other
-// rows.  So the work of a call is proportional to its sections, not to rows.
+// Bands: the host keeps, per array, plane and row breakpoints; the rows of
+// a band (planes [pbrk[i], pbrk[i+1]) x rows [rbrk[k], rbrk[k+1])) all have
+// the list stored at the band's first row, its representative (the other
+// rows' storage is stale unless the array was last used row by row).  A
+// call's derivation works on cells (a band of planes x a band of rows on
+// which the arrays' bands and the call's use and def sections are uniform):
+// one slice per cell with use sections, read from the cell's first row, and
+// one GDEF update per cell, written to that row only; a cell that does not
+// start a band first gets its band's list copied to its first row.  So the
+// work of a call is proportional to its sections, not to rows.
 #pragma once
 #include <stdint.h>
 
@@ -132,8 +135,18 @@ struct RepRec {
 };
 
 // One task of the GDEF update: rows [k0, k0 + kCellChunk) (clipped) of the
-// cell of record t, rows numbered row-major over the cell's planes x rows.
+// cell of record t, rows numbered row-major over the cell's planes x rows
+// (plan instances: one task per cell, its first row).
 constexpr int kCellChunk = 32;
+
+// A band list copied from one row to another of the same array before a
+// derivation (src: the band's representative, dst: the first row of a cell
+// that splits the band).
+struct MatRec {
+  int32_t arr;
+  int32_t pad;
+  int64_t src, dst;
+};
 struct GTask {
   int32_t t;
   int32_t k0;

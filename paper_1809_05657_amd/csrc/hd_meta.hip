@@ -229,6 +229,19 @@ __global__ __launch_bounds__(64) void k_gdef_tasks(PlanDev P, ArrDev *__restrict
   for (int q = blockIdx.x; q < P.ntask; q += gridDim.x) gdef_task(P, A, W, q, S);
 }
 
+// Band lists copied to the first rows of cells that split a band: one
+// wave per record.
+__global__ __launch_bounds__(64) void k_mat(const MatRec *__restrict__ M, int n, ArrDev *__restrict__ A) {
+  const int lane = threadIdx.x & 63;
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const MatRec m = M[q];
+    ArrDev &a = A[m.arr];
+    const int c = a.cnt[m.src];
+    for (int e = lane; e < c; e += 64) a.ivl[m.dst * a.cap + e] = a.ivl[m.src * a.cap + e];
+    if (lane == 0) a.cnt[m.dst] = c;
+  }
+}
+
 // Every row starts as one interval [0, n2) owned and held by the host.
 __global__ void k_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < rows; g += (int64_t)gridDim.x * blockDim.x) {
@@ -239,6 +252,13 @@ __global__ void k_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap) {
 
 // ------------------------------------------------------------- launchers
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_mat(const MatRec *m, int n, ArrDev *A, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mat, dim3(n < 4096 ? n : 4096), dim3(64), 0, s, m, n, A);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_compact(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, MsgHdr *hdr,
                           int64_t cap, int mode, hipStream_t s) {

@@ -56,6 +56,7 @@ hipError_t launch_reduce_scratch(int device, int type, int op, const WorkBox *wb
                                  void **res_dev, hipStream_t s);
 int batch_max_blocks(int max_per_cu);
 hipError_t launch_batch(const BatchArgs &a, int th, int hf, int grid, hipStream_t s);
+hipError_t launch_mat(const MatRec *m, int n, ArrDev *A, hipStream_t s);
 int64_t adj_tiles(const WorkBox &B, const int64_t *n);
 hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const float *coef, double *part,
                           double *cbar, const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg,
@@ -102,8 +103,11 @@ struct hd_array {
   std::vector<uint64_t> hist;
   bool hist_ok = false;
   // GDEF bands: sorted plane / row breakpoints (with 0 and n); all rows of
-  // planes [pbrk[i], pbrk[i+1]) x rows [rbrk[k], rbrk[k+1]) hold the same list
+  // planes [pbrk[i], pbrk[i+1]) x rows [rbrk[k], rbrk[k+1]) have the list
+  // stored at the band's first row (the other rows' storage is stale);
+  // bver counts their changes
   std::vector<int64_t> pbrk, rbrk;
+  uint64_t bver = 0;
 };
 
 struct Partition {
@@ -148,7 +152,12 @@ struct Plan {
   std::map<std::vector<int64_t>, PlanInst *> insts;
   PlanInst *cur = nullptr;
   std::vector<int64_t> cur_key;
-  bool rowwise = false;  // one cell per row whatever the bands (batched plans)
+  // device lists of band copies per (instance, array bands): {records, count}
+  std::map<std::vector<int64_t>, std::pair<void *, int>> mats;
+  // the arrays' band versions at the last selection, and its copy list
+  std::vector<uint64_t> sel_ver;
+  const MatRec *sel_mat = nullptr;
+  int sel_nmat = 0;
   PlanInst *last_inst = nullptr;  // instance of the plan cache's last derivation
   int64_t stg_bound = 0;  // bytes
   // user kernel
@@ -1177,7 +1186,6 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
   std::vector<Seg> useg, dseg, us, ds;
   std::vector<SliceRec> srec;
   std::vector<GRowRec> grec;
-  std::vector<RepRec> rep;
   std::vector<GTask> tasks;
   PlanInst *in = new PlanInst();
   PlanDev &P = in->P;
@@ -1247,11 +1255,7 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
         }
         dseg.insert(dseg.end(), ds.begin(), ds.end());
         g.full = full ? 1 : 0;
-        g.rep = -1;
-        if ((pe - pa) * (re - ra) > 1) {
-          g.rep = (int32_t)rep.size();
-          rep.push_back(RepRec{(int32_t)a->id, (int32_t)pa, (int32_t)pe, (int32_t)ra, (int32_t)re, 0, grow});
-        }
+        g.rep = -1;  // the update writes the cell's first row only
         grec.push_back(g);
       }
     }
@@ -1294,16 +1298,9 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
     }
     P.gdef_lane = rest > 0 && small * 10 >= rest * 9 ? 1 : 0;
   }
-  P.nrep = (int32_t)rep.size();
-  // update tasks: kCellChunk rows of one cell each (after the reordering)
-  for (size_t t = 0; t < grec.size(); ++t) {
-    int64_t rows = 1;
-    if (grec[t].rep >= 0) {
-      const RepRec &r = rep[grec[t].rep];
-      rows = (int64_t)(r.p1 - r.p0) * (r.r1 - r.r0);
-    }
-    for (int64_t k0 = 0; k0 < rows; k0 += kCellChunk) tasks.push_back(GTask{(int32_t)t, (int32_t)k0});
-  }
+  P.nrep = 0;
+  // update tasks: one per cell (after the reordering)
+  for (size_t t = 0; t < grec.size(); ++t) tasks.push_back(GTask{(int32_t)t, 0});
   P.ntask = (int32_t)tasks.size();
   // one device allocation for all instance arrays
   std::vector<char> blob;
@@ -1315,7 +1312,7 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
   size_t o_ga = push_blob(blob, grp_aidx), o_gp = push_blob(blob, grp_plane);
   size_t o_g2 = push_blob(blob, grp2), o_p2 = push_blob(blob, pos2), o_pe2 = push_blob(blob, pend2);
   size_t o_grec = push_blob(blob, grec), o_ds = push_blob(blob, dseg);
-  size_t o_rep = push_blob(blob, rep), o_task = push_blob(blob, tasks);
+  size_t o_task = push_blob(blob, tasks);
   in->mem = dalloc(blob.size());
   if (!in->mem) {
     delete in;
@@ -1339,7 +1336,7 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
   P.pend2 = (const int32_t *)(b + o_pe2);
   P.grec = (const GRowRec *)(b + o_grec);
   P.dseg = (const Seg *)(b + o_ds);
-  P.rep = (const RepRec *)(b + o_rep);
+  P.rep = nullptr;
   P.task = (const GTask *)(b + o_task);
   if (hipMemcpy(in->mem, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
     free_inst(in);
@@ -1354,26 +1351,99 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
 // most kMaxInst instances; past that the others are dropped (after the
 // streams are idle, so no queued work reads them).
 constexpr size_t kMaxInst = 32;
+static int copy_band_lists(Plan *pl, const std::vector<std::vector<int64_t>> &pb,
+                           const std::vector<std::vector<int64_t>> &qb, const std::vector<int64_t> &ikey,
+                           bool may_build);
+
+// The band copies of the selected instance, then the band versions that
+// let the next selection skip all this while no array's bands change.
+static int select_done(Plan *pl, const std::vector<std::vector<int64_t>> &pb,
+                       const std::vector<std::vector<int64_t>> &qb, const std::vector<int64_t> &key, bool may_build) {
+  if (copy_band_lists(pl, pb, qb, key, may_build) != HD_OK) return g_last_error;
+  for (const CallArray &ca : pl->cas) pl->sel_ver.push_back(ca.a->bver);
+  return HD_OK;
+}
+
+// The stream of the metadata work (the data stream in serial mode).
+static hipStream_t meta_stream() { return R.serial ? R.data : R.meta; }
+
+// A cell of the instance that does not start one of its array's bands
+// reads and writes its own first row, so the band's list is copied there
+// first: the copies are queued on the metadata stream ahead of the call's
+// derivation and GDEF update (repeating them is harmless: they read band
+// representatives, which nothing in between writes).  Their device lists
+// are kept per (instance, array bands); none are needed once the arrays'
+// bands are the instance's, as in a repeated call.
+static int copy_band_lists(Plan *pl, const std::vector<std::vector<int64_t>> &pb,
+                           const std::vector<std::vector<int64_t>> &qb, const std::vector<int64_t> &ikey,
+                           bool may_build) {
+  std::vector<MatRec> mat;
+  std::vector<int64_t> key = ikey;
+  for (size_t j = 0; j < pl->cas.size(); ++j) {
+    const hd_array *a = pl->cas[j].a;
+    for (size_t ip = 0; ip + 1 < pb[j].size(); ++ip) {
+      const int64_t pa = pb[j][ip];
+      const int64_t pband = *(std::upper_bound(a->pbrk.begin(), a->pbrk.end(), pa) - 1);
+      for (size_t ir = 0; ir + 1 < qb[j].size(); ++ir) {
+        const int64_t ra = qb[j][ir];
+        const int64_t rband = *(std::upper_bound(a->rbrk.begin(), a->rbrk.end(), ra) - 1);
+        if (pband != pa || rband != ra)
+          mat.push_back(MatRec{(int32_t)a->id, 0, pband * a->n[1] + rband, pa * a->n[1] + ra});
+      }
+    }
+    key.push_back(-3);
+    key.insert(key.end(), a->pbrk.begin(), a->pbrk.end());
+    key.push_back(-4);
+    key.insert(key.end(), a->rbrk.begin(), a->rbrk.end());
+  }
+  pl->sel_mat = nullptr;
+  pl->sel_nmat = 0;
+  if (mat.empty()) return HD_OK;
+  auto it = pl->mats.find(key);
+  if (it == pl->mats.end()) {
+    if (!may_build) return fail(HD_ENOPLAN);
+    if (pl->mats.size() >= kMaxInst) {
+      // queued copies may still read the lists
+      HIPCK(hipStreamSynchronize(R.meta));
+      HIPCK(hipStreamSynchronize(R.data));
+      for (auto &kv : pl->mats) dfree(kv.second.first);
+      pl->mats.clear();
+    }
+    void *m = dalloc(sizeof(MatRec) * mat.size());
+    if (!m) return fail(HD_ENOMEM);
+    HIPCK(hipMemcpy(m, mat.data(), sizeof(MatRec) * mat.size(), hipMemcpyHostToDevice));
+    it = pl->mats.emplace(key, std::make_pair(m, (int)mat.size())).first;
+  }
+  pl->sel_mat = (const MatRec *)it->second.first;
+  pl->sel_nmat = it->second.second;
+  HIPCK(launch_mat(pl->sel_mat, pl->sel_nmat, R.d_arrs, meta_stream()));
+  return HD_OK;
+}
+
 static int select_inst(Plan *pl, bool may_build = true) {
-  if (pl->rowwise && pl->cur) return HD_OK;
   const size_t nc = pl->cas.size();
+  // no array's bands changed since the last selection: same instance, same copies
+  if (pl->cur && pl->sel_ver.size() == nc) {
+    bool same = true;
+    for (size_t j = 0; j < nc && same; ++j) same = pl->cas[j].a->bver == pl->sel_ver[j];
+    if (same) {
+      if (pl->sel_nmat > 0) HIPCK(launch_mat(pl->sel_mat, pl->sel_nmat, R.d_arrs, meta_stream()));
+      return HD_OK;
+    }
+  }
   std::vector<std::vector<int64_t>> pb(nc), qb(nc);
   std::vector<int64_t> key;
   for (size_t j = 0; j < nc; ++j) {
     const hd_array *a = pl->cas[j].a;
-    if (pl->rowwise) {
-      for (int64_t p = 0; p <= a->n[0]; ++p) pb[j].push_back(p);
-      for (int64_t r = 0; r <= a->n[1]; ++r) qb[j].push_back(r);
-    } else {
-      pb[j] = merge_breaks(a->pbrk, pl->pbp[j]);
-      qb[j] = merge_breaks(a->rbrk, pl->rbp[j]);
-    }
+    pb[j] = merge_breaks(a->pbrk, pl->pbp[j]);
+    qb[j] = merge_breaks(a->rbrk, pl->rbp[j]);
     key.push_back(-1);
     key.insert(key.end(), pb[j].begin(), pb[j].end());
     key.push_back(-2);
     key.insert(key.end(), qb[j].begin(), qb[j].end());
   }
-  if (pl->cur && key == pl->cur_key) return HD_OK;
+  pl->sel_ver.clear();
+  if (pl->cur && key == pl->cur_key) return select_done(pl, pb, qb, key, may_build);
   PlanInst *in = nullptr;
   auto it = pl->insts.find(key);
   if (it != pl->insts.end()) {
@@ -1398,23 +1468,22 @@ static int select_inst(Plan *pl, bool may_build = true) {
   pl->nsl1 = in->P.nsl1;
   pl->ngrp = in->P.ngrp;
   pl->ngrow = in->P.ngrow;
-  return HD_OK;
+  return select_done(pl, pb, qb, key, may_build);
 }
 
-// After a call's GDEF update: the bands every call-array now holds.  A call
-// that defines the whole array without using it leaves lists that depend
-// only on its definitions (bands: the plan's own); otherwise the old bands
-// are refined by the plan's.
+// After a call's GDEF update: the bands every call-array now holds, the old
+// bands refined by the plan's (the call's cells).  They are never
+// coarsened: a cell's first row holds its list, so a band that merged cells
+// would make the next call copy lists back to the cells' first rows; with
+// refinement only, the bands of arrays that a fixed set of plans touch
+// settle after a few calls and later calls copy nothing.
 static void advance_bands(const Plan *pl) {
   for (size_t j = 0; j < pl->cas.size(); ++j) {
     hd_array *a = pl->cas[j].a;
-    if (pl->ca_full[j]) {
-      a->pbrk = pl->pbp[j];
-      a->rbrk = pl->rbp[j];
-    } else {
-      a->pbrk = merge_breaks(a->pbrk, pl->pbp[j]);
-      a->rbrk = merge_breaks(a->rbrk, pl->rbp[j]);
-    }
+    const size_t np = a->pbrk.size(), nr = a->rbrk.size();
+    a->pbrk = merge_breaks(a->pbrk, pl->pbp[j]);
+    a->rbrk = merge_breaks(a->rbrk, pl->rbp[j]);
+    if (a->pbrk.size() != np || a->rbrk.size() != nr) ++a->bver;
   }
 }
 
@@ -1771,6 +1840,8 @@ static void plan_free(Plan *pl) {
   free_plan_buffers(pl);
   for (auto &kv : pl->insts) free_inst(kv.second);
   pl->insts.clear();
+  for (auto &kv : pl->mats) dfree(kv.second.first);
+  pl->mats.clear();
   dfree(pl->mem);
   dfree(pl->part);
   delete pl;
@@ -2391,7 +2462,7 @@ extern "C" int hdarray_write(hd_array_t *ah, const void *uA, int part) {
   // communication (the plan has no use rows)
   pl->ukind = 0;
   if (select_inst(pl) != HD_OK) return g_last_error;
-  HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, R.meta));
+  HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, meta_stream()));
   advance_hist(pl);
   advance_bands(pl);
   return HD_OK;
@@ -2540,9 +2611,13 @@ extern "C" int hdarray_debug_gdef(hd_array_t *ah, int8_t *owner, uint64_t *holde
   HIPCK(hipMemcpy(cnt.data(), a->cnt, 4 * rows, hipMemcpyDeviceToHost));
   HIPCK(hipMemcpy(iv.data(), a->ivl, sizeof(Ivl) * rows * a->cap, hipMemcpyDeviceToHost));
   for (int64_t g = 0; g < rows; ++g) {
-    const Ivl *L = iv.data() + g * a->cap;
-    for (int i = 0; i < cnt[g]; ++i) {
-      const int64_t e = (i + 1 < cnt[g]) ? L[i + 1].start : a->n[2];
+    // the row's list is stored at its band's first row
+    const int64_t p = g / a->n[1], r = g % a->n[1];
+    const int64_t src = *(std::upper_bound(a->pbrk.begin(), a->pbrk.end(), p) - 1) * a->n[1] +
+                        *(std::upper_bound(a->rbrk.begin(), a->rbrk.end(), r) - 1);
+    const Ivl *L = iv.data() + src * a->cap;
+    for (int i = 0; i < cnt[src]; ++i) {
+      const int64_t e = (i + 1 < cnt[src]) ? L[i + 1].start : a->n[2];
       for (int64_t c = L[i].start; c < e; ++c) {
         if (owner) owner[g * a->n[2] + c] = (int8_t)L[i].owner;
         if (holders) holders[g * a->n[2] + c] = L[i].holders;
@@ -2599,6 +2674,7 @@ struct Batch {
   hipGraphExec_t exec = nullptr;
   int64_t epoch = -1;
   int gth = 0, ghf = 0, ggrid = 0;
+  const PlanInst *ginst = nullptr;  // the plan instance the graph was captured with
 };
 
 static void drop_graph(Batch *b) {
@@ -2613,6 +2689,7 @@ static void free_batches() {
     if (!b) continue;
     drop_graph(b);
     for (auto &kv : b->pl.insts) free_inst(kv.second);
+    for (auto &kv : b->pl.mats) dfree(kv.second.first);
     dfree(b->pl.mem);
     dfree(b->d_wb);
     dfree(b->d_tbox);
@@ -2702,10 +2779,9 @@ extern "C" int hdarray_batch_end(void) {
   }
   R.rec.clear();
   Batch *b = new Batch();
-  // the batch's graph keeps one plan instance, valid for any bands
-  b->pl.rowwise = true;
   if (build_plan(all, &b->pl) != HD_OK) {
     for (auto &kv : b->pl.insts) free_inst(kv.second);
+    for (auto &kv : b->pl.mats) dfree(kv.second.first);
     dfree(b->pl.mem);
     delete b;
     return g_last_error;
@@ -2772,6 +2848,7 @@ static int batch_capture(Batch *b) {
   b->gth = b->th;
   b->ghf = b->hf;
   b->ggrid = b->grid;
+  b->ginst = b->pl.cur;
   return HD_OK;
 }
 
@@ -2779,7 +2856,11 @@ extern "C" int hdarray_batch_run(int id) {
   if (!R.inited || R.recording) return fail(HD_ESTATE);
   if (id < 0 || id >= (int)R.batches.size() || !R.batches[id]) return fail(HD_EINVAL);
   Batch *b = R.batches[id];
-  if (!b->exec || b->epoch != R.ws_epoch || b->gth != b->th || b->ghf != b->hf || b->ggrid != b->grid)
+  // the instance for the arrays' current bands (its band-list copies go
+  // ahead on the metadata stream); the graph holds one instance's records
+  if (select_inst(&b->pl) != HD_OK) return g_last_error;
+  if (!b->exec || b->epoch != R.ws_epoch || b->gth != b->th || b->ghf != b->hf || b->ggrid != b->grid ||
+      b->ginst != b->pl.cur)
     if (batch_capture(b) != HD_OK) return g_last_error;
   // ordered after the metadata work of earlier calls, and before later ones
   HIPCK(hipEventRecord(R.ev_meta, R.meta));
@@ -2968,7 +3049,7 @@ extern "C" int hdarray_write_device(hd_array_t *ah, const void *dptr, int part) 
   // every device's region in one launch (rows of the regions, in device order)
   HIPCK(launch_ext_copy(pl->wbj[2], pl->xn, pl->xrows, R.d_arrs, a->id, const_cast<void *>(dptr), 0, R.data));
   if (select_inst(pl) != HD_OK) return g_last_error;
-  HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, R.meta));
+  HIPCK(launch_gdef(pl->P, R.d_arrs, R.W, meta_stream()));
   advance_hist(pl);
   advance_bands(pl);
   return HD_OK;
