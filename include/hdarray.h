@@ -321,6 +321,7 @@ typedef struct {
   int64_t stencil_order;   /* tile order of the last stencil launch (1 along rows, 0 down columns) */
   int64_t allocs;          /* device and pinned host allocations the library has made */
   int64_t stencil_vec;     /* 1: the last stencil launch read every row as float4; 2: also with its boxes passed by value */
+  int64_t cache_gdef_hits; /* plan-cache misses whose GDEF comparison on the GPU found the table current */
 } hd_stats_t;
 int hdarray_get_stats(hd_stats_t *st);
 
@@ -342,12 +343,17 @@ int hdarray_set_stencil_shape(int rows, int waves, int order);
  * whose arrays all have the GDEF that the call's plan last derived its
  * communication under reuses that plan's message table and runs: the
  * derivation is skipped and only the GDEF update and the data path run.
- * GDEF equality is decided exactly on the host: each array keeps the list
- * of plan updates applied to it since a call that defined all of it without
- * using it, and equal lists give equal GDEF; an array with no such call
- * behind it (or a list longer than 8) never hits.  Each plan gets its own
- * table and run buffers (the workspace's size) on its first cached call.
- * Results equal those with the cache off.  HD_ESTATE before hdarray_init. */
+ * First step, on the host: each array keeps the list of plan updates
+ * applied to it since a call that defined all of it without using it, and
+ * equal lists give equal GDEF (cache_hits).  Second step, when the lists do
+ * not decide (an array with no such call behind it, a list longer than 8,
+ * a different list): for plans of at most 64 cells with use sections, the
+ * GPU compares the lists the call's derivation would read with those the
+ * plan's last derivation read and leaves the derivation out when they are
+ * equal (cache_gdef_hits; such calls also count as cache_misses).  Each
+ * plan gets its own table, run and snapshot buffers on its first cached
+ * call.  Results equal those with the cache off.  HD_ESTATE before
+ * hdarray_init. */
 int hdarray_set_plan_cache(int on);
 
 /* Per-phase device timing with HIP events recorded on the stream each phase

@@ -50,7 +50,7 @@ class Stats(C.Structure):
                 ("total_messages", C.c_int64), ("total_bytes", C.c_int64), ("plans_built", C.c_int64),
                 ("stencil_rows", C.c_int64), ("stencil_waves", C.c_int64),
                 ("cache_hits", C.c_int64), ("cache_misses", C.c_int64), ("stencil_order", C.c_int64),
-                ("allocs", C.c_int64), ("stencil_vec", C.c_int64)]
+                ("allocs", C.c_int64), ("stencil_vec", C.c_int64), ("cache_gdef_hits", C.c_int64)]
 
 
 class Profile(C.Structure):

@@ -865,34 +865,6 @@ __device__ inline void gdef_state(int x, int n, int st, int ow, uint64_t ho, con
 // when the row has more than 64 boundaries; the caller then uses dev_gdef_row.
 // A row the definitions tile (touching spans of one device already merged by
 // the planner): the definitions are the new list.  One lane per row.
-// The rows one GDEF update writes: rows k0 .. k1-1 of a cell (row-major over
-// its planes x rows, k-th row (p0 + k / nr) * n1 + r0 + k % nr).  They hold
-// equal lists before the update and get the same edits, so the update reads
-// the first of them and writes the new list to all.  A record's own row
-// alone: the default.
-struct CellRows {
-  int32_t p0, r0, nr, k0, k1;
-  __device__ int64_t row(int k, int64_t n1) const { return (int64_t)(p0 + k / nr) * n1 + r0 + k % nr; }
-};
-
-__device__ inline CellRows cell_rows(const PlanDev &P, const GRowRec &gr, int64_t n1, int k0) {
-  CellRows c;
-  if (gr.rep < 0) {
-    c.p0 = (int32_t)(gr.grow / n1);
-    c.r0 = (int32_t)(gr.grow % n1);
-    c.nr = 1;
-    c.k0 = 0;
-    c.k1 = 1;
-    return c;
-  }
-  const RepRec r = P.rep[gr.rep];
-  c.p0 = r.p0;
-  c.r0 = r.r0;
-  c.nr = r.r1 - r.r0;
-  c.k0 = k0;
-  c.k1 = min(k0 + kCellChunk, (r.p1 - r.p0) * c.nr);
-  return c;
-}
 
 __device__ inline void dev_gdef_full_lane(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t) {
   const GRowRec gr = P.grec[t];
@@ -1059,16 +1031,11 @@ __device__ inline bool dev_gdef_small_lane(const PlanDev &P, ArrDev *__restrict_
   return true;
 }
 
-__device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t,
-                                         int k0 = -1) {
+__device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t) {
   const int lane = threadIdx.x & 63;
   const GRowRec gr = P.grec[t];
   ArrDev &a = A[gr.arr];
-  // k0 < 0: the record's own row only; else rows k0.. of its cell
-  const CellRows cr = k0 < 0 ? cell_rows(P, GRowRec{gr.arr, gr.slice, gr.dseg0, gr.ndseg, gr.grow, gr.full, -1},
-                                         a.n[1], 0)
-                             : cell_rows(P, gr, a.n[1], k0);
-  const int64_t grow = cr.row(cr.k0, a.n[1]);
+  const int64_t grow = gr.grow;
   Ivl *row = a.ivl + grow * (int64_t)a.cap;
   const Seg *ds = P.dseg + gr.dseg0;
   const int nds = gr.ndseg;
@@ -1090,14 +1057,11 @@ __device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ 
       if (lane == 0) set_err(W.err, -8);
       return true;
     }
-    for (int k = cr.k0; k < cr.k1; ++k) {
-      const int64_t g = cr.row(k, a.n[1]);
-      for (int e = lane; e < nds; e += 64) {
-        const Seg de = e < 64 ? d : ds[e];
-        a.ivl[g * a.cap + e] = Ivl{de.c0, de.dst, (1ull << de.dst) | ((de.flags & 1) ? (1ull << kHost) : 0ull)};
-      }
-      if (lane == 0) a.cnt[g] = nds;
+    for (int e = lane; e < nds; e += 64) {
+      const Seg de = e < 64 ? d : ds[e];
+      row[e] = Ivl{de.c0, de.dst, (1ull << de.dst) | ((de.flags & 1) ? (1ull << kHost) : 0ull)};
     }
+    if (lane == 0) a.cnt[grow] = nds;
     return true;
   }
   const int W2 = (int)a.n[2];
@@ -1153,11 +1117,8 @@ __device__ inline bool dev_gdef_row_fast(const PlanDev &P, ArrDev *__restrict__ 
     if (lane == 0) set_err(W.err, -8);
     return true;
   }
-  for (int k = cr.k0; k < cr.k1; ++k) {
-    const int64_t g = cr.row(k, a.n[1]);
-    if (keep) a.ivl[g * a.cap + idx] = Ivl{b, own, hol};
-    if (lane == 0) a.cnt[g] = nn;
-  }
+  if (keep) row[idx] = Ivl{b, own, hol};
+  if (lane == 0) a.cnt[grow] = nn;
   return true;
 }
 
@@ -1168,14 +1129,11 @@ struct GdefLds {
 };
 
 __device__ inline void dev_gdef_row(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t, GdefLds S,
-                                    int maxb, int k0 = -1) {
+                                    int maxb) {
   const int lane = threadIdx.x & 63;
   const GRowRec gr = P.grec[t];
   ArrDev &a = A[gr.arr];
-  const CellRows cr = k0 < 0 ? cell_rows(P, GRowRec{gr.arr, gr.slice, gr.dseg0, gr.ndseg, gr.grow, gr.full, -1},
-                                         a.n[1], 0)
-                             : cell_rows(P, gr, a.n[1], k0);
-  const int64_t grow = cr.row(cr.k0, a.n[1]);
+  const int64_t grow = gr.grow;
   const int n = a.cnt[grow];
   const int W2 = (int)a.n[2];
   Ivl *row = a.ivl + grow * (int64_t)a.cap;
@@ -1249,28 +1207,24 @@ __device__ inline void dev_gdef_row(const PlanDev &P, ArrDev *__restrict__ A, co
     S.hold[k] = hol;
   }
   wave_lds_sync();
-  // merge equal neighbours and write the new list to every row of the set
+  // merge equal neighbours and write the new list
   int nn = 0;
-  for (int kr = cr.k0; kr < cr.k1; ++kr) {
-    const int64_t g = cr.row(kr, a.n[1]);
-    Ivl *wrow = a.ivl + g * (int64_t)a.cap;
-    nn = 0;
-    for (int base = 0; base < nu; base += 64) {
-      const int k = base + lane;
-      const bool keep = k < nu && (k == 0 || S.own[k] != S.own[k - 1] || S.hold[k] != S.hold[k - 1]);
-      const uint64_t m = __ballot(keep);
-      if (keep) {
-        const int p = nn + __popcll(m & lanemask_lt());
-        if (p < a.cap) wrow[p] = Ivl{S.b[k], S.own[k], S.hold[k]};
-      }
-      nn += __popcll(m);
+  Ivl *wrow = a.ivl + grow * (int64_t)a.cap;
+  for (int base = 0; base < nu; base += 64) {
+    const int k = base + lane;
+    const bool keep = k < nu && (k == 0 || S.own[k] != S.own[k - 1] || S.hold[k] != S.hold[k - 1]);
+    const uint64_t m = __ballot(keep);
+    if (keep) {
+      const int p = nn + __popcll(m & lanemask_lt());
+      if (p < a.cap) wrow[p] = Ivl{S.b[k], S.own[k], S.hold[k]};
     }
-    if (lane == 0) {
-      if (nn > a.cap)
-        set_err(W.err, -8);
-      else
-        a.cnt[g] = nn;
-    }
+    nn += __popcll(m);
+  }
+  if (lane == 0) {
+    if (nn > a.cap)
+      set_err(W.err, -8);
+    else
+      a.cnt[grow] = nn;
   }
   wave_lds_sync();
 }

@@ -100,7 +100,7 @@ struct GRowRec {
   int32_t ndseg;
   int64_t grow;   // global row (plane * n1 + row)
   int32_t full;   // 1: the definitions tile the row and no holders are added
-  int32_t rep;    // the cell's RepRec when it has more than one row, else -1
+  int32_t pad;
 };
 
 struct MsgRec {
@@ -125,20 +125,6 @@ struct MsgHdr {
   int64_t bytes;
 };
 
-// A GDEF cell of more than one row: planes [p0, p1) x rows [r0, r1) of an
-// array; grow is the representative (p0, r0) as a global row.
-struct RepRec {
-  int32_t arr;
-  int32_t p0, p1, r0, r1;
-  int32_t pad;
-  int64_t grow;
-};
-
-// One task of the GDEF update: rows [k0, k0 + kCellChunk) (clipped) of the
-// cell of record t, rows numbered row-major over the cell's planes x rows
-// (plan instances: one task per cell, its first row).
-constexpr int kCellChunk = 32;
-
 // A band list copied from one row to another of the same array before a
 // derivation (src: the band's representative, dst: the first row of a cell
 // that splits the band).
@@ -146,10 +132,6 @@ struct MatRec {
   int32_t arr;
   int32_t pad;
   int64_t src, dst;
-};
-struct GTask {
-  int32_t t;
-  int32_t k0;
 };
 
 // One stacking level: slices with a (group, position) key and an item list.
@@ -235,13 +217,6 @@ struct PlanDev {
   int32_t gdef_lane;  // 1: update the other GDEF rows one per lane first (k_gdef), 0: one wave per row
   const GRowRec *grec;  // [ngrow]
   const Seg *dseg;
-  // cells of more than one row: their other rows take the representative's
-  // list after the update
-  int32_t nrep;
-  const RepRec *rep;
-  // the update as tasks of at most kCellChunk rows of one cell
-  int32_t ntask;
-  const GTask *task;
 };
 
 struct Work {
@@ -258,6 +233,9 @@ struct Work {
   Item *l1out;     // level-1 output (3-D)
   int64_t l1_cap;
   int32_t *err;    // device error word (first error wins)
+  // plan cache, second step: when non-null and *skip is set, the small-form
+  // derivation (runs and message table) is left out; the GDEF update runs
+  const int32_t *skip;
 };
 
 // Arguments of the persistent batched step.

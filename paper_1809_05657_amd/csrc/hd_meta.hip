@@ -167,6 +167,7 @@ __global__ __launch_bounds__(64 * kDerive1Waves) void k_runs1(PlanDev P, const A
   constexpr int kWaveLds = CAP * sizeof(Ivl) + kMaxRunsRow * sizeof(Run);
   __shared__ __align__(16) char s_buf[kDerive1Waves * kWaveLds];
   const int wv = threadIdx.x >> 6;
+  if (W.skip && *W.skip) return;  // the plan's stored runs are current
   // one workgroup: the spill pool can start over here
   if (threadIdx.x == 0) *W.run_top = 0;
   __syncthreads();
@@ -193,9 +194,10 @@ __global__ __launch_bounds__(64 * kDerive1Waves) void k_tail1(PlanDev P, ArrDev 
     int32_t *b = reinterpret_cast<int32_t *>(s_buf + sizeof(Ivl) * kMaxCap);
     GdefLds S{iv, b, b + kGdefMaxB, b + 2 * kGdefMaxB, reinterpret_cast<uint64_t *>(b + 3 * kGdefMaxB)};
     const int nw = (gridDim.x - 1) * kDerive1Waves;
-    for (int q = (blockIdx.x - 1) * kDerive1Waves + wv; q < P.ntask; q += nw) gdef_task(P, A, W, q, S);
+    for (int t = (blockIdx.x - 1) * kDerive1Waves + wv; t < P.ngrow; t += nw) gdef_task(P, A, W, t, S);
     return;
   }
+  if (W.skip && *W.skip) return;  // the plan's stored table is current
   for (int lv = 1; lv <= (has3d ? 2 : 1); ++lv) {
     const Level &L = lv == 1 ? L1 : L2;
     if (L.nsl > 0) {
@@ -211,14 +213,11 @@ __global__ __launch_bounds__(64 * kDerive1Waves) void k_tail1(PlanDev P, ArrDev 
   }
 }
 
-// The GDEF update as tasks of at most kCellChunk rows of one cell, one wave
-// each: the task reads its first row (every row of a cell holds the same
-// list before the update), applies the cell's edits and writes the new list
-// to all its rows, so no task waits for another; rows with more than 64
-// boundaries take the LDS form in the same wave.
-__device__ inline void gdef_task(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int q, GdefLds S) {
-  const GTask tk = P.task[q];
-  if (!dev_gdef_row_fast(P, A, W, tk.t, tk.k0)) dev_gdef_row(P, A, W, tk.t, S, kGdefMaxB, tk.k0);
+// The GDEF update of cell t, one wave: the cell's first row holds its list;
+// the task applies the cell's edits to it in registers, or through LDS when
+// the row has more than 64 boundaries.  No task waits for another.
+__device__ inline void gdef_task(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int t, GdefLds S) {
+  if (!dev_gdef_row_fast(P, A, W, t)) dev_gdef_row(P, A, W, t, S, kGdefMaxB);
 }
 
 __global__ __launch_bounds__(64) void k_gdef_tasks(PlanDev P, ArrDev *__restrict__ A, Work W) {
@@ -226,7 +225,7 @@ __global__ __launch_bounds__(64) void k_gdef_tasks(PlanDev P, ArrDev *__restrict
   __shared__ int32_t s_b[kGdefMaxB], s_u[kGdefMaxB], s_own[kGdefMaxB];
   __shared__ uint64_t s_hold[kGdefMaxB];
   GdefLds S{s_iv, s_b, s_u, s_own, s_hold};
-  for (int q = blockIdx.x; q < P.ntask; q += gridDim.x) gdef_task(P, A, W, q, S);
+  for (int t = blockIdx.x; t < P.ngrow; t += gridDim.x) gdef_task(P, A, W, t, S);
 }
 
 // Band lists copied to the first rows of cells that split a band: one
@@ -242,6 +241,52 @@ __global__ __launch_bounds__(64) void k_mat(const MatRec *__restrict__ M, int n,
   }
 }
 
+// Plan cache, second step (Sec. 4.2: compare the GDEF sections themselves
+// when the history does not decide).  One workgroup; snap holds, per slice
+// of the plan's small-form instance, the list its runs were derived from
+// (kMaxCap entries a slice, scnt the counts).  compare: *skip = 1 when every
+// slice's current list equals its snapshot (the plan's table and runs are
+// then current; *hits counts such calls); otherwise, or without compare,
+// *skip = 0 and the snapshot is refreshed from the current lists, which the
+// call's derivation is about to read.
+__global__ __launch_bounds__(512) void k_snap(PlanDev P, const ArrDev *__restrict__ A, Ivl *__restrict__ snap,
+                                              int32_t *__restrict__ scnt, int32_t *skip, int32_t *hits,
+                                              int compare) {
+  __shared__ int s_diff;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (threadIdx.x == 0) s_diff = compare ? 0 : 1;
+  __syncthreads();
+  if (compare) {
+    bool diff = false;
+    for (int s = wv; s < P.nsl1; s += nw) {
+      const SliceRec r = P.srec[s];
+      const ArrDev &a = A[r.arr];
+      const int n = a.cnt[r.grow];
+      bool d = n != scnt[s];
+      for (int e = lane; !d && e < n; e += 64) {
+        const Ivl x = a.ivl[r.grow * a.cap + e], y = snap[(int64_t)s * kMaxCap + e];
+        d = x.start != y.start || x.owner != y.owner || x.holders != y.holders;
+      }
+      diff = diff || d;
+    }
+    if (diff) s_diff = 1;
+  }
+  __syncthreads();
+  const bool same = s_diff == 0;
+  if (threadIdx.x == 0) {
+    *skip = same ? 1 : 0;
+    if (same) *hits += 1;
+  }
+  if (same) return;
+  for (int s = wv; s < P.nsl1; s += nw) {
+    const SliceRec r = P.srec[s];
+    const ArrDev &a = A[r.arr];
+    const int n = a.cnt[r.grow];
+    for (int e = lane; e < n; e += 64) snap[(int64_t)s * kMaxCap + e] = a.ivl[r.grow * a.cap + e];
+    if (lane == 0) scnt[s] = n;
+  }
+}
+
 // Every row starts as one interval [0, n2) owned and held by the host.
 __global__ void k_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < rows; g += (int64_t)gridDim.x * blockDim.x) {
@@ -252,6 +297,12 @@ __global__ void k_init_rows(Ivl *ivl, int32_t *cnt, int64_t rows, int cap) {
 
 // ------------------------------------------------------------- launchers
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_snap(const PlanDev &P, const ArrDev *A, Ivl *snap, int32_t *scnt, int32_t *skip, int32_t *hits,
+                       bool compare, hipStream_t s) {
+  hipLaunchKernelGGL(k_snap, dim3(1), dim3(512), 0, s, P, A, snap, scnt, skip, hits, compare ? 1 : 0);
+  return hipGetLastError();
+}
 
 hipError_t launch_mat(const MatRec *m, int n, ArrDev *A, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -353,7 +404,7 @@ hipError_t launch_derive1(const PlanDev &P, ArrDev *A, const Work &W, const Leve
     else
       hipLaunchKernelGGL(k_runs1<kMaxCap>, dim3(1), dim3(64 * kDerive1Waves), 0, s, P, A, W);
   }
-  const int gw = gdef && P.ntask > 0 ? (P.ntask + kDerive1Waves - 1) / kDerive1Waves : 0;
+  const int gw = gdef && P.ngrow > 0 ? (P.ngrow + kDerive1Waves - 1) / kDerive1Waves : 0;
   hipLaunchKernelGGL(k_tail1, dim3(1 + (gw < 1024 ? gw : 1024)), dim3(64 * kDerive1Waves), 0, s, P, A, W, L1, L2,
                      out, hdr, cap, P.has3d ? 1 : 0);
   return hipGetLastError();
@@ -371,10 +422,10 @@ hipError_t launch_gdef(const PlanDev &P, ArrDev *A, const Work &W, hipStream_t s
   int32_t *cur2 = W.ovf_cnt + 2 + p, *other2 = W.ovf_cnt + 2 + (1 - p);
   const int nfw = cdiv(P.ngfull, 64);
   const int rest = P.ngrow - P.ngfull;
-  if (P.nrep > 0 || P.ngrow <= 4096) {
-    // cells of several rows, or few cells: one launch of row-chunk tasks
-    if (P.ntask > 0) {
-      const int grid = P.ntask < (1 << 20) ? P.ntask : (1 << 20);
+  if (P.ngrow <= 4096) {
+    // few cells: one launch, one wave per cell
+    {
+      const int grid = P.ngrow;
       hipLaunchKernelGGL(k_gdef_tasks, dim3(grid), dim3(64), 0, s, P, A, W);
     }
     return hipGetLastError();

@@ -57,6 +57,8 @@ hipError_t launch_reduce_scratch(int device, int type, int op, const WorkBox *wb
 int batch_max_blocks(int max_per_cu);
 hipError_t launch_batch(const BatchArgs &a, int th, int hf, int grid, hipStream_t s);
 hipError_t launch_mat(const MatRec *m, int n, ArrDev *A, hipStream_t s);
+hipError_t launch_snap(const PlanDev &P, const ArrDev *A, Ivl *snap, int32_t *scnt, int32_t *skip, int32_t *hits,
+                       bool compare, hipStream_t s);
 int64_t adj_tiles(const WorkBox &B, const int64_t *n);
 hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const float *coef, double *part,
                           double *cbar, const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg,
@@ -189,6 +191,10 @@ struct Plan {
   hipEvent_t ev_ready = nullptr, ev_used = nullptr;
   bool used_pending = false, have = false;
   std::vector<uint64_t> last_key;
+  // second step: the lists the last small-form derivation read, and its instance
+  Ivl *snap = nullptr;
+  int32_t *scnt = nullptr;
+  const PlanInst *snap_inst = nullptr;
   // adjoint plans: extended-box tiles and coefficient partials
   bool adjoint = false;
   double *part = nullptr;
@@ -493,6 +499,8 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   HIPCK(hipMemset(R.counters, 0, 64));
   R.W.run_top = R.counters + 0;
   R.W.err = R.counters + 3;
+  // [8]: the plan cache's second-step verdict of the current call, [9]: its hits
+  R.W.skip = nullptr;
   // [4], [5]: rows listed past the one-lane GDEF update; [6], [7]: rows for
   // the LDS update; each pair alternates between calls
   R.W.ovf_cnt = R.counters + 4;
@@ -1186,7 +1194,6 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
   std::vector<Seg> useg, dseg, us, ds;
   std::vector<SliceRec> srec;
   std::vector<GRowRec> grec;
-  std::vector<GTask> tasks;
   PlanInst *in = new PlanInst();
   PlanDev &P = in->P;
   memset(&P, 0, sizeof(P));
@@ -1255,7 +1262,7 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
         }
         dseg.insert(dseg.end(), ds.begin(), ds.end());
         g.full = full ? 1 : 0;
-        g.rep = -1;  // the update writes the cell's first row only
+        g.pad = 0;
         grec.push_back(g);
       }
     }
@@ -1298,10 +1305,6 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
     }
     P.gdef_lane = rest > 0 && small * 10 >= rest * 9 ? 1 : 0;
   }
-  P.nrep = 0;
-  // update tasks: one per cell (after the reordering)
-  for (size_t t = 0; t < grec.size(); ++t) tasks.push_back(GTask{(int32_t)t, 0});
-  P.ntask = (int32_t)tasks.size();
   // one device allocation for all instance arrays
   std::vector<char> blob;
   size_t o_carr = push_blob(blob, carr);
@@ -1312,7 +1315,6 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
   size_t o_ga = push_blob(blob, grp_aidx), o_gp = push_blob(blob, grp_plane);
   size_t o_g2 = push_blob(blob, grp2), o_p2 = push_blob(blob, pos2), o_pe2 = push_blob(blob, pend2);
   size_t o_grec = push_blob(blob, grec), o_ds = push_blob(blob, dseg);
-  size_t o_task = push_blob(blob, tasks);
   in->mem = dalloc(blob.size());
   if (!in->mem) {
     delete in;
@@ -1336,8 +1338,7 @@ static PlanInst *build_inst(Plan *pl, const std::vector<std::vector<int64_t>> &P
   P.pend2 = (const int32_t *)(b + o_pe2);
   P.grec = (const GRowRec *)(b + o_grec);
   P.dseg = (const Seg *)(b + o_ds);
-  P.rep = nullptr;
-  P.task = (const GTask *)(b + o_task);
+
   if (hipMemcpy(in->mem, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
     free_inst(in);
     fail(HD_EHIP);
@@ -1804,8 +1805,15 @@ static void advance_hist(const Plan *pl) {
 }
 
 // the plan's own table, runs and events (allocated on its first cached call)
+// Snapshot of the lists a plan's small-form derivation last read (the plan
+// cache's second step): one kMaxCap list per slice, at most kDerive1Slices.
+constexpr int kDerive1Slices = 64;
+
 static int plan_buffers(Plan *pl) {
   if (pl->ptab) return HD_OK;
+  pl->snap = (Ivl *)dalloc(sizeof(Ivl) * kMaxCap * kDerive1Slices);
+  pl->scnt = (int32_t *)dalloc(4 * kDerive1Slices);
+  if (!pl->snap || !pl->scnt) return fail(HD_ENOMEM);
   pl->pcap = R.ws_items;
   pl->ptab = (MsgRec *)dalloc(sizeof(MsgRec) * pl->pcap);
   pl->phdr = (MsgHdr *)dalloc(sizeof(MsgHdr));
@@ -1820,6 +1828,11 @@ static int plan_buffers(Plan *pl) {
 }
 
 static void free_plan_buffers(Plan *pl) {
+  dfree(pl->snap);
+  dfree(pl->scnt);
+  pl->snap = nullptr;
+  pl->scnt = nullptr;
+  pl->snap_inst = nullptr;
   dfree(pl->ptab);
   dfree(pl->phdr);
   dfree(pl->pruns);
@@ -1909,6 +1922,18 @@ static int enqueue_cached(Plan *pl, const float *coef) {
       L1.ioff = W.roff;
       L1.icnt = W.rcnt;
       L1.items = W.runs;
+      // second step (Sec. 4.2): the history does not decide, so the slices'
+      // lists are compared on the GPU with those the plan's last derivation
+      // read (same instance); when equal the small-form derivation is left
+      // out and the plan's table and runs are used.  A miss refreshes them.
+      if (R.fused && P.nsl1 <= kDerive1Slices && P.ngrp <= kDerive1Slices) {
+        HIPCK(launch_snap(P, R.d_arrs, pl->snap, pl->scnt, R.counters + 8, R.counters + 9, pl->snap_inst == pl->cur,
+                          meta));
+        pl->snap_inst = pl->cur;
+        W.skip = R.counters + 8;
+      } else {
+        pl->snap_inst = nullptr;
+      }
       HIPCK(derive_and_update(P, W, L1, pl->ptab, pl->phdr, pl->pcap, pl->has3d, meta, pl->ev_ready));
       R.stats.cache_misses++;
     } else {
@@ -2549,6 +2574,12 @@ extern "C" int hdarray_get_stats(hd_stats_t *st) {
   MsgRec *ltab = nullptr;
   MsgHdr *lhdr = nullptr;
   if (R.inited) last_table(&ltab, &lhdr);
+  if (R.inited) {
+    int32_t h = 0;
+    HIPCK(hipStreamSynchronize(R.meta));
+    HIPCK(hipMemcpy(&h, R.counters + 9, 4, hipMemcpyDeviceToHost));
+    st->cache_gdef_hits = h;
+  }
   if (lhdr) {
     if (hipStreamSynchronize(R.meta) != hipSuccess || hipStreamSynchronize(R.data) != hipSuccess)
       return fail(HD_EHIP);

@@ -10,7 +10,7 @@ import pytest
 import oracle as O
 from workloads import programs as prog
 from tests.test_gpu_parity import same_call
-from workloads import S3D_COEFFS
+from workloads import CONV9_WEIGHTS, S3D_COEFFS
 
 pytestmark = pytest.mark.gpu
 
@@ -175,3 +175,39 @@ def test_cache_random_programs(hd, seed):
     assert st["cache_hits"] + st["cache_misses"] == step, st
     for i in range(2):
         assert np.array_equal(rt.read(res[0][i], res[0][2]), orc.read(res[1][i], res[1][2]))
+
+
+@pytest.mark.parametrize("n0,n1,ndev,kind", [(70, 300, 16, prog.BLOCK), (130, 45, 6, prog.ROW)])
+def test_cache_gdef_compare(hd, n0, n1, ndev, kind):
+    """Second step (Sec. 4.2): the convolution's input is never redefined,
+    so its history grows with every call (a new key each call, dropped past
+    8 entries) and the host cannot decide; the GPU compares the input's
+    lists with those the plan's last derivation read, finds them unchanged
+    from the third call on (every halo is held after the first) and reuses
+    the table.  Every call checked against the oracle, which derives."""
+    say(f"case cache gdef compare {n0}x{n1} ndev={ndev} kind={kind}")
+    rng = np.random.default_rng(n0 * 11 + n1)
+    f0 = rng.random((n0, n1), dtype=np.float32)
+    w = [float(x) for x in CONV9_WEIGHTS]
+    rt, orc = hd.Runtime(), O.Oracle()
+    rt.set_plan_cache(True)
+    g = prog.conv2d(rt, f0, ndev, kind)
+    o = prog.conv2d(orc, f0, ndev, kind)
+    calls = 12
+    for it in range(calls):
+        rt.apply("convAB", g[2], [g[0], g[1]], w)
+        orc.apply("convAB", o[2], [o[0], o[1]], w)
+        same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], f"call {it}")
+    st = rt.stats()
+    assert st["cache_hits"] == 0, st
+    assert st["cache_gdef_hits"] == calls - 2, st
+    # a redefinition of the input makes the lists differ again: derived
+    rt.apply("convBA", g[2], [g[1], g[0]], w)
+    orc.apply("convBA", o[2], [o[1], o[0]], w)
+    same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], "redefine")
+    rt.apply("convAB", g[2], [g[0], g[1]], w)
+    orc.apply("convAB", o[2], [o[0], o[1]], w)
+    same_call(rt, orc, [(g[0], o[0]), (g[1], o[1])], "after redefine")
+    assert rt.stats()["cache_gdef_hits"] == calls - 2
+    for i in range(2):
+        assert np.array_equal(rt.read(g[i], g[2]), orc.read(o[i], o[2]))
