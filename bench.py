@@ -542,7 +542,9 @@ def bench_batched(hd, rt, steps, warmup):
             "config": {"workload": "batched: 64 arrays, sides log-uniform [512,4096], 2-32 irregular row "
                                    "partitions, 5-point or lower-triangular stencil, ping-pong",
                        "cells": cells, "plain_steps_per_s": 1.0 / t_plain, "batched_over_plain": t_plain / t_batch,
-                       "autotuned_rows": (cfg >> 8) & 255, "autotuned_row_first": cfg & 255,
+                       # rows per wave; tile shape 0: one wave, tiles down columns first, 1: one
+                       # wave, along rows, 2: four waves stacked (4 x rows per tile)
+                       "autotuned_rows": (cfg >> 8) & 255, "autotuned_tile_shape": cfg & 255,
                        "autotuned_workgroups_per_cu": cfg >> 16,
                        # phases of the persistent launch up to the message table (device-clock stamps
                        # of its workgroup 0); the rest of the step (pack + unpack and GDEF update in the

@@ -241,14 +241,15 @@ int hdarray_reduce_noalloc(hd_array_t *a, void *res, hd_reduce_t op, int part);
 int hdarray_batch_begin(void);
 int hdarray_batch_end(void);
 int hdarray_batch_run(int batch);
-/* Chooses the rows per stencil tile (4, 8, 16), the tile order (1: tiles
- * numbered along rows first, 0: down columns) and the workgroups per CU of
- * the persistent kernel (1, 2, 4; capped by its occupancy) of the given
- * batches by timing each of the 18 candidates
- * on `reps` runs of the sequence batches[0..n) after one warm-up run.  These
- * runs are real steps of the program: 18 * (reps + 1) sequences execute.
- * No candidate changes any result.  Returns the chosen
- * (per_cu << 16 | rows << 8 | order) or a negative error. */
+/* Chooses the stencil tile shape (one wave per tile of 4, 8 or 16 rows
+ * with tiles numbered along rows first (shape 1) or down columns (shape
+ * 0), or four waves of 4 rows stacked down a tile, sharing halo rows
+ * through LDS (shape 2)) and the workgroups per CU of the persistent kernel
+ * (1, 2, 4; capped by its occupancy) of the given batches by timing each of
+ * the 21 candidates on `reps` runs of the sequence batches[0..n) after one
+ * warm-up run.  These runs are real steps of the program: 21 * (reps + 1)
+ * sequences execute.  No candidate changes any result.  Returns the chosen
+ * (per_cu << 16 | rows << 8 | shape) or a negative error. */
 int hdarray_batch_autotune(const int *batches, int n, int reps);
 /* Device time of each phase of the last run of a batch, in microseconds, from
  * clock stamps taken by workgroup 0 at the phase boundaries (a measurement

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "hd_dev_data.hpp"
+#include "hd_dev_jacobi.hpp"
 #include "hd_dev_meta.hpp"
 
 namespace hd {
@@ -239,10 +240,42 @@ __global__ __launch_bounds__(64) void k_batch_tiles(const WorkBox *__restrict__ 
     dev_copy_tile(bx, t - bx.tile0, A);
 }
 
+// The same tiles four waves at a time, stacked down a tile of 16 rows
+// (halo rows shared through LDS when the box's rows can be read as float4,
+// the per-box choice uniform over the workgroup); a copy box's tiles go
+// four to a workgroup, one per wave.
+__global__ __launch_bounds__(256) void k_batch_stack(const WorkBox *__restrict__ wb, const int32_t *__restrict__ tbox,
+                                                     const ArrDev *__restrict__ A, int64_t ntiles) {
+  const int64_t t = xcd_remap(blockIdx.x, ntiles);
+  const WorkBox bx = wb[tbox[t]];
+  const int64_t lt = t - bx.tile0;
+  if (bx.kind == 2) {
+    const int64_t ct = 4 * lt + (threadIdx.x >> 6);
+    if (ct < copy_tiles(bx, A[bx.ain].esize)) dev_copy_tile(bx, ct, A);
+    return;
+  }
+  const bool vec = ((bx.lo[2] & 3) == 0) && ((A[bx.ain].n[2] & 3) == 0) && ((A[bx.ain].rs[bx.dev] & 3) == 0) &&
+                   ((A[bx.aout].rs[bx.dev] & 3) == 0);
+  if (bx.kind == 1) {
+    if (vec)
+      dev_stack_tile<4, 4, 0, true>(bx, lt, A, Coef9{});
+    else
+      dev_stack_tile<4, 4, 0, false>(bx, lt, A, Coef9{});
+  } else if (bx.kind == 5) {
+    if (vec)
+      dev_stack_tile<4, 4, 1, true>(bx, lt, A, Coef9{});
+    else
+      dev_stack_tile<4, 4, 1, false>(bx, lt, A, Coef9{});
+  }
+}
+
 typedef void (*tiles_kernel_t)(const WorkBox *, const int32_t *, const ArrDev *, int64_t);
 
-// th: rows per stencil tile; hf: tiles numbered along rows first
+// th: rows per wave; hf: 1 one-wave tiles numbered along rows first, 0 down
+// columns first, 2 four waves of 4 rows stacked (th is 4; more rows per wave
+// in this kernel leave one wave per SIMD)
 static tiles_kernel_t pick_tiles(int th, int hf) {
+  if (hf == 2) return k_batch_stack;
   if (th == 4) return hf ? k_batch_tiles<4, true> : k_batch_tiles<4, false>;
   if (th == 16) return hf ? k_batch_tiles<16, true> : k_batch_tiles<16, false>;
   return hf ? k_batch_tiles<8, true> : k_batch_tiles<8, false>;
@@ -265,7 +298,7 @@ hipError_t launch_batch(const BatchArgs &a, int th, int hf, int grid, hipStream_
   hipLaunchKernelGGL(k_zero_bar, dim3(1), dim3(64), 0, s, a.bar);
   hipLaunchKernelGGL(k_batch, dim3(grid), dim3(256), 0, s, a);
   if (a.ntiles > 0)
-    hipLaunchKernelGGL(pick_tiles(th, hf), dim3((unsigned)a.ntiles), dim3(64), 0, s, a.wb, a.tbox,
+    hipLaunchKernelGGL(pick_tiles(th, hf), dim3((unsigned)a.ntiles), dim3(hf == 2 ? 256 : 64), 0, s, a.wb, a.tbox,
                        (const ArrDev *)a.A, a.ntiles);
   return hipGetLastError();
 }

@@ -180,7 +180,6 @@ __global__ __launch_bounds__(64 * kDerive1Waves) void k_runs1(PlanDev P, const A
   }
 }
 
-__device__ inline void gdef_task(const PlanDev &P, ArrDev *__restrict__ A, const Work &W, int q, GdefLds S);
 
 __global__ __launch_bounds__(64 * kDerive1Waves) void k_tail1(PlanDev P, ArrDev *__restrict__ A, Work W, Level L1,
                                                             Level L2, MsgRec *out, MsgHdr *hdr, int64_t cap,
@@ -188,13 +187,27 @@ __global__ __launch_bounds__(64 * kDerive1Waves) void k_tail1(PlanDev P, ArrDev 
   // workgroup 0: the heads' scratch (2 * kHead1 items per wave), then the
   // compaction's; the others: one wave's LDS form of the GDEF update
   __shared__ __align__(16) char s_buf[sizeof(Ivl) * kMaxCap + (3 * 4 + 8) * kGdefMaxB];
+  __shared__ int32_t s_def[kDerive1Waves];
+  __shared__ int32_t s_ndef;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (blockIdx.x > 0) {
+    // one cell per wave in registers; the LDS scratch serves one wave, so
+    // the cells that need it (more than 64 boundaries) are updated after
+    // the others by wave 0, one after the other
     Ivl *iv = reinterpret_cast<Ivl *>(s_buf);
     int32_t *b = reinterpret_cast<int32_t *>(s_buf + sizeof(Ivl) * kMaxCap);
-    GdefLds S{iv, b, b + kGdefMaxB, b + 2 * kGdefMaxB, reinterpret_cast<uint64_t *>(b + 3 * kGdefMaxB)};
+    const GdefLds S{iv, b, b + kGdefMaxB, b + 2 * kGdefMaxB, reinterpret_cast<uint64_t *>(b + 3 * kGdefMaxB)};
     const int nw = (gridDim.x - 1) * kDerive1Waves;
-    for (int t = (blockIdx.x - 1) * kDerive1Waves + wv; t < P.ngrow; t += nw) gdef_task(P, A, W, t, S);
+    for (int t0 = (blockIdx.x - 1) * kDerive1Waves; t0 < P.ngrow; t0 += nw) {
+      if (threadIdx.x == 0) s_ndef = 0;
+      __syncthreads();
+      const int t = t0 + wv;
+      if (t < P.ngrow && !dev_gdef_row_fast(P, A, W, t) && lane == 0) s_def[atomicAdd(&s_ndef, 1)] = t;
+      __syncthreads();
+      if (wv == 0)
+        for (int k = 0; k < s_ndef; ++k) dev_gdef_row(P, A, W, s_def[k], S, kGdefMaxB);
+      __syncthreads();
+    }
     return;
   }
   if (W.skip && *W.skip) return;  // the plan's stored table is current

@@ -2749,11 +2749,21 @@ static void last_table(MsgRec **tab, MsgHdr **hdr) {
   }
 }
 
+// Tiles of one box of a batch: one-wave tiles of th rows (hf 0, 1) or
+// four waves stacked down 4 * th rows (hf 2; a copy box's one-wave tiles
+// four to a workgroup).
+static int64_t batch_tiles(const WorkBox &w, int th, int hf) {
+  const int esize = R.arrays[w.aout]->esize;
+  if (hf != 2) return tiles_for(w.kind, w, esize, th);
+  if (w.kind == 2) return (tiles_for(w.kind, w, esize, th) + 3) / 4;
+  return tiles_for(w.kind, w, esize, 4 * th);
+}
+
 static int batch_config(Batch *b, int th, int hf, int occ) {
   int64_t t0 = 0;
   for (WorkBox &w : b->boxes) {
     w.tile0 = t0;
-    t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, th);
+    t0 += batch_tiles(w, th, hf);
   }
   b->ntiles = t0;
   // one workgroup per tile in the user-kernel launch
@@ -2932,10 +2942,11 @@ extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
   if (!R.inited || !ids || n <= 0 || reps <= 0) return fail(HD_EINVAL);
   for (int i = 0; i < n; ++i)
     if (ids[i] < 0 || ids[i] >= (int)R.batches.size()) return fail(HD_EINVAL);
-  // rows per tile x tile order (1: along rows) x workgroups per CU of the
-  // persistent kernel (fewer make cheaper grid barriers, more run the
+  // rows per wave x tile shape (0: one wave, tiles down columns first; 1:
+  // one wave, along rows; 2: four waves stacked) x workgroups per CU of
+  // the persistent kernel (fewer make cheaper grid barriers, more run the
   // metadata phases wider)
-  const int ths[3] = {4, 8, 16}, hfs[2] = {0, 1}, occs[3] = {1, 2, 4};
+  const int ths[3] = {4, 8, 16}, hfs[3] = {0, 1, 2}, occs[3] = {1, 2, 4};
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
@@ -2944,6 +2955,7 @@ extern "C" int hdarray_batch_autotune(const int *ids, int n, int reps) {
   for (int occ : occs)
   for (int th : ths)
     for (int hf : hfs) {
+      if (hf == 2 && th != 4) continue;  // the stacked shape has four rows per wave
       for (int i = 0; i < n; ++i)
         if (batch_config(R.batches[ids[i]], th, hf, occ) != HD_OK) return g_last_error;
       for (int i = 0; i < n; ++i)

@@ -80,9 +80,9 @@ def test_batched_matches_oracle(hd, scale, narr):
             arr = (ctypes.c_int * 2)(*ids)
             cfg = rt.L.hdarray_batch_autotune(arr, 2, 1)
             assert cfg > 0
-            say(f"autotuned rows={(cfg >> 8) & 255} row_first={cfg & 255} per_cu={cfg >> 16}")
-            # the autotuner ran 18 candidates x (1 + reps) real pairs of steps
-            for _ in range(36):
+            say(f"autotuned rows={(cfg >> 8) & 255} shape={cfg & 255} per_cu={cfg >> 16}")
+            # the autotuner ran 21 candidates x (1 + reps) real pairs of steps
+            for _ in range(42):
                 _oracle_step(orc, oa, True)
                 _oracle_step(orc, oa, False)
         even = step % 2 == 0
