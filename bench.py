@@ -55,6 +55,19 @@ def committed_traffic(name, kernel, sources=KERNEL_SOURCES):
 KERNEL_SAMPLE = 4  # every 4th step of a timed loop times its stencil launch
 
 
+def committed_kernel_avg(name, kernel):
+    """Average duration (us) of a kernel in the committed rocprofv3 summary
+    profiles/NAME_kernels.txt, or None when absent."""
+    p = os.path.join(ROOT, "profiles", f"{name}_kernels.txt")
+    if not os.path.exists(p):
+        return None
+    for line in open(p):
+        f = line.split()
+        if len(f) == 6 and f[0] == kernel:
+            return float(f[3])
+    return None
+
+
 def short_kernel_name(n):
     """A profiler kernel name without namespace, return type, arguments or
     spaces (k_stack_a<4,0>)."""
@@ -767,7 +780,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic("jacobi2d_8192", kname),
                      "kernel": kname, "bytes_per_launch": bytes_kernel,
-                     "avg_launch_us": avg_kernel_ms * 1e3},
+                     "avg_launch_us": avg_kernel_ms * 1e3,
+                     # the same kernel's average in the committed rocprofv3 summary of this workload
+                     "profile_avg_us": committed_kernel_avg("jacobi2d_8192", kname)},
         "step_hbm_frac": bytes_kernel / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "phases_us": {k: (v[0] / max(v[1], 1)) * 1e3 for k, v in ph.items()},
         "pack_unpack": {"bytes": moved, "fused_pass_us": pk_ms * 1e3,
