@@ -53,6 +53,7 @@ def committed_traffic(name, kernel, sources=KERNEL_SOURCES):
 
 
 KERNEL_SAMPLE = 4  # every 4th step of a timed loop times its stencil launch
+TUNE_CALLS = 36    # calls that cover the runtime's tile-shape timing (4 shapes x 8 calls)
 
 
 def committed_kernel_avg(name, kernel):
@@ -163,13 +164,13 @@ def stencil_kernel_name(st, one, strip, op):
     return f"{one}<{rows}{tri},{'true' if order else 'false'}>"
 
 
-def setup_jacobi_large(rt, hd, n):
+def setup_jacobi_large(rt, hd, n, declare=True):
     from workloads import jacobi_inputs
     A0, B0 = jacobi_inputs(n, 2)
     A, B = rt.create(A0), rt.create(B0)
     p = rt.partition(hd.BLOCK, (n, n), ndev=16)
     offs = [(0, 0), (0, -1), (0, 1), (-1, 0), (1, 0)]
-    for k, out, inp in (("jacAB", A, B), ("jacBA", B, A)):
+    for k in ("jacAB", "jacBA") if declare else ():
         rt.kernel(k, hd.K_JACOBI2D)
         rt.set_offsets(k, 1, 0, offs)
         rt.set_offsets(k, 0, 1, [(0, 0)])
@@ -692,7 +693,16 @@ def main():
         print(json.dumps(out), flush=True)
         return
     n = args.n
-    A, B, p = setup_jacobi_large(rt, hd, n)
+    # tile-shape calibration: on the first calls of a box geometry the runtime
+    # times its candidate stencil tile shapes (TUNE_CALLS calls), then keeps
+    # the fastest for every plan with the same boxes.  Those calls run on a
+    # scratch pair of arrays of the same shape and partition, so that the
+    # warm-up and the timed steps below all run the chosen shape whatever W.
+    S_a, S_b, s_p = setup_jacobi_large(rt, hd, n)
+    for i in range(TUNE_CALLS):
+        rt.apply("jacAB" if i % 2 == 0 else "jacBA", s_p, [S_a, S_b] if i % 2 == 0 else [S_b, S_a])
+    rt.sync()
+    A, B, p = setup_jacobi_large(rt, hd, n, declare=False)
 
     def step(i):
         if i % 2 == 0:
@@ -776,7 +786,9 @@ def main():
         "config": {"workload": f"jacobi_large: 2-D 5-point Jacobi {n}x{n} fp32, 16 logical devices (4x4 blocks), "
                                f"use = own block +-1 (5-point offsets), def = own block, ping-pong",
                    "n": n, "partitions": 16, "messages_per_step": st["last_messages"],
-                   "halo_bytes_per_step": moved},
+                   "halo_bytes_per_step": moved,
+                   "tile_shape_calibration": f"{TUNE_CALLS} calls on a scratch pair of arrays of the same shape "
+                                             "and partition before the warm-up"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic("jacobi2d_8192", kname),
                      "kernel": kname, "bytes_per_launch": bytes_kernel,

@@ -335,8 +335,9 @@ int hdarray_get_stats(hd_stats_t *st);
  * tiles always run along rows).  rows = 32 or 64 selects tall strips of that
  * many rows, one wave each, streaming through an 8-row register window
  * (waves and order ignored).  (0, 0, any)
- * restores the default: the runtime times candidate shapes on the first
- * calls of each work-box geometry and keeps the fastest.  No shape changes
+ * restores the default: the runtime times four candidate shapes on the
+ * first 32 calls of each work-box geometry (eight calls each, interleaved)
+ * and keeps the one with the least median time.  No shape changes
  * a result.  HD_EINVAL for other values, HD_ESTATE before init. */
 int hdarray_set_stencil_shape(int rows, int waves, int order);
 

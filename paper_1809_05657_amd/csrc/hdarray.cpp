@@ -207,8 +207,9 @@ struct RecCall;
 struct Batch;
 
 // Stencil tile shapes tried on real calls, each timed kTuneReps times in
-// interleaved order; the fastest is kept.  The shape never changes a result.
-constexpr int kTuneN = 4, kTuneReps = 2;
+// interleaved order; the one with the least median time is kept.  The shape
+// never changes a result.
+constexpr int kTuneN = 4, kTuneReps = 8;
 // (rows per wave, waves per workgroup, order): one wave per tile with the
 // tiles of an XCD along rows (order 1) or down columns (0), or four waves
 // stacked down a tile of 4 x rows (halo rows shared through LDS)
@@ -1743,15 +1744,25 @@ static void stencil_shape(Plan *pl, int &th, int &waves, int &order, hipEvent_t 
     const bool ready = !ts.ev[last] || hipEventQuery(ts.ev[last]) == hipSuccess;
     (void)hipGetLastError();  // a not-ready query must not surface as an error of a later call
     if (ready) {
-      float best = 1e30f;
+      // the candidate with the least median time over its calls (one fast
+      // or slow call alone does not decide between shapes a few percent
+      // apart)
+      std::vector<float> t[kTuneN];
       for (int slot = 0; slot < kTuneN * kTuneReps; ++slot) {
         float ms = 0.f;
         if (!ts.ev[2 * slot] || !ts.ev[2 * slot + 1] ||
             hipEventElapsedTime(&ms, ts.ev[2 * slot], ts.ev[2 * slot + 1]) != hipSuccess)
           continue;
-        if (ms < best) {
-          best = ms;
-          ts.best = slot % kTuneN;
+        t[slot % kTuneN].push_back(ms);
+      }
+      float best = 1e30f;
+      for (int k = 0; k < kTuneN; ++k) {
+        if (t[k].empty()) continue;
+        std::sort(t[k].begin(), t[k].end());
+        const float med = t[k][t[k].size() / 2];
+        if (med < best) {
+          best = med;
+          ts.best = k;
         }
       }
       for (hipEvent_t &e : ts.ev)
