@@ -26,11 +26,15 @@ __device__ inline int64_t xcd_remap_mm(int64_t bid, int64_t ntiles) {
   return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-constexpr int BM = 128, BN = 128, BK = 16, LDP = BM + 4;
+// LDS row strides: B rows are written as float4 (stride a multiple of 4
+// words); A is written transposed, one word per lane, where 32 lanes hold
+// 8 rows x 4 k values: a stride of 2 mod 32 words puts them in 32 different
+// banks (a stride of 4 mod 32 gave two-way conflicts).
+constexpr int BM = 128, BN = 128, BK = 16, LDP = BM + 4, LDA = BM + 2;
 
 __global__ __launch_bounds__(256) void k_mm_mfma(const WorkBox *__restrict__ wb, int nbox,
                                                  const ArrDev *__restrict__ A, int64_t ntiles) {
-  __shared__ float sA[2][BK][LDP];
+  __shared__ float sA[2][BK][LDA];
   __shared__ float sB[2][BK][LDP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t t = xcd_remap_mm(blockIdx.x, ntiles);
