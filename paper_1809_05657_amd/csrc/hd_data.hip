@@ -11,7 +11,7 @@ namespace hd {
 
 static inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 int64_t mm_tiles(const int32_t *lo, const int32_t *hi);
-hipError_t launch_mm(const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles, hipStream_t s);
+hipError_t launch_mm(bool full, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles, hipStream_t s);
 hipError_t launch_jacobi(bool tri, int th, int waves, int order, bool vec, const WorkBox *wb, int nbox, const ArrDev *A,
                          int64_t ntiles, hipStream_t s);
 hipError_t launch_conv(int th, int waves, int order, bool vec, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles,
@@ -211,7 +211,8 @@ int64_t tiles_for(int kind, const WorkBox &B, int esize, int th) {
 }
 
 // vec: every box's rows can be read as float4 (row length and box start
-// multiples of 4); only the stacked 2-D stencil shape uses it.
+// multiples of 4), used by the stacked 2-D stencil shape; for the matmul,
+// every box is whole tiles (no bounds checks).
 hipError_t launch_user(int kind, int th, int waves, int order, bool vec, const WorkBox *wb, int nbox, const ArrDev *A,
                        int64_t ntiles, const float *coef, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
@@ -230,7 +231,7 @@ hipError_t launch_user(int kind, int th, int waves, int order, bool vec, const W
       hipLaunchKernelGGL(k_s3d, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, wb, nbox, A, ntiles, c);
     } break;
     case 4:
-      return launch_mm(wb, nbox, A, ntiles, s);
+      return launch_mm(vec, wb, nbox, A, ntiles, s);
   }
   return hipGetLastError();
 }

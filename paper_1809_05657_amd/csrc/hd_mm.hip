@@ -32,6 +32,18 @@ __device__ inline int64_t xcd_remap_mm(int64_t bid, int64_t ntiles) {
 // banks (a stride of 4 mod 32 gave two-way conflicts).
 constexpr int BM = 128, BN = 128, BK = 16, LDP = BM + 4, LDA = BM + 2;
 
+// Global-memory pointers: loads through them are global (not flat)
+// instructions, which count only against the vector-memory counter, so the
+// waits for LDS reads in the MFMA loop do not also wait for the next tile's
+// global loads.
+typedef const float __attribute__((address_space(1))) gfloat;
+typedef const f4 __attribute__((address_space(1))) gf4;
+typedef float __attribute__((address_space(1))) gfloat_w;
+
+// FULL: every box of the launch is a multiple of the tile in rows and
+// columns, K is a multiple of BK and rows of A and B are float4-aligned, so
+// no load or store needs a bounds check (the host checks this per plan).
+template <bool FULL>
 __global__ __launch_bounds__(256) void k_mm_mfma(const WorkBox *__restrict__ wb, int nbox,
                                                  const ArrDev *__restrict__ A, int64_t ntiles) {
   __shared__ float sA[2][BK][LDA];
@@ -54,16 +66,30 @@ __global__ __launch_bounds__(256) void k_mm_mfma(const WorkBox *__restrict__ wb,
   const int ty = (int)(lt % nty), tx = (int)(lt / nty);
   const int i0 = Bx.lo[1] + ty * BM, j0 = Bx.lo[2] + tx * BN;
   const ArrDev &ma = A[aa], &mb = A[ab], &mc = A[ac];
-  const float *__restrict__ a = reinterpret_cast<const float *>(ma.buf[Bx.dev]);
-  const float *__restrict__ b = reinterpret_cast<const float *>(mb.buf[Bx.dev]);
-  float *__restrict__ c = reinterpret_cast<float *>(mc.buf[Bx.dev]);
+  gfloat *__restrict__ a = (gfloat *)ma.buf[Bx.dev];
+  gfloat *__restrict__ b = (gfloat *)mb.buf[Bx.dev];
+  gfloat_w *__restrict__ c = (gfloat_w *)mc.buf[Bx.dev];
   const int K = (int)ma.n[2], M = (int)mb.n[2];
   const int ihi = Bx.hi[1], jhi = Bx.hi[2];
   const bool avec = (K & 3) == 0, bvec = (M & 3) == 0 && (j0 & 3) == 0;
 
   // global -> register staging: each thread moves 2 float4 of A and 2 of B
   f4 ra[2], rb[2];
+  // FULL: thread tid loads A rows tid/4 and 64 + tid/4 at k (tid%4)*4, and B
+  // rows tid/32 and 8 + tid/32 at column (tid%32)*4; the pointers advance by
+  // one K step per call
+  gfloat *pa = a + (int64_t)(i0 + tid / 4) * K + (tid % 4) * 4;
+  gfloat *pb = b + (int64_t)(tid / 32) * M + j0 + (tid % 32) * 4;
   auto gload = [&](int k0) {
+    if constexpr (FULL) {
+      ra[0] = *(gf4 *)pa;
+      ra[1] = *(gf4 *)(pa + (int64_t)64 * K);
+      rb[0] = *(gf4 *)pb;
+      rb[1] = *(gf4 *)(pb + (int64_t)8 * M);
+      pa += BK;
+      pb += (int64_t)BK * M;
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int v = tid + 256 * q;  // 512 float4 per operand tile
@@ -72,9 +98,9 @@ __global__ __launch_bounds__(256) void k_mm_mfma(const WorkBox *__restrict__ wb,
         const int ii = i0 + v / 4, kk = k0 + (v % 4) * 4;
         f4 x = {0.f, 0.f, 0.f, 0.f};
         if (ii < ihi) {
-          const float *p = a + (int64_t)ii * K + kk;
+          gfloat *p = a + (int64_t)ii * K + kk;
           if (avec && kk + 4 <= K) {
-            x = *reinterpret_cast<const f4 *>(p);
+            x = *(gf4 *)p;
           } else {
             if (kk < K) x.x = p[0];
             if (kk + 1 < K) x.y = p[1];
@@ -89,9 +115,9 @@ __global__ __launch_bounds__(256) void k_mm_mfma(const WorkBox *__restrict__ wb,
         const int kk = k0 + v / 32, jj = j0 + (v % 32) * 4;
         f4 x = {0.f, 0.f, 0.f, 0.f};
         if (kk < K) {
-          const float *p = b + (int64_t)kk * M + jj;
+          gfloat *p = b + (int64_t)kk * M + jj;
           if (bvec && jj + 4 <= jhi) {
-            x = *reinterpret_cast<const f4 *>(p);
+            x = *(gf4 *)p;
           } else {
             if (jj < jhi) x.x = p[0];
             if (jj + 1 < jhi) x.y = p[1];
@@ -127,30 +153,37 @@ __global__ __launch_bounds__(256) void k_mm_mfma(const WorkBox *__restrict__ wb,
 
   const int wi = (wv >> 1) * 64, wj = (wv & 1) * 64;
   const int lr = lane & 31, lk = lane >> 5;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  int cur = 0;
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    const bool more = k0 + BK < K;
-    if (more) gload(k0 + BK);
+  auto mma = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
-      const float a0 = sA[cur][kk + lk][wi + lr];
-      const float a1 = sA[cur][kk + lk][wi + 32 + lr];
-      const float b0 = sB[cur][kk + lk][wj + lr];
-      const float b1 = sB[cur][kk + lk][wj + 32 + lr];
+      const float a0 = sA[buf][kk + lk][wi + lr];
+      const float a1 = sA[buf][kk + lk][wi + 32 + lr];
+      const float b0 = sB[buf][kk + lk][wj + lr];
+      const float b1 = sB[buf][kk + lk][wj + 32 + lr];
       acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
     }
-    if (more) {
-      lstore(cur ^ 1);
-      __syncthreads();
-      cur ^= 1;
-    }
+  };
+  // one barrier per K step: the tile read from one buffer while the next
+  // is stored to the other (every wave has finished reading a buffer before
+  // the barrier that precedes its next store)
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = BK; k0 < K; k0 += BK) {
+    gload(k0);
+    // keep the next tile's global loads ahead of this tile's MFMAs (the
+    // scheduler would otherwise sink them to just before their LDS stores)
+    __builtin_amdgcn_sched_barrier(0);
+    mma(cur);
+    lstore(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
   }
+  mma(cur);
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -159,7 +192,7 @@ __global__ __launch_bounds__(256) void k_mm_mfma(const WorkBox *__restrict__ wb,
       for (int r = 0; r < 16; ++r) {
         const int ii = i0 + wi + 32 * x + 8 * (r >> 2) + 4 * lk + (r & 3);
         const int jj = j0 + wj + 32 * y + lr;
-        if (ii < ihi && jj < jhi) c[(int64_t)ii * M + jj] = acc[x][y][r];
+        if (FULL || (ii < ihi && jj < jhi)) c[(int64_t)ii * M + jj] = acc[x][y][r];
       }
 }
 
@@ -169,9 +202,17 @@ int64_t mm_tiles(const int32_t *lo, const int32_t *hi) {
   return ((h + BM - 1) / BM) * ((w + BN - 1) / BN);
 }
 
-hipError_t launch_mm(const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles, hipStream_t s) {
+bool mm_full(const int32_t *lo, const int32_t *hi, int64_t K, int64_t M) {
+  return (hi[1] - lo[1]) % BM == 0 && (hi[2] - lo[2]) % BN == 0 && K >= BK && K % BK == 0 && M % 4 == 0 &&
+         lo[2] % 4 == 0;
+}
+
+hipError_t launch_mm(bool full, const WorkBox *wb, int nbox, const ArrDev *A, int64_t ntiles, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mm_mfma, dim3(ntiles), dim3(256), 0, s, wb, nbox, A, ntiles);
+  if (full)
+    hipLaunchKernelGGL(k_mm_mfma<true>, dim3(ntiles), dim3(256), 0, s, wb, nbox, A, ntiles);
+  else
+    hipLaunchKernelGGL(k_mm_mfma<false>, dim3(ntiles), dim3(256), 0, s, wb, nbox, A, ntiles);
   return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ hipError_t launch_level2(const PlanDev &P, const Work &W, const Level &L, MsgRec
 hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
                        int unpack, hipStream_t s);
 int64_t tiles_for(int kind, const WorkBox &B, int esize, int th);
+bool mm_full(const int32_t *lo, const int32_t *hi, int64_t K, int64_t M);
 hipError_t launch_ext_copy(const WorkBox *wb, int nbox, int64_t rows, const ArrDev *A, int arr, void *ext,
                            int to_ext, hipStream_t s);
 hipError_t launch_stack_args(int op, int th, const StackArgs &a, int64_t ntiles, const float *coef, hipStream_t s);
@@ -169,7 +170,8 @@ struct Plan {
   // key of the tile-shape tuning shared by plans with the same boxes
   WorkBox *wbj[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   std::vector<WorkBox> hwbj[5];  // host copies (for launches that pass the boxes by value)
-  bool vec = false;  // every work box's rows can be read as float4
+  bool vec = false;  // every work box's rows can be read as float4 (matmul:
+                     // every box is whole tiles, no bounds checks needed)
   int64_t ntj[5] = {0, 0, 0, 0, 0};
   std::vector<int64_t> tkey;
   // device-pointer Write / Read plans: the partition's regions as boxes whose
@@ -2370,6 +2372,11 @@ extern "C" int hdarray_apply_kernel(const char *kname, int part, int nargs, cons
         t0 += tiles_for(w.kind, w, R.arrays[w.aout]->esize, pl->th);
       }
       pl->ntiles = t0;
+      if (pl->ukind == 4) {
+        pl->vec = true;
+        for (const WorkBox &w : wb)
+          if (!mm_full(w.lo, w.hi, R.arrays[w.ain]->n[2], R.arrays[w.ain2]->n[2])) pl->vec = false;
+      }
       if (!wb.empty()) HIPCK(hipMemcpy(pl->wb, wb.data(), sizeof(WorkBox) * wb.size(), hipMemcpyHostToDevice));
     }
     R.plans[key] = pl;

@@ -265,10 +265,12 @@ def test_stencil_shapes_parity(hd, rows, waves, order):
     assert np.array_equal(rt.read(g[0], g[2]), orc.read(o[0], o[2]))
 
 
-@pytest.mark.parametrize("n,P", [(64, 4), (96, 3)])
+@pytest.mark.parametrize("n,P", [(64, 4), (96, 3), (256, 2)])
 def test_gemm_parity(hd, n, P):
     """Listings 2-3 GEMM: the gather of B (first call), then no messages;
-    random inputs within the FP32 bound, ternary inputs bit-exact."""
+    random inputs within the FP32 bound, ternary inputs bit-exact.  64 / 4
+    and 96 / 3 take the bounds-checked tile path (boxes of 16 and 32 rows),
+    256 / 2 the unchecked one (two 128 x 256 boxes of whole tiles)."""
     say(f"case gemm n={n} P={P}")
     for kind, (a0, b0) in (("random", matmul_inputs(n, 3)), ("ternary", ternary_matmul_inputs(n, 4))):
         rt, orc = hd.Runtime(), O.Oracle()
