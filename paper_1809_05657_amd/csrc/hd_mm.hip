@@ -153,18 +153,36 @@ __global__ __launch_bounds__(256) void k_mm_mfma(const WorkBox *__restrict__ wb,
 
   const int wi = (wv >> 1) * 64, wj = (wv & 1) * 64;
   const int lr = lane & 31, lk = lane >> 5;
+  // the operands of k pair kk + 2 are read from LDS before the MFMAs of
+  // pair kk are issued
   auto mma = [&](int buf) {
+    float oa[2][2], ob[2][2];
+    auto rd = [&](int kk, int s) {
+      oa[s][0] = sA[buf][kk + lk][wi + lr];
+      oa[s][1] = sA[buf][kk + lk][wi + 32 + lr];
+      ob[s][0] = sB[buf][kk + lk][wj + lr];
+      ob[s][1] = sB[buf][kk + lk][wj + 32 + lr];
+    };
+    rd(0, 0);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 2) {
-      const float a0 = sA[buf][kk + lk][wi + lr];
-      const float a1 = sA[buf][kk + lk][wi + 32 + lr];
-      const float b0 = sB[buf][kk + lk][wj + lr];
-      const float b1 = sB[buf][kk + lk][wj + 32 + lr];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+      const int s = (kk >> 1) & 1;
+      if (kk + 2 < BK) rd(kk + 2, s ^ 1);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(oa[s][0], ob[s][0], acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(oa[s][0], ob[s][1], acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(oa[s][1], ob[s][0], acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(oa[s][1], ob[s][1], acc[1][1], 0, 0, 0);
     }
+    // instruction order: two LDS reads, then (two LDS reads, four MFMAs)
+    // per k pair, so each wave has the next pair's reads in flight while
+    // its MFMAs issue
+    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+    for (int kk = 0; kk < BK - 2; kk += 2) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
   };
   // one barrier per K step: the tile read from one buffer while the next
   // is stored to the other (every wave has finished reading a buffer before
