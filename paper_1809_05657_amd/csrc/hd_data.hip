@@ -54,10 +54,12 @@ __global__ __launch_bounds__(64) void k_copy(const WorkBox *__restrict__ wb, int
 // the loads in flight, so the register budget is held to six waves per SIMD
 // (78 VGPRs, no spills; the unconstrained build takes 83 and fits five):
 // 307 against 351 us per 512^3 launch.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_s3d(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_s3d(const WorkBox *__restrict__ wb, int nbox, const ArrDev *__restrict__ A,
                                              int64_t ntiles, Coef7 cf) {
   const int64_t nwg = (ntiles + 3) >> 2;
-  const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
+  // the wave's tile index, made explicitly wave-uniform so that the box
+  // lookup and the march's geometry live in scalar registers
+  const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (t >= ntiles) return;
   const WorkBox B = wb[find_box(wb, nbox, t)];
   dev_s3d_march(B, t - B.tile0, A, cf);

@@ -10,6 +10,15 @@ namespace hd {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// Global-memory views of device buffers.  Loads through them compile to
+// global (not flat) instructions, which count only against the vector-memory
+// counter: a wait for an LDS operation (a cross-lane shuffle, an LDS read)
+// then does not also wait for global loads still in flight.
+typedef const float __attribute__((address_space(1))) gcf;
+typedef const f4 __attribute__((address_space(1))) gcf4;
+typedef float __attribute__((address_space(1))) gwf;
+typedef f4 __attribute__((address_space(1))) gwf4;
+
 struct Coef7 {
   float c[7];
 };

@@ -167,6 +167,10 @@ __host__ __device__ inline int64_t copy_tiles(const WorkBox &B, int esize) {
 // loads at once, as the 2-D kernel does, measured slower on the 512^3
 // workload: 900 vs 580 us forward, 2600 vs 1730 us adjoint.)
 constexpr int kS3dSeg = 32;
+#ifndef HD_S3D_DIST
+#define HD_S3D_DIST 2
+#endif
+constexpr int kS3dDist = HD_S3D_DIST;
 
 // Four consecutive elements of a row at columns [c, c + 4) (zeros outside
 // the row); vec: rows are 16-byte aligned and c is a multiple of 4.
@@ -227,77 +231,168 @@ __host__ __device__ inline int64_t s3d_tiles(const WorkBox &B) {
   return march_tiles(B.lo[0], B.hi[0], B.lo[1], B.hi[1], B.lo[2], B.hi[2], seg_of(B));
 }
 
-__device__ inline void dev_s3d_march(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef7 &cf) {
+// Geometry of one wave's row chunk for the marching kernels: columns
+// [c, c + 4) of lane `lane`, and the halo column (c - 1 for lane 0, c + 4 for
+// lane 63).  Every row load of the march is unconditional: plane, row and
+// column indices are clamped into the array, so each load is in bounds, and
+// a value read through a clamped index only ever feeds a boundary cell,
+// whose output is its own input (or a column the chunk does not write).
+// Loads for the next plane therefore never sit behind branches, and the
+// waits before a plane's arithmetic cover only that plane's loads.
+struct MarchRow {
+  int c, n2;
+  uint32_t uc, hc;  // c and the halo column as unsigned offsets: a uniform
+                    // row base plus a zero-extended 32-bit lane offset is
+                    // the scalar-base form of a global load
+};
+
+// c0: the chunk's first column (wave-uniform)
+__device__ inline MarchRow march_row(int c0, int n2, int lane) {
+  MarchRow m;
+  m.c = c0 + 4 * lane;
+  m.n2 = n2;
+  const int h = lane == 0 ? m.c - 1 : m.c + 4;
+  m.hc = (uint32_t)(h < 0 ? 0 : h >= n2 ? n2 - 1 : h);
+  m.uc = (uint32_t)(m.c < 0 ? 0 : m.c);
+  return m;
+}
+
+// row (i, j) with both indices clamped into the array
+__device__ inline gcf *grow_clamp(gcf *u, int i, int j, int n0, int n1, int n2) {
+  i = i < 0 ? 0 : i >= n0 ? n0 - 1 : i;
+  j = j < 0 ? 0 : j >= n1 ? n1 - 1 : j;
+  return u + ((int64_t)i * n1 + j) * n2;
+}
+
+// FULL: the row length is a multiple of 4 and the chunk's 256 columns lie
+// in the row (one float4 per lane); otherwise clamped loads
+template <bool FULL>
+__device__ inline f4 mrd4(gcf *row, const MarchRow &m) {
+  if constexpr (FULL) {
+    return *(gcf4 *)(row + m.uc);
+  } else {
+    f4 x;
+    float *px = reinterpret_cast<float *>(&x);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = m.c + e;
+      px[e] = row[k < 0 ? 0 : k >= m.n2 ? m.n2 - 1 : k];
+    }
+    return x;
+  }
+}
+
+// a row chunk with the lane's halo column (lanes 0 and 63 use it)
+struct MRow {
+  f4 v;
+  float h;
+};
+
+template <bool FULL>
+__device__ inline MRow mrdq(gcf *row, const MarchRow &m) {
+  MRow q;
+  q.v = mrd4<FULL>(row, m);
+  q.h = row[m.hc];
+  return q;
+}
+
+// One plane step of the 7-point stencil for lane's four columns: pm / pp
+// the row j of planes i -+ 1, cu (with its halo column) plane i, jm / jp the
+// rows j -+ 1 of plane i; iint: plane i and row j are interior.
+__device__ inline void s3d_point(const Coef7 &cf, const WorkBox &B, const MarchRow &m, int lane, bool iint,
+                                 const f4 &pm, const MRow &cu, const f4 &pp, const f4 &jm, const f4 &jp, gwf *q,
+                                 bool wfull) {
+  const float lw = __shfl_up(cu.v.w, 1), rx = __shfl_down(cu.v.x, 1);
+  const float kl[4] = {lane == 0 ? cu.h : lw, cu.v.x, cu.v.y, cu.v.z};
+  const float kr[4] = {cu.v.y, cu.v.z, cu.v.w, lane == 63 ? cu.h : rx};
+  float o[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = m.c + e;
+    const float x = f4at(cu.v, e);
+    float acc = cf.c[0] * x;
+    acc = __builtin_fmaf(cf.c[1], f4at(pm, e), acc);
+    acc = __builtin_fmaf(cf.c[2], f4at(pp, e), acc);
+    acc = __builtin_fmaf(cf.c[3], f4at(jm, e), acc);
+    acc = __builtin_fmaf(cf.c[4], f4at(jp, e), acc);
+    acc = __builtin_fmaf(cf.c[5], kl[e], acc);
+    acc = __builtin_fmaf(cf.c[6], kr[e], acc);
+    o[e] = iint && k >= 1 && k <= m.n2 - 2 ? acc : x;
+  }
+  if (wfull) {
+    __builtin_nontemporal_store(f4{o[0], o[1], o[2], o[3]}, (gwf4 *)(q + m.c));
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = m.c + e;
+      if (k >= B.lo[2] && k < B.hi[2]) q[k] = o[e];
+    }
+  }
+}
+
+// The march over planes [i0, i1) of one row chunk, with the loads for plane
+// i + D issued before plane i is computed.  The rows live in rings of
+// registers: row j of planes i - 1 .. i + 1 + D (NR slots) and rows j -+ 1
+// of planes i .. i + D (NJ slots); the loop is unrolled U = lcm(NR, NJ)
+// times so that every slot is a fixed set of registers and nothing is
+// copied between slots (a copy of a slot still being loaded would wait for
+// that load).
+template <bool FULL, int D>
+__device__ inline void s3d_march_rows(const WorkBox &B, const Coef7 &cf, gcf *u, gwf *out, int N0, int N1, int N2,
+                                      int i0, int i1, int j, int c0, bool wfull) {
+  static_assert(D == 1 || D == 2, "prefetch distance");
+  constexpr int NR = D == 1 ? 4 : 6, NJ = D == 1 ? 2 : 3, U = D == 1 ? 4 : 6;
   const int lane = threadIdx.x & 63;
+  const MarchRow m = march_row(c0, N2, lane);
+  const bool jint = j >= 1 && j <= N1 - 2;
+  MRow R[NR];
+  f4 JM[NJ], JP[NJ];
+  // slot of plane p: (p - i0 + 1) % NR for row j, (p - i0) % NJ for j -+ 1
+#pragma unroll
+  for (int q = 0; q < D + 2; ++q) R[q] = mrdq<FULL>(grow_clamp(u, i0 - 1 + q, j, N0, N1, N2), m);
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    JM[q] = mrd4<FULL>(grow_clamp(u, i0 + q, j - 1, N0, N1, N2), m);
+    JP[q] = mrd4<FULL>(grow_clamp(u, i0 + q, j + 1, N0, N1, N2), m);
+  }
+  for (int ib = i0; ib < i1; ib += U) {
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+      const int i = ib + s;
+      if (i >= i1) break;
+      // rows for plane i + D (past the segment's end they are read and not
+      // used)
+      R[(s + 2 + D) % NR] = mrdq<FULL>(grow_clamp(u, i + 1 + D, j, N0, N1, N2), m);
+      JM[(s + D) % NJ] = mrd4<FULL>(grow_clamp(u, i + D, j - 1, N0, N1, N2), m);
+      JP[(s + D) % NJ] = mrd4<FULL>(grow_clamp(u, i + D, j + 1, N0, N1, N2), m);
+      const bool iint = jint && i >= 1 && i <= N0 - 2;
+      s3d_point(cf, B, m, lane, iint, R[s % NR].v, R[(s + 1) % NR], R[(s + 2) % NR].v, JM[s % NJ], JP[s % NJ],
+                out + ((int64_t)i * N1 + j) * N2, wfull);
+    }
+  }
+}
+
+// lt: the wave's tile within box B (wave-uniform)
+__device__ inline void dev_s3d_march(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef7 &cf) {
   const int jrows = B.hi[1] - B.lo[1];
   const int kb = B.lo[2] & ~3;
   const int nk = (B.hi[2] - kb + 255) / 256;
   const int j = B.lo[1] + (int)(lt % jrows);
   const int64_t rest = lt / jrows;
-  const int c = kb + (int)(rest % nk) * 256 + 4 * lane;
+  const int c0 = kb + (int)(rest % nk) * 256;
   const int seg = seg_of(B);
   const int i0 = B.lo[0] + (int)(rest / nk) * seg;
   const int i1 = min(i0 + seg, B.hi[0]);
   const ArrDev &ai = A[B.ain];
-  const float *__restrict__ u = reinterpret_cast<const float *>(ai.buf[B.dev]);
-  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  gcf *u = (gcf *)ai.buf[B.dev];
+  gwf *out = (gwf *)A[B.aout].buf[B.dev];
   const int N0 = (int)ai.n[0], N1 = (int)ai.n[1], N2 = (int)ai.n[2];
   const bool vec = (N2 & 3) == 0;
-  const bool jint = j >= 1 && j <= N1 - 2;
-  // planes i-1 (row j), i (rows j-1, j, j+1), i+1 (row j)
-  f4 pm = ld_rowv(row_ptr(u, i0 - 1, j, N0, N1, N2), c, N2, vec);
-  RowQ cu = ld_rowq(row_ptr(u, i0, j, N0, N1, N2), c, N2, vec, lane);
-  f4 jm = ld_rowv(row_ptr(u, i0, j - 1, N0, N1, N2), c, N2, vec);
-  f4 jp = ld_rowv(row_ptr(u, i0, j + 1, N0, N1, N2), c, N2, vec);
-  RowQ pp = ld_rowq(row_ptr(u, i0 + 1, j, N0, N1, N2), c, N2, vec, lane);
-  for (int i = i0; i < i1; ++i) {
-    // the next plane's rows, requested before this plane is computed
-    RowQ nq{};
-    f4 njm{}, njp{};
-    const bool more = i + 1 < i1;
-    if (more) {
-      nq = ld_rowq(row_ptr(u, i + 2, j, N0, N1, N2), c, N2, vec, lane);
-      njm = ld_rowv(row_ptr(u, i + 1, j - 1, N0, N1, N2), c, N2, vec);
-      njp = ld_rowv(row_ptr(u, i + 1, j + 1, N0, N1, N2), c, N2, vec);
-    }
-    const float lw = __shfl_up(cu.v.w, 1), rx = __shfl_down(cu.v.x, 1);
-    const float kl[4] = {lane == 0 ? cu.l : lw, cu.v.x, cu.v.y, cu.v.z};
-    const float kr[4] = {cu.v.y, cu.v.z, cu.v.w, lane == 63 ? cu.r : rx};
-    const bool iint = jint && i >= 1 && i <= N0 - 2;
-    float o[4];
-    bool wr[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int k = c + e;
-      wr[e] = k >= B.lo[2] && k < B.hi[2];
-      const float x = f4at(cu.v, e);
-      if (iint && k >= 1 && k <= N2 - 2) {
-        float acc = cf.c[0] * x;
-        acc = __builtin_fmaf(cf.c[1], f4at(pm, e), acc);
-        acc = __builtin_fmaf(cf.c[2], f4at(pp.v, e), acc);
-        acc = __builtin_fmaf(cf.c[3], f4at(jm, e), acc);
-        acc = __builtin_fmaf(cf.c[4], f4at(jp, e), acc);
-        acc = __builtin_fmaf(cf.c[5], kl[e], acc);
-        acc = __builtin_fmaf(cf.c[6], kr[e], acc);
-        o[e] = acc;
-      } else {
-        o[e] = x;
-      }
-    }
-    float *q = out + ((int64_t)i * N1 + j) * N2 + c;
-    if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
-      __builtin_nontemporal_store(f4{o[0], o[1], o[2], o[3]}, reinterpret_cast<f4 *>(q));
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (wr[e]) q[e] = o[e];
-    }
-    pm = cu.v;
-    cu = pp;
-    pp = nq;
-    jm = njm;
-    jp = njp;
-  }
+  const bool wfull = vec && c0 >= B.lo[2] && c0 + 256 <= B.hi[2];
+  if (vec && c0 + 256 <= N2)
+    s3d_march_rows<true, kS3dDist>(B, cf, u, out, N0, N1, N2, i0, i1, j, c0, wfull);
+  else
+    s3d_march_rows<false, 1>(B, cf, u, out, N0, N1, N2, i0, i1, j, c0, wfull);
 }
 
 }  // namespace hd
