@@ -168,7 +168,7 @@ __host__ __device__ inline int64_t copy_tiles(const WorkBox &B, int esize) {
 // workload: 900 vs 580 us forward, 2600 vs 1730 us adjoint.)
 constexpr int kS3dSeg = 32;
 #ifndef HD_S3D_DIST
-#define HD_S3D_DIST 2
+#define HD_S3D_DIST 1
 #endif
 constexpr int kS3dDist = HD_S3D_DIST;
 
@@ -227,8 +227,10 @@ __host__ __device__ inline int64_t march_tiles(int lo0, int hi0, int lo1, int hi
   return (int64_t)((hi0 - lo0 + seg - 1) / seg) * ((hi2 - kb + 255) / 256) * (hi1 - lo1);
 }
 
+// the forward march takes two rows per wave (rows j, j + 1 of a row pair)
 __host__ __device__ inline int64_t s3d_tiles(const WorkBox &B) {
-  return march_tiles(B.lo[0], B.hi[0], B.lo[1], B.hi[1], B.lo[2], B.hi[2], seg_of(B));
+  const int pairs = (B.hi[1] - B.lo[1] + 1) / 2;
+  return march_tiles(B.lo[0], B.hi[0], 0, pairs, B.lo[2], B.hi[2], seg_of(B));
 }
 
 // Geometry of one wave's row chunk for the marching kernels: columns
@@ -330,30 +332,37 @@ __device__ inline void s3d_point(const Coef7 &cf, const WorkBox &B, const MarchR
   }
 }
 
-// The march over planes [i0, i1) of one row chunk, with the loads for plane
-// i + D issued before plane i is computed.  The rows live in rings of
-// registers: row j of planes i - 1 .. i + 1 + D (NR slots) and rows j -+ 1
-// of planes i .. i + D (NJ slots); the loop is unrolled U = lcm(NR, NJ)
-// times so that every slot is a fixed set of registers and nothing is
-// copied between slots (a copy of a slot still being loaded would wait for
-// that load).
+// The march over planes [i0, i1) of one chunk of the row pair j, j + 1,
+// with the loads for plane i + D issued before plane i is computed.  Each
+// row of the pair is the other's j-neighbour, so a plane costs four row
+// loads for two output rows (rows j - 1 and j + 2 besides the pair).  The
+// rows live in rings of registers: each row of the pair for planes
+// i - 1 .. i + 1 + D (NR slots), rows j - 1 and j + 2 for planes i .. i + D
+// (NJ slots); the loop is unrolled U = lcm(NR, NJ) times so that every slot
+// is a fixed set of registers and nothing is copied between slots (a copy
+// of a slot still being loaded would wait for that load).  two: row j + 1
+// lies in the box (else it is read as a neighbour only).
 template <bool FULL, int D>
 __device__ inline void s3d_march_rows(const WorkBox &B, const Coef7 &cf, gcf *u, gwf *out, int N0, int N1, int N2,
-                                      int i0, int i1, int j, int c0, bool wfull) {
+                                      int i0, int i1, int j, bool two, int c0, bool wfull) {
   static_assert(D == 1 || D == 2, "prefetch distance");
   constexpr int NR = D == 1 ? 4 : 6, NJ = D == 1 ? 2 : 3, U = D == 1 ? 4 : 6;
   const int lane = threadIdx.x & 63;
   const MarchRow m = march_row(c0, N2, lane);
-  const bool jint = j >= 1 && j <= N1 - 2;
-  MRow R[NR];
+  const bool jint0 = j >= 1 && j <= N1 - 2, jint1 = j + 1 >= 1 && j + 1 <= N1 - 2;
+  MRow R0[NR], R1[NR];
   f4 JM[NJ], JP[NJ];
-  // slot of plane p: (p - i0 + 1) % NR for row j, (p - i0) % NJ for j -+ 1
+  // slot of plane p: (p - i0 + 1) % NR for the pair, (p - i0) % NJ for
+  // rows j - 1 and j + 2
 #pragma unroll
-  for (int q = 0; q < D + 2; ++q) R[q] = mrdq<FULL>(grow_clamp(u, i0 - 1 + q, j, N0, N1, N2), m);
+  for (int q = 0; q < D + 2; ++q) {
+    R0[q] = mrdq<FULL>(grow_clamp(u, i0 - 1 + q, j, N0, N1, N2), m);
+    R1[q] = mrdq<FULL>(grow_clamp(u, i0 - 1 + q, j + 1, N0, N1, N2), m);
+  }
 #pragma unroll
   for (int q = 0; q < D; ++q) {
     JM[q] = mrd4<FULL>(grow_clamp(u, i0 + q, j - 1, N0, N1, N2), m);
-    JP[q] = mrd4<FULL>(grow_clamp(u, i0 + q, j + 1, N0, N1, N2), m);
+    JP[q] = mrd4<FULL>(grow_clamp(u, i0 + q, j + 2, N0, N1, N2), m);
   }
   for (int ib = i0; ib < i1; ib += U) {
 #pragma unroll
@@ -362,23 +371,30 @@ __device__ inline void s3d_march_rows(const WorkBox &B, const Coef7 &cf, gcf *u,
       if (i >= i1) break;
       // rows for plane i + D (past the segment's end they are read and not
       // used)
-      R[(s + 2 + D) % NR] = mrdq<FULL>(grow_clamp(u, i + 1 + D, j, N0, N1, N2), m);
+      R0[(s + 2 + D) % NR] = mrdq<FULL>(grow_clamp(u, i + 1 + D, j, N0, N1, N2), m);
+      R1[(s + 2 + D) % NR] = mrdq<FULL>(grow_clamp(u, i + 1 + D, j + 1, N0, N1, N2), m);
       JM[(s + D) % NJ] = mrd4<FULL>(grow_clamp(u, i + D, j - 1, N0, N1, N2), m);
-      JP[(s + D) % NJ] = mrd4<FULL>(grow_clamp(u, i + D, j + 1, N0, N1, N2), m);
-      const bool iint = jint && i >= 1 && i <= N0 - 2;
-      s3d_point(cf, B, m, lane, iint, R[s % NR].v, R[(s + 1) % NR], R[(s + 2) % NR].v, JM[s % NJ], JP[s % NJ],
-                out + ((int64_t)i * N1 + j) * N2, wfull);
+      JP[(s + D) % NJ] = mrd4<FULL>(grow_clamp(u, i + D, j + 2, N0, N1, N2), m);
+      const bool iint = i >= 1 && i <= N0 - 2;
+      gwf *q = out + ((int64_t)i * N1 + j) * N2;
+      s3d_point(cf, B, m, lane, iint && jint0, R0[s % NR].v, R0[(s + 1) % NR], R0[(s + 2) % NR].v, JM[s % NJ],
+                R1[(s + 1) % NR].v, q, wfull);
+      if (two)
+        s3d_point(cf, B, m, lane, iint && jint1, R1[s % NR].v, R1[(s + 1) % NR], R1[(s + 2) % NR].v,
+                  R0[(s + 1) % NR].v, JP[s % NJ], q + N2, wfull);
     }
   }
 }
 
-// lt: the wave's tile within box B (wave-uniform)
+// lt: the wave's tile within box B (wave-uniform): row pair, then column
+// chunk, then plane segment
 __device__ inline void dev_s3d_march(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef7 &cf) {
-  const int jrows = B.hi[1] - B.lo[1];
+  const int pairs = (B.hi[1] - B.lo[1] + 1) / 2;
   const int kb = B.lo[2] & ~3;
   const int nk = (B.hi[2] - kb + 255) / 256;
-  const int j = B.lo[1] + (int)(lt % jrows);
-  const int64_t rest = lt / jrows;
+  const int j = B.lo[1] + 2 * (int)(lt % pairs);
+  const bool two = j + 1 < B.hi[1];
+  const int64_t rest = lt / pairs;
   const int c0 = kb + (int)(rest % nk) * 256;
   const int seg = seg_of(B);
   const int i0 = B.lo[0] + (int)(rest / nk) * seg;
@@ -390,9 +406,9 @@ __device__ inline void dev_s3d_march(const WorkBox &B, int64_t lt, const ArrDev 
   const bool vec = (N2 & 3) == 0;
   const bool wfull = vec && c0 >= B.lo[2] && c0 + 256 <= B.hi[2];
   if (vec && c0 + 256 <= N2)
-    s3d_march_rows<true, kS3dDist>(B, cf, u, out, N0, N1, N2, i0, i1, j, c0, wfull);
+    s3d_march_rows<true, kS3dDist>(B, cf, u, out, N0, N1, N2, i0, i1, j, two, c0, wfull);
   else
-    s3d_march_rows<false, 1>(B, cf, u, out, N0, N1, N2, i0, i1, j, c0, wfull);
+    s3d_march_rows<false, 1>(B, cf, u, out, N0, N1, N2, i0, i1, j, two, c0, wfull);
 }
 
 }  // namespace hd
