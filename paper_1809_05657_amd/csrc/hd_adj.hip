@@ -60,9 +60,123 @@ __device__ inline float adj_elem(const Coef7 &cf, bool pi, bool pim, bool pip, b
   return acc;
 }
 
+// One plane of the adjoint for lane's four columns of row j: gpm / gpp the
+// du1 row j of planes i -+ 1, gcu (with its halo column) plane i, gjm / gjp
+// du1 rows j -+ 1 of plane i, wcu (with its halo column) the u row j of
+// plane i.  Writes du of the extended box's cells and adds the coefficient
+// gradient terms to cb.
+struct AdjRow {
+  bool rj, rjm, rjp, jown, jint;
+};
+
+__device__ inline void adj_point(const Coef7 &cf, const WorkBox &B, const int *lo, const int *hi, const MarchRow &m,
+                                 int lane, int i, int N0, int N2, const AdjRow &R, const f4 &gpm, const MRow &gcu,
+                                 const f4 &gpp, const f4 &gjm, const f4 &gjp, const MRow &wcu, gwf *q, bool wfull,
+                                 bool xl, bool xr, double *cb) {
+  const float glw = __shfl_up(gcu.v.w, 1), grx = __shfl_down(gcu.v.x, 1);
+  const float gkl[4] = {lane == 0 ? gcu.h : glw, gcu.v.x, gcu.v.y, gcu.v.z};
+  const float gkr[4] = {gcu.v.y, gcu.v.z, gcu.v.w, lane == 63 ? gcu.h : grx};
+  const bool pi = adj_in(i, B.lo[0], B.hi[0], N0), pim = adj_in(i - 1, B.lo[0], B.hi[0], N0),
+             pip = adj_in(i + 1, B.lo[0], B.hi[0], N0);
+  const bool iown = i >= B.lo[0] && i < B.hi[0], iint = i >= 1 && i <= N0 - 2;
+  float o[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = m.c + e;
+    const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
+               kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
+    const float gx = f4at(gcu.v, e);
+    const bool xown = iown && R.jown && k >= B.lo[2] && k < B.hi[2];
+    const bool xint = iint && R.jint && k >= 1 && k <= N2 - 2;
+    o[e] = adj_elem(cf, pi, pim, pip, R.rj, R.rjm, R.rjp, kk, kkm, kkp, gx, f4at(gpp, e), f4at(gpm, e),
+                    f4at(gjp, e), f4at(gjm, e), gkr[e], gkl[e], xown, xint);
+    // the terms of adj_elem, each times u[y]
+    const double uy = (double)f4at(wcu.v, e);
+    if (pi && R.rj && kk) cb[0] += uy * (double)gx;
+    if (pip && R.rj && kk) cb[1] += uy * (double)f4at(gpp, e);
+    if (pim && R.rj && kk) cb[2] += uy * (double)f4at(gpm, e);
+    if (pi && R.rjp && kk) cb[3] += uy * (double)f4at(gjp, e);
+    if (pi && R.rjm && kk) cb[4] += uy * (double)f4at(gjm, e);
+    if (pi && R.rj && kkp) cb[5] += uy * (double)gkr[e];
+    if (pi && R.rj && kkm) cb[6] += uy * (double)gkl[e];
+  }
+  if (wfull) {
+    *(gwf4 *)(q + m.c) = f4{o[0], o[1], o[2], o[3]};
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = m.c + e;
+      if (k >= lo[2] && k < hi[2]) q[k] = o[e];
+    }
+  }
+  // the extended column next to the box: only the term of its neighbour
+  // inside the box can be nonzero (every other term needs the cell itself
+  // inside the box), so the values it does not read are passed as zero
+  if (xl) {
+    const int k = m.c - 1;
+    const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
+               kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
+    q[k] = adj_elem(cf, pi, pim, pip, R.rj, R.rjm, R.rjp, kk, kkm, kkp, gcu.h, 0.f, 0.f, 0.f, 0.f, gcu.v.x, 0.f,
+                    false, false);
+    if (pi && R.rj && kkp) cb[5] += (double)wcu.h * (double)gcu.v.x;
+  }
+  if (xr) {
+    const int k = m.c + 4;
+    const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
+               kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
+    q[k] = adj_elem(cf, pi, pim, pip, R.rj, R.rjm, R.rjp, kk, kkm, kkp, gcu.h, 0.f, 0.f, 0.f, 0.f, 0.f, gcu.v.w,
+                    false, false);
+    if (pi && R.rj && kkm) cb[6] += (double)wcu.h * (double)gcu.v.w;
+  }
+}
+
+// The adjoint march over planes [i0, i1) of one row chunk of the extended
+// box, with the loads for plane i + 1 issued before plane i is computed.
+// Rings of registers as in the forward march: du1 row j of planes
+// i - 1 .. i + 2 (four slots), du1 rows j -+ 1 and the u row j of planes
+// i, i + 1 (two slots each); the loop is unrolled four times so that every
+// slot is a fixed set of registers.  Every load is unconditional with
+// clamped indices; a value read through a clamped index only ever enters a
+// term whose flags exclude it.
+template <bool FULL>
+__device__ inline void adj_march(const Coef7 &cf, const WorkBox &B, const int *lo, const int *hi, gcf *g1, gcf *u,
+                                 gwf *g0, int N0, int N1, int N2, int i0, int i1, int j, int c0, bool wfull,
+                                 bool xl, bool xr, double *cb) {
+  const int lane = threadIdx.x & 63;
+  const MarchRow m = march_row(c0, N2, lane);
+  AdjRow R;
+  R.rj = adj_in(j, B.lo[1], B.hi[1], N1);
+  R.rjm = adj_in(j - 1, B.lo[1], B.hi[1], N1);
+  R.rjp = adj_in(j + 1, B.lo[1], B.hi[1], N1);
+  R.jown = j >= B.lo[1] && j < B.hi[1];
+  R.jint = j >= 1 && j <= N1 - 2;
+  MRow G[4], W[2];
+  f4 JM[2], JP[2];
+  // slot of plane p: (p - i0 + 1) & 3 for G, (p - i0) & 1 for the others
+  G[0] = mrdq<FULL>(grow_clamp(g1, i0 - 1, j, N0, N1, N2), m);
+  G[1] = mrdq<FULL>(grow_clamp(g1, i0, j, N0, N1, N2), m);
+  G[2] = mrdq<FULL>(grow_clamp(g1, i0 + 1, j, N0, N1, N2), m);
+  JM[0] = mrd4<FULL>(grow_clamp(g1, i0, j - 1, N0, N1, N2), m);
+  JP[0] = mrd4<FULL>(grow_clamp(g1, i0, j + 1, N0, N1, N2), m);
+  W[0] = mrdq<FULL>(grow_clamp(u, i0, j, N0, N1, N2), m);
+  for (int ib = i0; ib < i1; ib += 4) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = ib + s;
+      if (i >= i1) break;
+      G[(s + 3) & 3] = mrdq<FULL>(grow_clamp(g1, i + 2, j, N0, N1, N2), m);
+      JM[(s + 1) & 1] = mrd4<FULL>(grow_clamp(g1, i + 1, j - 1, N0, N1, N2), m);
+      JP[(s + 1) & 1] = mrd4<FULL>(grow_clamp(g1, i + 1, j + 1, N0, N1, N2), m);
+      W[(s + 1) & 1] = mrdq<FULL>(grow_clamp(u, i + 1, j, N0, N1, N2), m);
+      adj_point(cf, B, lo, hi, m, lane, i, N0, N2, R, G[s & 3].v, G[(s + 1) & 3], G[(s + 2) & 3].v, JM[s & 1],
+                JP[s & 1], W[s & 1], g0 + ((int64_t)i * N1 + j) * N2, wfull, xl, xr, cb);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__restrict__ A) {
   __shared__ double s_red[4][8];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double cb[7] = {0, 0, 0, 0, 0, 0, 0};
   const int64_t nwg = (a.ntiles + 3) >> 2;
   const int64_t t = xcd_remap(blockIdx.x, nwg) * 4 + wv;
@@ -78,7 +192,7 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
     const int j = lo[1] + (int)(lt % jrows);
     const int64_t rest = lt / jrows;
     const int tk = (int)(rest % nk);
-    const int c = kb + tk * 256 + 4 * lane;
+    const int c0 = kb + tk * 256;
     // extended columns outside the column tiles
     const bool xl = lane == 0 && tk == 0 && lo[2] < kb;
     const bool xr = lane == 63 && tk == nk - 1 && hi[2] > kb + nk * 256;
@@ -87,88 +201,14 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
     const int i1 = min(i0 + seg, hi[0]);
     const int N0 = (int)ag.n[0], N1 = (int)ag.n[1], N2 = (int)ag.n[2];
     const bool vec = (N2 & 3) == 0;
-    const float *__restrict__ g1 = reinterpret_cast<const float *>(ag.buf[B.dev]);
-    const float *__restrict__ u = reinterpret_cast<const float *>(au.buf[B.dev]);
-    float *__restrict__ g0 = reinterpret_cast<float *>(ao.buf[B.dev]);
-    const Coef7 &cf = a.cf;
-    // rows of planes i-1 / i / i+1 of du1 (g) and u (w)
-    f4 gpm = ld_rowv(row_ptr(g1, i0 - 1, j, N0, N1, N2), c, N2, vec);
-    RowQ gcu = ld_rowq(row_ptr(g1, i0, j, N0, N1, N2), c, N2, vec, lane);
-    f4 gjm = ld_rowv(row_ptr(g1, i0, j - 1, N0, N1, N2), c, N2, vec);
-    f4 gjp = ld_rowv(row_ptr(g1, i0, j + 1, N0, N1, N2), c, N2, vec);
-    RowQ gpp = ld_rowq(row_ptr(g1, i0 + 1, j, N0, N1, N2), c, N2, vec, lane);
-    // u only at the cell itself: the coefficient gradients are summed over
-    // the cells y this wave visits, c_e-bar += u[y] * du1[y - off_e] for
-    // every y whose output y - off_e is an owned interior cell -- the same
-    // terms as du1[x] * u[x + off_e] over the owned interior outputs x, and
-    // du1 at the neighbours is already in registers
-    RowQ wcu = ld_rowq(row_ptr(u, i0, j, N0, N1, N2), c, N2, vec, lane);
-    const bool rj = adj_in(j, B.lo[1], B.hi[1], N1), rjm = adj_in(j - 1, B.lo[1], B.hi[1], N1),
-               rjp = adj_in(j + 1, B.lo[1], B.hi[1], N1);
-    const bool jown = j >= B.lo[1] && j < B.hi[1], jint = j >= 1 && j <= N1 - 2;
-    for (int i = i0; i < i1; ++i) {
-      RowQ gnq{}, wnq{};
-      f4 gnjm{}, gnjp{};
-      if (i + 1 < i1) {
-        gnq = ld_rowq(row_ptr(g1, i + 2, j, N0, N1, N2), c, N2, vec, lane);
-        gnjm = ld_rowv(row_ptr(g1, i + 1, j - 1, N0, N1, N2), c, N2, vec);
-        gnjp = ld_rowv(row_ptr(g1, i + 1, j + 1, N0, N1, N2), c, N2, vec);
-        wnq = ld_rowq(row_ptr(u, i + 1, j, N0, N1, N2), c, N2, vec, lane);
-      }
-      const float glw = __shfl_up(gcu.v.w, 1), grx = __shfl_down(gcu.v.x, 1);
-      const float gkl[4] = {lane == 0 ? gcu.l : glw, gcu.v.x, gcu.v.y, gcu.v.z};
-      const float gkr[4] = {gcu.v.y, gcu.v.z, gcu.v.w, lane == 63 ? gcu.r : grx};
-      const bool pi = adj_in(i, B.lo[0], B.hi[0], N0), pim = adj_in(i - 1, B.lo[0], B.hi[0], N0),
-                 pip = adj_in(i + 1, B.lo[0], B.hi[0], N0);
-      const bool iown = i >= B.lo[0] && i < B.hi[0], iint = i >= 1 && i <= N0 - 2;
-      float *q = g0 + ((int64_t)i * N1 + j) * N2;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int k = c + e;
-        if (k < lo[2] || k >= hi[2]) continue;
-        const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
-                   kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
-        const float gx = f4at(gcu.v, e);
-        const bool xown = iown && jown && k >= B.lo[2] && k < B.hi[2];
-        const bool xint = iint && jint && k >= 1 && k <= N2 - 2;
-        q[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gx, f4at(gpp.v, e), f4at(gpm, e), f4at(gjp, e),
-                        f4at(gjm, e), gkr[e], gkl[e], xown, xint);
-        // the terms of adj_elem, each times u[y]
-        const double uy = (double)f4at(wcu.v, e);
-        if (pi && rj && kk) cb[0] += uy * (double)gx;
-        if (pip && rj && kk) cb[1] += uy * (double)f4at(gpp.v, e);
-        if (pim && rj && kk) cb[2] += uy * (double)f4at(gpm, e);
-        if (pi && rjp && kk) cb[3] += uy * (double)f4at(gjp, e);
-        if (pi && rjm && kk) cb[4] += uy * (double)f4at(gjm, e);
-        if (pi && rj && kkp) cb[5] += uy * (double)gkr[e];
-        if (pi && rj && kkm) cb[6] += uy * (double)gkl[e];
-      }
-      // the extended column next to the box: only the term of its neighbour
-      // inside the box can be nonzero (every other term needs the cell itself
-      // inside the box), so the values it does not read are passed as zero
-      if (xl) {
-        const int k = c - 1;
-        const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
-                   kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
-        q[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gcu.l, 0.f, 0.f, 0.f, 0.f, gcu.v.x, 0.f, false,
-                        false);
-        if (pi && rj && kkp) cb[5] += (double)wcu.l * (double)gcu.v.x;
-      }
-      if (xr) {
-        const int k = c + 4;
-        const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
-                   kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
-        q[k] = adj_elem(cf, pi, pim, pip, rj, rjm, rjp, kk, kkm, kkp, gcu.r, 0.f, 0.f, 0.f, 0.f, 0.f, gcu.v.w, false,
-                        false);
-        if (pi && rj && kkm) cb[6] += (double)wcu.r * (double)gcu.v.w;
-      }
-      gpm = gcu.v;
-      gcu = gpp;
-      gpp = gnq;
-      gjm = gnjm;
-      gjp = gnjp;
-      wcu = wnq;
-    }
+    gcf *g1 = (gcf *)ag.buf[B.dev];
+    gcf *u = (gcf *)au.buf[B.dev];
+    gwf *g0 = (gwf *)ao.buf[B.dev];
+    const bool wfull = vec && c0 >= lo[2] && c0 + 256 <= hi[2];
+    if (vec && c0 + 256 <= N2)
+      adj_march<true>(a.cf, B, lo, hi, g1, u, g0, N0, N1, N2, i0, i1, j, c0, wfull, xl, xr, cb);
+    else
+      adj_march<false>(a.cf, B, lo, hi, g1, u, g0, N0, N1, N2, i0, i1, j, c0, wfull, xl, xr, cb);
   }
   // fixed-order reduction of the FP64 coefficient partials of this workgroup
 #pragma unroll
