@@ -153,29 +153,29 @@ __global__ __launch_bounds__(64) void k_gdef_large(PlanDev P, ArrDev *__restrict
 // long), and each GDEF cell is updated by one wave.
 constexpr int kDerive1Max = 64;  // slices (and level-2 groups) of the small form
 
-// Two launches per call.  k_runs1 (one workgroup of eight waves): the runs,
-// one wave per slice (the intervals in lanes, runs by ballot).  k_tail1:
+// Two launches per call.  k_runs1: the runs, one wave per slice (the
+// intervals in lanes, runs by ballot).  k_tail1:
 // workgroup 0 turns the runs into the message table (band flags, band scan,
 // heads shared out band by band over its waves with item lists of up to
 // kHead1 items staged in LDS, compaction) while the other workgroups update
 // GDEF (both only read the runs), so the table and the update finish
 // together.
 constexpr int kDerive1Waves = 8, kHead1 = 32;
-
+// k_runs1: one wave per workgroup and one workgroup per slice.  Each slice
+// is a short chain of dependent global loads (slice record, the cell's list,
+// the runs' store).  The kernel runs beside the previous call's user
+// kernel, which holds most of every SIMD's registers: a one-wave workgroup
+// of about 48 VGPRs fits in what is left, where a workgroup of several
+// waves on one CU waits until that CU drains.  The spill pool's top is
+// reset by the compaction that consumes the runs (and at initialisation).
 template <int CAP>
-__global__ __launch_bounds__(64 * kDerive1Waves) void k_runs1(PlanDev P, const ArrDev *__restrict__ A, Work W) {
-  constexpr int kWaveLds = CAP * sizeof(Ivl) + kMaxRunsRow * sizeof(Run);
-  __shared__ __align__(16) char s_buf[kDerive1Waves * kWaveLds];
-  const int wv = threadIdx.x >> 6;
+__global__ __launch_bounds__(64) void k_runs1(PlanDev P, const ArrDev *__restrict__ A, Work W) {
+  __shared__ __align__(16) Ivl s_iv[CAP];
+  __shared__ __align__(16) Run s_rr[kMaxRunsRow];
   if (W.skip && *W.skip) return;  // the plan's stored runs are current
-  // one workgroup: the spill pool can start over here
-  if (threadIdx.x == 0) *W.run_top = 0;
-  __syncthreads();
-  Ivl *iv = reinterpret_cast<Ivl *>(s_buf + wv * kWaveLds);
-  Run *rr = reinterpret_cast<Run *>(s_buf + wv * kWaveLds + CAP * sizeof(Ivl));
-  for (int sl = wv; sl < P.nsl1; sl += kDerive1Waves) {
-    const int nr = dev_runs_find(P, A, W, sl, iv, rr);
-    dev_runs_store(P, W, sl, rr, nr);
+  for (int sl = blockIdx.x; sl < P.nsl1; sl += gridDim.x) {
+    const int nr = dev_runs_find(P, A, W, sl, s_iv, s_rr);
+    dev_runs_store(P, W, sl, s_rr, nr);
     wave_lds_sync();
   }
 }
@@ -413,9 +413,9 @@ hipError_t launch_derive1(const PlanDev &P, ArrDev *A, const Work &W, const Leve
   if (P.nsl1 > kDerive1Max || P.ngrp > kDerive1Max) return hipErrorNotSupported;
   if (P.nsl1 > 0) {
     if (row_cap <= 64)
-      hipLaunchKernelGGL(k_runs1<64>, dim3(1), dim3(64 * kDerive1Waves), 0, s, P, A, W);
+      hipLaunchKernelGGL(k_runs1<64>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
     else
-      hipLaunchKernelGGL(k_runs1<kMaxCap>, dim3(1), dim3(64 * kDerive1Waves), 0, s, P, A, W);
+      hipLaunchKernelGGL(k_runs1<kMaxCap>, dim3(P.nsl1), dim3(64), 0, s, P, A, W);
   }
   const int gw = gdef && P.ngrow > 0 ? (P.ngrow + kDerive1Waves - 1) / kDerive1Waves : 0;
   hipLaunchKernelGGL(k_tail1, dim3(1 + (gw < 1024 ? gw : 1024)), dim3(64 * kDerive1Waves), 0, s, P, A, W, L1, L2,
