@@ -33,15 +33,15 @@ __device__ inline void tile_pos(const WorkBox &B, int64_t lt, int &tx, int &ty) 
 // One row of the lane's 4 columns with its left / right neighbour column
 // (zero when the row is outside the array or past rlim; such rows are never
 // used).  Called by whole waves (the neighbours come from adjacent lanes).
-__device__ inline void load_row(const float *__restrict__ in, int64_t rs, int r, int rlim, int c, int N1, int N2, bool vec,
+__device__ inline void load_row(gcf *__restrict__ in, int64_t rs, int r, int rlim, int c, int N1, int N2, bool vec,
                                 f4 &v, float &Lh, float &Rh) {
   const int lane = threadIdx.x & 63;
   f4 x = {0.f, 0.f, 0.f, 0.f};
   float l = 0.f, rr = 0.f;
   if (r >= 0 && r < N1 && r <= rlim) {
-    const float *p = in + (int64_t)r * rs;
+    gcf *p = in + (int64_t)r * rs;
     if (vec && c + 4 <= N2) {
-      x = *reinterpret_cast<const f4 *>(p + c);
+      x = *(gcf4 *)(p + c);
     } else {
       if (c < N2) x.x = p[c];
       if (c + 1 < N2) x.y = p[c + 1];
@@ -61,16 +61,16 @@ __device__ inline void load_row(const float *__restrict__ in, int64_t rs, int r,
 // Rows r0-1 .. r0+TH of the lane's 4 columns (rows past r1 or outside the
 // array read as zero and are never used).
 template <int TH>
-__device__ inline void load_rows(const float *__restrict__ in, int64_t rs, int r0, int r1, int c, int N1, int N2, bool vec,
+__device__ inline void load_rows(gcf *__restrict__ in, int64_t rs, int r0, int r1, int c, int N1, int N2, bool vec,
                                  f4 *v, float *Lh, float *Rh) {
 #pragma unroll
   for (int k = 0; k < TH + 2; ++k) load_row(in, rs, r0 - 1 + k, r1, c, N1, N2, vec, v[k], Lh[k], Rh[k]);
 }
 
-__device__ inline void store4(float *q, const float *o, const bool *wr, bool vec) {
+__device__ inline void store4(gwf *q, const float *o, const bool *wr, bool vec) {
   if (vec && wr[0] && wr[1] && wr[2] && wr[3]) {
     f4 ov = {o[0], o[1], o[2], o[3]};
-    __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q));
+    __builtin_nontemporal_store(ov, (gwf4 *)(q));
   } else {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
@@ -88,12 +88,12 @@ struct RowI {
   float x[4], l[4], r[4];
 };
 
-__device__ inline RowI load_row_i(const float *__restrict__ in, int64_t rs, int r, int rlim, int tc, int N1, int N2) {
+__device__ inline RowI load_row_i(gcf *__restrict__ in, int64_t rs, int r, int rlim, int tc, int N1, int N2) {
   const int lane = threadIdx.x & 63;
   RowI q;
   float el = 0.f, er = 0.f;
   const bool ok = r >= 0 && r < N1 && r <= rlim;
-  const float *p = in + (int64_t)r * rs;
+  gcf *p = in + (int64_t)r * rs;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int col = tc + 64 * e + lane;
@@ -114,8 +114,8 @@ __device__ inline RowI load_row_i(const float *__restrict__ in, int64_t rs, int 
 }
 
 template <int TH, bool TRI, bool HF>
-__device__ inline void dev_jacobi_tile_i(const WorkBox &B, int tx, int r0, int r1, const float *__restrict__ in,
-                                         float *__restrict__ out, int64_t rsi, int64_t rso, int N1, int N2) {
+__device__ inline void dev_jacobi_tile_i(const WorkBox &B, int tx, int r0, int r1, gcf *__restrict__ in,
+                                         gwf *__restrict__ out, int64_t rsi, int64_t rso, int N1, int N2) {
   const int lane = threadIdx.x & 63;
   const int tc = B.lo[2] + tx * 256;
   RowI v[TH + 2];
@@ -154,8 +154,8 @@ __device__ inline void dev_jacobi_tile(const WorkBox &B, int64_t lt, const ArrDe
   if (TRI && B.lo[2] + tx * 256 > r1 - 1) return;
   const int c = B.lo[2] + tx * 256 + 4 * lane;
   const ArrDev &ai = A[B.ain];
-  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
-  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  gcf *__restrict__ in = (gcf *)ai.buf[B.dev];
+  gwf *__restrict__ out = (gwf *)A[B.aout].buf[B.dev];
   const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
   const int64_t rsi = ai.rs[B.dev], rso = A[B.aout].rs[B.dev];
   const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
@@ -214,8 +214,8 @@ __device__ inline void dev_conv_tile(const WorkBox &B, int64_t lt, const ArrDev 
   const int r1 = min(r0 + TH, B.hi[1]);
   const int c = B.lo[2] + tx * 256 + 4 * lane;
   const ArrDev &ai = A[B.ain];
-  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
-  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  gcf *__restrict__ in = (gcf *)ai.buf[B.dev];
+  gwf *__restrict__ out = (gwf *)A[B.aout].buf[B.dev];
   const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
   const int64_t rsi = ai.rs[B.dev], rso = A[B.aout].rs[B.dev];
   const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
@@ -261,7 +261,7 @@ __device__ inline void dev_conv_tile(const WorkBox &B, int64_t lt, const ArrDev 
 template <int OP>
 __device__ inline void strip_row(int i, int c, int N1, int N2, int64_t rso, const WorkBox &B, const f4 &up, const f4 &cu,
                                  const f4 &dn, float Lu, float Ru, float Lc, float Rc, float Ld, float Rd,
-                                 const Coef9 &W, float *__restrict__ out, bool vec) {
+                                 const Coef9 &W, gwf *__restrict__ out, bool vec) {
   float o[4];
   bool wr[4];
   const float cv[6] = {Lc, cu.x, cu.y, cu.z, cu.w, Rc};
@@ -317,8 +317,8 @@ __device__ inline void dev_strip(const WorkBox &B, int64_t lt, const ArrDev *__r
   if (OP == 1 && B.lo[2] + tx * 256 > r1 - 1) return;
   const int c = B.lo[2] + tx * 256 + 4 * lane;
   const ArrDev &ai = A[B.ain];
-  const float *__restrict__ in = reinterpret_cast<const float *>(ai.buf[B.dev]);
-  float *__restrict__ out = reinterpret_cast<float *>(A[B.aout].buf[B.dev]);
+  gcf *__restrict__ in = (gcf *)ai.buf[B.dev];
+  gwf *__restrict__ out = (gwf *)A[B.aout].buf[B.dev];
   const int N1 = (int)ai.n[1], N2 = (int)ai.n[2];
   const int64_t rsi = ai.rs[B.dev], rso = A[B.aout].rs[B.dev];
   const bool vec = ((N2 & 3) == 0) && ((B.lo[2] & 3) == 0);
@@ -365,8 +365,8 @@ __device__ inline void dev_strip(const WorkBox &B, int64_t lt, const ArrDev *__r
 // of 4); otherwise each wave takes the coalesced per-wave path (no LDS).
 // OP: 0 Jacobi, 1 lower-triangular Jacobi, 2 3 x 3 convolution.
 template <int W, int TH, int OP, bool VEC>
-__device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const float *__restrict__ in, int64_t rsi,
-                                        float *__restrict__ out, int64_t rso, int N1, int N2, const Coef9 &Wt) {
+__device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, gcf *__restrict__ in, int64_t rsi,
+                                        gwf *__restrict__ out, int64_t rso, int N1, int N2, const Coef9 &Wt) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int tx, ty;
   tile_pos<W * TH, true>(B, lt, tx, ty);
@@ -407,11 +407,11 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
   // and written, so no per-lane guard is needed.
   const int tc = B.lo[2] + tx * 256;
   if (OP != 1 && t0 >= 1 && t0 + W * TH <= min(B.hi[1], N1 - 1) && tc >= 1 && tc + 256 <= min(B.hi[2], N2 - 1)) {
-    const float *p = in + (int64_t)(r0 - 1) * rsi + c;
+    gcf *p = in + (int64_t)(r0 - 1) * rsi + c;
 #pragma unroll
-    for (int k = 1; k <= TH; ++k) v[k] = *reinterpret_cast<const f4 *>(p + (int64_t)k * rsi);
-    if (wv == 0) v[0] = *reinterpret_cast<const f4 *>(p);
-    if (wv == W - 1) v[TH + 1] = *reinterpret_cast<const f4 *>(p + (int64_t)(TH + 1) * rsi);
+    for (int k = 1; k <= TH; ++k) v[k] = *(gcf4 *)(p + (int64_t)k * rsi);
+    if (wv == 0) v[0] = *(gcf4 *)(p);
+    if (wv == W - 1) v[TH + 1] = *(gcf4 *)(p + (int64_t)(TH + 1) * rsi);
     const int k0 = OP == 2 ? 0 : 1, k1 = OP == 2 ? TH + 1 : TH;
     float le[TH + 2], ri[TH + 2];
 #pragma unroll
@@ -456,7 +456,7 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
         R[TH + 1] = sr[0][wv + 1][lane];
       }
     }
-    float *q = out + (int64_t)r0 * rso + c;
+    gwf *q = out + (int64_t)r0 * rso + c;
 #pragma unroll
     for (int k = 1; k <= TH; ++k) {
       const f4 up = v[k - 1], cu = v[k], dn = v[k + 1];
@@ -490,7 +490,7 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
         }
       }
       const f4 ov = {o[0], o[1], o[2], o[3]};
-      __builtin_nontemporal_store(ov, reinterpret_cast<f4 *>(q + (int64_t)(k - 1) * rso));
+      __builtin_nontemporal_store(ov, (gwf4 *)(q + (int64_t)(k - 1) * rso));
     }
     return;
   }
@@ -535,9 +535,8 @@ __device__ inline void dev_stack_tile_p(const WorkBox &B, int64_t lt, const floa
 template <int W, int TH, int OP, bool VEC>
 __device__ inline void dev_stack_tile(const WorkBox &B, int64_t lt, const ArrDev *__restrict__ A, const Coef9 &Wt) {
   const ArrDev &ai = A[B.ain], &ao = A[B.aout];
-  dev_stack_tile_p<W, TH, OP, VEC>(B, lt, reinterpret_cast<const float *>(ai.buf[B.dev]), ai.rs[B.dev],
-                                   reinterpret_cast<float *>(ao.buf[B.dev]), ao.rs[B.dev], (int)ai.n[1], (int)ai.n[2],
-                                   Wt);
+  dev_stack_tile_p<W, TH, OP, VEC>(B, lt, (gcf *)ai.buf[B.dev], ai.rs[B.dev], (gwf *)ao.buf[B.dev], ao.rs[B.dev],
+                                   (int)ai.n[1], (int)ai.n[2], Wt);
 }
 
 

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_stack_a(StackArgs a, int64_t ntiles, Co
   B.lo[2] = a.lo2[b];
   B.hi[1] = a.hi1[b];
   B.hi[2] = a.hi2[b];
-  dev_stack_tile_p<4, TH, OP, true>(B, t - a.tile0[b], a.in[b], a.rsi[b], a.out[b], a.rso[b], a.N1, a.N2, w);
+  dev_stack_tile_p<4, TH, OP, true>(B, t - a.tile0[b], (gcf *)a.in[b], a.rsi[b], (gwf *)a.out[b], a.rso[b], a.N1, a.N2, w);
 }
 
 hipError_t launch_stack_args(int op, int th, const StackArgs &a, int64_t ntiles, const float *coef, hipStream_t s) {
