@@ -269,35 +269,48 @@ __device__ inline bool msg_has(const MsgRec &r, int64_t p, int64_t q, int64_t c)
 
 // ordered scatter-add into the owners: the thread of the first message (in
 // table order) that carries a cell adds every contribution to that cell, in
-// table order, to the owner's value
+// table order, to the owner's value.  Each cell scans the message table
+// twice, so the table is staged in LDS when it is small (the records are
+// then LDS reads, not dependent global loads), and the owner's values and
+// the staging words are read through global-address pointers (flat loads
+// would also be waited for by every LDS read).
+constexpr int kUnpackLdsMsgs = 128;
+
 __global__ __launch_bounds__(256) void k_unpack_add(const MsgRec *__restrict__ M, const MsgHdr *__restrict__ H,
                                                     const ArrDev *__restrict__ A, const float *__restrict__ stg) {
+  __shared__ MsgRec s_m[kUnpackLdsMsgs];
   const int64_t n = H->nmsg, words = H->bytes >> 2;
+  const bool in_lds = n <= kUnpackLdsMsgs;
+  if (in_lds)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s_m[i] = M[i];
+  __syncthreads();
+  const MsgRec *T = in_lds ? s_m : M;
+  gcf *sg = (gcf *)stg;
   int m = 0;
   for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x) {
-    if (!(M[m].off <= 4 * w && 4 * w < M[m].off + M[m].bytes)) m = find_msg(M, n, 4 * w);
-    const MsgRec &r = M[m];
+    if (!(T[m].off <= 4 * w && 4 * w < T[m].off + T[m].bytes)) m = find_msg(T, n, 4 * w);
+    const MsgRec &r = T[m];
     const int64_t lw = w - (r.off >> 2);
     if (4 * lw >= r.bytes) continue;
     const int64_t wid = r.hi[2] - r.lo[2], rows = r.hi[1] - r.lo[1];
     const int64_t c = r.lo[2] + lw % wid, t = lw / wid, q = r.lo[1] + t % rows, p = r.lo[0] + t / rows;
     bool first = true;
     for (int64_t m2 = 0; m2 < m; ++m2)
-      if (M[m2].src == r.src && M[m2].arr == r.arr && msg_has(M[m2], p, q, c)) {
+      if (T[m2].src == r.src && T[m2].arr == r.arr && msg_has(T[m2], p, q, c)) {
         first = false;
         break;
       }
     if (!first) continue;
     const ArrDev &a = A[r.arr];
-    float *own = reinterpret_cast<float *>(a.buf[r.src]);
-    const int64_t g = (p * a.n[1] + q) * a.n[2] + c;
+    gwf *own = (gwf *)a.buf[r.src];
+    const int64_t g = HD_EOFF(a, r.src, p, q, c);
     float v = own[g];
     for (int64_t m2 = m; m2 < n; ++m2) {
-      const MsgRec &s = M[m2];
-      if (s.src != r.src || s.arr != r.arr || !msg_has(s, p, q, c)) continue;
-      const int64_t sw = s.hi[2] - s.lo[2], sr = s.hi[1] - s.lo[1];
-      const int64_t idx = ((p - s.lo[0]) * sr + (q - s.lo[1])) * sw + (c - s.lo[2]);
-      v = v + stg[(s.off >> 2) + idx];
+      const MsgRec &e = T[m2];
+      if (e.src != r.src || e.arr != r.arr || !msg_has(e, p, q, c)) continue;
+      const int64_t sw = e.hi[2] - e.lo[2], sr = e.hi[1] - e.lo[1];
+      const int64_t idx = ((p - e.lo[0]) * sr + (q - e.lo[1])) * sw + (c - e.lo[2]);
+      v = v + sg[(e.off >> 2) + idx];
     }
     own[g] = v;
   }
