@@ -140,7 +140,22 @@ __device__ inline void dev_copy_tile(const WorkBox &B, int64_t lt, const ArrDev 
   // window columns start at multiples of 4, so with row strides of a
   // multiple of 4 words an aligned column gives aligned words
   const bool vec = (c0 & 3) == 0 && ((ai.rs[B.dev] * k) & 3) == 0 && ((ao.rs[B.dev] * k) & 3) == 0;
-  for (int r = B.lo[1] + ty * 16; r < min(B.lo[1] + ty * 16 + 16, B.hi[1]); ++r) {
+  const int rb = B.lo[1] + ty * 16;
+  const int64_t wc0 = (int64_t)B.lo[2] * k + (int64_t)tx * 256;
+  if (rb + 16 <= B.hi[1] && wc0 + 256 <= cend && vec) {
+    // a whole tile (wave-uniform test): all sixteen rows' loads in flight
+    // before the first store
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    typedef const u4 __attribute__((address_space(1))) guint4;
+    typedef u4 __attribute__((address_space(1))) gwuint4;
+    u4 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = *(guint4 *)((gcf *)in + HD_EOFF(ai, B.dev, p, rb + q, 0) * k + c0);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) *(gwuint4 *)((gwf *)out + HD_EOFF(ao, B.dev, p, rb + q, 0) * k + c0) = v[q];
+    return;
+  }
+  for (int r = rb; r < min(rb + 16, B.hi[1]); ++r) {
     const int64_t bi = HD_EOFF(ai, B.dev, p, r, 0) * k, bo = HD_EOFF(ao, B.dev, p, r, 0) * k;
     if (vec && c0 + 4 <= cend) {
       *reinterpret_cast<uint4 *>(out + bo + c0) = *reinterpret_cast<const uint4 *>(in + bi + c0);
