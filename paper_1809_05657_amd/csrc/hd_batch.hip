@@ -3,7 +3,8 @@
 //
 // Phases (the same device functions as the per-call kernels, so results are
 // identical bit for bit), separated by grid-wide barriers:
-//   runs -> band flags -> band scan (block 0) -> heads -> compaction (three
+//   runs -> band flags -> band scan (every block, redundantly) and heads,
+//   with no barrier between them -> compaction (three
 //   phases: chunk scans, prefixes and padding in block 0, writes)
 //   [3-D arrays: level-1 compaction in block 0, then level-2 stacking]
 //   -> pack + unpack (one pass) with the GDEF update.
@@ -140,8 +141,11 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
   for (int c = gw; c * 64 < B.L1.nsl; c += nw) dev_bandflags(B.L1, c * 64 + lane);
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
   stamp();
-  if (blockIdx.x == 0 && B.L1.nsl) dev_bandscan(B.L1);
-  if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+  // every workgroup scans the band flags itself: the scan is cheap, its
+  // writes are the same values from every workgroup, and each workgroup's
+  // heads then read what it wrote, so no grid barrier separates the scan
+  // from the heads
+  if (B.L1.nsl) dev_bandscan(B.L1);
   stamp();
   {
     const int nb = B.L1.nsl ? *B.L1.nb : 0;
@@ -159,8 +163,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs B) {
     for (int c = gw; c * 64 < B.L2.nsl; c += nw) dev_bandflags(B.L2, c * 64 + lane);
     if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
     stamp();
-    if (blockIdx.x == 0 && B.L2.nsl) dev_bandscan(B.L2);
-    if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return;
+    if (B.L2.nsl) dev_bandscan(B.L2);
     stamp();
     {
       const int nb = B.L2.nsl ? *B.L2.nb : 0;
