@@ -5,7 +5,8 @@
 // identical bit for bit), separated by grid-wide barriers:
 //   runs -> band flags -> band scan (every block, redundantly) and heads,
 //   with no barrier between them -> compaction (three
-//   phases: chunk scans, prefixes and padding in block 0, writes)
+//   phases: chunk scans, then prefixes and padding in every block and the
+//   writes, without a barrier between those two)
 //   [3-D arrays: level-1 compaction in block 0, then level-2 stacking]
 //   -> pack + unpack (one pass) with the GDEF update.
 // The user kernels (Jacobi / triangular / copy tiles of every box) follow
@@ -90,18 +91,18 @@ __device__ inline bool grid_sync(unsigned *bar, unsigned nblk, unsigned &target,
   return s_ok != 0;
 }
 
-// the three compaction phases (modes 0 and 2) with their barriers
+// the three compaction phases (modes 0 and 2): a grid barrier after the
+// chunk scans; phase 2 runs in every workgroup, so phase 3 follows at once
 __device__ inline bool batch_compact(const BatchArgs &B, const Level &L, int mode, unsigned nblk, unsigned &target,
                                      int32_t *err, int &ph, int64_t *lds) {
   dev_compact_p1(L, B.cs, mode);
   if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return false;
   if (blockIdx.x == 0 && threadIdx.x == 0) B.clk[ph] = wall_clock64();
   ++ph;
-  if (blockIdx.x == 0) dev_compact_p2(B.P, L, B.W, B.hdr, B.tab_cap, B.cs, (int)nblk, mode, lds);
-  if (!grid_sync(B.bar, nblk, target, err, B.spin_limit)) return false;
+  dev_compact_p2(B.P, L, B.W, B.hdr, B.tab_cap, B.cs, (int)nblk, mode, lds);
   if (blockIdx.x == 0 && threadIdx.x == 0) B.clk[ph] = wall_clock64();
   ++ph;
-  dev_compact_p3(B.P, L, B.W, B.tab, B.tab_cap, B.cs, mode);
+  dev_compact_p3(B.P, L, B.W, B.tab, B.tab_cap, B.cs, mode, lds + 2 * kCompactCarr);
   return true;
 }
 

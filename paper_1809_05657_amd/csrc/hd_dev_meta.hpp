@@ -736,6 +736,10 @@ __device__ inline void dev_compact_p1(const Level &L, int64_t *cs, int mode) {
 
 // phase 2 (one workgroup): chunk prefixes, padding per call-array, totals
 // lds: 4 * kCompactCarr int64 of LDS scratch
+// Every workgroup runs phase 2 itself (the same values from each, so the
+// shared writes agree) and keeps the call-arrays' padding in its own LDS
+// (lds + 2 * kCompactCarr) for phase 3, so no grid barrier separates the
+// two phases.
 __device__ inline void dev_compact_p2(const PlanDev &P, const Level &L, const Work &W, MsgHdr *hdr, int64_t out_cap,
                                       int64_t *cs, int nchunk, int mode, int64_t *lds) {
   // all threads load into LDS and scan; one thread walks the call-arrays in
@@ -802,12 +806,12 @@ __device__ inline void dev_compact_p2(const PlanDev &P, const Level &L, const Wo
     *W.run_top = 0;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < ncarr; j += nt) c.first_b[j] = s_at[j];
 }
 
-// phase 3: every workgroup writes the messages of its chunk
+// phase 3: every workgroup writes the messages of its chunk; pad: the
+// call-arrays' padding that phase 2 left in this workgroup's LDS
 __device__ inline void dev_compact_p3(const PlanDev &P, const Level &L, const Work &W, MsgRec *out, int64_t out_cap,
-                                      int64_t *cs, int mode) {
+                                      int64_t *cs, int mode, const int64_t *pad) {
   CScratch c(cs);
   const int nb = L.nsl ? *L.nb : 0;
   const int G = gridDim.x, w = blockIdx.x;
@@ -816,7 +820,7 @@ __device__ inline void dev_compact_p3(const PlanDev &P, const Level &L, const Wo
   for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
     const int j = L.bcarr[b];
     compact_band(P, L, W, out, out_cap, mode, b, (int)(L.nofs[b] + pn),
-                 L.bofs[b] + pb + (j < kCompactCarr ? c.first_b[j] : 0));
+                 L.bofs[b] + pb + (j < kCompactCarr ? pad[j] : 0));
   }
 }
 
