@@ -230,9 +230,9 @@ __global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__rest
 // thread t sums partials t, t + 256, ... in increasing order, then a
 // pairwise tree over the threads; the order depends only on the count, so
 // the result is reproducible.
-__global__ __launch_bounds__(256) void k_cbar_final(const double *part, int64_t nblk, double *cbar) {
+__device__ inline void cbar_final(const double *part, int64_t nblk, double *cbar, int e) {
   __shared__ double s[256];
-  const int e = blockIdx.x, t = threadIdx.x;
+  const int t = threadIdx.x;
   double v = 0.0;
   for (int64_t b = t; b < nblk; b += 256) v += part[b * 8 + e];
   s[t] = v;
@@ -245,12 +245,19 @@ __global__ __launch_bounds__(256) void k_cbar_final(const double *part, int64_t 
 }
 
 // reverse pack: the partial sums at the halo cells of the device that holds
-// them (the forward destination) go to the staging buffer
+// them (the forward destination) go to the staging buffer.  Workgroups past
+// the first npack sum the coefficient partials instead (one per
+// coefficient), beside the pack rather than in a launch of their own.
 __global__ __launch_bounds__(256) void k_rev_pack(const MsgRec *__restrict__ M, const MsgHdr *__restrict__ H,
-                                                  const ArrDev *__restrict__ A, uint32_t *__restrict__ stg) {
+                                                  const ArrDev *__restrict__ A, uint32_t *__restrict__ stg, int npack,
+                                                  const double *part, int64_t nblk, double *cbar) {
+  if ((int)blockIdx.x >= npack) {
+    cbar_final(part, nblk, cbar, (int)blockIdx.x - npack);
+    return;
+  }
   const int64_t n = H->nmsg, words = H->bytes >> 2;
   int m = 0;
-  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (int64_t)npack * blockDim.x) {
     if (!(M[m].off <= 4 * w && 4 * w < M[m].off + M[m].bytes)) m = find_msg(M, n, 4 * w);
     const MsgRec &r = M[m];
     const int64_t lw = w - (r.off >> 2);
@@ -331,15 +338,17 @@ hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const flo
   a.ntiles = ntiles;
   for (int e = 0; e < 7; ++e) a.cf.c[e] = coef[e];
   a.part = part;
+  int64_t nwg = 0;
   if (ntiles > 0) {
-    const int64_t nwg = (ntiles + 3) / 4;
+    nwg = (ntiles + 3) / 4;
     hipLaunchKernelGGL(k_s3d_adj, dim3((unsigned)nwg), dim3(256), 0, s, a, A);
-    if (cbar) hipLaunchKernelGGL(k_cbar_final, dim3(7), dim3(256), 0, s, part, nwg, cbar);
   }
   int grid = (int)((bound_words + 255) / 256);
   if (grid > 4096) grid = 4096;
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_rev_pack, dim3(grid), dim3(256), 0, s, M, H, A, stg);
+  // seven more workgroups reduce the coefficient partials
+  const int ncb = cbar && nwg > 0 ? 7 : 0;
+  hipLaunchKernelGGL(k_rev_pack, dim3(grid + ncb), dim3(256), 0, s, M, H, A, stg, grid, part, nwg, cbar);
   hipLaunchKernelGGL(k_unpack_add, dim3(grid), dim3(256), 0, s, M, H, A, (const float *)stg);
   return hipGetLastError();
 }
