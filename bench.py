@@ -102,7 +102,7 @@ TRAFFIC_WORKLOADS = {
     "stencil3d_512": {"workload": "stencil3d 512^3 fp32, 8 devices (2x2x2), T=64, checkpoint every 8: forward and "
                                   "adjoint steps", "sources": S3D_SOURCES,
                       "bytes": {"k_s3d": 8 * 512 ** 3, "k_s3d_adj": 12 * 512 ** 3, "adjoint_step": 12 * 512 ** 3},
-                      "adjoint_step": ["k_rev_pack", "k_s3d_adj", "k_unpack_add"],
+                      "adjoint_step": ["k_s3d_adj", "k_unpack_add"],
                       "bench": "python3 bench.py --workload stencil3d"},
 }
 
@@ -617,7 +617,7 @@ def bench_stencil3d(hd, rt, steps, warmup, n=512, T=64, ckpt=8):
             "roofline": {"bound": "hbm", "achieved": adj_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": adj_gbs / HBM_PEAK_GBS if adj_gbs else None,
                          "traffic": committed_traffic("stencil3d_512", "adjoint_step", S3D_SOURCES),
-                         "kernel": "adjoint step (k_rev_pack, k_s3d_adj, k_unpack_add)",
+                         "kernel": "adjoint step (k_s3d_adj, k_unpack_add)",
                          "bytes_per_launch": adj_bytes, "avg_launch_us": adj_us},
             "forward_kernel": {"kernel": "k_s3d", "bytes_per_launch": fwd_bytes, "avg_launch_us": fwd_us,
                                "GBps": fwd_gbs, "frac": fwd_gbs / HBM_PEAK_GBS if fwd_gbs else None,

@@ -244,47 +244,30 @@ __device__ inline void cbar_final(const double *part, int64_t nblk, double *cbar
   if (t == 0) cbar[e] += s[0];
 }
 
-// reverse pack: the partial sums at the halo cells of the device that holds
-// them (the forward destination) go to the staging buffer.  Workgroups past
-// the first npack sum the coefficient partials instead (one per
-// coefficient), beside the pack rather than in a launch of their own.
-__global__ __launch_bounds__(256) void k_rev_pack(const MsgRec *__restrict__ M, const MsgHdr *__restrict__ H,
-                                                  const ArrDev *__restrict__ A, uint32_t *__restrict__ stg, int npack,
-                                                  const double *part, int64_t nblk, double *cbar) {
-  if ((int)blockIdx.x >= npack) {
-    cbar_final(part, nblk, cbar, (int)blockIdx.x - npack);
-    return;
-  }
-  const int64_t n = H->nmsg, words = H->bytes >> 2;
-  int m = 0;
-  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (int64_t)npack * blockDim.x) {
-    if (!(M[m].off <= 4 * w && 4 * w < M[m].off + M[m].bytes)) m = find_msg(M, n, 4 * w);
-    const MsgRec &r = M[m];
-    const int64_t lw = w - (r.off >> 2);
-    if (4 * lw >= r.bytes) continue;
-    const int64_t wid = r.hi[2] - r.lo[2], rows = r.hi[1] - r.lo[1];
-    const int64_t c = lw % wid, t = lw / wid, rr = t % rows, p = t / rows;
-    const ArrDev &a = A[r.arr];
-    const int64_t g = ((r.lo[0] + p) * a.n[1] + r.lo[1] + rr) * a.n[2] + r.lo[2] + c;
-    stg[w] = reinterpret_cast<const uint32_t *>(a.buf[r.dst])[g];
-  }
-}
-
 __device__ inline bool msg_has(const MsgRec &r, int64_t p, int64_t q, int64_t c) {
   return p >= r.lo[0] && p < r.hi[0] && q >= r.lo[1] && q < r.hi[1] && c >= r.lo[2] && c < r.hi[2];
 }
 
-// ordered scatter-add into the owners: the thread of the first message (in
-// table order) that carries a cell adds every contribution to that cell, in
-// table order, to the owner's value.  Each cell scans the message table
-// twice, so the table is staged in LDS when it is small (the records are
-// then LDS reads, not dependent global loads), and the owner's values and
-// the staging words are read through global-address pointers (flat loads
-// would also be waited for by every LDS read).
+// The reverse exchange in one pass over the words of the reverse messages:
+// each thread copies its word, the partial sum held by the message's user
+// (the forward destination), into the staging buffer (the wire), and the
+// thread of the first message (in table order) that carries a cell adds
+// every contribution to that cell, in table order, to the owner's value,
+// reading the partials where the users hold them (the same values the
+// staging words carry).  Each cell scans the message table twice, so the
+// table is staged in LDS when it is small, and the buffers are read through
+// global-address pointers (flat loads would also be waited for by every
+// LDS read).  Workgroups past the first npack sum the coefficient partials
+// instead, one per coefficient.
 constexpr int kUnpackLdsMsgs = 128;
 
 __global__ __launch_bounds__(256) void k_unpack_add(const MsgRec *__restrict__ M, const MsgHdr *__restrict__ H,
-                                                    const ArrDev *__restrict__ A, const float *__restrict__ stg) {
+                                                    const ArrDev *__restrict__ A, uint32_t *__restrict__ stg,
+                                                    int npack, const double *part, int64_t nblk, double *cbar) {
+  if ((int)blockIdx.x >= npack) {
+    cbar_final(part, nblk, cbar, (int)blockIdx.x - npack);
+    return;
+  }
   __shared__ MsgRec s_m[kUnpackLdsMsgs];
   const int64_t n = H->nmsg, words = H->bytes >> 2;
   const bool in_lds = n <= kUnpackLdsMsgs;
@@ -292,15 +275,18 @@ __global__ __launch_bounds__(256) void k_unpack_add(const MsgRec *__restrict__ M
     for (int i = threadIdx.x; i < n; i += blockDim.x) s_m[i] = M[i];
   __syncthreads();
   const MsgRec *T = in_lds ? s_m : M;
-  gcf *sg = (gcf *)stg;
+  gwf *sg = (gwf *)stg;
   int m = 0;
-  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (int64_t)npack * blockDim.x) {
     if (!(T[m].off <= 4 * w && 4 * w < T[m].off + T[m].bytes)) m = find_msg(T, n, 4 * w);
     const MsgRec &r = T[m];
     const int64_t lw = w - (r.off >> 2);
     if (4 * lw >= r.bytes) continue;
     const int64_t wid = r.hi[2] - r.lo[2], rows = r.hi[1] - r.lo[1];
     const int64_t c = r.lo[2] + lw % wid, t = lw / wid, q = r.lo[1] + t % rows, p = r.lo[0] + t / rows;
+    const ArrDev &a = A[r.arr];
+    const float mine = ((gcf *)a.buf[r.dst])[HD_EOFF(a, r.dst, p, q, c)];
+    sg[w] = mine;
     bool first = true;
     for (int64_t m2 = 0; m2 < m; ++m2)
       if (T[m2].src == r.src && T[m2].arr == r.arr && msg_has(T[m2], p, q, c)) {
@@ -308,16 +294,13 @@ __global__ __launch_bounds__(256) void k_unpack_add(const MsgRec *__restrict__ M
         break;
       }
     if (!first) continue;
-    const ArrDev &a = A[r.arr];
     gwf *own = (gwf *)a.buf[r.src];
     const int64_t g = HD_EOFF(a, r.src, p, q, c);
-    float v = own[g];
-    for (int64_t m2 = m; m2 < n; ++m2) {
+    float v = own[g] + mine;
+    for (int64_t m2 = m + 1; m2 < n; ++m2) {
       const MsgRec &e = T[m2];
       if (e.src != r.src || e.arr != r.arr || !msg_has(e, p, q, c)) continue;
-      const int64_t sw = e.hi[2] - e.lo[2], sr = e.hi[1] - e.lo[1];
-      const int64_t idx = ((p - e.lo[0]) * sr + (q - e.lo[1])) * sw + (c - e.lo[2]);
-      v = v + sg[(e.off >> 2) + idx];
+      v = v + ((gcf *)a.buf[e.dst])[HD_EOFF(a, e.dst, p, q, c)];
     }
     own[g] = v;
   }
@@ -348,8 +331,7 @@ hipError_t launch_adjoint(const WorkBox *wb, int nbox, int64_t ntiles, const flo
   if (grid < 1) grid = 1;
   // seven more workgroups reduce the coefficient partials
   const int ncb = cbar && nwg > 0 ? 7 : 0;
-  hipLaunchKernelGGL(k_rev_pack, dim3(grid + ncb), dim3(256), 0, s, M, H, A, stg, grid, part, nwg, cbar);
-  hipLaunchKernelGGL(k_unpack_add, dim3(grid), dim3(256), 0, s, M, H, A, (const float *)stg);
+  hipLaunchKernelGGL(k_unpack_add, dim3(grid + ncb), dim3(256), 0, s, M, H, A, stg, grid, part, nwg, cbar);
   return hipGetLastError();
 }
 
