@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_pack(const MsgRec *__restrict__ M, cons
   if (nmsg <= 0) return;
   const int64_t words = H->bytes >> 2;
   const int64_t G = gridDim.x;
-  int64_t S = (words + nmsg * 1024 - 1) / (nmsg * 1024);
+  int64_t S = (words + nmsg * 256 - 1) / (nmsg * 256);
   const int64_t smax = G / nmsg > 1 ? G / nmsg : 1;
   if (S > smax) S = smax;
   if (S < 1) S = 1;
@@ -188,7 +188,8 @@ __global__ void k_reduce_final(int nbox, const double *pf, const uint32_t *pi, v
 hipError_t launch_pack(const MsgRec *M, const MsgHdr *H, const ArrDev *A, uint32_t *stg, int64_t bound_words,
                        int unpack, hipStream_t s) {
   // up to 4 workgroups per CU; fewer when the table cannot be that large
-  int grid = cdiv(bound_words, 1024);
+  // (a workgroup per 256 words: one word per thread and pass)
+  int grid = cdiv(bound_words, 256);
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k_pack, dim3(grid), dim3(256), 0, s, M, H, A, stg, unpack);
