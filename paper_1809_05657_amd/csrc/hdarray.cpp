@@ -290,7 +290,7 @@ struct Runtime {
   hipStream_t meta2 = nullptr;
   hipEvent_t ev_runs = nullptr, ev_gdef = nullptr;
   bool system_events = false;
-  unsigned sync_ev = 0, time_ev = 0;
+  unsigned sync_ev = 0, time_ev = 0, free_ev = 0;
   double *adj_cbar = nullptr;
   // opt-in phase timing
   int prof = 0;  // bit p: time phase p
@@ -483,6 +483,7 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   // writes caches back for the host); timing events need no fence at all
   if (const char *e = getenv("HD_EVENT_SCOPE")) R.system_events = !strcmp(e, "system");
   R.sync_ev = hipEventDisableTiming | (R.system_events ? 0u : (unsigned)hipEventReleaseToDevice);
+  R.free_ev = hipEventDisableTiming | (R.system_events ? 0u : (unsigned)hipEventDisableSystemFence);
   R.time_ev = R.system_events ? 0u : (unsigned)hipEventDisableSystemFence;
   HIPCK(hipEventCreateWithFlags(&R.ev_runs, R.sync_ev));
   HIPCK(hipEventCreateWithFlags(&R.ev_gdef, R.sync_ev));
@@ -1836,7 +1837,13 @@ static int plan_buffers(Plan *pl) {
   if (!pl->ptab || !pl->phdr || !pl->pruns || !pl->proff || !pl->prcnt) return fail(HD_ENOMEM);
   HIPCK(hipMemset(pl->phdr, 0, sizeof(MsgHdr)));
   HIPCK(hipEventCreateWithFlags(&pl->ev_ready, R.sync_ev));
-  HIPCK(hipEventCreateWithFlags(&pl->ev_used, R.sync_ev));
+  // the marker that the plan's stored table has been read by the pack: it
+  // orders a later rewrite of the table after those reads (write after
+  // read), so it carries no data and is recorded without a release fence
+  // (measured: 9735-9762 -> 9906 steps/s with the plan cache on; the same
+  // for the derive-every-step slots measured slower, 9190-9220 -> 8565-8595,
+  // so those keep the device-scope release)
+  HIPCK(hipEventCreateWithFlags(&pl->ev_used, R.free_ev));
   return HD_OK;
 }
 
