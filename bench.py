@@ -675,7 +675,7 @@ def main():
         print(json.dumps({k: v.get("traffic_over_algorithmic") for k, v in out["kernels"].items()}))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs the ApplyKernel path on one GPU only (the logical devices are "
+        print("bench.py: the runtime runs the ApplyKernel path on one GPU only (the logical devices are "
               "partitions of one MI355X); multi-GPU runs are not supported.", file=sys.stderr)
         sys.exit(2)
     import torch

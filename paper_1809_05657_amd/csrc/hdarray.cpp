@@ -503,7 +503,7 @@ extern "C" int hdarray_init(int argc, char **argv, const char *kpath, const char
   HIPCK(hipMemset(R.counters, 0, 64));
   R.W.run_top = R.counters + 0;
   R.W.err = R.counters + 3;
-  // [8]: the plan cache's second-step verdict of the current call, [9]: its hits
+  // [8]: the plan cache's second-step decision for the current call, [9]: its hits
   R.W.skip = nullptr;
   // [4], [5]: rows listed past the one-lane GDEF update; [6], [7]: rows for
   // the LDS update; each pair alternates between calls
