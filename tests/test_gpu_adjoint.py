@@ -176,3 +176,31 @@ def test_adjoint_wide_rows(env, shape):
     g64, gc64 = O.s3d_adjoint64(u0.astype(np.float64), c64, T, w.astype(np.float64))
     assert np.linalg.norm(g0 - g64) / np.linalg.norm(g64) <= 1e-4
     assert np.all(np.abs(cb - gc64) <= 1e-4 * np.abs(gc64))
+
+
+def test_plan_cache_pass_bit_identical(env):
+    """A checkpointed forward + adjoint pass with the plan cache on (Sec.
+    4.2: the forward and recomputation calls skip their derivation when the
+    history decides) gives the same gradient and coefficient gradients, bit
+    for bit, as the pass that derives every call."""
+    hdm, ag, torch = env
+    n = 20
+    say(f"case plan cache pass {n}^3 T=8 ckpt=4")
+    u0, w = stencil3d_inputs(n, seed=9)
+    dev = torch.device("cuda:0")
+    out = []
+    for cache in (False, True):
+        rt = hdm.Runtime()
+        rt.set_plan_cache(cache)
+        solver = ag.Stencil3D(rt, (n, n, n), ndev=8, T=8, ckpt=4)
+        uT = solver.forward(torch.from_numpy(u0).to(dev), list(S3D_COEFFS)).cpu().numpy()
+        g, cb = solver.backward(torch.from_numpy(w).to(dev))
+        g, cb = g.cpu().numpy(), cb.cpu().numpy()
+        # a second pass on the same solver (the cache now holds its plans)
+        uT2 = solver.forward(torch.from_numpy(u0).to(dev), list(S3D_COEFFS)).cpu().numpy()
+        g2, cb2 = solver.backward(torch.from_numpy(w).to(dev))
+        out.append((uT, g, cb, uT2, g2.cpu().numpy(), cb2.cpu().numpy(), rt.stats()))
+        rt.close()
+    for a, b in zip(out[0][:6], out[1][:6]):
+        assert np.array_equal(a, b)
+    assert out[1][6]["cache_hits"] > 0
