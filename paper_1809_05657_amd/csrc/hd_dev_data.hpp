@@ -173,19 +173,19 @@ __host__ __device__ inline int64_t copy_tiles(const WorkBox &B, int esize) {
 }
 
 // ------------------------------------------------------------- stencil3d
-// One wave computes one row (j) of 256 columns (4 per lane) over a segment of
-// planes (B.seg, kS3dSeg when unset), marching in i: the rows of planes
-// i-1, i, i+1 stay in registers, so each plane of the input is read from
-// memory about once; the next plane's rows are requested before the current
-// plane is computed.  Four consecutive rows per workgroup share their
-// j-neighbour rows in cache.  (Plane tiles that issue all of a tile's row
-// loads at once, as the 2-D kernel does, measured slower on the 512^3
-// workload: 900 vs 580 us forward, 2600 vs 1730 us adjoint.)
+// The forward march: one wave computes a pair of rows (j, j + 1) of 256
+// columns (4 per lane) over a segment of planes (B.seg, kS3dSeg when
+// unset), marching in i with the rows of the planes around i in registers
+// (s3d_march_rows below), so each plane of the input is read from memory
+// about once; the adjoint marches one row per wave the same way.  Four
+// consecutive row pairs per workgroup share their j-neighbour rows in
+// cache.  (Plane tiles that issue all of a tile's row loads at once, as
+// the 2-D kernel does, measured slower on the 512^3 workload: 900 vs 580 us
+// forward, 2600 vs 1730 us adjoint.)
 constexpr int kS3dSeg = 32;
-#ifndef HD_S3D_DIST
-#define HD_S3D_DIST 1
-#endif
-constexpr int kS3dDist = HD_S3D_DIST;
+// planes between a row's load and its use in the forward march (two planes
+// ahead measured no faster than one)
+constexpr int kS3dDist = 1;
 
 // Four consecutive elements of a row at columns [c, c + 4) (zeros outside
 // the row); vec: rows are 16-byte aligned and c is a multiple of 4.
