@@ -551,6 +551,50 @@ def test_s3d_adjoint_fp64_dot_product_and_fd():
         assert abs(fd - gc[e]) <= 1e-6 * abs(fd)
 
 
+def _s3d_gather_adjoint(u0, c, T, w, sign=1):
+    """The adjoint of the fixed-boundary 7-point step in gather form (the
+    transposed stencil): every point x collects c_e g(x - o_e) from the
+    interior points that read it through offset o_e, plus g(x) itself when x
+    is a boundary point (copied forward).  sign=-1 mirrors every offset."""
+    n = u0.shape
+    inner = np.zeros(n, dtype=bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    offs = [(0, 0), (0, -1), (0, 1), (1, -1), (1, 1), (2, -1), (2, 1)]
+    states = [u0]
+    for _ in range(T):
+        states.append(O.s3d_forward64(states[-1], c, 1))
+    g = w.copy()
+    gc = np.zeros(7)
+    for t in range(T - 1, -1, -1):
+        gi = np.where(inner, g, 0.0)  # zero on the boundary planes: rolls wrap in zeros
+        h = np.where(inner, 0.0, g)
+        for e, (ax, o) in enumerate(offs):
+            h += c[e] * np.roll(gi, sign * o, axis=ax)
+            gc[e] += np.sum(gi * np.roll(states[t], -sign * o, axis=ax))
+        g = h
+    return g, gc
+
+
+def test_s3d_adjoint_gather_form_matches_scatter_add():
+    """The oracle's adjoint scatters c_e g(y) into y + o_e from every interior
+    y; the gather form (transposed stencil, the form the GPU adjoint kernel
+    evaluates) reaches the same dL/du0 and dL/dc within 1e-6 relative on a
+    non-cubic block over several steps; mirroring the offsets in the gather
+    form breaks the agreement (the asymmetric coefficients see to it)."""
+    rng = np.random.default_rng(61)
+    c = np.array(S3D_COEFFS, dtype=np.float64)
+    u0 = rng.random((7, 9, 6))
+    w = rng.random((7, 9, 6))
+    T = 4
+    gs, gcs = O.s3d_adjoint64(u0, c, T, w)
+    gg, gcg = _s3d_gather_adjoint(u0, c, T, w)
+    assert np.max(np.abs(gg - gs)) <= 1e-6 * np.max(np.abs(gs))
+    assert np.all(np.abs(gcg - gcs) <= 1e-6 * np.abs(gcs))
+    gm, gcm = _s3d_gather_adjoint(u0, c, T, w, sign=-1)
+    assert np.max(np.abs(gm - gs)) > 1e-3 * np.max(np.abs(gs))
+    assert np.max(np.abs(gcm - gcs) / np.abs(gcs)) > 1e-3
+
+
 # --------------------------------------------------------------- partitions
 def test_partition_even_and_manual():
     """Table 2 Partition splits the region evenly; Listing 1's manual regions
