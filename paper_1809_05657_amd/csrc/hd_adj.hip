@@ -42,63 +42,80 @@ __host__ __device__ inline void ext_box(const WorkBox &B, const int64_t *n, int 
 // y is an interior cell of the array inside the work box (one coordinate)
 __device__ inline bool adj_in(int y, int lo, int hi, int n) { return y >= 1 && y <= n - 2 && y >= lo && y < hi; }
 
-// Adjoint value at x: contributions c_e * du1[y] of the outputs y = x - off_e
-// the device owns (interior cells of its box, flags per coordinate), in the
-// order e = 0..6, then du1[x] itself when x is an owned boundary cell.
-__device__ inline float adj_elem(const Coef7 &cf, bool pi, bool pim, bool pip, bool rj, bool rjm, bool rjp,
-                                 bool kk, bool kkm, bool kkp, float gx, float gip, float gim, float gjp, float gjm,
-                                 float gkp, float gkm, bool xown, bool xint) {
-  float acc = 0.f;
-  if (pi && rj && kk) acc = __builtin_fmaf(cf.c[0], gx, acc);
-  if (pip && rj && kk) acc = __builtin_fmaf(cf.c[1], gip, acc);
-  if (pim && rj && kk) acc = __builtin_fmaf(cf.c[2], gim, acc);
-  if (pi && rjp && kk) acc = __builtin_fmaf(cf.c[3], gjp, acc);
-  if (pi && rjm && kk) acc = __builtin_fmaf(cf.c[4], gjm, acc);
-  if (pi && rj && kkp) acc = __builtin_fmaf(cf.c[5], gkp, acc);
-  if (pi && rj && kkm) acc = __builtin_fmaf(cf.c[6], gkm, acc);
-  if (xown && !xint) acc = acc + gx;
-  return acc;
-}
-
-// One plane of the adjoint for lane's four columns of row j: gpm / gpp the
-// du1 row j of planes i -+ 1, gcu (with its halo column) plane i, gjm / gjp
-// du1 rows j -+ 1 of plane i, wcu (with its halo column) the u row j of
-// plane i.  Writes du of the extended box's cells and adds the coefficient
-// gradient terms to cb.
+// row flags of the march: rows j, j -+ 1 interior in the box; row j owned, interior
 struct AdjRow {
   bool rj, rjm, rjp, jown, jint;
 };
 
+// Every du1 value enters the adjoint only through the outputs the device
+// owns: the term c_e du1[y] reaches x = y + off_e, and du1[y] u[y + off_e]
+// enters dc_e, exactly when y is an interior cell of the work box.  So each
+// du1 value is masked once by that flag of its own position (a bit mask,
+// all ones or zero), after which every term is an unconditional fused
+// multiply-add: a masked value adds a zero product, which leaves the sums
+// bitwise unchanged, and a value read through a clamped index is always
+// masked.  The flags split into a column part, fixed per lane for the whole
+// march (VGPR bit masks), and a plane / row part, uniform across the wave.
+struct AdjMask {
+  uint32_t kz[4];  // column of element e is inside the box and interior
+  uint32_t kh;     // the same for the halo column (lane 0: left, lane 63: right)
+  uint32_t cpa[4]; // boundary copy on a boundary plane: row and column owned
+  uint32_t cpb[4]; // boundary copy on an interior plane: owned, not interior
+};
+
+__device__ inline float msk(float v, uint32_t m) { return __uint_as_float(__float_as_uint(v) & m); }
+__device__ inline uint32_t ones(bool b) { return b ? 0xffffffffu : 0u; }
+
+// One plane of the adjoint for lane's four columns of row j: gpm / gpp the
+// du1 row j of planes i -+ 1, gcu (with its halo column) plane i, gjm / gjp
+// du1 rows j -+ 1 of plane i, wcu (with its halo column) the u row j of
+// plane i.  Writes du of the extended box's cells (terms in the order
+// e = 0..6, then du1[x] itself when x is an owned boundary cell) and adds
+// the coefficient gradient terms u[y] du1[y - off_e] to cb.
 __device__ inline void adj_point(const Coef7 &cf, const WorkBox &B, const int *lo, const int *hi, const MarchRow &m,
-                                 int lane, int i, int N0, int N2, const AdjRow &R, const f4 &gpm, const MRow &gcu,
-                                 const f4 &gpp, const f4 &gjm, const f4 &gjp, const MRow &wcu, gwf *q, bool wfull,
-                                 bool xl, bool xr, double *cb) {
-  const float glw = __shfl_up(gcu.v.w, 1), grx = __shfl_down(gcu.v.x, 1);
-  const float gkl[4] = {lane == 0 ? gcu.h : glw, gcu.v.x, gcu.v.y, gcu.v.z};
-  const float gkr[4] = {gcu.v.y, gcu.v.z, gcu.v.w, lane == 63 ? gcu.h : grx};
+                                 int lane, int i, int N0, const AdjRow &R, const AdjMask &M, const f4 &gpm,
+                                 const MRow &gcu, const f4 &gpp, const f4 &gjm, const f4 &gjp, const MRow &wcu,
+                                 gwf *q, bool wfull, bool xl, bool xr, double *cb) {
   const bool pi = adj_in(i, B.lo[0], B.hi[0], N0), pim = adj_in(i - 1, B.lo[0], B.hi[0], N0),
              pip = adj_in(i + 1, B.lo[0], B.hi[0], N0);
   const bool iown = i >= B.lo[0] && i < B.hi[0], iint = i >= 1 && i <= N0 - 2;
+  const uint32_t rc = ones(pi && R.rj), rp = ones(pip && R.rj), rm = ones(pim && R.rj), rjp = ones(pi && R.rjp),
+                 rjm = ones(pi && R.rjm);
+  float zx[4], zp[4], zm[4], zjp[4], zjm[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    zx[e] = msk(f4at(gcu.v, e), M.kz[e] & rc);
+    zp[e] = msk(f4at(gpp, e), M.kz[e] & rp);
+    zm[e] = msk(f4at(gpm, e), M.kz[e] & rm);
+    zjp[e] = msk(f4at(gjp, e), M.kz[e] & rjp);
+    zjm[e] = msk(f4at(gjm, e), M.kz[e] & rjm);
+  }
+  const float zh = msk(gcu.h, M.kh & rc);
+  const float zlw = __shfl_up(zx[3], 1), zrx = __shfl_down(zx[0], 1);
+  const float zkl[4] = {lane == 0 ? zh : zlw, zx[0], zx[1], zx[2]};
+  const float zkr[4] = {zx[1], zx[2], zx[3], lane == 63 ? zh : zrx};
   float o[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int k = m.c + e;
-    const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
-               kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
-    const float gx = f4at(gcu.v, e);
-    const bool xown = iown && R.jown && k >= B.lo[2] && k < B.hi[2];
-    const bool xint = iint && R.jint && k >= 1 && k <= N2 - 2;
-    o[e] = adj_elem(cf, pi, pim, pip, R.rj, R.rjm, R.rjp, kk, kkm, kkp, gx, f4at(gpp, e), f4at(gpm, e),
-                    f4at(gjp, e), f4at(gjm, e), gkr[e], gkl[e], xown, xint);
-    // the terms of adj_elem, each times u[y]
+    float acc = __builtin_fmaf(cf.c[0], zx[e], 0.f);
+    acc = __builtin_fmaf(cf.c[1], zp[e], acc);
+    acc = __builtin_fmaf(cf.c[2], zm[e], acc);
+    acc = __builtin_fmaf(cf.c[3], zjp[e], acc);
+    acc = __builtin_fmaf(cf.c[4], zjm[e], acc);
+    acc = __builtin_fmaf(cf.c[5], zkr[e], acc);
+    acc = __builtin_fmaf(cf.c[6], zkl[e], acc);
+    const uint32_t cp = iown ? (iint ? M.cpb[e] : M.cpa[e]) : 0u;
+    o[e] = acc + msk(f4at(gcu.v, e), cp);
+    // u[y] du1[y - off_e]: the FP64 product of two FP32 values is exact, so
+    // the fused form rounds exactly like a product followed by an add
     const double uy = (double)f4at(wcu.v, e);
-    if (pi && R.rj && kk) cb[0] += uy * (double)gx;
-    if (pip && R.rj && kk) cb[1] += uy * (double)f4at(gpp, e);
-    if (pim && R.rj && kk) cb[2] += uy * (double)f4at(gpm, e);
-    if (pi && R.rjp && kk) cb[3] += uy * (double)f4at(gjp, e);
-    if (pi && R.rjm && kk) cb[4] += uy * (double)f4at(gjm, e);
-    if (pi && R.rj && kkp) cb[5] += uy * (double)gkr[e];
-    if (pi && R.rj && kkm) cb[6] += uy * (double)gkl[e];
+    cb[0] = __builtin_fma(uy, (double)zx[e], cb[0]);
+    cb[1] = __builtin_fma(uy, (double)zp[e], cb[1]);
+    cb[2] = __builtin_fma(uy, (double)zm[e], cb[2]);
+    cb[3] = __builtin_fma(uy, (double)zjp[e], cb[3]);
+    cb[4] = __builtin_fma(uy, (double)zjm[e], cb[4]);
+    cb[5] = __builtin_fma(uy, (double)zkr[e], cb[5]);
+    cb[6] = __builtin_fma(uy, (double)zkl[e], cb[6]);
   }
   if (wfull) {
     *(gwf4 *)(q + m.c) = f4{o[0], o[1], o[2], o[3]};
@@ -109,24 +126,15 @@ __device__ inline void adj_point(const Coef7 &cf, const WorkBox &B, const int *l
       if (k >= lo[2] && k < hi[2]) q[k] = o[e];
     }
   }
-  // the extended column next to the box: only the term of its neighbour
-  // inside the box can be nonzero (every other term needs the cell itself
-  // inside the box), so the values it does not read are passed as zero
+  // the extended column next to the box (outside it, so never owned): only
+  // the term of its neighbour inside the box reaches it
   if (xl) {
-    const int k = m.c - 1;
-    const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
-               kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
-    q[k] = adj_elem(cf, pi, pim, pip, R.rj, R.rjm, R.rjp, kk, kkm, kkp, gcu.h, 0.f, 0.f, 0.f, 0.f, gcu.v.x, 0.f,
-                    false, false);
-    if (pi && R.rj && kkp) cb[5] += (double)wcu.h * (double)gcu.v.x;
+    q[m.c - 1] = __builtin_fmaf(cf.c[5], zx[0], 0.f);
+    cb[5] = __builtin_fma((double)wcu.h, (double)zx[0], cb[5]);
   }
   if (xr) {
-    const int k = m.c + 4;
-    const bool kk = adj_in(k, B.lo[2], B.hi[2], N2), kkp = adj_in(k + 1, B.lo[2], B.hi[2], N2),
-               kkm = adj_in(k - 1, B.lo[2], B.hi[2], N2);
-    q[k] = adj_elem(cf, pi, pim, pip, R.rj, R.rjm, R.rjp, kk, kkm, kkp, gcu.h, 0.f, 0.f, 0.f, 0.f, 0.f, gcu.v.w,
-                    false, false);
-    if (pi && R.rj && kkm) cb[6] += (double)wcu.h * (double)gcu.v.w;
+    q[m.c + 4] = __builtin_fmaf(cf.c[6], zx[3], 0.f);
+    cb[6] = __builtin_fma((double)wcu.h, (double)zx[3], cb[6]);
   }
 }
 
@@ -136,8 +144,7 @@ __device__ inline void adj_point(const Coef7 &cf, const WorkBox &B, const int *l
 // i - 1 .. i + 2 (four slots), du1 rows j -+ 1 and the u row j of planes
 // i, i + 1 (two slots each); the loop is unrolled four times so that every
 // slot is a fixed set of registers.  Every load is unconditional with
-// clamped indices; a value read through a clamped index only ever enters a
-// term whose flags exclude it.
+// clamped indices; a value read through a clamped index is always masked.
 template <bool FULL>
 __device__ inline void adj_march(const Coef7 &cf, const WorkBox &B, const int *lo, const int *hi, gcf *g1, gcf *u,
                                  gwf *g0, int N0, int N1, int N2, int i0, int i1, int j, int c0, bool wfull,
@@ -150,6 +157,16 @@ __device__ inline void adj_march(const Coef7 &cf, const WorkBox &B, const int *l
   R.rjp = adj_in(j + 1, B.lo[1], B.hi[1], N1);
   R.jown = j >= B.lo[1] && j < B.hi[1];
   R.jint = j >= 1 && j <= N1 - 2;
+  AdjMask M;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int k = m.c + e;
+    const bool kown = k >= B.lo[2] && k < B.hi[2], kint = k >= 1 && k <= N2 - 2;
+    M.kz[e] = ones(adj_in(k, B.lo[2], B.hi[2], N2));
+    M.cpa[e] = ones(R.jown && kown);
+    M.cpb[e] = ones(R.jown && kown && !(R.jint && kint));
+  }
+  M.kh = ones(adj_in(lane == 0 ? m.c - 1 : m.c + 4, B.lo[2], B.hi[2], N2));
   MRow G[4], W[2];
   f4 JM[2], JP[2];
   // slot of plane p: (p - i0 + 1) & 3 for G, (p - i0) & 1 for the others
@@ -168,13 +185,13 @@ __device__ inline void adj_march(const Coef7 &cf, const WorkBox &B, const int *l
       JM[(s + 1) & 1] = mrd4<FULL>(grow_clamp(g1, i + 1, j - 1, N0, N1, N2), m);
       JP[(s + 1) & 1] = mrd4<FULL>(grow_clamp(g1, i + 1, j + 1, N0, N1, N2), m);
       W[(s + 1) & 1] = mrdq<FULL>(grow_clamp(u, i + 1, j, N0, N1, N2), m);
-      adj_point(cf, B, lo, hi, m, lane, i, N0, N2, R, G[s & 3].v, G[(s + 1) & 3], G[(s + 2) & 3].v, JM[s & 1],
+      adj_point(cf, B, lo, hi, m, lane, i, N0, R, M, G[s & 3].v, G[(s + 1) & 3], G[(s + 2) & 3].v, JM[s & 1],
                 JP[s & 1], W[s & 1], g0 + ((int64_t)i * N1 + j) * N2, wfull, xl, xr, cb);
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_s3d_adj(AdjArgs a, const ArrDev *__restrict__ A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_s3d_adj(AdjArgs a, const ArrDev *__restrict__ A) {
   __shared__ double s_red[4][8];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double cb[7] = {0, 0, 0, 0, 0, 0, 0};
